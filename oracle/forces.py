@@ -1,0 +1,61 @@
+"""Immersed-boundary force laws and their energies -- oracle side.
+
+Test infrastructure only (see the package docstring).
+"""
+
+import numpy as np
+
+
+def tension_force_2d(X, K):
+    """Closed elastic curve: F_j = K (X_{j+1} + X_{j-1} - 2 X_j) / dtheta^2 (Sec. 6.2.1, eq. elstic_force_2d).
+
+    theta_j = j dtheta, dtheta = 2*pi/M, indices periodic.  X is the unfolded
+    (continuous) curve; the force uses differences only, so it is
+    translation-equivariant.  This is a force density per unit theta: the
+    spread uses quadrature weights w_j = dtheta (eq. force_spreading_quad).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    M = X.shape[0]
+    dth = 2.0 * np.pi / M
+    return K * (np.roll(X, -1, axis=0) + np.roll(X, 1, axis=0) - 2.0 * X) / (dth * dth)
+
+
+def tension_energy_2d(X, K):
+    """E = (K/2) sum_j |X_{j+1} - X_j|^2 / dtheta, whose gradient gives w_j F_j = -dE/dX_j with w_j = dtheta."""
+    X = np.asarray(X, dtype=np.float64)
+    M = X.shape[0]
+    dth = 2.0 * np.pi / M
+    D = np.roll(X, -1, axis=0) - X
+    return 0.5 * K * float(np.sum(D * D)) / dth
+
+
+def surface_tension_force_3d(X, tris, gamma):
+    """Surface tension: F_i = -(gamma/2) sum_{(i,j,k) in Delta_i} (X_j - X_k) x n_ijk (Sec. 6.2.3).
+
+    Each triangle (i, j, k) is visited in its three cyclic rotations; n_ijk is
+    the unit normal by the right-hand rule of (X_i, X_j, X_k).  This is the
+    nodal force -dE/dX_i of E = gamma * (sum of triangle areas), so the spread
+    uses quadrature weights w_i = 1.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    A, B, C = X[tris[:, 0]], X[tris[:, 1]], X[tris[:, 2]]
+    n = np.cross(B - A, C - A)
+    n = n / np.linalg.norm(n, axis=1)[:, None]
+    F = np.zeros_like(X)
+    np.add.at(F, tris[:, 0], -0.5 * gamma * np.cross(B - C, n))
+    np.add.at(F, tris[:, 1], -0.5 * gamma * np.cross(C - A, n))
+    np.add.at(F, tris[:, 2], -0.5 * gamma * np.cross(A - B, n))
+    return F
+
+
+def surface_area(X, tris):
+    """Sum of triangle areas (the surface-tension energy is gamma times this, Sec. 6.2.3)."""
+    X = np.asarray(X, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    A, B, C = X[tris[:, 0]], X[tris[:, 1]], X[tris[:, 2]]
+    return 0.5 * float(np.sum(np.linalg.norm(np.cross(B - A, C - A), axis=1)))
+
+
+def surface_tension_energy_3d(X, tris, gamma):
+    return gamma * surface_area(X, tris)

@@ -1,0 +1,97 @@
+"""One FSIB time step (Alg. 1) and the steady-Stokes variant -- oracle side.
+
+Test infrastructure only (see the package docstring).
+"""
+
+import numpy as np
+
+from . import nudft, fluid, forces
+from .modes import nyquist_mask
+
+
+class ForceLaw:
+    """A force model F(X) with its quadrature weights w_j.
+
+    kind "tension2d": closed curve, eq. elstic_force_2d, w_j = dtheta = 2*pi/M.
+    kind "surface3d": triangulated surface tension (Sec. 6.2.3), w_j = 1.
+    """
+
+    def __init__(self, kind, K, tris=None):
+        self.kind = kind
+        self.K = float(K)
+        self.tris = None if tris is None else np.asarray(tris, dtype=np.int64)
+
+    def __call__(self, X):
+        M = X.shape[0]
+        if self.kind == "tension2d":
+            return forces.tension_force_2d(X, self.K), 2.0 * np.pi / M
+        if self.kind == "surface3d":
+            return forces.surface_tension_force_3d(X, self.tris, self.K), 1.0
+        raise ValueError(self.kind)
+
+
+def spread_force(X, F, w, Ns, L):
+    """fhat(k) = L^-d sum_j w_j F_j exp(-i k.X_j), k in K_N (eq. force_spreading_quad); shape (d, spectral)."""
+    d = X.shape[1]
+    c = (np.asarray(w) * np.ones(X.shape[0]))[None, :] * np.asarray(F, dtype=np.float64).T
+    return nudft.type1(X, c.astype(np.complex128), Ns, L, scale=float(L) ** (-d))
+
+
+def interp_velocity(X, uhat, Ns, L):
+    """U_j = sum_{k in K_N} uhat(k) exp(i k.X_j) (eq. velo_intp_fini); returns the real part, (M, d).
+
+    For Nyquist-zeroed Hermitian uhat the sum is real up to rounding.
+    """
+    return np.real(nudft.type2(X, uhat, Ns, L)).T.copy()
+
+
+def stokes_velocity(X, force, Ns, L, mu):
+    """Steady Stokes boundary velocity U(X) = interp(Stokeslet(spread(F(X))), X) (Sec. 6.1).
+
+    Reading: the Stokes variant drops the time derivative and nonlinear term,
+    so the fluid velocity is a function of the boundary configuration.
+    Returns (U, uhat), uhat Nyquist-zeroed.
+    """
+    F, w = force(X)
+    fhat = spread_force(X, F, w, Ns, L)
+    uhat = fluid.stokeslet(fhat, Ns, L, mu)
+    uhat[:, nyquist_mask(Ns)] = 0.0
+    return interp_velocity(X, uhat, Ns, L), uhat
+
+
+def stokes_step(X, U, force, Ns, L, mu, dt):
+    """Midpoint step for the Stokes variant (eqs. spatial_1 and spatial_4 with U from stokes_velocity).
+
+    Returns (X_new, U_new, uhat_new) where U_new = U(X_new) is U^m of the next step.
+    """
+    Xh = X + 0.5 * dt * U
+    Uh, _ = stokes_velocity(Xh, force, Ns, L, mu)
+    Xn = X + dt * Uh
+    Un, uhat = stokes_velocity(Xn, force, Ns, L, mu)
+    return Xn, Un, uhat
+
+
+def ns_step(X, U, uhat, force, Ns, L, rho, mu, dt, npad=None, return_mid=False):
+    """One step of Alg. 1 (Navier-Stokes).
+
+    X^{m+1/2} = X^m + dt/2 U^m                              (eq. spatial_1)
+    F^{m+1/2} = F(X^{m+1/2}); fhat from the type-1 sum      (eq. force_spreading_quad)
+    uhat^{m+1/2}, uhat^{m+1} by the two Fourier updates      (eqs. spatial_2, spatial_3)
+    U^{m+1/2} = interp(uhat^{m+1/2}, X^{m+1/2})
+    X^{m+1}   = X^m + dt U^{m+1/2}                          (eq. spatial_4)
+    U^{m+1}   = interp(uhat^{m+1}, X^{m+1})
+
+    Reading: Alg. 1 does not say where U^{m+1/2} and U^{m+1} are evaluated;
+    they are taken at X^{m+1/2} and X^{m+1} respectively, the latter being the
+    U^m of the next step.
+    """
+    Xh = X + 0.5 * dt * U
+    F, w = force(Xh)
+    fhat = spread_force(Xh, F, w, Ns, L)
+    uh, un = fluid.ns_update(fhat, uhat, Ns, L, rho, mu, dt, npad)
+    Uh = interp_velocity(Xh, uh, Ns, L)
+    Xn = X + dt * Uh
+    Un = interp_velocity(Xn, un, Ns, L)
+    if return_mid:
+        return Xn, Un, un, dict(Xh=Xh, F=F, w=w, fhat=fhat, uhat_half=uh, U_half=Uh)
+    return Xn, Un, un
