@@ -1,0 +1,185 @@
+/*
+ * fsib.h -- C ABI of the MI355X (gfx950) Fourier spectral immersed boundary (FSIB) hot path.
+ *
+ * Method: Chen & Peskin, "A Fourier spectral immersed boundary method with exact translation
+ * invariance, improved boundary resolution, and a divergence-free velocity field".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named X, c, fhat, F, S, U, uhat, ... are DEVICE pointers owned by the caller, unless
+ *    a comment says "host".  The library never frees or keeps them after the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream).  Every call that
+ *    takes a stream only enqueues work on it and returns without synchronising, except
+ *    fsib_plan_create (allocates and synchronises once) and fsib_plan_check (synchronises).
+ *  - The truncated mode set K_N (Sec. 3.1, eq. kNh): per axis m in [-N/2, N/2-1] (even N) or
+ *    [-(N-1)/2, (N-1)/2] (odd N), k = 2*pi*m/L.  Spectral arrays are in FFT order (m = 0, 1, ...,
+ *    then the negative modes; the zero mode first) with the x index fastest, then y, then z.
+ *  - "Full" spectral array of one transform: N_z*N_y*N_x complex values (2D: N_y*N_x).
+ *    "Half" spectral array of one real field: N_z*N_y*H_x complex values, H_x = floor(N_x/2)+1,
+ *    holding m_x = 0..H_x-1 (the other half is the complex conjugate).  Vector fields are
+ *    component-major: d consecutive scalar arrays (d = dim).
+ *  - Complex values are interleaved (re, im) pairs of the plan precision: double for FSIB_F64,
+ *    float for FSIB_F32.  "prec" below means that scalar type.
+ *  - Positions X are always double, shape (M, dim) row-major, any real values: the L-periodicity
+ *    is applied inside (x is folded to [0, L) in double before any rounding to prec).
+ *  - Argument checks happen before anything is enqueued; on error nothing is written and the
+ *    status says why (fsib_last_error() gives a message, per thread).  HIP failures map to
+ *    FSIB_ERR_HIP.
+ *  - The compute entry points allocate no memory: the plan owns its workspace, sized at creation
+ *    for dim, N, precision, ntrans and max_points.
+ *  - A plan is not thread-safe: calls that share a plan must be issued in order on one stream.
+ */
+#ifndef FSIB_H
+#define FSIB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsib_plan_s* fsib_plan;
+
+typedef enum { FSIB_F64 = 0, FSIB_F32 = 1 } fsib_prec;
+
+typedef enum {
+  FSIB_OK = 0,
+  FSIB_ERR_ARG = 1,        /* invalid argument (null pointer, size out of range, unsupported option) */
+  FSIB_ERR_TOL = 2,        /* requested tolerance not reachable in the plan precision */
+  FSIB_ERR_NO_DEVICE = 3,  /* no HIP device visible */
+  FSIB_ERR_OOM = 4,        /* workspace allocation failed at plan creation */
+  FSIB_ERR_HIP = 5,        /* a HIP runtime call failed; fsib_last_error() holds its message */
+  FSIB_ERR_NONFINITE = 6,  /* a NaN/Inf position was seen since the last fsib_plan_check */
+  FSIB_ERR_STATE = 7       /* the plan lacks the workspace this call needs (see fsib_plan_opts) */
+} fsib_status;
+
+typedef struct {
+  int dim;              /* 2 or 3 */
+  int64_t n_modes[3];   /* N per axis (x, y, z), each >= 2; n_modes[2] ignored in 2D */
+  double L;             /* period of the box [0, L)^dim, > 0 */
+  int prec;             /* fsib_prec: arithmetic of grids, FFTs, spectral update, U */
+  double tol;           /* relative l2 accuracy asked of the nonuniform transforms:
+                           FP64 in [1e-14, 1e-1], FP32 in [1e-6, 1e-1] (else FSIB_ERR_TOL) */
+  double upsampfac;     /* fine-grid oversampling; 0 or 2.0 (the only supported value) */
+  int ntrans;           /* complex transforms per fsib_spread / fsib_interp call, >= 1 */
+  int64_t max_points;   /* largest M accepted by any call, >= 0 */
+  int fluid;            /* 0: NUFFT only; 1: also the FSIB workspace (force spread, velocity
+                           interp, fluid step, time step) */
+  int navier_stokes;    /* with fluid = 1: 1 also allocates the dealiasing workspace (Sec. 3.1) */
+} fsib_plan_opts;
+
+/* Read-only facts about a plan (host struct filled by fsib_plan_info). */
+typedef struct {
+  int w;                /* kernel width in fine-grid cells */
+  double beta;          /* Kaiser-Bessel shape parameter (App. A, eq. kernel_KB) */
+  int degree;           /* degree of the piecewise polynomial that evaluates the kernel */
+  int64_t n_fine[3];    /* fine (oversampled) grid per axis */
+  int64_t n_dealias[3]; /* dealiasing grid per axis (0 unless navier_stokes) */
+  int64_t tile[3];      /* spreading tile (= bin) size per axis in fine cells */
+  int64_t workspace_bytes;
+} fsib_plan_info_t;
+
+typedef enum { FSIB_STOKES = 0, FSIB_NAVIER_STOKES = 1 } fsib_model;
+
+typedef struct {
+  int model;            /* fsib_model */
+  double rho, mu, dt;   /* density, viscosity (> 0), time step */
+} fsib_fluid_params;
+
+typedef enum { FSIB_FORCE_CURVE_TENSION = 0, FSIB_FORCE_SURFACE_TENSION = 1 } fsib_force_kind;
+
+typedef struct {
+  int kind;                 /* fsib_force_kind */
+  double K;                 /* stiffness K (curve tension) or surface tension gamma */
+  const int32_t* tris;      /* SURFACE_TENSION: device (ntris, 3) vertex indices, counter-clockwise
+                               seen from outside */
+  int64_t ntris;
+  const int32_t* v2t_ptr;   /* device CSR (M+1) offsets: triangles incident to each vertex */
+  const int32_t* v2t_idx;   /* device CSR (3*ntris) triangle ids */
+} fsib_force;
+
+/* ---- library ------------------------------------------------------------------------------- */
+const char* fsib_version(void);
+const char* fsib_status_string(fsib_status s);
+const char* fsib_last_error(void);  /* message of the last failing call on this thread */
+int fsib_device_count(void);        /* visible HIP devices (0 when none or no driver) */
+
+/* ---- plans ---------------------------------------------------------------------------------- */
+/* Chooses the kernel width/shape for `tol` (App. A.3), the fine grid (upsampfac * N rounded to a
+ * 2^a 3^b 5^c multiple of the tile), twiddle and deconvolution tables, and allocates the workspace
+ * on the current device.  *out is written only on success. */
+fsib_status fsib_plan_create(const fsib_plan_opts* opts, fsib_plan* out);
+fsib_status fsib_plan_destroy(fsib_plan plan);  /* waits for the plan's work, frees the workspace */
+fsib_status fsib_plan_info(fsib_plan plan, fsib_plan_info_t* info /* host */);
+/* Synchronises `stream`; returns FSIB_ERR_NONFINITE (and clears the flag) if any call since the
+ * last check saw a non-finite position (such points are treated as x = 0), else FSIB_OK. */
+fsib_status fsib_plan_check(fsib_plan plan, void* stream);
+
+/* ---- nonuniform transforms (App. A) --------------------------------------------------------- */
+/* Type-1 (App. A, eq. type1; with scale = L^-d it is eq. force_spreading_quad):
+ *   fhat[t][k] = scale * sum_j c[t][j] exp(-i k.X_j),  k in K_N,  t < ntrans.
+ * c: ntrans x M complex prec (transform-major); fhat: ntrans full spectral arrays.
+ * Computed by spreading onto the fine grid with the plan kernel, an FFT, truncation to K_N and
+ * division by the kernel transform (eqs. type1_conv, type1_deco); relative l2 error ~ tol. */
+fsib_status fsib_spread(fsib_plan plan, int64_t M, const double* X, const void* c, void* fhat,
+                        double scale, void* stream);
+/* Type-2 (App. A, eq. type2): c[t][j] = sum_{k in K_N} fhat[t][k] exp(+i k.X_j).
+ * fhat: ntrans full spectral arrays; c: ntrans x M complex prec (eqs. type2_divi, type2_conv). */
+fsib_status fsib_interp(fsib_plan plan, int64_t M, const double* X, const void* fhat, void* c,
+                        void* stream);
+
+/* ---- FSIB coupling (Sec. 3.1); plans created with fluid = 1 ---------------------------------- */
+/* Force spreading of real vector strengths S (M, dim) prec (S_j = w_j F_j):
+ *   fhat[a][k] = scale * sum_j S[j][a] exp(-i k.X_j)   (eq. force_spreading_quad, scale = L^-d),
+ * written as dim half spectral arrays. */
+fsib_status fsib_force_spread(fsib_plan plan, int64_t M, const double* X, const void* S,
+                              void* fhat_half, double scale, void* stream);
+/* Velocity interpolation U[j][a] = sum_{k in K_N} uhat_a(k) exp(i k.X_j) (eq. velo_intp_fini)
+ * from dim half spectral arrays (the field is real: uhat(-k) = conj uhat(k)); modes with any
+ * m_a = -N_a/2 (even N_a) must be zero -- the fluid step guarantees it -- and are ignored.
+ * U: (M, dim) prec. */
+fsib_status fsib_velocity_interp(fsib_plan plan, int64_t M, const double* X, const void* uhat_half,
+                                 void* U, void* stream);
+/* Fourier-space fluid update on half spectral arrays (dim components each).
+ *  NAVIER_STOKES (Alg. 1, eqs. spatial_2 and spatial_3, with V-hat of Alg. 2 and the dealiased
+ *  nonlinear term of eq. nonlinear_kspace; plan needs navier_stokes = 1):
+ *    uhat_mid = (dt/2 V(fhat, uhat) + uhat)/(1+a);  uhat <- (dt V(fhat, uhat_mid) + (1-a) uhat)/(1+a),
+ *    a = mu dt |k|^2 / (2 rho);  uhat_mid may be NULL.
+ *  STOKES (Sec. 6.1, eq. stokeslet): uhat <- (1/mu)(I/|k|^2 - k k^T/|k|^4) fhat, uhat(0) = 0;
+ *    uhat_mid, if not NULL, receives the same.
+ * fhat is the output of fsib_force_spread with scale L^-d.  Every output has the modes with any
+ * m_a = -N_a/2 (even N_a) set to zero. */
+fsib_status fsib_fluid_step(fsib_plan plan, const fsib_fluid_params* params, const void* fhat_half,
+                            void* uhat_half, void* uhat_mid, void* stream);
+/* Nodal force F(X) of a built-in model, double (M, dim):
+ *  CURVE_TENSION (dim 2, Sec. 6.2.1 eq. elstic_force_2d): F_j = K (X_{j+1}+X_{j-1}-2X_j)/dtheta^2,
+ *    dtheta = 2 pi / M (force per unit theta; quadrature weight dtheta).
+ *  SURFACE_TENSION (dim 3, Sec. 6.2.3): F_i = -(K/2) sum_{(i,j,k)} (X_j - X_k) x n_ijk (nodal force,
+ *    weight 1).  Needs tris and the vertex->triangle CSR. */
+fsib_status fsib_compute_force(const fsib_force* force, int dim, int64_t M, const double* X,
+                               double* F, void* stream);
+/* Boundary velocity at X for the current state:  NAVIER_STOKES: U = interp(uhat, X) (uhat is
+ * input).  STOKES: uhat <- Stokeslet(spread(w F(X))), U = interp(uhat, X) (uhat is output).
+ * This gives U^0 for the first fsib_step. */
+fsib_status fsib_velocity(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force,
+                          int64_t M, const double* X, void* U, void* uhat_half, void* stream);
+/* One time step of Alg. 1 (Sec. 3.3): X (double, in/out), U (prec, in U^m, out U^{m+1}),
+ * uhat_half (in/out).  X^{m+1/2} = X^m + dt/2 U^m; F^{m+1/2} = F(X^{m+1/2}); fhat from the spread;
+ * the fluid update; U^{m+1/2} = interp(uhat^{m+1/2}, X^{m+1/2}); X^{m+1} = X^m + dt U^{m+1/2};
+ * U^{m+1} = interp(uhat^{m+1}, X^{m+1}).  STOKES: uhat is a function of X (see fsib_velocity).
+ * X stays double in both precisions.  diag (device, nullable) receives FSIB_DIAG_COUNT doubles:
+ *   [0..2] sum_j w_j F_j^{m+1/2}          (Sec. 5.3; [2] = 0 in 2D)
+ *   [3..5] Re uhat^{m+1}(k = 0)
+ *   [6]    E_K = rho/2 L^d sum_k |uhat^{m+1}|^2                     (Sec. 5.4)
+ *   [7]    mu L^d sum_k |k|^2 |uhat^{m+1}|^2 (viscous dissipation)   (Sec. 5.4)
+ *   [8]    sum_j w_j F_j^{m+1/2} . U_j^{m+1/2} (power)               (Sec. 5.4)
+ *   [9]    max_k |k . uhat^{m+1}| / (|k| |uhat^{m+1}|)               (Sec. 5.1)
+ *   [10]   area (2D, shoelace) or volume (3D, signed tetrahedra) enclosed by X^{m+1} (Sec. 6.2) */
+#define FSIB_DIAG_COUNT 11
+fsib_status fsib_step(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force,
+                      int64_t M, double* X, void* U, void* uhat_half, double* diag, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSIB_H */

@@ -1,0 +1,293 @@
+"""ctypes marshalling for libfsib.so (argument checks and pointer passing only)."""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libfsib.so"
+DIAG_COUNT = 11
+
+FSIB_F64, FSIB_F32 = 0, 1
+FSIB_STOKES, FSIB_NAVIER_STOKES = 0, 1
+FSIB_FORCE_CURVE_TENSION, FSIB_FORCE_SURFACE_TENSION = 0, 1
+
+
+class FSIBError(RuntimeError):
+    def __init__(self, status, name, message):
+        super().__init__(f"{name}: {message} (status {status})")
+        self.status = status
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_modes", ctypes.c_int64 * 3), ("L", ctypes.c_double),
+                ("prec", ctypes.c_int), ("tol", ctypes.c_double), ("upsampfac", ctypes.c_double),
+                ("ntrans", ctypes.c_int), ("max_points", ctypes.c_int64), ("fluid", ctypes.c_int),
+                ("navier_stokes", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int), ("beta", ctypes.c_double), ("degree", ctypes.c_int),
+                ("n_fine", ctypes.c_int64 * 3), ("n_dealias", ctypes.c_int64 * 3), ("tile", ctypes.c_int64 * 3),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
+class _Force(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("K", ctypes.c_double), ("tris", ctypes.c_void_p), ("ntris", ctypes.c_int64),
+                ("v2t_ptr", ctypes.c_void_p), ("v2t_idx", ctypes.c_void_p)]
+
+
+_SIGS = {
+    "fsib_version": (ctypes.c_char_p, []),
+    "fsib_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fsib_last_error": (ctypes.c_char_p, []),
+    "fsib_device_count": (ctypes.c_int, []),
+    "fsib_plan_create": (ctypes.c_int, [ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_void_p)]),
+    "fsib_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fsib_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
+    "fsib_plan_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_spread": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_double, ctypes.c_void_p]),
+    "fsib_interp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
+    "fsib_force_spread": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "fsib_velocity_interp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_fluid_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_compute_force": (ctypes.c_int, [ctypes.POINTER(_Force), ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_velocity": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def library_path():
+    return os.path.join(_HERE, _LIBNAME)
+
+
+def load_library():
+    """Load libfsib.so (built in-tree by paper_2302_08694_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run `python -m paper_2302_08694_amd.build` "
+                              "(the FSIB path has no CPU fallback)")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status, name):
+    if status != 0:
+        lib = load_library()
+        raise FSIBError(status, name, lib.fsib_last_error().decode())
+
+
+def version():
+    return load_library().fsib_version().decode()
+
+
+def device_count():
+    return int(load_library().fsib_device_count())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else 0)
+
+
+def _need(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor (the FSIB path runs on the GPU only)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class FluidParams:
+    def __init__(self, model="navier_stokes", rho=1.0, mu=1.0, dt=1e-3):
+        m = {"stokes": FSIB_STOKES, "navier_stokes": FSIB_NAVIER_STOKES}[model]
+        self._s = _Params(m, float(rho), float(mu), float(dt))
+        self.model, self.rho, self.mu, self.dt = model, rho, mu, dt
+
+
+class Force:
+    """Built-in force law: kind "tension2d" (closed curve) or "surface3d" (triangulated surface).
+
+    For "surface3d" give tris (T,3) and the vertex->triangle CSR (ptr, idx) as int32 device tensors.
+    """
+
+    def __init__(self, kind, K, tris=None, v2t_ptr=None, v2t_idx=None):
+        k = {"tension2d": FSIB_FORCE_CURVE_TENSION, "surface3d": FSIB_FORCE_SURFACE_TENSION}[kind]
+        self.kind = kind
+        self._keep = (tris, v2t_ptr, v2t_idx)
+        ntris = 0
+        if kind == "surface3d":
+            _need(tris, "tris", torch.int32)
+            _need(v2t_ptr, "v2t_ptr", torch.int32)
+            _need(v2t_idx, "v2t_idx", torch.int32)
+            ntris = tris.shape[0]
+        self._s = _Force(k, float(K), _ptr(tris).value if tris is not None else None, ntris,
+                         _ptr(v2t_ptr).value if v2t_ptr is not None else None,
+                         _ptr(v2t_idx).value if v2t_idx is not None else None)
+
+
+def compute_force(force, X):
+    """Nodal force F(X) (double, same shape as X) of a built-in force law."""
+    lib = load_library()
+    dim = X.shape[1]
+    _need(X, "X", torch.float64)
+    F = torch.empty_like(X)
+    _check(lib.fsib_compute_force(ctypes.byref(force._s), dim, X.shape[0], _ptr(X), _ptr(F), _stream()),
+           "fsib_compute_force")
+    return F
+
+
+class Plan:
+    def __init__(self, dim, n_modes, L=1.0, prec="f64", tol=1e-6, ntrans=1, max_points=1 << 16, fluid=False,
+                 navier_stokes=False):
+        lib = load_library()
+        nm = list(n_modes) + [1] * (3 - len(n_modes))
+        self.dim = int(dim)
+        self.n_modes = tuple(int(n) for n in n_modes[:dim])
+        self.L = float(L)
+        self.prec = prec
+        self.rdtype = {"f64": torch.float64, "f32": torch.float32}[prec]
+        self.cdtype = {"f64": torch.complex128, "f32": torch.complex64}[prec]
+        self.ntrans = int(ntrans)
+        self.max_points = int(max_points)
+        opts = _Opts(self.dim, (ctypes.c_int64 * 3)(*nm), self.L, FSIB_F64 if prec == "f64" else FSIB_F32,
+                     float(tol), 2.0, self.ntrans, self.max_points, int(bool(fluid)), int(bool(navier_stokes)))
+        h = ctypes.c_void_p()
+        _check(lib.fsib_plan_create(ctypes.byref(opts), ctypes.byref(h)), "fsib_plan_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fsib_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes
+    @property
+    def spectral_shape(self):
+        return tuple(reversed(self.n_modes))
+
+    @property
+    def half_shape(self):
+        s = list(reversed(self.n_modes))
+        s[-1] = self.n_modes[0] // 2 + 1
+        return tuple(s)
+
+    def info(self):
+        inf = _Info()
+        _check(self._lib.fsib_plan_info(self._h, ctypes.byref(inf)), "fsib_plan_info")
+        return dict(w=inf.w, beta=inf.beta, degree=inf.degree, n_fine=tuple(inf.n_fine)[: self.dim],
+                    n_dealias=tuple(inf.n_dealias)[: self.dim], tile=tuple(inf.tile)[: self.dim],
+                    workspace_bytes=inf.workspace_bytes)
+
+    def check(self):
+        _check(self._lib.fsib_plan_check(self._h, _stream()), "fsib_plan_check")
+
+    def _X(self, X):
+        _need(X, "X", torch.float64)
+        if X.dim() != 2 or X.shape[1] != self.dim:
+            raise ValueError(f"X must have shape (M, {self.dim})")
+        return X.shape[0]
+
+    def spread(self, X, c, scale=1.0, out=None):
+        M = self._X(X)
+        c = _need(c, "c", self.cdtype)
+        if tuple(c.shape) not in ((self.ntrans, M),) + (((M,),) if self.ntrans == 1 else ()):
+            raise ValueError("c must have shape (ntrans, M) (or (M,) with ntrans = 1)")
+        shp = ((self.ntrans,) if self.ntrans > 1 or c.dim() == 2 else ()) + self.spectral_shape
+        out = torch.empty(shp, dtype=self.cdtype, device=X.device) if out is None else _need(out, "fhat", self.cdtype, shp)
+        _check(self._lib.fsib_spread(self._h, M, _ptr(X), _ptr(c), _ptr(out), float(scale), _stream()), "fsib_spread")
+        return out
+
+    def interp(self, X, fhat, out=None):
+        M = self._X(X)
+        fhat = _need(fhat, "fhat", self.cdtype)
+        if fhat.numel() != self.ntrans * int(torch.tensor(self.spectral_shape).prod()):
+            raise ValueError("fhat must hold ntrans full spectral arrays")
+        shp = (self.ntrans, M) if (self.ntrans > 1 or fhat.dim() == self.dim + 1) else (M,)
+        out = torch.empty(shp, dtype=self.cdtype, device=X.device) if out is None else _need(out, "c", self.cdtype, shp)
+        _check(self._lib.fsib_interp(self._h, M, _ptr(X), _ptr(fhat), _ptr(out), _stream()), "fsib_interp")
+        return out
+
+    def force_spread(self, X, S, scale, out=None):
+        M = self._X(X)
+        _need(S, "S", self.rdtype, (M, self.dim))
+        shp = (self.dim,) + self.half_shape
+        out = torch.empty(shp, dtype=self.cdtype, device=X.device) if out is None else _need(out, "fhat", self.cdtype, shp)
+        _check(self._lib.fsib_force_spread(self._h, M, _ptr(X), _ptr(S), _ptr(out), float(scale), _stream()),
+               "fsib_force_spread")
+        return out
+
+    def velocity_interp(self, X, uhat, out=None):
+        M = self._X(X)
+        _need(uhat, "uhat", self.cdtype, (self.dim,) + self.half_shape)
+        out = torch.empty((M, self.dim), dtype=self.rdtype, device=X.device) if out is None else \
+            _need(out, "U", self.rdtype, (M, self.dim))
+        _check(self._lib.fsib_velocity_interp(self._h, M, _ptr(X), _ptr(uhat), _ptr(out), _stream()),
+               "fsib_velocity_interp")
+        return out
+
+    def fluid_step(self, params, fhat, uhat, uhat_mid=None):
+        shp = (self.dim,) + self.half_shape
+        _need(fhat, "fhat", self.cdtype, shp)
+        _need(uhat, "uhat", self.cdtype, shp)
+        if uhat_mid is not None:
+            _need(uhat_mid, "uhat_mid", self.cdtype, shp)
+        _check(self._lib.fsib_fluid_step(self._h, ctypes.byref(params._s), _ptr(fhat), _ptr(uhat), _ptr(uhat_mid),
+                                         _stream()), "fsib_fluid_step")
+        return uhat
+
+    def velocity(self, params, force, X, uhat, out=None):
+        M = self._X(X)
+        _need(uhat, "uhat", self.cdtype, (self.dim,) + self.half_shape)
+        out = torch.empty((M, self.dim), dtype=self.rdtype, device=X.device) if out is None else \
+            _need(out, "U", self.rdtype, (M, self.dim))
+        _check(self._lib.fsib_velocity(self._h, ctypes.byref(params._s), ctypes.byref(force._s) if force else None, M,
+                                       _ptr(X), _ptr(out), _ptr(uhat), _stream()), "fsib_velocity")
+        return out
+
+    def step(self, params, force, X, U, uhat, diag=None):
+        M = self._X(X)
+        _need(U, "U", self.rdtype, (M, self.dim))
+        _need(uhat, "uhat", self.cdtype, (self.dim,) + self.half_shape)
+        if diag is not None:
+            _need(diag, "diag", torch.float64, (DIAG_COUNT,))
+        _check(self._lib.fsib_step(self._h, ctypes.byref(params._s), ctypes.byref(force._s), M, _ptr(X), _ptr(U),
+                                   _ptr(uhat), _ptr(diag), _stream()), "fsib_step")

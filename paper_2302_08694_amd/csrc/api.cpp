@@ -1,0 +1,634 @@
+// C ABI of the FSIB library: plan construction and the orchestration of the kernels for the
+// nonuniform transforms (App. A), the FSIB coupling (Sec. 3.1), the fluid update and Alg. 1.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+struct fsib_plan_s {
+  fsib::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fsib_status fail(fsib_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define FSIB_HIP(call)                                                                                  \
+  do {                                                                                                  \
+    hipError_t e_ = (call);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      return fail(FSIB_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+
+#define FSIB_TRY(call)                 \
+  do {                                 \
+    fsib_status s_ = (call);           \
+    if (s_ != FSIB_OK) return s_;      \
+  } while (0)
+
+using fsib::Plan;
+
+int64_t ceil_half(int64_t n) { return (n + 1) / 2; }
+
+struct Alloc {
+  Plan& p;
+  fsib_status status = FSIB_OK;
+  template <typename P>
+  void get(P*& ptr, int64_t bytes) {
+    if (status != FSIB_OK) return;
+    if (bytes <= 0) bytes = 256;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)bytes);
+    if (e != hipSuccess) {
+      status = FSIB_ERR_OOM;
+      g_last_error = std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e);
+      return;
+    }
+    ptr = (P*)q;
+    p.ws_bytes += bytes;
+  }
+};
+
+void free_plan(Plan& p) {
+  auto fr = [](void* q) {
+    if (q) (void)hipFree(q);
+  };
+  fr(p.coef);
+  for (int a = 0; a < 3; ++a) fr(p.fac[a]);
+  for (auto& kv : p.tw) fr(kv.second);
+  p.tw.clear();
+  fr(p.counts);
+  fr(p.offsets);
+  fr(p.pt_bin);
+  fr(p.pt_rank);
+  fr(p.s_idx);
+  fr(p.s_i0);
+  fr(p.s_y);
+  fr(p.flag);
+  fr(p.grid);
+  fr(p.B1);
+  fr(p.B2);
+  fr(p.Xh);
+  fr(p.F64);
+  fr(p.S);
+  fr(p.Uh);
+  fr(p.fhat);
+  fr(p.uhat_mid);
+  fr(p.pihat);
+  fr(p.D1);
+  fr(p.D2);
+  fr(p.ureal);
+  fr(p.prod);
+  fr(p.part);
+}
+
+// host -> device copy of a double table converted to the plan precision
+fsib_status upload(const Plan& p, void* dst, const std::vector<double>& v) {
+  if (p.prec == FSIB_F64) {
+    FSIB_HIP(hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(v.begin(), v.end());
+    FSIB_HIP(hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return FSIB_OK;
+}
+
+fsib_status validate_opts(const fsib_plan_opts* o) {
+  if (!o) return fail(FSIB_ERR_ARG, "opts is NULL");
+  if (o->dim != 2 && o->dim != 3) return fail(FSIB_ERR_ARG, "dim must be 2 or 3");
+  for (int a = 0; a < o->dim; ++a)
+    if (o->n_modes[a] < 2 || o->n_modes[a] > 4096) return fail(FSIB_ERR_ARG, "n_modes must be in [2, 4096]");
+  if (!(o->L > 0) || !std::isfinite(o->L)) return fail(FSIB_ERR_ARG, "L must be positive and finite");
+  if (o->prec != FSIB_F64 && o->prec != FSIB_F32) return fail(FSIB_ERR_ARG, "prec must be FSIB_F64 or FSIB_F32");
+  if (!(o->upsampfac == 0.0 || o->upsampfac == 2.0)) return fail(FSIB_ERR_ARG, "upsampfac must be 0 or 2.0");
+  if (o->ntrans < 1 || o->ntrans > 65535) return fail(FSIB_ERR_ARG, "ntrans must be in [1, 65535]");
+  if (o->max_points < 0 || o->max_points > (int64_t)1 << 30) return fail(FSIB_ERR_ARG, "max_points out of range");
+  if (!std::isfinite(o->tol) || o->tol > 0.1) return fail(FSIB_ERR_TOL, "tol must be <= 0.1");
+  if (o->prec == FSIB_F64 && !(o->tol >= 1e-14)) return fail(FSIB_ERR_TOL, "FP64 plans reach tol >= 1e-14");
+  if (o->prec == FSIB_F32 && !(o->tol >= 1e-6)) return fail(FSIB_ERR_TOL, "FP32 plans reach tol >= 1e-6");
+  if (o->navier_stokes && !o->fluid) return fail(FSIB_ERR_ARG, "navier_stokes needs fluid = 1");
+  return FSIB_OK;
+}
+
+fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
+  p.dim = o->dim;
+  for (int a = 0; a < 3; ++a) p.N[a] = a < o->dim ? o->n_modes[a] : 1;
+  p.L = o->L;
+  p.prec = o->prec;
+  p.tol = o->tol;
+  p.ntrans = o->ntrans;
+  p.max_points = o->max_points;
+  p.fluid = o->fluid ? 1 : 0;
+  p.ns = o->navier_stokes ? 1 : 0;
+  FSIB_HIP(hipGetDevice(&p.device));
+  // kernel (App. A.3): width from tol, Kaiser-Bessel shape, polynomial degree
+  p.w = fsib::choose_width(p.tol, p.dim);
+  p.beta = fsib::choose_beta(p.w);
+  p.deg = fsib::choose_degree(p.w);
+  // fine grid and tiles: n_f >= 2N and >= 2w, 2^a 3^b 5^c, a multiple of the tile
+  const int64_t tile3[3] = {16, 8, 8}, tile2[3] = {32, 32, 1};
+  for (int a = 0; a < 3; ++a) {
+    if (a >= p.dim) {
+      p.nf[a] = p.tb[a] = p.nt[a] = 1;
+      continue;
+    }
+    const int64_t tb = p.dim == 3 ? tile3[a] : tile2[a];
+    int64_t need = 2 * p.N[a];
+    if (need < 2 * p.w) need = 2 * p.w;
+    if (need < tb) need = tb;
+    p.nf[a] = fsib::smooth_at_least(need, tb);
+    p.tb[a] = tb;
+    p.nt[a] = p.nf[a] / tb;
+  }
+  if (p.dim == 3 && (p.nf[0] > 1024 || p.nf[1] > 1024 || p.nf[2] > 1024))
+    return fail(FSIB_ERR_ARG, "3D fine grid above 1024 per axis (n_modes above 512) is not supported");
+  if (p.dim == 2 && (p.nf[0] > 65535 || p.nf[1] > 65535)) return fail(FSIB_ERR_ARG, "2D fine grid too large");
+  p.nbins = p.nt[0] * p.nt[1] * p.nt[2];
+  p.Hx = p.N[0] / 2 + 1;
+  if (p.ns) {
+    for (int a = 0; a < 3; ++a) {
+      if (a >= p.dim) {
+        p.nd[a] = 1;
+        continue;
+      }
+      const int64_t n = p.N[a];
+      // Ntilde >= 3N/2 (Sec. 3.1) for the Nyquist-free field; odd N: > 3(N-1)/2
+      const int64_t need = n % 2 == 0 ? (3 * n) / 2 : (3 * (n - 1)) / 2 + 1;
+      p.nd[a] = fsib::smooth_at_least(need, 2);
+    }
+  }
+  // FFT lengths must have a radix plan
+  std::set<int> lengths;
+  for (int a = 0; a < p.dim; ++a) {
+    lengths.insert((int)p.nf[a]);
+    if (p.ns) lengths.insert((int)p.nd[a]);
+  }
+  for (int n : lengths) {
+    int r[fsib::kMaxStages];
+    if (fsib::radix_plan(n, r) == 0) return fail(FSIB_ERR_ARG, "no FFT radix plan for length " + std::to_string(n));
+    // one FFT line (two LDS buffers) must fit the 64 KiB a workgroup may use
+    if ((int64_t)n * 2 * 2 * (int64_t)p.real_size() > 65536)
+      return fail(FSIB_ERR_ARG, "FFT length " + std::to_string(n) + " exceeds the LDS budget of one workgroup");
+  }
+
+  const int64_t rs = (int64_t)p.real_size();
+  const int64_t cs = 2 * rs;
+  const int64_t Mx = p.max_points > 0 ? p.max_points : 1;
+  const int64_t d = p.dim;
+  const int64_t nfc = p.fine_cells();
+  Alloc A{p};
+  A.get(p.coef, (int64_t)(p.deg + 1) * p.w * rs);
+  for (int a = 0; a < p.dim; ++a) A.get(p.fac[a], p.N[a] * rs);
+  for (int n : lengths) {
+    void* t = nullptr;
+    A.get(t, (int64_t)n * cs);
+    if (t) p.tw[n] = t;
+  }
+  A.get(p.counts, (p.nbins + 1) * 4);
+  A.get(p.offsets, (p.nbins + 1) * 4);
+  A.get(p.pt_bin, Mx * 4);
+  A.get(p.pt_rank, Mx * 4);
+  A.get(p.s_idx, Mx * 4);
+  A.get(p.s_i0, Mx * 4);
+  A.get(p.s_y, Mx * d * rs);
+  A.get(p.flag, 256);
+  // grid and FFT buffers: complex transforms (ntrans) and, for fluid plans, dim real fields
+  int64_t grid_b = (int64_t)p.ntrans * nfc * cs;
+  int64_t b1 = p.dim == 3 ? (int64_t)p.ntrans * p.nf[2] * p.nf[1] * p.N[0] * cs : (int64_t)p.ntrans * p.nf[1] * p.N[0] * cs;
+  int64_t b2 = p.dim == 3 ? (int64_t)p.ntrans * p.nf[2] * p.N[1] * p.N[0] * cs : 0;
+  if (p.fluid) {
+    const int64_t gr = d * nfc * rs;
+    const int64_t r1 = p.dim == 3 ? d * p.nf[2] * p.nf[1] * p.Hx * cs : d * p.nf[1] * p.Hx * cs;
+    const int64_t r2 = p.dim == 3 ? d * p.nf[2] * p.N[1] * p.Hx * cs : 0;
+    grid_b = grid_b > gr ? grid_b : gr;
+    b1 = b1 > r1 ? b1 : r1;
+    b2 = b2 > r2 ? b2 : r2;
+  }
+  A.get(p.grid, grid_b);
+  A.get(p.B1, b1);
+  A.get(p.B2, b2);
+  if (p.fluid) {
+    A.get(p.Xh, Mx * d * 8);
+    A.get(p.F64, Mx * d * 8);
+    A.get(p.S, Mx * d * rs);
+    A.get(p.Uh, Mx * d * rs);
+    A.get(p.fhat, d * p.modes_half() * cs);
+    A.get(p.uhat_mid, d * p.modes_half() * cs);
+    A.get(p.part, 256 * 12 * 8);
+  }
+  if (p.ns) {
+    const int64_t nc = p.nprod() > d ? p.nprod() : d;
+    A.get(p.pihat, p.nprod() * p.modes_half() * cs);
+    A.get(p.D1, p.dim == 3 ? nc * p.nd[2] * p.N[1] * p.Hx * cs : 0);
+    A.get(p.D2, p.dim == 3 ? nc * p.nd[2] * p.nd[1] * p.Hx * cs : nc * p.nd[1] * p.Hx * cs);
+    A.get(p.ureal, d * p.dealias_cells() * rs);
+    A.get(p.prod, p.nprod() * p.dealias_cells() * rs);
+  }
+  if (A.status != FSIB_OK) return A.status;
+
+  // tables
+  std::vector<double> coef((size_t)(p.deg + 1) * p.w);
+  fsib::fit_kernel_pieces(p.w, p.beta, p.deg, coef.data());
+  FSIB_TRY(upload(p, p.coef, coef));
+  for (int a = 0; a < p.dim; ++a) {
+    // deconvolution: the fine-grid FFT of the spread carries (w/2) Ghat(pi m w / n_f) per axis
+    std::vector<double> f((size_t)p.N[a]);
+    for (int64_t i = 0; i < p.N[a]; ++i) {
+      const int64_t m = i < ceil_half(p.N[a]) ? i : i - p.N[a];
+      f[(size_t)i] = 2.0 / (p.w * fsib::kb_transform(M_PI * (double)m * p.w / (double)p.nf[a], p.beta));
+    }
+    FSIB_TRY(upload(p, p.fac[a], f));
+  }
+  for (auto& kv : p.tw) {
+    const int n = kv.first;
+    std::vector<double> t(2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+      const long double ang = -2.0L * (long double)M_PI * (long double)i / (long double)n;
+      t[2 * (size_t)i] = (double)cosl(ang);
+      t[2 * (size_t)i + 1] = (double)sinl(ang);
+    }
+    FSIB_TRY(upload(p, kv.second, t));
+  }
+  FSIB_HIP(hipMemset(p.flag, 0, 256));
+  FSIB_HIP(hipDeviceSynchronize());
+  return FSIB_OK;
+}
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+fsib_status check_points(const Plan& p, int64_t M, const void* X) {
+  if (M < 0 || M > p.max_points) return fail(FSIB_ERR_ARG, "M must be in [0, max_points]");
+  if (M > 0 && !X) return fail(FSIB_ERR_ARG, "X is NULL");
+  return FSIB_OK;
+}
+
+// ---- transform pipelines ----
+fsib_status type1_complex(Plan& p, int64_t M, const double* X, const void* c, void* fhat, double scale, hipStream_t st) {
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, st));
+  FSIB_HIP(fsib::launch_spread(p, M, c, 0, st));
+  const int64_t T = p.ntrans;
+  if (p.dim == 3) {
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.grid, p.B1, (int)p.nf[0], -1, 1, T * p.nf[2] * p.nf[1], (int)p.nf[0],
+                                  (int)p.nf[0], (int)p.N[0], (int)ceil_half(p.N[0]), nullptr, p.fac[0], 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, p.B2, (int)p.nf[1], -1, p.N[0], T * p.nf[2], (int)p.nf[1], (int)p.nf[1],
+                                  (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, p.fac[1], 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B2, fhat, (int)p.nf[2], -1, p.N[1] * p.N[0], T, (int)p.nf[2], (int)p.nf[2],
+                                  (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, p.fac[2], scale, st));
+  } else {
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.grid, p.B1, (int)p.nf[0], -1, 1, T * p.nf[1], (int)p.nf[0], (int)p.nf[0],
+                                  (int)p.N[0], (int)ceil_half(p.N[0]), nullptr, p.fac[0], 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, fhat, (int)p.nf[1], -1, p.N[0], T, (int)p.nf[1], (int)p.nf[1], (int)p.N[1],
+                                  (int)ceil_half(p.N[1]), nullptr, p.fac[1], scale, st));
+  }
+  return FSIB_OK;
+}
+
+fsib_status type2_complex(Plan& p, int64_t M, const double* X, const void* fhat, void* c, hipStream_t st) {
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, st));
+  const int64_t T = p.ntrans;
+  if (p.dim == 3) {
+    FSIB_HIP(fsib::launch_fft_c2c(p, fhat, p.B2, (int)p.nf[2], +1, p.N[1] * p.N[0], T, (int)p.N[2],
+                                  (int)ceil_half(p.N[2]), (int)p.nf[2], (int)p.nf[2], p.fac[2], nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B2, p.B1, (int)p.nf[1], +1, p.N[0], T * p.nf[2], (int)p.N[1],
+                                  (int)ceil_half(p.N[1]), (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, p.grid, (int)p.nf[0], +1, 1, T * p.nf[2] * p.nf[1], (int)p.N[0],
+                                  (int)ceil_half(p.N[0]), (int)p.nf[0], (int)p.nf[0], p.fac[0], nullptr, 1.0, st));
+  } else {
+    FSIB_HIP(fsib::launch_fft_c2c(p, fhat, p.B1, (int)p.nf[1], +1, p.N[0], T, (int)p.N[1], (int)ceil_half(p.N[1]),
+                                  (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, p.grid, (int)p.nf[0], +1, 1, T * p.nf[1], (int)p.N[0],
+                                  (int)ceil_half(p.N[0]), (int)p.nf[0], (int)p.nf[0], p.fac[0], nullptr, 1.0, st));
+  }
+  FSIB_HIP(fsib::launch_interp(p, M, c, 0, st));
+  return FSIB_OK;
+}
+
+// real vector strengths (sorted point set already in place) -> dim half spectra
+fsib_status force_spread_sorted(Plan& p, int64_t M, const void* S_, void* fhat, double scale, hipStream_t st) {
+  FSIB_HIP(fsib::launch_spread(p, M, S_, p.dim, st));
+  const int64_t d = p.dim;
+  if (p.dim == 3) {
+    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.grid, p.B1, (int)p.nf[0], d * p.nf[2] * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, p.B2, (int)p.nf[1], -1, p.Hx, d * p.nf[2], (int)p.nf[1], (int)p.nf[1],
+                                  (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, p.fac[1], 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B2, fhat, (int)p.nf[2], -1, p.N[1] * p.Hx, d, (int)p.nf[2], (int)p.nf[2],
+                                  (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, p.fac[2], scale, st));
+  } else {
+    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.grid, p.B1, (int)p.nf[0], d * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, fhat, (int)p.nf[1], -1, p.Hx, d, (int)p.nf[1], (int)p.nf[1], (int)p.N[1],
+                                  (int)ceil_half(p.N[1]), nullptr, p.fac[1], scale, st));
+  }
+  return FSIB_OK;
+}
+
+// dim half spectra -> real vector velocity at the sorted point set
+fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U, hipStream_t st) {
+  const int64_t d = p.dim;
+  if (p.dim == 3) {
+    FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.B2, (int)p.nf[2], +1, p.N[1] * p.Hx, d, (int)p.N[2],
+                                  (int)ceil_half(p.N[2]), (int)p.nf[2], (int)p.nf[2], p.fac[2], nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.B2, p.B1, (int)p.nf[1], +1, p.Hx, d * p.nf[2], (int)p.N[1],
+                                  (int)ceil_half(p.N[1]), (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.B1, p.grid, (int)p.nf[0], d * p.nf[2] * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st));
+  } else {
+    FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.B1, (int)p.nf[1], +1, p.Hx, d, (int)p.N[1], (int)ceil_half(p.N[1]),
+                                  (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.B1, p.grid, (int)p.nf[0], d * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st));
+  }
+  FSIB_HIP(fsib::launch_interp(p, M, U, p.dim, st));
+  return FSIB_OK;
+}
+
+// dealiased products of the field uhat (dim half spectra) -> p.pihat (nprod half spectra)
+fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st) {
+  const int64_t d = p.dim, np = p.nprod();
+  if (p.dim == 3) {
+    FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.D1, (int)p.nd[2], +1, p.N[1] * p.Hx, d, (int)p.N[2],
+                                  (int)ceil_half(p.N[2]), (int)p.nd[2], (int)p.nd[2], nullptr, nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.D1, p.D2, (int)p.nd[1], +1, p.Hx, d * p.nd[2], (int)p.N[1],
+                                  (int)ceil_half(p.N[1]), (int)p.nd[1], (int)p.nd[1], nullptr, nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.D2, p.ureal, (int)p.nd[0], d * p.nd[2] * p.nd[1], (int)p.Hx, nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_products(p, st));
+    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.prod, p.D2, (int)p.nd[0], np * p.nd[2] * p.nd[1], (int)p.Hx, nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.D2, p.D1, (int)p.nd[1], -1, p.Hx, np * p.nd[2], (int)p.nd[1], (int)p.nd[1],
+                                  (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.D1, p.pihat, (int)p.nd[2], -1, p.N[1] * p.Hx, np, (int)p.nd[2], (int)p.nd[2],
+                                  (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, nullptr, 1.0, st));
+  } else {
+    FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.D2, (int)p.nd[1], +1, p.Hx, d, (int)p.N[1], (int)ceil_half(p.N[1]),
+                                  (int)p.nd[1], (int)p.nd[1], nullptr, nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.D2, p.ureal, (int)p.nd[0], d * p.nd[1], (int)p.Hx, nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_products(p, st));
+    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.prod, p.D2, (int)p.nd[0], np * p.nd[1], (int)p.Hx, nullptr, 1.0, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.D2, p.pihat, (int)p.nd[1], -1, p.Hx, np, (int)p.nd[1], (int)p.nd[1],
+                                  (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, nullptr, 1.0, st));
+  }
+  return FSIB_OK;
+}
+
+fsib_status fluid_impl(Plan& p, const fsib_fluid_params& prm, const void* fhat, void* uhat, void* umid, hipStream_t st) {
+  if (prm.model == FSIB_STOKES) {
+    FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_STOKES, prm, fhat, nullptr, uhat, st));
+    if (umid)
+      FSIB_HIP(hipMemcpyAsync(umid, uhat, (size_t)p.dim * p.modes_half() * 2 * p.real_size(), hipMemcpyDeviceToDevice, st));
+    return FSIB_OK;
+  }
+  void* mid = umid ? umid : p.uhat_mid;
+  FSIB_TRY(dealiased_products(p, uhat, st));
+  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_HALF, prm, fhat, uhat, mid, st));
+  FSIB_TRY(dealiased_products(p, mid, st));
+  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_FULL, prm, fhat, uhat, uhat, st));
+  return FSIB_OK;
+}
+
+fsib_status check_fluid(const Plan& p, const fsib_fluid_params* prm) {
+  if (!p.fluid) return fail(FSIB_ERR_STATE, "plan was created without fluid = 1");
+  if (!prm) return fail(FSIB_ERR_ARG, "params is NULL");
+  if (prm->model != FSIB_STOKES && prm->model != FSIB_NAVIER_STOKES) return fail(FSIB_ERR_ARG, "unknown model");
+  if (!(prm->mu > 0) || !std::isfinite(prm->mu)) return fail(FSIB_ERR_ARG, "mu must be positive");
+  if (prm->model == FSIB_NAVIER_STOKES) {
+    if (!p.ns) return fail(FSIB_ERR_STATE, "plan was created without navier_stokes = 1");
+    if (!(prm->rho > 0) || !std::isfinite(prm->rho)) return fail(FSIB_ERR_ARG, "rho must be positive");
+  }
+  if (!std::isfinite(prm->dt)) return fail(FSIB_ERR_ARG, "dt must be finite");
+  return FSIB_OK;
+}
+
+fsib_status check_force(const fsib_force* f, int dim, int64_t M) {
+  if (!f) return fail(FSIB_ERR_ARG, "force is NULL");
+  if (!std::isfinite(f->K)) return fail(FSIB_ERR_ARG, "force K must be finite");
+  if (f->kind == FSIB_FORCE_CURVE_TENSION) {
+    if (dim != 2) return fail(FSIB_ERR_ARG, "curve tension needs dim = 2");
+    if (M > 0 && M < 3) return fail(FSIB_ERR_ARG, "curve tension needs M >= 3");
+    return FSIB_OK;
+  }
+  if (f->kind == FSIB_FORCE_SURFACE_TENSION) {
+    if (dim != 3) return fail(FSIB_ERR_ARG, "surface tension needs dim = 3");
+    if (M > 0 && (!f->tris || !f->v2t_ptr || !f->v2t_idx || f->ntris <= 0))
+      return fail(FSIB_ERR_ARG, "surface tension needs tris and the vertex-triangle CSR");
+    return FSIB_OK;
+  }
+  return fail(FSIB_ERR_ARG, "unknown force kind");
+}
+
+// Stokes boundary velocity at X: force, spread, Stokeslet, interp.  uhat receives the field.
+fsib_status stokes_velocity(Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M, const double* X,
+                            void* U, void* uhat, hipStream_t st) {
+  const double Ld = p.dim == 3 ? p.L * p.L * p.L : p.L * p.L;
+  FSIB_HIP(fsib::launch_force(f, p.dim, M, X, p.F64, st));
+  FSIB_HIP(fsib::launch_weighted_strengths(p, f.kind, M, p.F64, p.S, st));
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, st));
+  FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, st));
+  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_STOKES, prm, p.fhat, nullptr, uhat, st));
+  FSIB_TRY(velocity_interp_sorted(p, M, uhat, U, st));
+  return FSIB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fsib_version(void) { return "fsib-mi355x 0.1.0 (gfx950)"; }
+
+const char* fsib_status_string(fsib_status s) {
+  switch (s) {
+    case FSIB_OK: return "ok";
+    case FSIB_ERR_ARG: return "invalid argument";
+    case FSIB_ERR_TOL: return "tolerance not reachable in this precision";
+    case FSIB_ERR_NO_DEVICE: return "no HIP device";
+    case FSIB_ERR_OOM: return "out of device memory";
+    case FSIB_ERR_HIP: return "HIP runtime error";
+    case FSIB_ERR_NONFINITE: return "non-finite position seen";
+    case FSIB_ERR_STATE: return "plan lacks the workspace for this call";
+  }
+  return "unknown status";
+}
+
+const char* fsib_last_error(void) { return g_last_error.c_str(); }
+
+int fsib_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+fsib_status fsib_plan_create(const fsib_plan_opts* opts, fsib_plan* out) {
+  if (!out) return fail(FSIB_ERR_ARG, "out is NULL");
+  FSIB_TRY(validate_opts(opts));
+  if (fsib_device_count() <= 0) return fail(FSIB_ERR_NO_DEVICE, "no HIP device visible");
+  fsib_plan h = new (std::nothrow) fsib_plan_s();
+  if (!h) return fail(FSIB_ERR_OOM, "host allocation failed");
+  fsib_status s = build_plan(h->p, opts);
+  if (s != FSIB_OK) {
+    free_plan(h->p);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return FSIB_OK;
+}
+
+fsib_status fsib_plan_destroy(fsib_plan plan) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  (void)hipDeviceSynchronize();
+  free_plan(plan->p);
+  delete plan;
+  return FSIB_OK;
+}
+
+fsib_status fsib_plan_info(fsib_plan plan, fsib_plan_info_t* info) {
+  if (!plan || !info) return fail(FSIB_ERR_ARG, "plan or info is NULL");
+  const Plan& p = plan->p;
+  info->w = p.w;
+  info->beta = p.beta;
+  info->degree = p.deg;
+  for (int a = 0; a < 3; ++a) {
+    info->n_fine[a] = p.nf[a];
+    info->n_dealias[a] = p.ns ? p.nd[a] : 0;
+    info->tile[a] = p.tb[a];
+  }
+  info->workspace_bytes = p.ws_bytes;
+  return FSIB_OK;
+}
+
+fsib_status fsib_plan_check(fsib_plan plan, void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  int flag = 0;
+  FSIB_HIP(hipMemcpyAsync(&flag, plan->p.flag, sizeof(int), hipMemcpyDeviceToHost, S(stream)));
+  FSIB_HIP(hipStreamSynchronize(S(stream)));
+  if (flag) {
+    FSIB_HIP(hipMemsetAsync(plan->p.flag, 0, sizeof(int), S(stream)));
+    FSIB_HIP(hipStreamSynchronize(S(stream)));
+    return fail(FSIB_ERR_NONFINITE, "a non-finite position was seen (treated as x = 0)");
+  }
+  return FSIB_OK;
+}
+
+fsib_status fsib_spread(fsib_plan plan, int64_t M, const double* X, const void* c, void* fhat, double scale,
+                        void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  FSIB_TRY(check_points(p, M, X));
+  if (M > 0 && !c) return fail(FSIB_ERR_ARG, "c is NULL");
+  if (!fhat) return fail(FSIB_ERR_ARG, "fhat is NULL");
+  if (!std::isfinite(scale)) return fail(FSIB_ERR_ARG, "scale must be finite");
+  return type1_complex(p, M, X, c, fhat, scale, S(stream));
+}
+
+fsib_status fsib_interp(fsib_plan plan, int64_t M, const double* X, const void* fhat, void* c, void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  FSIB_TRY(check_points(p, M, X));
+  if (!fhat) return fail(FSIB_ERR_ARG, "fhat is NULL");
+  if (M > 0 && !c) return fail(FSIB_ERR_ARG, "c is NULL");
+  return type2_complex(p, M, X, fhat, c, S(stream));
+}
+
+fsib_status fsib_force_spread(fsib_plan plan, int64_t M, const double* X, const void* S_, void* fhat_half, double scale,
+                              void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (!p.fluid) return fail(FSIB_ERR_STATE, "plan was created without fluid = 1");
+  FSIB_TRY(check_points(p, M, X));
+  if (M > 0 && !S_) return fail(FSIB_ERR_ARG, "S is NULL");
+  if (!fhat_half) return fail(FSIB_ERR_ARG, "fhat_half is NULL");
+  if (!std::isfinite(scale)) return fail(FSIB_ERR_ARG, "scale must be finite");
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, S(stream)));
+  return force_spread_sorted(p, M, S_, fhat_half, scale, S(stream));
+}
+
+fsib_status fsib_velocity_interp(fsib_plan plan, int64_t M, const double* X, const void* uhat_half, void* U,
+                                 void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (!p.fluid) return fail(FSIB_ERR_STATE, "plan was created without fluid = 1");
+  FSIB_TRY(check_points(p, M, X));
+  if (!uhat_half) return fail(FSIB_ERR_ARG, "uhat_half is NULL");
+  if (M > 0 && !U) return fail(FSIB_ERR_ARG, "U is NULL");
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, S(stream)));
+  return velocity_interp_sorted(p, M, uhat_half, U, S(stream));
+}
+
+fsib_status fsib_fluid_step(fsib_plan plan, const fsib_fluid_params* params, const void* fhat_half, void* uhat_half,
+                            void* uhat_mid, void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  FSIB_TRY(check_fluid(p, params));
+  if (!fhat_half || !uhat_half) return fail(FSIB_ERR_ARG, "fhat_half and uhat_half must not be NULL");
+  return fluid_impl(p, *params, fhat_half, uhat_half, uhat_mid, S(stream));
+}
+
+fsib_status fsib_compute_force(const fsib_force* force, int dim, int64_t M, const double* X, double* F, void* stream) {
+  if (dim != 2 && dim != 3) return fail(FSIB_ERR_ARG, "dim must be 2 or 3");
+  if (M < 0) return fail(FSIB_ERR_ARG, "M must be >= 0");
+  FSIB_TRY(check_force(force, dim, M));
+  if (M > 0 && (!X || !F)) return fail(FSIB_ERR_ARG, "X and F must not be NULL");
+  FSIB_HIP(fsib::launch_force(*force, dim, M, X, F, S(stream)));
+  return FSIB_OK;
+}
+
+fsib_status fsib_velocity(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force, int64_t M,
+                          const double* X, void* U, void* uhat_half, void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  FSIB_TRY(check_fluid(p, params));
+  FSIB_TRY(check_points(p, M, X));
+  if (M > 0 && !U) return fail(FSIB_ERR_ARG, "U is NULL");
+  if (!uhat_half) return fail(FSIB_ERR_ARG, "uhat_half is NULL");
+  if (params->model == FSIB_NAVIER_STOKES) {
+    FSIB_HIP(fsib::launch_sort_points(p, M, X, S(stream)));
+    return velocity_interp_sorted(p, M, uhat_half, U, S(stream));
+  }
+  FSIB_TRY(check_force(force, p.dim, M));
+  return stokes_velocity(p, *params, *force, M, X, U, uhat_half, S(stream));
+}
+
+fsib_status fsib_step(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force, int64_t M, double* X,
+                      void* U, void* uhat_half, double* diag, void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  FSIB_TRY(check_fluid(p, params));
+  FSIB_TRY(check_points(p, M, X));
+  FSIB_TRY(check_force(force, p.dim, M));
+  if (M > 0 && !U) return fail(FSIB_ERR_ARG, "U is NULL");
+  if (!uhat_half) return fail(FSIB_ERR_ARG, "uhat_half is NULL");
+  const hipStream_t st = S(stream);
+  const fsib_fluid_params& prm = *params;
+  const double dt = prm.dt;
+  // X^{m+1/2} = X^m + dt/2 U^m (eq. spatial_1)
+  FSIB_HIP(fsib::launch_axpy_positions(p, M, p.Xh, X, U, 0.5 * dt, st));
+  if (prm.model == FSIB_STOKES) {
+    FSIB_TRY(stokes_velocity(p, prm, *force, M, p.Xh, p.Uh, p.uhat_mid, st));
+    FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, st));
+    FSIB_TRY(stokes_velocity(p, prm, *force, M, X, U, uhat_half, st));
+    if (diag) FSIB_HIP(fsib::launch_diag(p, prm, *force, M, p.F64, U, uhat_half, X, diag, st));
+    return FSIB_OK;
+  }
+  const double Ld = p.dim == 3 ? p.L * p.L * p.L : p.L * p.L;
+  // F^{m+1/2} and fhat^{m+1/2} (eq. force_spreading_quad)
+  FSIB_HIP(fsib::launch_force(*force, p.dim, M, p.Xh, p.F64, st));
+  FSIB_HIP(fsib::launch_weighted_strengths(p, force->kind, M, p.F64, p.S, st));
+  FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, st));
+  FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, st));
+  // uhat^{m+1/2}, uhat^{m+1} (eqs. spatial_2, spatial_3)
+  FSIB_TRY(fluid_impl(p, prm, p.fhat, uhat_half, p.uhat_mid, st));
+  // U^{m+1/2} at X^{m+1/2} (points still sorted), X^{m+1} (eq. spatial_4), U^{m+1} at X^{m+1}
+  FSIB_TRY(velocity_interp_sorted(p, M, p.uhat_mid, p.Uh, st));
+  FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, st));
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, st));
+  FSIB_TRY(velocity_interp_sorted(p, M, uhat_half, U, st));
+  if (diag) FSIB_HIP(fsib::launch_diag(p, prm, *force, M, p.F64, p.Uh, uhat_half, X, diag, st));
+  return FSIB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,416 @@
+// Fourier-space fluid update, dealiased products, force laws and FP64 diagnostics.
+//
+// Fluid update on half spectra (one thread per mode, all components at once):
+//   Stokes (Sec. 6.1, eq. stokeslet):  uhat = (fhat - k (k.fhat)/|k|^2) / (mu |k|^2), uhat(0) = 0.
+//   Navier-Stokes (Alg. 1 with V-hat of Alg. 2):
+//     P = fhat/rho - shat,  Q = P - k (k.P)/|k|^2  (|k|^2 := 1 at k = 0, projection only),
+//     half step  u_mid = (dt/2 Q + u)/(1 + a),  full step  u_new = (dt Q + (1 - a) u)/(1 + a),
+//     a = mu dt |k|^2 / (2 rho) with the true |k|^2.
+//   shat enters in divergence form, shat_a = sum_b i k_b (u_a u_b)^, which equals the advective
+//   form of eq. nonlinear_physical for the divergence-free fields the update produces; the
+//   products are formed on the dealiasing grid (three-halves rule, Sec. 3.1).
+//   Modes with any m_a = -N_a/2 (even N_a) are set to zero so the field stays real.
+#include "plan.hpp"
+
+namespace fsib {
+
+struct ModeGeo {
+  int dim;
+  int64_t N[3];
+  int64_t Hx;
+  double L;
+};
+
+__device__ __forceinline__ int64_t mode_of(int64_t i, int64_t n) { return i < (n + 1) / 2 ? i : i - n; }
+
+template <typename T>
+__global__ void k_products(int64_t cells, int dim, const T* __restrict__ u, T* __restrict__ prod, T inv_cells) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cells) return;
+  if (dim == 3) {
+    const T a = u[i], b = u[cells + i], c = u[2 * cells + i];
+    prod[i] = a * a * inv_cells;
+    prod[cells + i] = a * b * inv_cells;
+    prod[2 * cells + i] = a * c * inv_cells;
+    prod[3 * cells + i] = b * b * inv_cells;
+    prod[4 * cells + i] = b * c * inv_cells;
+    prod[5 * cells + i] = c * c * inv_cells;
+  } else {
+    const T a = u[i], b = u[cells + i];
+    prod[i] = a * a * inv_cells;
+    prod[cells + i] = a * b * inv_cells;
+    prod[2 * cells + i] = b * b * inv_cells;
+  }
+}
+
+__device__ __forceinline__ int sym_index(int a, int b, int dim) {
+  if (a > b) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
+  if (dim == 3) {
+    const int base[3] = {0, 3, 5};
+    return base[a] + (b - a);
+  }
+  return a == 0 ? b : 2;
+}
+
+template <typename T, int DIM>
+__global__ void k_fluid(ModeGeo g, int mode, T rho, T mu, T dt, const cplx<T>* __restrict__ fhat,
+                        const cplx<T>* __restrict__ pihat, const cplx<T>* uin, cplx<T>* uout) {
+  const int64_t nm = g.Hx * g.N[1] * (DIM == 3 ? g.N[2] : 1);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nm) return;
+  const int64_t ix = idx % g.Hx;
+  const int64_t iy = (idx / g.Hx) % g.N[1];
+  const int64_t iz = DIM == 3 ? idx / (g.Hx * g.N[1]) : 0;
+  const int64_t m[3] = {ix, mode_of(iy, g.N[1]), DIM == 3 ? mode_of(iz, g.N[2]) : 0};
+  bool nyq = false;
+  for (int a = 0; a < DIM; ++a)
+    if (g.N[a] % 2 == 0 && (a == 0 ? ix == g.N[0] / 2 : m[a] == -g.N[a] / 2)) nyq = true;
+  if (nyq) {
+    for (int a = 0; a < DIM; ++a) uout[a * nm + idx] = mk((T)0, (T)0);
+    return;
+  }
+  const T twopi_L = (T)(6.283185307179586476925286766559 / g.L);
+  T k[3];
+  T k2 = 0;
+  for (int a = 0; a < DIM; ++a) {
+    k[a] = twopi_L * (T)m[a];
+    k2 += k[a] * k[a];
+  }
+  if (mode == FLUID_STOKES) {
+    if (k2 == (T)0) {
+      for (int a = 0; a < DIM; ++a) uout[a * nm + idx] = mk((T)0, (T)0);
+      return;
+    }
+    cplx<T> f[3];
+    cplx<T> kf = mk((T)0, (T)0);
+    for (int a = 0; a < DIM; ++a) {
+      f[a] = fhat[a * nm + idx];
+      kf = kf + f[a] * k[a];
+    }
+    const T inv = (T)1 / (mu * k2);
+    for (int a = 0; a < DIM; ++a) uout[a * nm + idx] = (f[a] - kf * (k[a] / k2)) * inv;
+    return;
+  }
+  // Navier-Stokes
+  cplx<T> P[3];
+  cplx<T> kP = mk((T)0, (T)0);
+  const T inv_rho = (T)1 / rho;
+  for (int a = 0; a < DIM; ++a) {
+    cplx<T> s = mk((T)0, (T)0);
+    for (int b = 0; b < DIM; ++b) s = s + mul_i(pihat[sym_index(a, b, DIM) * nm + idx], k[b]);
+    P[a] = fhat[a * nm + idx] * inv_rho - s;
+    kP = kP + P[a] * k[a];
+  }
+  const T k2p = k2 == (T)0 ? (T)1 : k2;
+  const T av = mu * dt * k2 / ((T)2 * rho);
+  const T den = (T)1 / ((T)1 + av);
+  for (int a = 0; a < DIM; ++a) {
+    const cplx<T> Q = P[a] - kP * (k[a] / k2p);
+    const cplx<T> u = uin[a * nm + idx];
+    cplx<T> r;
+    if (mode == FLUID_NS_HALF)
+      r = (Q * (dt * (T)0.5) + u) * den;
+    else
+      r = (Q * dt + u * ((T)1 - av)) * den;
+    uout[a * nm + idx] = r;
+  }
+}
+
+hipError_t launch_products(const Plan& p, hipStream_t st) {
+  const int64_t cells = p.dealias_cells();
+  const unsigned nblk = (unsigned)((cells + 255) / 256);
+  if (p.prec == FSIB_F64)
+    hipLaunchKernelGGL(k_products<double>, dim3(nblk), dim3(256), 0, st, cells, p.dim, (const double*)p.ureal,
+                       (double*)p.prod, 1.0 / (double)cells);
+  else
+    hipLaunchKernelGGL(k_products<float>, dim3(nblk), dim3(256), 0, st, cells, p.dim, (const float*)p.ureal,
+                       (float*)p.prod, (float)(1.0 / (double)cells));
+  return hipGetLastError();
+}
+
+hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
+                               const void* uin, void* uout, hipStream_t st) {
+  ModeGeo g;
+  g.dim = p.dim;
+  for (int a = 0; a < 3; ++a) g.N[a] = p.N[a];
+  g.Hx = p.Hx;
+  g.L = p.L;
+  const int64_t nm = p.modes_half();
+  const unsigned nblk = (unsigned)((nm + 255) / 256);
+  if (p.prec == FSIB_F64) {
+    using T = double;
+    if (p.dim == 3)
+      hipLaunchKernelGGL((k_fluid<T, 3>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
+                         (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+    else
+      hipLaunchKernelGGL((k_fluid<T, 2>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
+                         (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+  } else {
+    using T = float;
+    if (p.dim == 3)
+      hipLaunchKernelGGL((k_fluid<T, 3>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
+                         (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+    else
+      hipLaunchKernelGGL((k_fluid<T, 2>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
+                         (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+  }
+  return hipGetLastError();
+}
+
+// ---- force laws (double) ----
+
+// Closed curve, Sec. 6.2.1 eq. elstic_force_2d: F_j = K (X_{j+1} + X_{j-1} - 2 X_j) / dtheta^2.
+__global__ void k_force_curve(int64_t M, const double* __restrict__ X, double K, double* __restrict__ F) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const int64_t jp = j + 1 == M ? 0 : j + 1, jm = j == 0 ? M - 1 : j - 1;
+  const double dth = 6.283185307179586476925286766559 / (double)M;
+  const double c = K / (dth * dth);
+  for (int a = 0; a < 2; ++a) F[j * 2 + a] = c * (X[jp * 2 + a] + X[jm * 2 + a] - 2.0 * X[j * 2 + a]);
+}
+
+// Surface tension, Sec. 6.2.3: F_i = -(gamma/2) sum over incident triangles (i, j, k) (in the
+// triangle's cyclic order starting at i) of (X_j - X_k) x n, n the unit normal of (X_i, X_j, X_k).
+__global__ void k_force_surface(int64_t M, const double* __restrict__ X, double gamma, const int32_t* __restrict__ tris,
+                                const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                                double* __restrict__ F) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  double f0 = 0, f1 = 0, f2 = 0;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+    const int t = idx[e];
+    const int v0 = tris[3 * t], v1 = tris[3 * t + 1], v2 = tris[3 * t + 2];
+    int j, k;
+    if (v0 == i) {
+      j = v1;
+      k = v2;
+    } else if (v1 == i) {
+      j = v2;
+      k = v0;
+    } else {
+      j = v0;
+      k = v1;
+    }
+    const double ax = X[3 * j] - X[3 * i], ay = X[3 * j + 1] - X[3 * i + 1], az = X[3 * j + 2] - X[3 * i + 2];
+    const double bx = X[3 * k] - X[3 * i], by = X[3 * k + 1] - X[3 * i + 1], bz = X[3 * k + 2] - X[3 * i + 2];
+    double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+    if (nn > 0) {
+      nx /= nn;
+      ny /= nn;
+      nz /= nn;
+    }
+    const double dx = ax - bx, dy = ay - by, dz = az - bz;  // X_j - X_k
+    f0 += dy * nz - dz * ny;
+    f1 += dz * nx - dx * nz;
+    f2 += dx * ny - dy * nx;
+  }
+  F[3 * i] = -0.5 * gamma * f0;
+  F[3 * i + 1] = -0.5 * gamma * f1;
+  F[3 * i + 2] = -0.5 * gamma * f2;
+}
+
+hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  const unsigned nblk = (unsigned)((M + 255) / 256);
+  if (f.kind == FSIB_FORCE_CURVE_TENSION)
+    hipLaunchKernelGGL(k_force_curve, dim3(nblk), dim3(256), 0, st, M, X, f.K, F);
+  else
+    hipLaunchKernelGGL(k_force_surface, dim3(nblk), dim3(256), 0, st, M, X, f.K, f.tris, f.v2t_ptr, f.v2t_idx, F);
+  return hipGetLastError();
+}
+
+// Strengths S_j = w_j F_j in the plan precision (quadrature weights of eq. force_spreading_quad).
+template <typename T>
+__global__ void k_strengths(int64_t n, const double* __restrict__ F, double w, T* __restrict__ S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) S[i] = (T)(w * F[i]);
+}
+
+double force_weight(int kind, int64_t M) {
+  return kind == FSIB_FORCE_CURVE_TENSION ? 6.283185307179586476925286766559 / (double)M : 1.0;
+}
+
+hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S, hipStream_t st) {
+  const int64_t n = M * p.dim;
+  if (n <= 0) return hipSuccess;
+  const double w = force_weight(kind, M);
+  const unsigned nblk = (unsigned)((n + 255) / 256);
+  if (p.prec == FSIB_F64)
+    hipLaunchKernelGGL(k_strengths<double>, dim3(nblk), dim3(256), 0, st, n, F, w, (double*)S);
+  else
+    hipLaunchKernelGGL(k_strengths<float>, dim3(nblk), dim3(256), 0, st, n, F, w, (float*)S);
+  return hipGetLastError();
+}
+
+// ---- diagnostics: fixed-order FP64 reductions (deterministic) ----
+constexpr int kDiagBlocks = 256;
+constexpr int kDiagThreads = 256;
+constexpr int kDiagSlots = 12;  // per block: 0..2 sum wF, 3 power, 4 E_K, 5 dissipation, 6 max div, 7 volume
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kDiagThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kDiagThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDiagThreads) void k_diag_points(int64_t M, int dim, double w, const double* __restrict__ F,
+                                                              const T* __restrict__ U, double* __restrict__ part) {
+  __shared__ double sh[kDiagThreads];
+  double s[3] = {0, 0, 0}, pw = 0;
+  for (int64_t j = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; j < M; j += (int64_t)kDiagBlocks * kDiagThreads) {
+    for (int a = 0; a < dim; ++a) {
+      const double f = w * F[j * dim + a];
+      s[a] += f;
+      pw += f * (double)U[j * dim + a];
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double r = block_sum(s[a], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + a] = r;
+  }
+  const double r = block_sum(pw, sh);
+  if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 3] = r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDiagThreads) void k_diag_modes(ModeGeo g, double rho, double mu,
+                                                             const cplx<T>* __restrict__ u, double* __restrict__ part) {
+  __shared__ double sh[kDiagThreads];
+  const int64_t nm = g.Hx * g.N[1] * (g.dim == 3 ? g.N[2] : 1);
+  double ek = 0, dis = 0, dv = 0;
+  const double twopi_L = 6.283185307179586476925286766559 / g.L;
+  for (int64_t idx = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; idx < nm;
+       idx += (int64_t)kDiagBlocks * kDiagThreads) {
+    const int64_t ix = idx % g.Hx;
+    const int64_t iy = (idx / g.Hx) % g.N[1];
+    const int64_t iz = g.dim == 3 ? idx / (g.Hx * g.N[1]) : 0;
+    const double k[3] = {twopi_L * (double)ix, twopi_L * (double)mode_of(iy, g.N[1]),
+                         g.dim == 3 ? twopi_L * (double)mode_of(iz, g.N[2]) : 0.0};
+    // each stored mode with 0 < m_x < N_x/2 stands for itself and its conjugate partner
+    const double wgt = (ix == 0 || 2 * ix == g.N[0]) ? 1.0 : 2.0;
+    double uu = 0, kr = 0, ki = 0, k2 = 0;
+    for (int a = 0; a < g.dim; ++a) {
+      const cplx<T> v = u[a * nm + idx];
+      uu += (double)v.x * v.x + (double)v.y * v.y;
+      kr += k[a] * (double)v.x;
+      ki += k[a] * (double)v.y;
+      k2 += k[a] * k[a];
+    }
+    ek += wgt * uu;
+    dis += wgt * k2 * uu;
+    if (k2 > 0 && uu > 0) dv = fmax(dv, sqrt((kr * kr + ki * ki) / (k2 * uu)));
+  }
+  double r = block_sum(ek, sh);
+  if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 4] = r;
+  r = block_sum(dis, sh);
+  if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 5] = r;
+  r = block_max(dv, sh);
+  if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 6] = r;
+}
+
+// enclosed area (2D shoelace over the closed curve) or volume (3D, (1/6) sum X_i . (X_j x X_k))
+__global__ __launch_bounds__(kDiagThreads) void k_diag_volume(int dim, int64_t M, const double* __restrict__ X,
+                                                              const int32_t* __restrict__ tris, int64_t ntris,
+                                                              double* __restrict__ part) {
+  __shared__ double sh[kDiagThreads];
+  double v = 0;
+  if (dim == 2) {
+    for (int64_t j = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; j < M; j += (int64_t)kDiagBlocks * kDiagThreads) {
+      const int64_t jp = j + 1 == M ? 0 : j + 1;
+      v += 0.5 * (X[2 * j] * X[2 * jp + 1] - X[2 * jp] * X[2 * j + 1]);
+    }
+  } else if (tris) {
+    for (int64_t t = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; t < ntris;
+         t += (int64_t)kDiagBlocks * kDiagThreads) {
+      const double* A = X + 3 * tris[3 * t];
+      const double* B = X + 3 * tris[3 * t + 1];
+      const double* C = X + 3 * tris[3 * t + 2];
+      v += (A[0] * (B[1] * C[2] - B[2] * C[1]) + A[1] * (B[2] * C[0] - B[0] * C[2]) + A[2] * (B[0] * C[1] - B[1] * C[0])) /
+           6.0;
+    }
+  }
+  const double r = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 7] = r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDiagThreads) void k_diag_final(int dim, double rho, double mu, double Ld,
+                                                             const cplx<T>* __restrict__ u, int64_t nm,
+                                                             const double* __restrict__ part, double* __restrict__ diag) {
+  __shared__ double sh[kDiagThreads];
+  double acc[8];
+  for (int q = 0; q < 8; ++q) {
+    const double v = threadIdx.x < kDiagBlocks ? part[threadIdx.x * kDiagSlots + q] : 0.0;
+    acc[q] = q == 6 ? block_max(v, sh) : block_sum(v, sh);
+  }
+  if (threadIdx.x == 0) {
+    diag[0] = acc[0];
+    diag[1] = acc[1];
+    diag[2] = dim == 3 ? acc[2] : 0.0;
+    for (int a = 0; a < 3; ++a) diag[3 + a] = a < dim ? (double)u[a * nm].x : 0.0;
+    diag[6] = 0.5 * rho * Ld * acc[4];
+    diag[7] = mu * Ld * acc[5];
+    diag[8] = acc[3];
+    diag[9] = acc[6];
+    diag[10] = acc[7];
+  }
+}
+
+hipError_t launch_diag(const Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M, const double* F,
+                       const void* Uh, const void* uhat, const double* X, double* diag, hipStream_t st) {
+  ModeGeo g;
+  g.dim = p.dim;
+  for (int a = 0; a < 3; ++a) g.N[a] = p.N[a];
+  g.Hx = p.Hx;
+  g.L = p.L;
+  const double w = force_weight(f.kind, M);
+  const double Ld = p.dim == 3 ? p.L * p.L * p.L : p.L * p.L;
+  if (p.prec == FSIB_F64) {
+    using T = double;
+    hipLaunchKernelGGL(k_diag_points<T>, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, M, p.dim, w, F, (const T*)Uh,
+                       p.part);
+    hipLaunchKernelGGL(k_diag_modes<T>, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, g, prm.rho, prm.mu,
+                       (const cplx<T>*)uhat, p.part);
+  } else {
+    using T = float;
+    hipLaunchKernelGGL(k_diag_points<T>, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, M, p.dim, w, F, (const T*)Uh,
+                       p.part);
+    hipLaunchKernelGGL(k_diag_modes<T>, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, g, prm.rho, prm.mu,
+                       (const cplx<T>*)uhat, p.part);
+  }
+  hipLaunchKernelGGL(k_diag_volume, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, p.dim, M, X,
+                     f.kind == FSIB_FORCE_SURFACE_TENSION ? f.tris : nullptr, f.ntris, p.part);
+  if (p.prec == FSIB_F64)
+    hipLaunchKernelGGL(k_diag_final<double>, dim3(1), dim3(kDiagThreads), 0, st, p.dim, prm.rho, prm.mu, Ld,
+                       (const cplx<double>*)uhat, p.modes_half(), (const double*)p.part, diag);
+  else
+    hipLaunchKernelGGL(k_diag_final<float>, dim3(1), dim3(kDiagThreads), 0, st, p.dim, prm.rho, prm.mu, Ld,
+                       (const cplx<float>*)uhat, p.modes_half(), (const double*)p.part, diag);
+  return hipGetLastError();
+}
+
+}  // namespace fsib

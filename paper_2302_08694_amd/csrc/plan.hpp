@@ -1,0 +1,116 @@
+// Plan (workspace + tables) of the FSIB library and the launchers of its kernels.
+#pragma once
+
+#include <map>
+#include <string>
+
+#include "common.hpp"
+#include "../../include/fsib.h"
+
+namespace fsib {
+
+// Host-side numerics chosen at plan time (params.cpp).
+double bessel_i0(double x);
+double kb_transform(double a, double beta);  // int_{-1}^{1} I0(beta sqrt(1-z^2))/I0(beta) cos(a z) dz
+int choose_width(double tol, int dim);
+double choose_beta(int w);
+int choose_degree(int w);
+void fit_kernel_pieces(int w, double beta, int deg, double* coef /* (deg+1)*w */);
+int64_t smooth_at_least(int64_t n, int64_t multiple);
+int radix_plan(int n, int* radix);
+
+struct Plan {
+  // options
+  int dim = 0;
+  int64_t N[3] = {1, 1, 1};
+  double L = 1.0;
+  int prec = FSIB_F64;
+  double tol = 1e-6;
+  int ntrans = 1;
+  int64_t max_points = 0;
+  int fluid = 0, ns = 0;
+  int device = 0;
+  // kernel
+  int w = 0, deg = 0;
+  double beta = 0.0;
+  // grids
+  int64_t nf[3] = {1, 1, 1};  // fine grid
+  int64_t nd[3] = {1, 1, 1};  // dealiasing grid
+  int64_t tb[3] = {1, 1, 1};  // tile (bin) size
+  int64_t nt[3] = {1, 1, 1};  // tiles per axis
+  int64_t nbins = 1;
+  int64_t Hx = 1;             // half-spectrum length along x
+  // device tables
+  void* coef = nullptr;              // (deg+1)*w scalars of prec
+  void* fac[3] = {nullptr, nullptr, nullptr};  // deconvolution factors per axis, N[a] scalars, FFT order
+  std::map<int, void*> tw;           // twiddles per FFT length
+  // point sort
+  int* counts = nullptr;   // nbins+1
+  int* offsets = nullptr;  // nbins+1
+  int* pt_bin = nullptr;   // M
+  int* pt_rank = nullptr;  // M
+  int* s_idx = nullptr;    // M: original index of sorted point
+  uint32_t* s_i0 = nullptr;  // M: packed first support cell (10 bits per axis)
+  void* s_y = nullptr;     // M*dim prec: sub-cell position in [-1, 1]
+  int* flag = nullptr;     // non-finite position seen
+  // grids / FFT buffers
+  void* grid = nullptr;
+  void* B1 = nullptr;
+  void* B2 = nullptr;
+  // FSIB workspace
+  double* Xh = nullptr;    // M*dim
+  double* F64 = nullptr;   // M*dim
+  void* S = nullptr;       // M*dim prec
+  void* Uh = nullptr;      // M*dim prec
+  void* fhat = nullptr;    // dim half spectra
+  void* uhat_mid = nullptr;
+  void* pihat = nullptr;   // dealiased products, nprod half spectra
+  void* D1 = nullptr;      // dealiasing FFT buffers
+  void* D2 = nullptr;
+  void* ureal = nullptr;   // dim real fields on the dealiasing grid
+  void* prod = nullptr;    // nprod real fields on the dealiasing grid
+  double* part = nullptr;  // reduction partials
+  int npart = 0;
+  int64_t ws_bytes = 0;
+
+  int64_t fine_cells() const { return nf[0] * nf[1] * nf[2]; }
+  int64_t modes_full() const { return N[0] * N[1] * N[2]; }
+  int64_t modes_half() const { return Hx * N[1] * N[2]; }
+  int64_t dealias_cells() const { return nd[0] * nd[1] * nd[2]; }
+  int nprod() const { return dim == 3 ? 6 : 3; }
+  size_t real_size() const { return prec == FSIB_F64 ? 8 : 4; }
+};
+
+// ---- launchers (all asynchronous on `st`) ----
+// points.hip
+hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st);
+hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const double* X, const void* U,
+                                 double a, hipStream_t st);  // Y = X + a*U
+hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
+// spread_interp.hip
+hipError_t launch_spread(Plan& p, int64_t M, const void* strengths, int real_comps, hipStream_t st);
+hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st);
+// fft.hip
+hipError_t launch_fft_c2c(const Plan& p, const void* in, void* out, int n, int sign, int64_t inner,
+                          int64_t outer, int nin, int pin, int nout, int pout, const void* fac_in,
+                          const void* fac_out, double scale, hipStream_t st);
+hipError_t launch_fft_r2c_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nout,
+                            const void* fac_out, double scale, hipStream_t st);
+hipError_t launch_fft_c2r_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nin,
+                            const void* fac_in, double scale, hipStream_t st);
+// fluid.hip
+hipError_t launch_products(const Plan& p, hipStream_t st);
+hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
+                               const void* uin, void* uout, hipStream_t st);
+hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F,
+                        hipStream_t st);
+hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S,
+                                     hipStream_t st);
+hipError_t launch_diag(const Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M,
+                       const double* F, const void* Uh, const void* uhat, const double* X, double* diag,
+                       hipStream_t st);
+
+// fluid update modes
+enum { FLUID_STOKES = 0, FLUID_NS_HALF = 1, FLUID_NS_FULL = 2 };
+
+}  // namespace fsib

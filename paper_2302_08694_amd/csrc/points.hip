@@ -1,0 +1,177 @@
+// Point preparation for spreading/interpolation: fold positions into the periodic box, locate the
+// first fine-grid cell of each point's kernel support, and counting-sort the points by tile (bin).
+//
+// Fold (periodicity, Sec. 2): x <- x - L floor(x/L) in double; the fine-grid coordinate
+// g = x n_f / L; the support of width w starts at i0 = ceil(g - w/2) (mod n_f) and the point's
+// sub-cell position y = 2 (i0 - g + w/2) - 1 in [-1, 1) selects the kernel values (see params.cpp).
+// Only (i0, y) are kept: the integer cell is exact and y is rounded to the plan precision, so FP32
+// plans keep full positional resolution within a cell.
+#include "plan.hpp"
+
+namespace fsib {
+
+struct Geo {
+  int dim;
+  int w;
+  double L;
+  int64_t nf[3];
+  int64_t tb[3];
+  int64_t nt[3];
+};
+
+__device__ __forceinline__ void locate(double x, double L, int64_t nf, int w, int& i0, double& y, bool& bad) {
+  if (!isfinite(x)) {
+    bad = true;
+    x = 0.0;
+  }
+  double xf = x - L * floor(x / L);
+  // rounding can leave xf at L (x just below a multiple of L) or, for huge |x|, anywhere; both
+  // are multiples of L to within that rounding
+  if (!(xf >= 0.0 && xf < L)) xf = 0.0;
+  double g = xf * ((double)nf / L);
+  if (!(g < (double)nf)) g = 0.0;
+  const double start = g - 0.5 * w;
+  int i = (int)ceil(start);
+  double s = (double)i - start;  // in [0, 1)
+  double yy = 2.0 * s - 1.0;
+  yy = yy < -1.0 ? -1.0 : (yy > 1.0 ? 1.0 : yy);
+  if (i < 0) i += (int)nf;
+  if (i < 0 || i >= (int)nf) i = 0;  // unreachable for g in [0, nf) and 2 <= w <= nf; keeps indices in range
+  i0 = i;
+  y = yy;
+}
+
+__global__ void k_bin_count(int64_t M, const double* __restrict__ X, Geo g, int* __restrict__ counts,
+                            int* __restrict__ pt_bin, int* __restrict__ pt_rank, int* __restrict__ flag) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  bool bad = false;
+  int64_t bin = 0, stride = 1;
+  for (int a = 0; a < g.dim; ++a) {
+    int i0;
+    double y;
+    locate(X[j * g.dim + a], g.L, g.nf[a], g.w, i0, y, bad);
+    bin += (i0 / g.tb[a]) * stride;
+    stride *= g.nt[a];
+  }
+  if (bad) flag[0] = 1;
+  pt_bin[j] = (int)bin;
+  pt_rank[j] = atomicAdd(&counts[bin], 1);
+}
+
+// Exclusive scan of counts[0..n) into offsets[0..n] by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan(int64_t n, const int* __restrict__ counts, int* __restrict__ offsets) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t b = t * chunk;
+  const int64_t e = b + chunk < n ? b + chunk : n;
+  int s = 0;
+  for (int64_t i = b; i < e; ++i) s += counts[i];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the 1024 chunk sums
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = t > 0 ? part[t - 1] : 0;
+  for (int64_t i = b; i < e; ++i) {
+    offsets[i] = run;
+    run += counts[i];
+  }
+  if (t == 1023) offsets[n] = part[1023];
+}
+
+template <typename T>
+__global__ void k_bin_scatter(int64_t M, const double* __restrict__ X, Geo g, const int* __restrict__ offsets,
+                              const int* __restrict__ pt_bin, const int* __restrict__ pt_rank,
+                              int* __restrict__ s_idx, uint32_t* __restrict__ s_i0, T* __restrict__ s_y) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const int64_t pos = (int64_t)offsets[pt_bin[j]] + pt_rank[j];
+  bool bad = false;
+  uint32_t packed = 0;
+  const int bits = g.dim == 3 ? 10 : 16;
+  for (int a = 0; a < g.dim; ++a) {
+    int i0;
+    double y;
+    locate(X[j * g.dim + a], g.L, g.nf[a], g.w, i0, y, bad);
+    packed |= (uint32_t)i0 << (bits * a);
+    s_y[pos * g.dim + a] = (T)y;
+  }
+  s_idx[pos] = (int)j;
+  s_i0[pos] = packed;
+}
+
+__global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+template <typename T>
+__global__ void k_axpy_pos(int64_t n, double* __restrict__ Y, const double* __restrict__ X, const T* __restrict__ U,
+                           double a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Y[i] = X[i] + a * (double)U[i];
+}
+
+static Geo make_geo(const Plan& p) {
+  Geo g;
+  g.dim = p.dim;
+  g.w = p.w;
+  g.L = p.L;
+  for (int a = 0; a < 3; ++a) {
+    g.nf[a] = p.nf[a];
+    g.tb[a] = p.tb[a];
+    g.nt[a] = p.nt[a];
+  }
+  return g;
+}
+
+hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st) {
+  const int64_t n = bytes / 4;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t*)ptr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st) {
+  Geo g = make_geo(p);
+  hipError_t e = launch_fill_zero(p.counts, (p.nbins + 1) * (int64_t)sizeof(int), st);
+  if (e != hipSuccess) return e;
+  if (M > 0) {
+    const unsigned nblk = (unsigned)((M + 255) / 256);
+    hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st, M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p.nbins, (const int*)p.counts, p.offsets);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (M > 0) {
+    const unsigned nblk = (unsigned)((M + 255) / 256);
+    if (p.prec == FSIB_F64)
+      hipLaunchKernelGGL(k_bin_scatter<double>, dim3(nblk), dim3(256), 0, st, M, X, g, (const int*)p.offsets,
+                         (const int*)p.pt_bin, (const int*)p.pt_rank, p.s_idx, p.s_i0, (double*)p.s_y);
+    else
+      hipLaunchKernelGGL(k_bin_scatter<float>, dim3(nblk), dim3(256), 0, st, M, X, g, (const int*)p.offsets,
+                         (const int*)p.pt_bin, (const int*)p.pt_rank, p.s_idx, p.s_i0, (float*)p.s_y);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const double* X, const void* U, double a,
+                                 hipStream_t st) {
+  const int64_t n = M * p.dim;
+  if (n <= 0) return hipSuccess;
+  const unsigned nblk = (unsigned)((n + 255) / 256);
+  if (p.prec == FSIB_F64)
+    hipLaunchKernelGGL(k_axpy_pos<double>, dim3(nblk), dim3(256), 0, st, n, Y, X, (const double*)U, a);
+  else
+    hipLaunchKernelGGL(k_axpy_pos<float>, dim3(nblk), dim3(256), 0, st, n, Y, X, (const float*)U, a);
+  return hipGetLastError();
+}
+
+}  // namespace fsib

@@ -1,0 +1,362 @@
+// Spreading onto and interpolation from the fine grid (App. A, eqs. type1_conv and type2_conv).
+//
+// Spreading is output-stationary: one workgroup owns one tile of the fine grid, accumulates every
+// point whose kernel support meets the tile into an LDS copy of the tile (LDS atomics), and
+// writes the tile once with plain coalesced stores -- no global atomics and no separate zeroing
+// pass.  Points are counting-sorted by the tile holding their first support cell, so the points
+// that reach a tile live in that tile's bin and in the Q bins before it along each axis,
+// Q = ceil((w-1)/tile).  Kernel values are the piecewise polynomials of params.cpp evaluated in
+// registers (Horner) from the point's sub-cell position.
+//
+// Interpolation gathers the w^d cells of each point from the grid (sorted order, so neighbouring
+// threads read neighbouring cells) and writes the result at the point's original index.
+#include "plan.hpp"
+
+namespace fsib {
+
+constexpr int kSpreadThreads = 256;
+constexpr int kChunk = 64;           // points staged per round
+constexpr int kMaxTileCells = 1024;  // cells of one tile
+
+template <typename T>
+struct SpreadArgs {
+  const T* coef;        // (deg+1)*w
+  int deg;
+  const int* offsets;   // nbins+1
+  const int* s_idx;
+  const uint32_t* s_i0;
+  const T* s_y;
+  const T* str;         // strengths: real (M, nch) or complex (ntrans, M)
+  T* grid;              // real: nch planes; complex: ntrans interleaved complex grids
+  int64_t M;
+  int nf[3];
+  int tb[3];
+  int nt[3];
+  int q[3];             // neighbour bins to visit per axis (0..q)
+};
+
+template <typename T, int W>
+__device__ __forceinline__ void kernel_values(const T* __restrict__ coef, int deg, T y, T* v) {
+#pragma unroll
+  for (int j = 0; j < W; ++j) v[j] = coef[deg * W + j];
+  for (int i = deg - 1; i >= 0; --i) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) v[j] = v[j] * y + coef[i * W + j];
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ int unpack_i0(uint32_t p, int a) {
+  return DIM == 3 ? (int)((p >> (10 * a)) & 1023u) : (int)((p >> (16 * a)) & 65535u);
+}
+
+// NCH channels per point: real vector strengths (NCH = components, planar grids) or one complex
+// strength (NCH = 2, interleaved complex grid, transform index = blockIdx.y).
+template <typename T, int DIM, int W, int NCH, bool CPLX>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
+  __shared__ T acc[NCH * kMaxTileCells];
+  __shared__ T wts[kChunk][DIM][W];
+  __shared__ T sv[kChunk][NCH];
+  __shared__ int vstart[kChunk][DIM];
+  __shared__ int rbeg[27], rlen[27];
+  __shared__ int nrange;
+
+  const int tid = threadIdx.x;
+  const int tr = blockIdx.y;
+  int tcoord[3];
+  {
+    int64_t tile = blockIdx.x;
+    tcoord[0] = (int)(tile % a.nt[0]);
+    tile /= a.nt[0];
+    tcoord[1] = (int)(tile % a.nt[1]);
+    tcoord[2] = DIM == 3 ? (int)(tile / a.nt[1]) : 0;
+  }
+  const int tcells = a.tb[0] * a.tb[1] * (DIM == 3 ? a.tb[2] : 1);
+  for (int i = tid; i < NCH * tcells; i += kSpreadThreads) acc[i] = (T)0;
+  if (tid == 0) {
+    int nr = 0;
+    const int qz = DIM == 3 ? a.q[2] : 0;
+    for (int dz = 0; dz <= qz; ++dz)
+      for (int dy = 0; dy <= a.q[1]; ++dy)
+        for (int dx = 0; dx <= a.q[0]; ++dx) {
+          const int bx = (tcoord[0] - dx + a.nt[0]) % a.nt[0];
+          const int by = (tcoord[1] - dy + a.nt[1]) % a.nt[1];
+          const int bz = DIM == 3 ? (tcoord[2] - dz + a.nt[2]) % a.nt[2] : 0;
+          const int b = bx + a.nt[0] * (by + a.nt[1] * bz);
+          const int s = a.offsets[b], e = a.offsets[b + 1];
+          if (e > s) {
+            rbeg[nr] = s;
+            rlen[nr] = e - s;
+            ++nr;
+          }
+        }
+    nrange = nr;
+  }
+  __syncthreads();
+  int total = 0;
+  for (int r = 0; r < nrange; ++r) total += rlen[r];
+  int base[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; ++d) base[d] = tcoord[d] * a.tb[d];
+
+  for (int c0 = 0; c0 < total; c0 += kChunk) {
+    const int cnt = total - c0 < kChunk ? total - c0 : kChunk;
+    // stage: kernel values per axis, start offset relative to the tile, strengths
+    for (int it = tid; it < cnt * DIM; it += kSpreadThreads) {
+      const int pl = it / DIM, d = it % DIM;
+      int vi = c0 + pl, r = 0;
+      while (vi >= rlen[r]) vi -= rlen[r++];
+      const int64_t pos = (int64_t)rbeg[r] + vi;
+      T v[W];
+      kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + d], v);
+#pragma unroll
+      for (int j = 0; j < W; ++j) wts[pl][d][j] = v[j];
+      int s = unpack_i0<DIM>(a.s_i0[pos], d) - base[d];
+      if (s < 0) s += a.nf[d];
+      vstart[pl][d] = s;
+      if (d == 0) {
+        const int64_t j0 = a.s_idx[pos];
+        if (CPLX) {
+          sv[pl][0] = a.str[((int64_t)tr * a.M + j0) * 2 + 0];
+          sv[pl][1] = a.str[((int64_t)tr * a.M + j0) * 2 + 1];
+        } else {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) sv[pl][ch] = a.str[j0 * NCH + ch];
+        }
+      }
+    }
+    __syncthreads();
+    // accumulate: one item = one (point, y-line[, z-line]) of the support, looping over x
+    const int lines = DIM == 3 ? W * W : W;
+    for (int it = tid; it < cnt * lines; it += kSpreadThreads) {
+      const int pl = it / lines;
+      const int l = it % lines;
+      const int jy = l % W;
+      const int jz = DIM == 3 ? l / W : 0;
+      int ly = vstart[pl][1] + jy;
+      if (ly >= a.nf[1]) ly -= a.nf[1];
+      if (ly >= a.tb[1]) continue;
+      int lz = 0;
+      T wyz = wts[pl][1][jy];
+      if (DIM == 3) {
+        lz = vstart[pl][2] + jz;
+        if (lz >= a.nf[2]) lz -= a.nf[2];
+        if (lz >= a.tb[2]) continue;
+        wyz *= wts[pl][2][jz];
+      }
+      T s[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) s[ch] = wyz * sv[pl][ch];
+      const int row = (lz * a.tb[1] + ly) * a.tb[0];
+      const int vx = vstart[pl][0];
+#pragma unroll
+      for (int jx = 0; jx < W; ++jx) {
+        int lx = vx + jx;
+        if (lx >= a.nf[0]) lx -= a.nf[0];
+        if (lx < a.tb[0]) {
+          const T wx = wts[pl][0][jx];
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) atomicAdd(&acc[ch * kMaxTileCells + row + lx], s[ch] * wx);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // write the tile once
+  const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
+  for (int i = tid; i < tcells; i += kSpreadThreads) {
+    const int lx = i % a.tb[0];
+    const int ly = (i / a.tb[0]) % a.tb[1];
+    const int lz = DIM == 3 ? i / (a.tb[0] * a.tb[1]) : 0;
+    const int gz = DIM == 3 ? base[2] + lz : 0;
+    const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + ly) * a.nf[0] + base[0] + lx;
+    if (CPLX) {
+      cplx<T> v = mk(acc[i], acc[kMaxTileCells + i]);
+      reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = v;
+    } else {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = acc[ch * kMaxTileCells + i];
+    }
+  }
+}
+
+template <typename T>
+struct InterpArgs {
+  const T* coef;
+  int deg;
+  const int* s_idx;
+  const uint32_t* s_i0;
+  const T* s_y;
+  const T* grid;
+  T* out;   // real: (M, nch); complex: (ntrans, M)
+  int64_t M;
+  int nf[3];
+};
+
+template <typename T, int DIM, int W, int NCH, bool CPLX>
+__global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= a.M) return;
+  const int tr = blockIdx.y;
+  const uint32_t pk = a.s_i0[pos];
+  T wx[W], wy[W], wz[W];
+  kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 0], wx);
+  kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 1], wy);
+  if (DIM == 3) kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 2], wz);
+  const int ix = unpack_i0<DIM>(pk, 0), iy = unpack_i0<DIM>(pk, 1), iz = DIM == 3 ? unpack_i0<DIM>(pk, 2) : 0;
+  const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
+  T acc[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) acc[ch] = (T)0;
+  const int nz = DIM == 3 ? W : 1;
+  for (int jz = 0; jz < nz; ++jz) {
+    int z = iz + jz;
+    if (DIM == 3 && z >= a.nf[2]) z -= a.nf[2];
+    const T wzz = DIM == 3 ? wz[jz] : (T)1;
+    for (int jy = 0; jy < W; ++jy) {
+      int y = iy + jy;
+      if (y >= a.nf[1]) y -= a.nf[1];
+      const T wyz = wzz * wy[jy];
+      const int64_t row = ((int64_t)z * a.nf[1] + y) * a.nf[0];
+      T racc[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) racc[ch] = (T)0;
+#pragma unroll
+      for (int jx = 0; jx < W; ++jx) {
+        int x = ix + jx;
+        if (x >= a.nf[0]) x -= a.nf[0];
+        if (CPLX) {
+          const cplx<T> v = reinterpret_cast<const cplx<T>*>(a.grid)[(int64_t)tr * cells + row + x];
+          racc[0] += wx[jx] * v.x;
+          racc[1] += wx[jx] * v.y;
+        } else {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) racc[ch] += wx[jx] * a.grid[ch * cells + row + x];
+        }
+      }
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) acc[ch] += wyz * racc[ch];
+    }
+  }
+  const int64_t j = a.s_idx[pos];
+  if (CPLX) {
+    a.out[((int64_t)tr * a.M + j) * 2 + 0] = acc[0];
+    a.out[((int64_t)tr * a.M + j) * 2 + 1] = acc[1];
+  } else {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) a.out[j * NCH + ch] = acc[ch];
+  }
+}
+
+// ---- dispatch over (precision, dim, w, channels) ----
+template <typename T, int DIM, int NCH, bool CPLX, int W>
+static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipStream_t st) {
+  SpreadArgs<T> a;
+  a.coef = (const T*)p.coef;
+  a.deg = p.deg;
+  a.offsets = p.offsets;
+  a.s_idx = p.s_idx;
+  a.s_i0 = p.s_i0;
+  a.s_y = (const T*)p.s_y;
+  a.str = (const T*)str;
+  a.grid = (T*)p.grid;
+  a.M = M;
+  for (int d = 0; d < 3; ++d) {
+    a.nf[d] = (int)p.nf[d];
+    a.tb[d] = (int)p.tb[d];
+    a.nt[d] = (int)p.nt[d];
+    int q = (int)((W - 1 + p.tb[d] - 1) / p.tb[d]);
+    if (q > p.nt[d] - 1) q = (int)p.nt[d] - 1;
+    a.q[d] = d < DIM ? q : 0;
+  }
+  hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX>), dim3((unsigned)p.nbins, (unsigned)ntr), dim3(kSpreadThreads),
+                     0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int NCH, bool CPLX, int W>
+static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t st) {
+  InterpArgs<T> a;
+  a.coef = (const T*)p.coef;
+  a.deg = p.deg;
+  a.s_idx = p.s_idx;
+  a.s_i0 = p.s_i0;
+  a.s_y = (const T*)p.s_y;
+  a.grid = (const T*)p.grid;
+  a.out = (T*)out;
+  a.M = M;
+  for (int d = 0; d < 3; ++d) a.nf[d] = (int)p.nf[d];
+  if (M == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_interp<T, DIM, W, NCH, CPLX>), dim3((unsigned)((M + 255) / 256), (unsigned)ntr), dim3(256), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+#define FSIB_W_SWITCH(W_, CALL)                                     \
+  switch (W_) {                                                     \
+    case 2: return CALL(2);                                         \
+    case 3: return CALL(3);                                         \
+    case 4: return CALL(4);                                         \
+    case 5: return CALL(5);                                         \
+    case 6: return CALL(6);                                         \
+    case 7: return CALL(7);                                         \
+    case 8: return CALL(8);                                         \
+    case 9: return CALL(9);                                         \
+    case 10: return CALL(10);                                       \
+    case 11: return CALL(11);                                       \
+    case 12: return CALL(12);                                       \
+    case 13: return CALL(13);                                       \
+    case 14: return CALL(14);                                       \
+    case 15: return CALL(15);                                       \
+    case 16: return CALL(16);                                       \
+    default: return hipErrorInvalidValue;                           \
+  }
+
+template <typename T, int DIM, int NCH, bool CPLX>
+static hipError_t spread_dispatch(Plan& p, int64_t M, const void* str, int ntr, hipStream_t st) {
+#define CALL_S(w) run_spread<T, DIM, NCH, CPLX, w>(p, M, str, ntr, st)
+  FSIB_W_SWITCH(p.w, CALL_S)
+#undef CALL_S
+}
+
+template <typename T, int DIM, int NCH, bool CPLX>
+static hipError_t interp_dispatch(Plan& p, int64_t M, void* out, int ntr, hipStream_t st) {
+#define CALL_I(w) run_interp<T, DIM, NCH, CPLX, w>(p, M, out, ntr, st)
+  FSIB_W_SWITCH(p.w, CALL_I)
+#undef CALL_I
+}
+
+// real_comps > 0: real vector strengths with dim components; 0: complex, p.ntrans transforms.
+// The point set is the one last sorted by launch_sort_points.
+hipError_t launch_spread(Plan& p, int64_t M, const void* str, int real_comps, hipStream_t st) {
+  const bool f64 = p.prec == FSIB_F64;
+  if (real_comps == 0) {
+    if (p.dim == 2)
+      return f64 ? spread_dispatch<double, 2, 2, true>(p, M, str, p.ntrans, st)
+                 : spread_dispatch<float, 2, 2, true>(p, M, str, p.ntrans, st);
+    return f64 ? spread_dispatch<double, 3, 2, true>(p, M, str, p.ntrans, st)
+               : spread_dispatch<float, 3, 2, true>(p, M, str, p.ntrans, st);
+  }
+  if (p.dim == 2)
+    return f64 ? spread_dispatch<double, 2, 2, false>(p, M, str, 1, st)
+               : spread_dispatch<float, 2, 2, false>(p, M, str, 1, st);
+  return f64 ? spread_dispatch<double, 3, 3, false>(p, M, str, 1, st)
+             : spread_dispatch<float, 3, 3, false>(p, M, str, 1, st);
+}
+
+hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st) {
+  const bool f64 = p.prec == FSIB_F64;
+  if (real_comps == 0) {
+    if (p.dim == 2)
+      return f64 ? interp_dispatch<double, 2, 2, true>(p, M, out, p.ntrans, st)
+                 : interp_dispatch<float, 2, 2, true>(p, M, out, p.ntrans, st);
+    return f64 ? interp_dispatch<double, 3, 2, true>(p, M, out, p.ntrans, st)
+               : interp_dispatch<float, 3, 2, true>(p, M, out, p.ntrans, st);
+  }
+  if (p.dim == 2)
+    return f64 ? interp_dispatch<double, 2, 2, false>(p, M, out, 1, st)
+               : interp_dispatch<float, 2, 2, false>(p, M, out, 1, st);
+  return f64 ? interp_dispatch<double, 3, 3, false>(p, M, out, 1, st)
+             : interp_dispatch<float, 3, 3, false>(p, M, out, 1, st);
+}
+
+}  // namespace fsib

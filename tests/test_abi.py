@@ -1,0 +1,74 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point declared in
+include/fsib.h, validates arguments before touching a device, and reports the missing device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2302_08694_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fsib.h")).read()
+    return sorted(set(re.findall(r"\b(fsib_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = B.load_library()
+    names = _declared()
+    assert "fsib_spread" in names and "fsib_step" in names and len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_status_strings():
+    lib = B.load_library()
+    assert b"gfx950" in lib.fsib_version()
+    for s in range(8):
+        assert lib.fsib_status_string(s)
+    assert lib.fsib_status_string(99) == b"unknown status"
+
+
+def _opts(**kw):
+    o = dict(dim=3, n_modes=(16, 16, 16), L=1.0, prec=0, tol=1e-6, upsampfac=2.0, ntrans=1, max_points=100,
+             fluid=0, navier_stokes=0)
+    o.update(kw)
+    return B._Opts(o["dim"], (ctypes.c_int64 * 3)(*o["n_modes"]), o["L"], o["prec"], o["tol"], o["upsampfac"],
+                   o["ntrans"], o["max_points"], o["fluid"], o["navier_stokes"])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dim=1), 1), (dict(dim=4), 1), (dict(n_modes=(1, 16, 16)), 1), (dict(L=0.0), 1), (dict(L=float("nan")), 1),
+    (dict(prec=7), 1), (dict(upsampfac=1.5), 1), (dict(ntrans=0), 1), (dict(max_points=-1), 1),
+    (dict(navier_stokes=1, fluid=0), 1),
+    (dict(prec=1, tol=1e-10), 2), (dict(prec=0, tol=1e-16), 2), (dict(tol=0.5), 2),
+])
+def test_plan_argument_errors_come_before_device_use(kw, status):
+    lib = B.load_library()
+    h = ctypes.c_void_p()
+    assert lib.fsib_plan_create(ctypes.byref(_opts(**kw)), ctypes.byref(h)) == status
+    assert h.value is None
+    assert lib.fsib_last_error()
+
+
+def test_null_arguments_rejected():
+    lib = B.load_library()
+    assert lib.fsib_plan_create(None, None) == 1
+    assert lib.fsib_plan_destroy(None) == 1
+    assert lib.fsib_spread(None, 0, None, None, None, 1.0, None) == 1
+    assert lib.fsib_interp(None, 0, None, None, None, None) == 1
+    assert lib.fsib_step(None, None, None, 0, None, None, None, None, None) == 1
+    f = B._Force(99, 1.0, None, 0, None, None)
+    assert lib.fsib_compute_force(ctypes.byref(f), 3, 10, None, None, None) == 1
+
+
+@pytest.mark.skipif(B.device_count() > 0, reason="only meaningful on a host without a GPU")
+def test_no_device_reported():
+    lib = B.load_library()
+    assert lib.fsib_device_count() == 0
+    h = ctypes.c_void_p()
+    assert lib.fsib_plan_create(ctypes.byref(_opts()), ctypes.byref(h)) == 3
