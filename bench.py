@@ -1,0 +1,200 @@
+"""FSIB hot-path benchmark on one MI355X.
+
+Workload: 3D Navier-Stokes FSIB, N = 128^3 Fourier modes, M = 40,000 surface points (lat-long
+200 x 200 sphere of radius 0.25 stretched to an ellipsoid 0.3/0.25/0.2), surface tension K = 1,
+rho = 1, mu = 0.01, dt = 5e-4, uhat^0 = 0.  One step = one Alg. 1 step (fsib_step): force,
+type-1 spread, two dealiased Fourier updates, two type-2 interpolations, the position updates.
+Inputs are synthetic and resident on the device before timing starts.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu-baseline]
+
+Prints one JSON line: FSIB steps/s in FP64 at NUFFT tolerance 1e-5 (value), with the FP32 form,
+the NUFFT spread+interp points/s at 128^3, the roofline of the dominant kernel and the CPU oracle
+timed on the host.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=128, help="modes per axis")
+    ap.add_argument("--rings", type=int, default=200)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def setup(F, torch, prec, tol, N, rings):
+    import workloads
+    case = workloads.ns3d_case(n_rings=rings, n_lon=rings, N=N)
+    X0, tris = case["X"], case["tris"]
+    M = X0.shape[0]
+    ptr, idx = workloads.vertex_triangle_csr(tris, M)
+    dev = "cuda:0"
+    plan = F.Plan(3, case["N"], L=case["L"], prec=prec, tol=tol, max_points=M, fluid=True, navier_stokes=True)
+    force = F.Force("surface3d", case["K"], torch.as_tensor(tris).to(dev), torch.as_tensor(ptr).to(dev),
+                    torch.as_tensor(idx).to(dev))
+    params = F.FluidParams("navier_stokes", rho=case["rho"], mu=case["mu"], dt=case["dt"])
+    X = torch.as_tensor(X0).to(dev).contiguous()
+    U = torch.zeros((M, 3), dtype=plan.rdtype, device=dev)
+    uh = torch.zeros((3,) + plan.half_shape, dtype=plan.cdtype, device=dev)
+    return dict(plan=plan, force=force, params=params, X=X, U=U, uh=uh, M=M, X0=X0, tris=tris, case=case)
+
+
+def time_steps(torch, s, steps, warmup):
+    plan, force, params = s["plan"], s["force"], s["params"]
+    for _ in range(warmup):
+        plan.step(params, force, s["X"], s["U"], s["uh"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.step(params, force, s["X"], s["U"], s["uh"])
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def time_nufft(torch, s, reps=20):
+    """Force spreading and velocity interpolation at the surface points (sort + spread + FFT + deconvolution)."""
+    plan = s["plan"]
+    X = s["X"]
+    M = s["M"]
+    S = torch.randn((M, 3), dtype=plan.rdtype, device=X.device)
+    fh = plan.force_spread(X, S, 1.0)
+    fh[..., -1] = 0
+    U = plan.velocity_interp(X, fh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.force_spread(X, S, 1.0, out=fh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        plan.velocity_interp(X, fh, out=U)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ts, ti = (t1 - t0) / reps, (t2 - t1) / reps
+    return dict(spread_pts_per_s=M / ts, interp_pts_per_s=M / ti, spread_interp_pts_per_s=M / (ts + ti),
+                spread_ms=ts * 1e3, interp_ms=ti * 1e3)
+
+
+def cpu_baseline(N, rings, sample_points=2048):
+    """The FP64 oracle on a bounded sample of one step, extrapolated to steps/s.
+
+    Sample: the oracle's force spreading and one velocity interpolation of `sample_points` of the
+    M surface points at the full N^3 mode set (direct sums, cost linear in the points), and one
+    dealiased nonlinear term at the full size.  A step is one spreading, two interpolations and
+    two nonlinear terms.
+    """
+    import workloads
+    from oracle import fluid, step
+    from oracle.modes import spectral_shape
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        blas_threads = os.cpu_count()
+    case = workloads.ns3d_case(n_rings=rings, n_lon=rings, N=N)
+    X = case["X"]
+    M = X.shape[0]
+    Ns = case["N"]
+    rng = np.random.default_rng(0)
+    sel = rng.choice(M, size=min(sample_points, M), replace=False)
+    Xs = X[sel]
+    Fs = rng.standard_normal((len(sel), 3))
+    t0 = time.perf_counter()
+    fh = step.spread_force(Xs, Fs, 1.0, Ns, 1.0)
+    t1 = time.perf_counter()
+    step.interp_velocity(Xs, fh, Ns, 1.0)
+    t2 = time.perf_counter()
+    uh = fluid.zero_nyquist(fluid.project(fh, Ns, 1.0), Ns)
+    t3 = time.perf_counter()
+    fluid.nonlinear(uh, Ns, 1.0)
+    t4 = time.perf_counter()
+    scale = M / len(sel)
+    t_step = (t1 - t0) * scale + 2 * (t2 - t1) * scale + 2 * (t4 - t3)
+    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": int(blas_threads), "kind": "oracle",
+            "sample": (f"oracle force spreading + velocity interpolation of {len(sel)} of {M} points at N={N}^3 "
+                       f"(direct sums, {t1 - t0:.2f}s + {t2 - t1:.2f}s, scaled by M/{len(sel)}) and one dealiased "
+                       f"nonlinear term at N={N}^3 ({t4 - t3:.2f}s); step = 1 spread + 2 interp + 2 nonlinear; "
+                       f"extrapolated {t_step:.1f} s/step"),
+            "seconds_per_step": t_step}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2302_08694_amd as F
+    if F.device_count() < 1:
+        raise SystemExit("no HIP device visible")
+    log("setup FP64")
+    s64 = setup(F, torch, "f64", a.tol, a.n, a.rings)
+    log(f"plan f64: {s64['plan'].info()}")
+    t64 = time_steps(torch, s64, a.steps, a.warmup)
+    log(f"f64 {t64 * 1e3:.3f} ms/step")
+    nu64 = time_nufft(torch, s64)
+    X64 = s64["X"].cpu().numpy()
+    s64["plan"].close()
+    del s64
+    log("setup FP32")
+    s32 = setup(F, torch, "f32", a.tol, a.n, a.rings)
+    t32 = time_steps(torch, s32, a.steps, a.warmup)
+    log(f"f32 {t32 * 1e3:.3f} ms/step")
+    nu32 = time_nufft(torch, s32)
+    X32 = s32["X"].cpu().numpy()
+    s32["plan"].close()
+    del s32
+    d64 = X64 - s64_X0(a)
+    err32 = float(np.linalg.norm(X32 - X64) / max(np.linalg.norm(d64), 1e-300))
+    out = {
+        "metric": "FSIB steps/sec (3D Navier-Stokes, 128^3 modes, M=40,000) with NUFFT spread+interp pts/sec, "
+                  "FP64 and FP32 at tol 1e-5",
+        "value": 1.0 / t64,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": t64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D Navier-Stokes FSIB, N={a.n}^3, M={a.rings * a.rings} lat-long ellipsoid "
+                               f"(0.3/0.25/0.2), surface tension K=1, rho=1, mu=0.01, dt=5e-4, NUFFT tol {a.tol:g}",
+                   "n_modes": a.n, "points": a.rings * a.rings, "tol": a.tol},
+        "fp32": {"steps_per_s": 1.0 / t32, "ms_per_step": t32 * 1e3,
+                 "rel_err_displacement_vs_fp64": err32, "steps_compared": a.steps + a.warmup},
+        "nufft_at_128": {"f64": nu64, "f32": nu32},
+        "roofline": None,
+    }
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(a.n, a.rings)
+    print(json.dumps(out), flush=True)
+
+
+def s64_X0(a):
+    import workloads
+    return workloads.ns3d_case(n_rings=a.rings, n_lon=a.rings, N=a.n)["X"]
+
+
+if __name__ == "__main__":
+    main()

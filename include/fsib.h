@@ -16,8 +16,11 @@
  *    then the negative modes; the zero mode first) with the x index fastest, then y, then z.
  *  - "Full" spectral array of one transform: N_z*N_y*N_x complex values (2D: N_y*N_x).
  *    "Half" spectral array of one real field: N_z*N_y*H_x complex values, H_x = floor(N_x/2)+1,
- *    holding m_x = 0..H_x-1 (the other half is the complex conjugate).  Vector fields are
- *    component-major: d consecutive scalar arrays (d = dim).
+ *    holding m_x = 0..H_x-1 (the other half is the complex conjugate).  For even N_x the last
+ *    entry is the wavenumber +N_x/2, the conjugate partner of the K_N modes with m_x = -N_x/2:
+ *    fsib_force_spread fills it, fsib_fluid_step sets it to zero and fsib_velocity_interp
+ *    requires it to be zero.  Vector fields are component-major: d consecutive scalar arrays
+ *    (d = dim).
  *  - Complex values are interleaved (re, im) pairs of the plan precision: double for FSIB_F64,
  *    float for FSIB_F32.  "prec" below means that scalar type.
  *  - Positions X are always double, shape (M, dim) row-major, any real values: the L-periodicity
@@ -173,7 +176,7 @@ fsib_status fsib_velocity(fsib_plan plan, const fsib_fluid_params* params, const
  *   [6]    E_K = rho/2 L^d sum_k |uhat^{m+1}|^2                     (Sec. 5.4)
  *   [7]    mu L^d sum_k |k|^2 |uhat^{m+1}|^2 (viscous dissipation)   (Sec. 5.4)
  *   [8]    sum_j w_j F_j^{m+1/2} . U_j^{m+1/2} (power)               (Sec. 5.4)
- *   [9]    max_k |k . uhat^{m+1}| / (|k| |uhat^{m+1}|)               (Sec. 5.1)
+ *   [9]    max_k |k . uhat^{m+1}(k)| / max_k |k| |uhat^{m+1}(k)|     (Sec. 5.1)
  *   [10]   area (2D, shoelace) or volume (3D, signed tetrahedra) enclosed by X^{m+1} (Sec. 6.2) */
 #define FSIB_DIAG_COUNT 11
 fsib_status fsib_step(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force,

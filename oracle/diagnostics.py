@@ -35,14 +35,17 @@ def power(F, w, U):
 
 
 def divergence_residual(uhat, Ns, L):
-    """max_k |k . uhat(k)| / (|k| |uhat(k)|) over modes with nonzero |k| and uhat (Sec. 5.1)."""
+    """max_k |k . uhat(k)| / max_k |k| |uhat(k)| (Sec. 5.1); 0 for a field without nonzero modes.
+
+    Normalised by the largest mode rather than mode by mode, so that modes that are zero up to
+    rounding do not dominate.
+    """
     k = wavevector(Ns, L)
     kd = np.abs(sum(k[a] * uhat[a] for a in range(len(Ns))))
     kn = np.sqrt(ksquared(Ns, L))
     un = np.sqrt(np.sum(np.abs(uhat) ** 2, axis=0))
-    den = kn * un
-    ok = den > 0
-    return float(np.max(kd[ok] / den[ok])) if np.any(ok) else 0.0
+    den = float(np.max(kn * un))
+    return float(np.max(kd)) / den if den > 0 else 0.0
 
 
 def enclosed_area(X):

@@ -250,7 +250,8 @@ hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const d
 // ---- diagnostics: fixed-order FP64 reductions (deterministic) ----
 constexpr int kDiagBlocks = 256;
 constexpr int kDiagThreads = 256;
-constexpr int kDiagSlots = 12;  // per block: 0..2 sum wF, 3 power, 4 E_K, 5 dissipation, 6 max div, 7 volume
+constexpr int kDiagSlots = 12;  // per block: 0..2 sum wF, 3 power, 4 E_K, 5 dissipation, 6 max |k.u|,
+                                // 7 volume, 8 max |k||u|
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   sh[threadIdx.x] = v;
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_modes(ModeGeo g, double r
                                                              const cplx<T>* __restrict__ u, double* __restrict__ part) {
   __shared__ double sh[kDiagThreads];
   const int64_t nm = g.Hx * g.N[1] * (g.dim == 3 ? g.N[2] : 1);
-  double ek = 0, dis = 0, dv = 0;
+  double ek = 0, dis = 0, dv = 0, dn = 0;
   const double twopi_L = 6.283185307179586476925286766559 / g.L;
   for (int64_t idx = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; idx < nm;
        idx += (int64_t)kDiagBlocks * kDiagThreads) {
@@ -322,7 +323,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_modes(ModeGeo g, double r
     }
     ek += wgt * uu;
     dis += wgt * k2 * uu;
-    if (k2 > 0 && uu > 0) dv = fmax(dv, sqrt((kr * kr + ki * ki) / (k2 * uu)));
+    dv = fmax(dv, sqrt(kr * kr + ki * ki));
+    dn = fmax(dn, sqrt(k2 * uu));
   }
   double r = block_sum(ek, sh);
   if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 4] = r;
@@ -330,6 +332,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_modes(ModeGeo g, double r
   if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 5] = r;
   r = block_max(dv, sh);
   if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 6] = r;
+  r = block_max(dn, sh);
+  if (threadIdx.x == 0) part[blockIdx.x * kDiagSlots + 8] = r;
 }
 
 // enclosed area (2D shoelace over the closed curve) or volume (3D, (1/6) sum X_i . (X_j x X_k))
@@ -362,10 +366,10 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(int dim, double rho
                                                              const cplx<T>* __restrict__ u, int64_t nm,
                                                              const double* __restrict__ part, double* __restrict__ diag) {
   __shared__ double sh[kDiagThreads];
-  double acc[8];
-  for (int q = 0; q < 8; ++q) {
+  double acc[9];
+  for (int q = 0; q < 9; ++q) {
     const double v = threadIdx.x < kDiagBlocks ? part[threadIdx.x * kDiagSlots + q] : 0.0;
-    acc[q] = q == 6 ? block_max(v, sh) : block_sum(v, sh);
+    acc[q] = (q == 6 || q == 8) ? block_max(v, sh) : block_sum(v, sh);
   }
   if (threadIdx.x == 0) {
     diag[0] = acc[0];
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(int dim, double rho
     diag[6] = 0.5 * rho * Ld * acc[4];
     diag[7] = mu * Ld * acc[5];
     diag[8] = acc[3];
-    diag[9] = acc[6];
+    diag[9] = acc[8] > 0 ? acc[6] / acc[8] : 0.0;
     diag[10] = acc[7];
   }
 }
