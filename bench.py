@@ -55,16 +55,37 @@ def setup(F, torch, prec, tol, N, rings):
     return dict(plan=plan, force=force, params=params, X=X, U=U, uh=uh, M=M, X0=X0, tris=tris, case=case)
 
 
+ROUND = 10  # steps per round from the initial state (the specified dt is above the explicit
+            # surface-tension stability limit at h = 1/128: the uninterrupted run turns non-finite
+            # near step 60, so timing restarts from the initial state every ROUND steps)
+
+
+def reset(s):
+    s["X"].copy_(s["Xinit"])
+    s["U"].zero_()
+    s["uh"].zero_()
+
+
 def time_steps(torch, s, steps, warmup):
     plan, force, params = s["plan"], s["force"], s["params"]
+    s["Xinit"] = s["X"].clone()
     for _ in range(warmup):
         plan.step(params, force, s["X"], s["U"], s["uh"])
+    reset(s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
+        if k > 0 and k % ROUND == 0:
+            reset(s)  # inside the timed region
         plan.step(params, force, s["X"], s["U"], s["uh"])
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    el = (time.perf_counter() - t0) / steps
+    # state after ROUND steps from the initial state, for the FP32-vs-FP64 comparison
+    reset(s)
+    for _ in range(ROUND):
+        plan.step(params, force, s["X"], s["U"], s["uh"])
+    torch.cuda.synchronize()
+    return el
 
 
 def time_nufft(torch, s, reps=20):
@@ -149,16 +170,18 @@ def main():
     log(f"plan f64: {s64['plan'].info()}")
     t64 = time_steps(torch, s64, a.steps, a.warmup)
     log(f"f64 {t64 * 1e3:.3f} ms/step")
-    nu64 = time_nufft(torch, s64)
     X64 = s64["X"].cpu().numpy()
+    U64max = float(s64["U"].abs().max().item())
+    nu64 = time_nufft(torch, s64)
     s64["plan"].close()
     del s64
     log("setup FP32")
     s32 = setup(F, torch, "f32", a.tol, a.n, a.rings)
     t32 = time_steps(torch, s32, a.steps, a.warmup)
     log(f"f32 {t32 * 1e3:.3f} ms/step")
-    nu32 = time_nufft(torch, s32)
     X32 = s32["X"].cpu().numpy()
+    U32max = float(s32["U"].abs().max().item())
+    nu32 = time_nufft(torch, s32)
     s32["plan"].close()
     del s32
     d64 = X64 - s64_X0(a)
@@ -179,9 +202,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3D Navier-Stokes FSIB, N={a.n}^3, M={a.rings * a.rings} lat-long ellipsoid "
                                f"(0.3/0.25/0.2), surface tension K=1, rho=1, mu=0.01, dt=5e-4, NUFFT tol {a.tol:g}",
-                   "n_modes": a.n, "points": a.rings * a.rings, "tol": a.tol},
+                   "n_modes": a.n, "points": a.rings * a.rings, "tol": a.tol,
+                   "timing": f"rounds of {ROUND} steps from the initial state, state reset inside the timed "
+                             "region (dt = 5e-4 exceeds the explicit surface-tension stability limit at this "
+                             "resolution; the uninterrupted trajectory becomes non-finite near step 60)"},
+        "state_after_timed_steps": {"f64_max_abs_U": U64max, "f32_max_abs_U": U32max,
+                                    "f64_finite": bool(np.all(np.isfinite(X64))),
+                                    "f32_finite": bool(np.all(np.isfinite(X32)))},
         "fp32": {"steps_per_s": 1.0 / t32, "ms_per_step": t32 * 1e3,
-                 "rel_err_displacement_vs_fp64": err32, "steps_compared": a.steps + a.warmup},
+                 "rel_err_displacement_vs_fp64": err32, "steps_compared": ROUND},
         "nufft_at_128": {"f64": nu64, "f32": nu32},
         "roofline": None,
     }

@@ -38,6 +38,8 @@ fsib_status fail(fsib_status s, const std::string& msg) {
 
 using fsib::Plan;
 
+constexpr int64_t kSplitPoints = 1024;  // points per part of a heavy spreading tile (kSplit)
+
 int64_t ceil_half(int64_t n) { return (n + 1) / 2; }
 
 struct Alloc {
@@ -75,6 +77,12 @@ void free_plan(Plan& p) {
   fr(p.s_i0);
   fr(p.s_y);
   fr(p.flag);
+  fr(p.tile_parts);
+  fr(p.part_off);
+  fr(p.work);
+  fr(p.tile_slot);
+  fr(p.slot_ctr);
+  fr(p.split_scratch);
   fr(p.grid);
   fr(p.B1);
   fr(p.B2);
@@ -87,7 +95,6 @@ void free_plan(Plan& p) {
   fr(p.pihat);
   fr(p.D1);
   fr(p.D2);
-  fr(p.ureal);
   fr(p.prod);
   fr(p.part);
 }
@@ -136,7 +143,8 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   p.beta = fsib::choose_beta(p.w);
   p.deg = fsib::choose_degree(p.w);
   // fine grid and tiles: n_f >= 2N and >= 2w, 2^a 3^b 5^c, a multiple of the tile
-  const int64_t tile3[3] = {16, 8, 8}, tile2[3] = {32, 32, 1};
+  // spreading tiles: 16 cells along x (one register row per thread), <= 1024 cells, <= 256 rows
+  const int64_t tile3[3] = {16, 8, 8}, tile2[3] = {16, 16, 1};
   for (int a = 0; a < 3; ++a) {
     if (a >= p.dim) {
       p.nf[a] = p.tb[a] = p.nt[a] = 1;
@@ -202,6 +210,27 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   A.get(p.s_i0, Mx * 4);
   A.get(p.s_y, Mx * d * rs);
   A.get(p.flag, 256);
+  // spreading work list: part bound = tiles + visits / kSplit, visits <= M * prod(q + 1)
+  {
+    int64_t reach = 1;
+    for (int a = 0; a < p.dim; ++a) {
+      int64_t q = (p.w - 1 + p.tb[a] - 1) / p.tb[a];
+      if (q > p.nt[a] - 1) q = p.nt[a] - 1;
+      p.qn[a] = q;
+      reach *= q + 1;
+    }
+    const int64_t visits = Mx * reach;
+    p.work_blocks = p.nbins + visits / kSplitPoints + 1;
+    p.split_slots = 2 * visits / kSplitPoints + 2;
+    const int64_t nch_bytes = 2 * rs > d * rs ? 2 * rs : d * rs;  // complex or dim real channels
+    const int64_t tr = p.ntrans > 1 ? p.ntrans : 1;
+    A.get(p.tile_parts, p.nbins * 4);
+    A.get(p.part_off, (p.nbins + 1) * 4);
+    A.get(p.work, p.work_blocks * 8);
+    A.get(p.tile_slot, p.nbins * 4);
+    A.get(p.slot_ctr, 256);
+    A.get(p.split_scratch, tr * p.split_slots * 1024 * nch_bytes);
+  }
   // grid and FFT buffers: complex transforms (ntrans) and, for fluid plans, dim real fields
   int64_t grid_b = (int64_t)p.ntrans * nfc * cs;
   int64_t b1 = p.dim == 3 ? (int64_t)p.ntrans * p.nf[2] * p.nf[1] * p.N[0] * cs : (int64_t)p.ntrans * p.nf[1] * p.N[0] * cs;
@@ -231,8 +260,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
     A.get(p.pihat, p.nprod() * p.modes_half() * cs);
     A.get(p.D1, p.dim == 3 ? nc * p.nd[2] * p.N[1] * p.Hx * cs : 0);
     A.get(p.D2, p.dim == 3 ? nc * p.nd[2] * p.nd[1] * p.Hx * cs : nc * p.nd[1] * p.Hx * cs);
-    A.get(p.ureal, d * p.dealias_cells() * rs);
-    A.get(p.prod, p.nprod() * p.dealias_cells() * rs);
+    A.get(p.prod, p.dim == 3 ? p.nprod() * p.nd[2] * p.nd[1] * p.Hx * cs : p.nprod() * p.nd[1] * p.Hx * cs);
   }
   if (A.status != FSIB_OK) return A.status;
 
@@ -349,7 +377,9 @@ fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U
   return FSIB_OK;
 }
 
-// dealiased products of the field uhat (dim half spectra) -> p.pihat (nprod half spectra)
+// dealiased products of the field uhat (dim half spectra) -> p.pihat (nprod half spectra):
+// inverse passes along z and y onto the dealiasing grid, the fused x pass (inverse transform,
+// products, forward transform), forward passes along y and z back to K_N.
 fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st) {
   const int64_t d = p.dim, np = p.nprod();
   if (p.dim == 3) {
@@ -357,20 +387,16 @@ fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st) {
                                   (int)ceil_half(p.N[2]), (int)p.nd[2], (int)p.nd[2], nullptr, nullptr, 1.0, st));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.D1, p.D2, (int)p.nd[1], +1, p.Hx, d * p.nd[2], (int)p.N[1],
                                   (int)ceil_half(p.N[1]), (int)p.nd[1], (int)p.nd[1], nullptr, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.D2, p.ureal, (int)p.nd[0], d * p.nd[2] * p.nd[1], (int)p.Hx, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_products(p, st));
-    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.prod, p.D2, (int)p.nd[0], np * p.nd[2] * p.nd[1], (int)p.Hx, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_fft_c2c(p, p.D2, p.D1, (int)p.nd[1], -1, p.Hx, np * p.nd[2], (int)p.nd[1], (int)p.nd[1],
+    FSIB_HIP(fsib::launch_nl_xpass(p, p.D2, p.prod, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.prod, p.D1, (int)p.nd[1], -1, p.Hx, np * p.nd[2], (int)p.nd[1], (int)p.nd[1],
                                   (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, nullptr, 1.0, st));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.D1, p.pihat, (int)p.nd[2], -1, p.N[1] * p.Hx, np, (int)p.nd[2], (int)p.nd[2],
                                   (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, nullptr, 1.0, st));
   } else {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.D2, (int)p.nd[1], +1, p.Hx, d, (int)p.N[1], (int)ceil_half(p.N[1]),
                                   (int)p.nd[1], (int)p.nd[1], nullptr, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.D2, p.ureal, (int)p.nd[0], d * p.nd[1], (int)p.Hx, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_products(p, st));
-    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.prod, p.D2, (int)p.nd[0], np * p.nd[1], (int)p.Hx, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_fft_c2c(p, p.D2, p.pihat, (int)p.nd[1], -1, p.Hx, np, (int)p.nd[1], (int)p.nd[1],
+    FSIB_HIP(fsib::launch_nl_xpass(p, p.D2, p.prod, st));
+    FSIB_HIP(fsib::launch_fft_c2c(p, p.prod, p.pihat, (int)p.nd[1], -1, p.Hx, np, (int)p.nd[1], (int)p.nd[1],
                                   (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, nullptr, 1.0, st));
   }
   return FSIB_OK;

@@ -1,115 +1,31 @@
 // Batched mixed-radix (2, 3, 4, 5) Stockham FFT passes in LDS.
 //
 // One pass transforms every line of one axis of a [outer][len][inner] complex array.  A
-// workgroup loads `nb` lines into LDS (contiguous lines for the x axis; `nb` neighbouring columns
-// for strided axes, so that global accesses stay coalesced), runs the Stockham stages between two
-// LDS buffers, and stores.  Zero padding of the input and truncation of the output to a mode set
-// in FFT order, and per-mode real factors (the NUFFT deconvolution, App. A eqs. type1_deco and
-// type2_divi) are folded into the load and store, so pruned transforms read and write only the
-// entries that exist.  Real-data passes along x pack two real lines into one complex line.
+// workgroup holds `nb` lines in one LDS buffer (contiguous lines for the x axis; `nb` neighbouring
+// columns for strided axes, so that global accesses stay coalesced).  Each thread owns kEPT
+// elements: the load phase issues all of its global loads before writing LDS, and every Stockham
+// stage reads its butterfly inputs into registers, synchronises, and writes the outputs back into
+// the same buffer.  Zero padding of the input, truncation of the output to a mode set in FFT order,
+// and per-mode real factors (the NUFFT deconvolution, App. A eqs. type1_deco and type2_divi) are
+// folded into the load and store, so pruned transforms read and write only entries that exist.
+// Real-data passes along x pack two real lines into one complex line.
 //
 // Stockham stage (radix r, p = product of the radices already applied, m = n/r): butterfly i < m,
 // k = i mod p, inputs x[i + q m] (q < r) twiddled by exp(sign 2 pi i q k / (p r)), outputs
 // y[(i - k) r + k + q p].
+#include "fft_device.hpp"
 #include "plan.hpp"
 
 namespace fsib {
 
-constexpr int kFftThreads = 256;
-
-template <typename T>
-__device__ __forceinline__ void bfly(int r, cplx<T>* u, T sg) {
-  if (r == 2) {
-    const cplx<T> a = u[0], b = u[1];
-    u[0] = a + b;
-    u[1] = a - b;
-  } else if (r == 4) {
-    const cplx<T> s02 = u[0] + u[2], d02 = u[0] - u[2], s13 = u[1] + u[3], d13 = u[1] - u[3];
-    u[0] = s02 + s13;
-    u[2] = s02 - s13;
-    u[1] = d02 + mul_i(d13, sg);
-    u[3] = d02 - mul_i(d13, sg);
-  } else if (r == 3) {
-    const T c = (T)-0.5, s = (T)0.86602540378443864676;
-    const cplx<T> t = u[1] + u[2], d = u[1] - u[2];
-    const cplx<T> a = u[0] + t * c;
-    u[0] = u[0] + t;
-    const cplx<T> b = mul_i(d, sg * s);
-    u[1] = a + b;
-    u[2] = a - b;
-  } else {  // r == 5
-    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
-    const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
-    const cplx<T> t1 = u[1] + u[4], t2 = u[2] + u[3], t3 = u[1] - u[4], t4 = u[2] - u[3];
-    const cplx<T> a1 = u[0] + t1 * c1 + t2 * c2;
-    const cplx<T> a2 = u[0] + t1 * c2 + t2 * c1;
-    const cplx<T> b1 = mul_i(t3 * s1 + t4 * s2, sg);
-    const cplx<T> b2 = mul_i(t3 * s2 - t4 * s1, sg);
-    u[0] = u[0] + t1 + t2;
-    u[1] = a1 + b1;
-    u[4] = a1 - b1;
-    u[2] = a2 + b2;
-    u[3] = a2 - b2;
-  }
-}
-
-// LDS index of entry t of line b: lines contiguous (x passes) or interleaved (strided passes).
-template <bool CONTIG>
-__device__ __forceinline__ int lidx(int t, int b, int n, int nb) {
-  return CONTIG ? b * n + t : t * nb + b;
-}
-
-// Runs all Stockham stages on nb lines held in buf0; returns the buffer holding the result.
 template <typename T, bool CONTIG>
-__device__ cplx<T>* stockham(const FftArgs<T>& a, cplx<T>* buf0, cplx<T>* buf1) {
-  const int n = a.n, nb = a.nb;
-  const T sg = (T)a.sign;
-  cplx<T>* src = buf0;
-  cplx<T>* dst = buf1;
-  int p = 1;
-  for (int s = 0; s < a.nst; ++s) {
-    const int r = a.radix[s];
-    const int m = n / r;
-    const int twstride = n / (p * r);
-    for (int it = threadIdx.x; it < m * nb; it += kFftThreads) {
-      int i, b;
-      if (CONTIG) {
-        b = it / m;
-        i = it - b * m;
-      } else {
-        i = it / nb;
-        b = it - i * nb;
-      }
-      const int k = i % p;
-      cplx<T> u[5];
-      for (int q = 0; q < r; ++q) u[q] = src[lidx<CONTIG>(i + q * m, b, n, nb)];
-      if (p > 1) {
-        for (int q = 1; q < r; ++q) {
-          cplx<T> w = a.tw[q * k * twstride];
-          if (a.sign > 0) w.y = -w.y;
-          u[q] = cmul(u[q], w);
-        }
-      }
-      bfly<T>(r, u, sg);
-      const int j0 = (i - k) * r + k;
-      for (int q = 0; q < r; ++q) dst[lidx<CONTIG>(j0 + q * p, b, n, nb)] = u[q];
-    }
-    __syncthreads();
-    cplx<T>* tmp = src;
-    src = dst;
-    dst = tmp;
-    p *= r;
-  }
-  return src;
-}
-
-template <typename T, bool CONTIG>
-__global__ __launch_bounds__(kFftThreads) void k_fft_c2c(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                                         FftArgs<T> a) {
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __restrict__ in,
+                                                            cplx<T>* __restrict__ out, FftArgs<T> a) {
   extern __shared__ char smem_raw[];
-  cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* buf1 = buf0 + a.n * a.nb;
-  const int n = a.n, nb = a.nb;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n = a.n, nb = a.nb, nthr = blockDim.x;
+  cplx<T>* twl = buf + n * nb;
+  stage_twiddles(a.tw, twl, n);
   int64_t o0 = 0, q0 = 0;
   int ncol;
   if (CONTIG) {
@@ -121,81 +37,111 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_c2c(const cplx<T>* __restri
     ncol = (int)(a.inner - q0 < nb ? a.inner - q0 : nb);
   }
   // zero the padding gap [pin, n - (nin - pin))
-  const int g0 = a.pin, g1 = n - (a.nin - a.pin);
-  for (int it = threadIdx.x; it < (g1 - g0) * nb; it += kFftThreads) {
+  const int g0 = a.pin, gl = n - a.nin;
+  for (int it = threadIdx.x; it < gl * nb; it += nthr) {
     int t, b;
     if (CONTIG) {
-      b = it / (g1 - g0);
-      t = g0 + it - b * (g1 - g0);
+      b = it / gl;
+      t = g0 + it - b * gl;
     } else {
       t = g0 + it / nb;
       b = it % nb;
     }
-    buf0[lidx<CONTIG>(t, b, n, nb)] = mk((T)0, (T)0);
+    buf[lidx<CONTIG>(t, b, n, nb)] = mk((T)0, (T)0);
   }
-  for (int it = threadIdx.x; it < a.nin * nb; it += kFftThreads) {
-    int i, b;
-    if (CONTIG) {
-      b = it / a.nin;
-      i = it - b * a.nin;
-    } else {
-      i = it / nb;
-      b = it - i * nb;
+  // load: all global reads of this thread first, then the LDS writes
+  cplx<T> v[kEPT];
+  int li[kEPT];
+  const int nload = a.nin * nb;
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    li[j] = -1;
+    v[j] = mk((T)0, (T)0);
+    if (e < nload) {
+      int i, b;
+      if (CONTIG) {
+        b = e / a.nin;
+        i = e - b * a.nin;
+      } else {
+        i = e / nb;
+        b = e - i * nb;
+      }
+      const int t = i < a.pin ? i : n - (a.nin - i);
+      li[j] = lidx<CONTIG>(t, b, n, nb);
+      if (b < ncol) {
+        const int64_t gi = CONTIG ? (o0 + b) * a.nin + i : (o0 * a.nin + i) * a.inner + q0 + b;
+        v[j] = in[gi];
+        if (a.fac_in) v[j] = v[j] * a.fac_in[i];
+      }
     }
-    const int t = i < a.pin ? i : n - (a.nin - i);
-    cplx<T> v = mk((T)0, (T)0);
-    if (b < ncol) {
-      const int64_t gi = CONTIG ? (o0 + b) * a.nin + i : (o0 * a.nin + i) * a.inner + q0 + b;
-      v = in[gi];
-      if (a.fac_in) v = v * a.fac_in[i];
-    }
-    buf0[lidx<CONTIG>(t, b, n, nb)] = v;
   }
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j)
+    if (li[j] >= 0) buf[li[j]] = v[j];
   __syncthreads();
-  const cplx<T>* res = stockham<T, CONTIG>(a, buf0, buf1);
-  for (int it = threadIdx.x; it < a.nout * nb; it += kFftThreads) {
+  stockham<T, CONTIG>(a, buf, twl, a.nb, a.sign);
+  const int nstore = a.nout * nb;
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    if (e >= nstore) continue;
     int i, b;
     if (CONTIG) {
-      b = it / a.nout;
-      i = it - b * a.nout;
+      b = e / a.nout;
+      i = e - b * a.nout;
     } else {
-      i = it / nb;
-      b = it - i * nb;
+      i = e / nb;
+      b = e - i * nb;
     }
     if (b >= ncol) continue;
     const int t = i < a.pout ? i : n - (a.nout - i);
     T f = a.scale;
     if (a.fac_out) f *= a.fac_out[i];
     const int64_t go = CONTIG ? (o0 + b) * a.nout + i : (o0 * a.nout + i) * a.inner + q0 + b;
-    out[go] = res[lidx<CONTIG>(t, b, n, nb)] * f;
+    out[go] = buf[lidx<CONTIG>(t, b, n, nb)] * f;
   }
 }
 
 // Real lines along x -> half spectra: lines 2b and 2b+1 form z = a + i b; A_m = (Z_m + conj Z_{n-m})/2,
-// B_m = (Z_m - conj Z_{n-m})/(2i) for m < nout.  a.outer = number of real lines.
+// B_m = (Z_m - conj Z_{n-m})/(2i) for m < nout.  a.outer = number of real lines, a.nb = pairs per block.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_r2c_x(const T* __restrict__ in, cplx<T>* __restrict__ out,
-                                                           FftArgs<T> a) {
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restrict__ in, cplx<T>* __restrict__ out,
+                                                              FftArgs<T> a) {
   extern __shared__ char smem_raw[];
-  cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* buf1 = buf0 + a.n * a.nb;
-  const int n = a.n, nb = a.nb;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n = a.n, nb = a.nb, nthr = blockDim.x;
+  cplx<T>* twl = buf + n * nb;
+  stage_twiddles(a.tw, twl, n);
   const int64_t pair0 = (int64_t)blockIdx.x * nb;
-  for (int it = threadIdx.x; it < n * nb; it += kFftThreads) {
-    const int b = it / n, t = it - b * n;
-    const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
-    const T re = r0 < a.outer ? in[r0 * n + t] : (T)0;
-    const T im = r1 < a.outer ? in[r1 * n + t] : (T)0;
-    buf0[b * n + t] = mk(re, im);
+  cplx<T> v[kEPT];
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    v[j] = mk((T)0, (T)0);
+    if (e < n * nb) {
+      const int b = e / n, t = e - b * n;
+      const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
+      if (r0 < a.outer) v[j].x = in[r0 * n + t];
+      if (r1 < a.outer) v[j].y = in[r1 * n + t];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    if (e < n * nb) buf[e] = v[j];  // [b][t] layout: e = b*n + t
   }
   __syncthreads();
-  const cplx<T>* res = stockham<T, true>(a, buf0, buf1);
-  for (int it = threadIdx.x; it < a.nout * nb; it += kFftThreads) {
-    const int b = it / a.nout, m = it - b * a.nout;
+  stockham<T, true>(a, buf, twl, a.nb, a.sign);
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    if (e >= a.nout * nb) continue;
+    const int b = e / a.nout, m = e - b * a.nout;
     const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
     if (r0 >= a.outer) continue;
-    const cplx<T> Z = res[b * n + m];
-    const cplx<T> Zc = conj(res[b * n + (m == 0 ? 0 : n - m)]);
+    const cplx<T> Z = buf[b * n + m];
+    const cplx<T> Zc = conj(buf[b * n + (m == 0 ? 0 : n - m)]);
     T f = a.scale * (T)0.5;
     if (a.fac_out) f *= a.fac_out[m];
     const cplx<T> s = Z + Zc, d = Z - Zc;
@@ -206,42 +152,64 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_r2c_x(const T* __restrict__
 
 // Half spectra along x (nin entries m = 0..nin-1, the rest zero) -> real lines of length n; two
 // lines per complex transform: Z_t = A_t + i B_t with A_{n-m} = conj A_m, then Re/Im of the
-// inverse transform.  a.outer = number of real lines.
+// inverse transform.  a.outer = number of real lines, a.nb = pairs per block.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_c2r_x(const cplx<T>* __restrict__ in, T* __restrict__ out,
-                                                           FftArgs<T> a) {
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __restrict__ in, T* __restrict__ out,
+                                                              FftArgs<T> a) {
   extern __shared__ char smem_raw[];
-  cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* buf1 = buf0 + a.n * a.nb;
-  const int n = a.n, nb = a.nb;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n = a.n, nb = a.nb, nthr = blockDim.x;
+  cplx<T>* twl = buf + n * nb;
+  stage_twiddles(a.tw, twl, n);
   const int64_t pair0 = (int64_t)blockIdx.x * nb;
-  for (int it = threadIdx.x; it < n * nb; it += kFftThreads) {
-    const int b = it / n, t = it - b * n;
-    const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
-    const bool front = 2 * t <= n;
-    const int m = front ? t : n - t;
-    cplx<T> A = mk((T)0, (T)0), B = mk((T)0, (T)0);
-    if (m < a.nin) {
-      T f = (T)1;
-      if (a.fac_in) f = a.fac_in[m];
-      if (r0 < a.outer) A = in[r0 * a.nin + m] * f;
-      if (r1 < a.outer) B = in[r1 * a.nin + m] * f;
-      if (m == 0 || 2 * m == n) {
-        A.y = (T)0;
-        B.y = (T)0;
-      } else if (!front) {
-        A = conj(A);
-        B = conj(B);
+  cplx<T> A[kEPT], B[kEPT];
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    A[j] = mk((T)0, (T)0);
+    B[j] = mk((T)0, (T)0);
+    if (e < n * nb) {
+      const int b = e / n, t = e - b * n;
+      const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
+      const int m = 2 * t <= n ? t : n - t;
+      if (m < a.nin) {
+        if (r0 < a.outer) A[j] = in[r0 * a.nin + m];
+        if (r1 < a.outer) B[j] = in[r1 * a.nin + m];
       }
     }
-    buf0[b * n + t] = mk(A.x - B.y, A.y + B.x);
+  }
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    if (e < n * nb) {
+      const int t = e % n;
+      const bool front = 2 * t <= n;
+      const int m = front ? t : n - t;
+      cplx<T> x = A[j], y = B[j];
+      if (m < a.nin) {
+        const T f = a.fac_in ? a.fac_in[m] : (T)1;
+        x = x * f;
+        y = y * f;
+        if (m == 0 || 2 * m == n) {
+          x.y = (T)0;
+          y.y = (T)0;
+        } else if (!front) {
+          x = conj(x);
+          y = conj(y);
+        }
+      }
+      buf[e] = mk(x.x - y.y, x.y + y.x);
+    }
   }
   __syncthreads();
-  const cplx<T>* res = stockham<T, true>(a, buf0, buf1);
-  for (int it = threadIdx.x; it < n * nb; it += kFftThreads) {
-    const int b = it / n, t = it - b * n;
+  stockham<T, true>(a, buf, twl, a.nb, a.sign);
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    if (e >= n * nb) continue;
+    const int b = e / n, t = e - b * n;
     const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
-    const cplx<T> z = res[b * n + t];
+    const cplx<T> z = buf[e];
     if (r0 < a.outer) out[r0 * n + t] = z.x * a.scale;
     if (r1 < a.outer) out[r1 * n + t] = z.y * a.scale;
   }
@@ -260,12 +228,29 @@ static FftArgs<T> base_args(const Plan& p, int n, int sign) {
   return a;
 }
 
-// LDS budget: two buffers of n*nb complex values within 64 KiB.
+static int gcd_int(int a, int b) {
+  while (b) {
+    const int t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Lines per workgroup: n*nb*sizeof(complex) within 32 KiB, n*nb a multiple of kEPT (every thread
+// owns kEPT elements), preferring whole wavefronts; `cap` bounds nb (columns that exist).
 template <typename T>
-static int lines_per_block(int n) {
-  const int budget = (int)(32768 / sizeof(cplx<T>));  // complex entries per buffer
+static int lines_per_block(int n, int64_t cap) {
+  const int budget = (int)(32768 / sizeof(cplx<T>));
+  const int step = kEPT / gcd_int(n, kEPT);  // nb multiple of step -> n*nb multiple of kEPT
   int nb = budget / n;
-  return nb < 1 ? 1 : (nb > 16 ? 16 : nb);
+  if (cap > 0 && nb > cap) nb = (int)cap;
+  nb = nb / step * step;
+  if (nb < step) nb = step;
+  // prefer a whole number of 64-wide wavefronts
+  for (int c = nb; c >= step; c -= step)
+    if (((int64_t)n * c / kEPT) % 64 == 0) return c;
+  return nb;
 }
 
 template <typename T>
@@ -282,19 +267,16 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
   a.fac_in = (const T*)fin;
   a.fac_out = (const T*)fout;
   a.scale = (T)scale;
-  int nb = lines_per_block<T>(n);
-  if (inner == 1) {
-    a.nb = nb;
-    const size_t lds = 2 * (size_t)n * nb * sizeof(cplx<T>);
-    hipLaunchKernelGGL((k_fft_c2c<T, true>), dim3((unsigned)((outer + nb - 1) / nb)), dim3(kFftThreads), lds, st,
+  const bool contig = inner == 1;
+  a.nb = lines_per_block<T>(n, contig ? outer : inner);
+  const int nthr = n * a.nb / kEPT;
+  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  if (contig)
+    hipLaunchKernelGGL((k_fft_c2c<T, true>), dim3((unsigned)((outer + a.nb - 1) / a.nb)), dim3(nthr), lds, st,
                        (const cplx<T>*)in, (cplx<T>*)out, a);
-  } else {
-    if (nb > inner) nb = (int)inner;
-    a.nb = nb;
-    const size_t lds = 2 * (size_t)n * nb * sizeof(cplx<T>);
-    hipLaunchKernelGGL((k_fft_c2c<T, false>), dim3((unsigned)((inner + nb - 1) / nb), (unsigned)outer),
-                       dim3(kFftThreads), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
-  }
+  else
+    hipLaunchKernelGGL((k_fft_c2c<T, false>), dim3((unsigned)((inner + a.nb - 1) / a.nb), (unsigned)outer), dim3(nthr),
+                       lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
   return hipGetLastError();
 }
 
@@ -319,11 +301,12 @@ static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int6
   a.pout = nout;
   a.fac_out = (const T*)fout;
   a.scale = (T)scale;
-  a.nb = lines_per_block<T>(n);
   const int64_t pairs = (rows + 1) / 2;
-  const size_t lds = 2 * (size_t)n * a.nb * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_fft_r2c_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(kFftThreads), lds, st,
-                     (const T*)in, (cplx<T>*)out, a);
+  a.nb = lines_per_block<T>(n, pairs);
+  const int nthr = n * a.nb / kEPT;
+  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_fft_r2c_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(nthr), lds, st, (const T*)in,
+                     (cplx<T>*)out, a);
   return hipGetLastError();
 }
 
@@ -339,10 +322,11 @@ static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int6
   a.pout = n;
   a.fac_in = (const T*)fin;
   a.scale = (T)scale;
-  a.nb = lines_per_block<T>(n);
   const int64_t pairs = (rows + 1) / 2;
-  const size_t lds = 2 * (size_t)n * a.nb * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_fft_c2r_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(kFftThreads), lds, st,
+  a.nb = lines_per_block<T>(n, pairs);
+  const int nthr = n * a.nb / kEPT;
+  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_fft_c2r_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(nthr), lds, st,
                      (const cplx<T>*)in, (T*)out, a);
   return hipGetLastError();
 }

@@ -23,26 +23,6 @@ struct ModeGeo {
 
 __device__ __forceinline__ int64_t mode_of(int64_t i, int64_t n) { return i < (n + 1) / 2 ? i : i - n; }
 
-template <typename T>
-__global__ void k_products(int64_t cells, int dim, const T* __restrict__ u, T* __restrict__ prod, T inv_cells) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cells) return;
-  if (dim == 3) {
-    const T a = u[i], b = u[cells + i], c = u[2 * cells + i];
-    prod[i] = a * a * inv_cells;
-    prod[cells + i] = a * b * inv_cells;
-    prod[2 * cells + i] = a * c * inv_cells;
-    prod[3 * cells + i] = b * b * inv_cells;
-    prod[4 * cells + i] = b * c * inv_cells;
-    prod[5 * cells + i] = c * c * inv_cells;
-  } else {
-    const T a = u[i], b = u[cells + i];
-    prod[i] = a * a * inv_cells;
-    prod[cells + i] = a * b * inv_cells;
-    prod[2 * cells + i] = b * b * inv_cells;
-  }
-}
-
 __device__ __forceinline__ int sym_index(int a, int b, int dim) {
   if (a > b) {
     const int t = a;
@@ -118,18 +98,6 @@ __global__ void k_fluid(ModeGeo g, int mode, T rho, T mu, T dt, const cplx<T>* _
       r = (Q * dt + u * ((T)1 - av)) * den;
     uout[a * nm + idx] = r;
   }
-}
-
-hipError_t launch_products(const Plan& p, hipStream_t st) {
-  const int64_t cells = p.dealias_cells();
-  const unsigned nblk = (unsigned)((cells + 255) / 256);
-  if (p.prec == FSIB_F64)
-    hipLaunchKernelGGL(k_products<double>, dim3(nblk), dim3(256), 0, st, cells, p.dim, (const double*)p.ureal,
-                       (double*)p.prod, 1.0 / (double)cells);
-  else
-    hipLaunchKernelGGL(k_products<float>, dim3(nblk), dim3(256), 0, st, cells, p.dim, (const float*)p.ureal,
-                       (float*)p.prod, (float)(1.0 / (double)cells));
-  return hipGetLastError();
 }
 
 hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,

@@ -1,0 +1,169 @@
+// Dealiased quadratic products of the velocity along x in one kernel (three-halves rule, Sec. 3.1).
+//
+// Input: the velocity components on the dealiasing grid in y and z, still as half spectra in x
+// ([d][rows][Hx] complex, rows = Ntilde_z * Ntilde_y).  For a pair of rows (a, b) a workgroup
+// forms the complex lines u_x(a) + i u_y(a), u_x(b) + i u_y(b) (and u_z(a) + i u_z(b) in 3D),
+// inverse-transforms them in LDS (length Ntilde_x), multiplies u_alpha u_beta point by point, packs
+// the products of the two rows into complex lines, forward-transforms them and keeps the first Hx
+// modes of each -- so neither the velocity nor the products on the padded grid ever reach memory.
+// Output: the products' half spectra in x ([nprod][rows][Hx]), scaled by 1/Ntilde^d (the H of
+// eq. nonlinear_physical), ready for the forward passes along y and z.
+#include "fft_device.hpp"
+#include "plan.hpp"
+
+namespace fsib {
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                   FftArgs<T> a, int64_t rows, int hx, int pp, T inv_cells) {
+  constexpr int IL = DIM == 3 ? 3 : 2;  // inverse lines per row pair
+  constexpr int FL = DIM == 3 ? 6 : 3;  // forward lines per row pair (products)
+  extern __shared__ char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n = a.n, nthr = blockDim.x;
+  cplx<T>* twl = buf + FL * pp * n;
+  stage_twiddles(a.tw, twl, n);
+  const int64_t pair0 = (int64_t)blockIdx.x * pp;
+  const int64_t cs = rows * hx;  // component stride of in/out
+  // ---- gather the Hermitian-extended lines (inverse) ----
+  const int nin = IL * pp * n;
+  cplx<T> A[kEPT], B[kEPT];
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    A[j] = mk((T)0, (T)0);
+    B[j] = mk((T)0, (T)0);
+    if (e < nin) {
+      const int ln = e / n, t = e - ln * n;
+      const int q = ln / IL, l = ln - q * IL;
+      const int64_t ra = 2 * (pair0 + q), rb = ra + 1;
+      const int m = 2 * t <= n ? t : n - t;
+      if (m < hx) {
+        // line l: (comp, row) of its real part A and imaginary part B
+        int ca, cb;
+        int64_t rowa, rowb;
+        if (l == 0) {
+          ca = 0; cb = 1; rowa = ra; rowb = ra;
+        } else if (l == 1) {
+          ca = 0; cb = 1; rowa = rb; rowb = rb;
+        } else {
+          ca = 2; cb = 2; rowa = ra; rowb = rb;
+        }
+        if (rowa < rows) A[j] = in[ca * cs + rowa * hx + m];
+        if (rowb < rows) B[j] = in[cb * cs + rowb * hx + m];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    if (e < nin) {
+      const int t = e % n;
+      const bool front = 2 * t <= n;
+      const int m = front ? t : n - t;
+      cplx<T> x = A[j], y = B[j];
+      if (m == 0 || 2 * m == n) {
+        x.y = (T)0;
+        y.y = (T)0;
+      } else if (!front) {
+        x = conj(x);
+        y = conj(y);
+      }
+      buf[e] = mk(x.x - y.y, x.y + y.x);
+    }
+  }
+  __syncthreads();
+  stockham<T, true>(a, buf, twl, IL * pp, +1);
+  // ---- products, packed two rows per complex line: line (q, f) = prod_f(row a) + i prod_f(row b) ----
+  constexpr int PPT = (kEPT + FL - 1) / FL;  // (pair, t) positions per thread
+  T pa[PPT][FL], pb[PPT][FL];
+  int pos[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    pos[j] = -1;
+    if (e < pp * n) {
+      const int q = e / n, t = e - q * n;
+      pos[j] = e;
+      const cplx<T> l0 = buf[(q * IL + 0) * n + t], l1 = buf[(q * IL + 1) * n + t];
+      const T uxa = l0.x, uya = l0.y, uxb = l1.x, uyb = l1.y;
+      if constexpr (DIM == 3) {
+        const cplx<T> l2 = buf[(q * IL + 2) * n + t];
+        const T uza = l2.x, uzb = l2.y;
+        pa[j][0] = uxa * uxa; pa[j][1] = uxa * uya; pa[j][2] = uxa * uza;
+        pa[j][3] = uya * uya; pa[j][4] = uya * uza; pa[j][5] = uza * uza;
+        pb[j][0] = uxb * uxb; pb[j][1] = uxb * uyb; pb[j][2] = uxb * uzb;
+        pb[j][3] = uyb * uyb; pb[j][4] = uyb * uzb; pb[j][5] = uzb * uzb;
+      } else {
+        pa[j][0] = uxa * uxa; pa[j][1] = uxa * uya; pa[j][2] = uya * uya;
+        pb[j][0] = uxb * uxb; pb[j][1] = uxb * uyb; pb[j][2] = uyb * uyb;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    if (pos[j] >= 0) {
+      const int q = pos[j] / n, t = pos[j] - q * n;
+#pragma unroll
+      for (int f = 0; f < FL; ++f) buf[(q * FL + f) * n + t] = mk(pa[j][f], pb[j][f]);
+    }
+  }
+  __syncthreads();
+  stockham<T, true>(a, buf, twl, FL * pp, -1);
+  // ---- unpack the two rows of each line, keep m < Hx ----
+  const int nst = FL * pp * hx;
+  for (int e = threadIdx.x; e < nst; e += nthr) {
+    const int ln = e / hx, m = e - ln * hx;
+    const int q = ln / FL, f = ln - q * FL;
+    const int64_t ra = 2 * (pair0 + q), rb = ra + 1;
+    if (ra >= rows) continue;
+    const cplx<T> Z = buf[ln * n + m];
+    const cplx<T> Zc = conj(buf[ln * n + (m == 0 ? 0 : n - m)]);
+    const T s = (T)0.5 * inv_cells;
+    const cplx<T> su = Z + Zc, d = Z - Zc;
+    out[f * cs + ra * hx + m] = su * s;
+    if (rb < rows) out[f * cs + rb * hx + m] = mk(d.y * s, -d.x * s);
+  }
+}
+
+template <typename T>
+static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t st) {
+  const int n = (int)p.nd[0];
+  FftArgs<T> a;
+  a.n = n;
+  a.nst = radix_plan(n, a.radix);
+  a.tw = (const cplx<T>*)p.tw.at(n);
+  a.sign = -1;
+  a.inner = 1;
+  a.outer = 0;
+  a.nin = a.pin = a.nout = a.pout = n;
+  a.fac_in = a.fac_out = nullptr;
+  a.scale = (T)1;
+  a.nb = 0;
+  const int64_t rows = p.dim == 3 ? p.nd[2] * p.nd[1] : p.nd[1];
+  const int fl = p.dim == 3 ? 6 : 3;
+  // row pairs per workgroup: the forward lines fit 36 KiB of LDS and 1024 threads
+  int pp = (int)(36864 / ((size_t)fl * n * sizeof(cplx<T>)));
+  if (pp < 1) pp = 1;
+  while (pp > 1 && (fl * pp * n + kEPT - 1) / kEPT > 1024) --pp;
+  const int64_t pairs = (rows + 1) / 2;
+  if (pp > pairs) pp = (int)pairs;
+  const int nthr = (fl * pp * n + kEPT - 1) / kEPT;
+  const size_t lds = (size_t)(fl * pp + 1) * n * sizeof(cplx<T>);
+  const unsigned nblk = (unsigned)((pairs + pp - 1) / pp);
+  const T inv = (T)(1.0 / (double)p.dealias_cells());
+  if (p.dim == 3)
+    hipLaunchKernelGGL((k_nl_xpass<T, 3>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a, rows,
+                       (int)p.Hx, pp, inv);
+  else
+    hipLaunchKernelGGL((k_nl_xpass<T, 2>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a, rows,
+                       (int)p.Hx, pp, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, hipStream_t st) {
+  return p.prec == FSIB_F64 ? nl_impl<double>(p, in, out, st) : nl_impl<float>(p, in, out, st);
+}
+
+}  // namespace fsib

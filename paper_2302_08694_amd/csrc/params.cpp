@@ -113,11 +113,12 @@ int64_t smooth_at_least(int64_t n, int64_t multiple) {
   return m;
 }
 
-// Radices for a length-n Stockham FFT: 4 first, then 2, 3, 5; returns the stage count (0 if n
+// Radices for a length-n Stockham FFT: 8 first, then 4, 2, 3, 5; returns the stage count (0 if n
 // has another prime factor or needs too many stages).
 int radix_plan(int n, int* radix) {
   int ns = 0;
   int m = n;
+  while (m % 8 == 0 && ns < kMaxStages) { radix[ns++] = 8; m /= 8; }
   while (m % 4 == 0 && ns < kMaxStages) { radix[ns++] = 4; m /= 4; }
   while (m % 2 == 0 && ns < kMaxStages) { radix[ns++] = 2; m /= 2; }
   while (m % 3 == 0 && ns < kMaxStages) { radix[ns++] = 3; m /= 3; }

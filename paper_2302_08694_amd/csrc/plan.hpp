@@ -53,6 +53,16 @@ struct Plan {
   uint32_t* s_i0 = nullptr;  // M: packed first support cell (10 bits per axis)
   void* s_y = nullptr;     // M*dim prec: sub-cell position in [-1, 1]
   int* flag = nullptr;     // non-finite position seen
+  // spreading work list (heavy tiles split into parts of at most kSplit points)
+  int64_t qn[3] = {0, 0, 0};   // bins before a tile, per axis, whose points can reach it
+  int* tile_parts = nullptr;   // nbins
+  int* part_off = nullptr;     // nbins+1
+  int* work = nullptr;         // 2 ints per part, work_blocks parts at most
+  int* tile_slot = nullptr;    // nbins
+  int* slot_ctr = nullptr;
+  void* split_scratch = nullptr;
+  int64_t work_blocks = 0;     // bound on the number of parts
+  int64_t split_slots = 0;     // bound on the partial tiles of split tiles (per transform)
   // grids / FFT buffers
   void* grid = nullptr;
   void* B1 = nullptr;
@@ -67,8 +77,7 @@ struct Plan {
   void* pihat = nullptr;   // dealiased products, nprod half spectra
   void* D1 = nullptr;      // dealiasing FFT buffers
   void* D2 = nullptr;
-  void* ureal = nullptr;   // dim real fields on the dealiasing grid
-  void* prod = nullptr;    // nprod real fields on the dealiasing grid
+  void* prod = nullptr;    // nprod half spectra in x on the dealiasing grid in y, z
   double* part = nullptr;  // reduction partials
   int npart = 0;
   int64_t ws_bytes = 0;
@@ -87,6 +96,7 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
 hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const double* X, const void* U,
                                  double a, hipStream_t st);  // Y = X + a*U
 hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
+hipError_t launch_scan(int64_t n, const int* counts, int* offsets, hipStream_t st);  // exclusive, n+1 outputs
 // spread_interp.hip
 hipError_t launch_spread(Plan& p, int64_t M, const void* strengths, int real_comps, hipStream_t st);
 hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st);
@@ -99,7 +109,7 @@ hipError_t launch_fft_r2c_x(const Plan& p, const void* in, void* out, int n, int
 hipError_t launch_fft_c2r_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nin,
                             const void* fac_in, double scale, hipStream_t st);
 // fluid.hip
-hipError_t launch_products(const Plan& p, hipStream_t st);
+hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, hipStream_t st);  // nonlinear.hip
 hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
                                const void* uin, void* uout, hipStream_t st);
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F,

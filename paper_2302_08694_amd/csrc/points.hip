@@ -138,6 +138,11 @@ hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_scan(int64_t n, const int* counts, int* offsets, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, n, counts, offsets);
+  return hipGetLastError();
+}
+
 hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st) {
   Geo g = make_geo(p);
   hipError_t e = launch_fill_zero(p.counts, (p.nbins + 1) * (int64_t)sizeof(int), st);
@@ -147,8 +152,7 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
     hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st, M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p.nbins, (const int*)p.counts, p.offsets);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_scan(p.nbins, p.counts, p.offsets, st)) != hipSuccess) return e;
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     if (p.prec == FSIB_F64)

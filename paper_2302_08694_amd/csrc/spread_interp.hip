@@ -1,9 +1,8 @@
 // Spreading onto and interpolation from the fine grid (App. A, eqs. type1_conv and type2_conv).
 //
 // Spreading is output-stationary: one workgroup owns one tile of the fine grid, accumulates every
-// point whose kernel support meets the tile into an LDS copy of the tile (LDS atomics), and
-// writes the tile once with plain coalesced stores -- no global atomics and no separate zeroing
-// pass.  Points are counting-sorted by the tile holding their first support cell, so the points
+// point whose kernel support meets the tile (register rows, see k_spread), and writes the tile
+// once with plain coalesced stores -- no atomics and no separate zeroing pass.  Points are counting-sorted by the tile holding their first support cell, so the points
 // that reach a tile live in that tile's bin and in the Q bins before it along each axis,
 // Q = ceil((w-1)/tile).  Kernel values are the piecewise polynomials of params.cpp evaluated in
 // registers (Horner) from the point's sub-cell position.
@@ -17,6 +16,9 @@ namespace fsib {
 constexpr int kSpreadThreads = 256;
 constexpr int kChunk = 64;           // points staged per round
 constexpr int kMaxTileCells = 1024;  // cells of one tile
+constexpr int kTileX = 16;           // tile extent along x (one register row per thread)
+
+constexpr int kSplit = 1024;         // points per part of a heavy tile
 
 template <typename T>
 struct SpreadArgs {
@@ -33,6 +35,13 @@ struct SpreadArgs {
   int tb[3];
   int nt[3];
   int q[3];             // neighbour bins to visit per axis (0..q)
+  // work list: part b of the launch spreads points [q*kSplit, (q+1)*kSplit) of tile t
+  const int* part_off;  // nbins+1 (exclusive scan of tile_parts)
+  const int2* work;     // (t, q) per part
+  const int* tile_parts;
+  const int* tile_slot; // first scratch slot of a split tile
+  T* scratch;           // split tiles: [ntrans][slots][NCH][kMaxTileCells] partial tiles
+  int64_t slots;        // scratch slots per transform
 };
 
 template <typename T, int W>
@@ -52,9 +61,17 @@ __device__ __forceinline__ int unpack_i0(uint32_t p, int a) {
 
 // NCH channels per point: real vector strengths (NCH = components, planar grids) or one complex
 // strength (NCH = 2, interleaved complex grid, transform index = blockIdx.y).
+//
+// Inside a tile every thread owns one row of kTileX cells along x (rows = tile_y * tile_z) and
+// accumulates it in registers for a 1/TPR share of the tile's points; the lanes of a wavefront
+// hold different rows and visit the same point together, so point data are LDS broadcasts and no
+// atomics are needed.  The TPR partial rows are then summed in a fixed order through LDS and the
+// tile is written once.  Dense clusters (e.g. the poles of a lat-long mesh, where thousands of
+// points share a few cells) cost the same per point as isolated points.
 template <typename T, int DIM, int W, int NCH, bool CPLX>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
-  __shared__ T acc[NCH * kMaxTileCells];
+  constexpr int RS = kTileX + 1;  // padded LDS row stride
+  __shared__ T accs[NCH][kMaxTileCells / kTileX][RS];
   __shared__ T wts[kChunk][DIM][W];
   __shared__ T sv[kChunk][NCH];
   __shared__ int vstart[kChunk][DIM];
@@ -63,43 +80,81 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
 
   const int tid = threadIdx.x;
   const int tr = blockIdx.y;
+  if ((int)blockIdx.x >= a.part_off[a.nt[0] * a.nt[1] * a.nt[2]]) return;  // beyond the work list
+  const int2 wk = a.work[blockIdx.x];
+  const int tile_id = wk.x, part = wk.y;
+  const int nparts = a.tile_parts[tile_id];
   int tcoord[3];
   {
-    int64_t tile = blockIdx.x;
+    int64_t tile = tile_id;
     tcoord[0] = (int)(tile % a.nt[0]);
     tile /= a.nt[0];
     tcoord[1] = (int)(tile % a.nt[1]);
     tcoord[2] = DIM == 3 ? (int)(tile / a.nt[1]) : 0;
   }
-  const int tcells = a.tb[0] * a.tb[1] * (DIM == 3 ? a.tb[2] : 1);
-  for (int i = tid; i < NCH * tcells; i += kSpreadThreads) acc[i] = (T)0;
-  if (tid == 0) {
-    int nr = 0;
-    const int qz = DIM == 3 ? a.q[2] : 0;
-    for (int dz = 0; dz <= qz; ++dz)
-      for (int dy = 0; dy <= a.q[1]; ++dy)
-        for (int dx = 0; dx <= a.q[0]; ++dx) {
-          const int bx = (tcoord[0] - dx + a.nt[0]) % a.nt[0];
-          const int by = (tcoord[1] - dy + a.nt[1]) % a.nt[1];
-          const int bz = DIM == 3 ? (tcoord[2] - dz + a.nt[2]) % a.nt[2] : 0;
-          const int b = bx + a.nt[0] * (by + a.nt[1] * bz);
-          const int s = a.offsets[b], e = a.offsets[b + 1];
-          if (e > s) {
-            rbeg[nr] = s;
-            rlen[nr] = e - s;
-            ++nr;
-          }
-        }
-    nrange = nr;
-  }
-  __syncthreads();
-  int total = 0;
-  for (int r = 0; r < nrange; ++r) total += rlen[r];
+  const int rows = a.tb[1] * (DIM == 3 ? a.tb[2] : 1);
+  const int tcells = kTileX * rows;
   int base[3] = {0, 0, 0};
   for (int d = 0; d < DIM; ++d) base[d] = tcoord[d] * a.tb[d];
+  const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
+  // bins that can reach this tile: this one and up to q before it along each axis, read in parallel
+  {
+    const int qx = a.q[0] + 1, qy = a.q[1] + 1, qz = DIM == 3 ? a.q[2] + 1 : 1;
+    if (tid < qx * qy * qz) {
+      const int dx = tid % qx, dy = (tid / qx) % qy, dz = tid / (qx * qy);
+      const int bx = (tcoord[0] - dx + a.nt[0]) % a.nt[0];
+      const int by = (tcoord[1] - dy + a.nt[1]) % a.nt[1];
+      const int bz = DIM == 3 ? (tcoord[2] - dz + a.nt[2]) % a.nt[2] : 0;
+      const int b = bx + a.nt[0] * (by + a.nt[1] * bz);
+      const int s0 = a.offsets[b], e0 = a.offsets[b + 1];
+      rbeg[tid] = s0;
+      rlen[tid] = e0 - s0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int nr = 0;
+      for (int r = 0; r < qx * qy * qz; ++r)
+        if (rlen[r] > 0) {
+          rbeg[nr] = rbeg[r];
+          rlen[nr] = rlen[r];
+          ++nr;
+        }
+      nrange = nr;
+    }
+    __syncthreads();
+  }
+  int total = 0;
+  for (int r = 0; r < nrange; ++r) total += rlen[r];
+  const int cbeg = part * kSplit;
+  const int cend = total < cbeg + kSplit ? total : cbeg + kSplit;
+  if (total == 0) {  // no point reaches this tile: write zeros
+    for (int i = tid; i < tcells; i += kSpreadThreads) {
+      const int lx = i % kTileX;
+      const int ly = (i / kTileX) % a.tb[1];
+      const int lz = DIM == 3 ? i / (kTileX * a.tb[1]) : 0;
+      const int gz = DIM == 3 ? base[2] + lz : 0;
+      const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + ly) * a.nf[0] + base[0] + lx;
+      if (CPLX) {
+        reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = mk((T)0, (T)0);
+      } else {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = (T)0;
+      }
+    }
+    return;
+  }
+  const int tpr = kSpreadThreads / rows;  // threads per row
+  const int row = tid % rows, sub = tid / rows;
+  const int ly = row % a.tb[1];
+  const int lz = DIM == 3 ? row / a.tb[1] : 0;
+  T acc[kTileX][NCH];
+#pragma unroll
+  for (int x = 0; x < kTileX; ++x)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[x][ch] = (T)0;
 
-  for (int c0 = 0; c0 < total; c0 += kChunk) {
-    const int cnt = total - c0 < kChunk ? total - c0 : kChunk;
+  for (int c0 = cbeg; c0 < cend; c0 += kChunk) {
+    const int cnt = cend - c0 < kChunk ? cend - c0 : kChunk;
     // stage: kernel values per axis, start offset relative to the tile, strengths
     for (int it = tid; it < cnt * DIM; it += kSpreadThreads) {
       const int pl = it / DIM, d = it % DIM;
@@ -125,56 +180,128 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
       }
     }
     __syncthreads();
-    // accumulate: one item = one (point, y-line[, z-line]) of the support, looping over x
-    const int lines = DIM == 3 ? W * W : W;
-    for (int it = tid; it < cnt * lines; it += kSpreadThreads) {
-      const int pl = it / lines;
-      const int l = it % lines;
-      const int jy = l % W;
-      const int jz = DIM == 3 ? l / W : 0;
-      int ly = vstart[pl][1] + jy;
-      if (ly >= a.nf[1]) ly -= a.nf[1];
-      if (ly >= a.tb[1]) continue;
-      int lz = 0;
-      T wyz = wts[pl][1][jy];
-      if (DIM == 3) {
-        lz = vstart[pl][2] + jz;
-        if (lz >= a.nf[2]) lz -= a.nf[2];
-        if (lz >= a.tb[2]) continue;
-        wyz *= wts[pl][2][jz];
-      }
-      T s[NCH];
+    if (sub < tpr) {
+      for (int pl = sub; pl < cnt; pl += tpr) {
+        // offset of this thread's row inside the point's support (cells (v + j) mod n_f, j < w)
+        int dy = ly - vstart[pl][1];
+        if (dy < 0) dy += a.nf[1];
+        if (dy >= W) continue;
+        T wyz = wts[pl][1][dy];
+        if (DIM == 3) {
+          int dz = lz - vstart[pl][2];
+          if (dz < 0) dz += a.nf[2];
+          if (dz >= W) continue;
+          wyz *= wts[pl][2][dz];
+        }
+        T s[NCH];
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) s[ch] = wyz * sv[pl][ch];
-      const int row = (lz * a.tb[1] + ly) * a.tb[0];
-      const int vx = vstart[pl][0];
+        for (int ch = 0; ch < NCH; ++ch) s[ch] = wyz * sv[pl][ch];
+        const int vx = vstart[pl][0];
 #pragma unroll
-      for (int jx = 0; jx < W; ++jx) {
-        int lx = vx + jx;
-        if (lx >= a.nf[0]) lx -= a.nf[0];
-        if (lx < a.tb[0]) {
-          const T wx = wts[pl][0][jx];
+        for (int x = 0; x < kTileX; ++x) {
+          int dx = x - vx;
+          if (dx < 0) dx += a.nf[0];
+          if (dx < W) {
+            const T wx = wts[pl][0][dx];
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) atomicAdd(&acc[ch * kMaxTileCells + row + lx], s[ch] * wx);
+            for (int ch = 0; ch < NCH; ++ch) acc[x][ch] += wx * s[ch];
+          }
         }
       }
     }
     __syncthreads();
   }
+  // fixed-order sum of the partial rows through LDS
+  for (int sidx = 0; sidx < tpr; ++sidx) {
+    if (sub == sidx) {
+#pragma unroll
+      for (int x = 0; x < kTileX; ++x)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) accs[ch][row][x] = (sidx == 0 ? (T)0 : accs[ch][row][x]) + acc[x][ch];
+    }
+    __syncthreads();
+  }
+  if (nparts > 1) {  // one part of a split tile: partial tile to scratch, summed by k_merge_tiles
+    T* dst = a.scratch + ((int64_t)tr * a.slots + a.tile_slot[tile_id] + part) * NCH * kMaxTileCells;
+    for (int i = tid; i < tcells; i += kSpreadThreads) {
+      const int lx = i % kTileX;
+      const int rw = i / kTileX;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) dst[ch * kMaxTileCells + i] = accs[ch][rw][lx];
+    }
+    return;
+  }
   // write the tile once
-  const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
   for (int i = tid; i < tcells; i += kSpreadThreads) {
-    const int lx = i % a.tb[0];
-    const int ly = (i / a.tb[0]) % a.tb[1];
-    const int lz = DIM == 3 ? i / (a.tb[0] * a.tb[1]) : 0;
-    const int gz = DIM == 3 ? base[2] + lz : 0;
-    const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + ly) * a.nf[0] + base[0] + lx;
+    const int lx = i % kTileX;
+    const int rw = i / kTileX;
+    const int lyy = rw % a.tb[1];
+    const int lzz = DIM == 3 ? rw / a.tb[1] : 0;
+    const int gz = DIM == 3 ? base[2] + lzz : 0;
+    const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + lyy) * a.nf[0] + base[0] + lx;
     if (CPLX) {
-      cplx<T> v = mk(acc[i], acc[kMaxTileCells + i]);
-      reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = v;
+      reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = mk(accs[0][rw][lx], accs[1][rw][lx]);
     } else {
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = acc[ch * kMaxTileCells + i];
+      for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = accs[ch][rw][lx];
+    }
+  }
+}
+
+// Points reaching each tile (its bin and the q bins before it per axis) and the parts it splits into.
+__global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1, int q2, const int* __restrict__ offsets,
+                             int* __restrict__ tile_parts) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt0 * nt1 * nt2) return;
+  const int tx = t % nt0, ty = (t / nt0) % nt1, tz = t / (nt0 * nt1);
+  int total = 0;
+  for (int dz = 0; dz <= (dim == 3 ? q2 : 0); ++dz)
+    for (int dy = 0; dy <= q1; ++dy)
+      for (int dx = 0; dx <= q0; ++dx) {
+        const int bx = (tx - dx + nt0) % nt0, by = (ty - dy + nt1) % nt1, bz = dim == 3 ? (tz - dz + nt2) % nt2 : 0;
+        const int b = bx + nt0 * (by + nt1 * bz);
+        total += offsets[b + 1] - offsets[b];
+      }
+  tile_parts[t] = total <= kSplit ? 1 : (total + kSplit - 1) / kSplit;
+}
+
+// Work list (tile, part) in tile order, and scratch slots for tiles split into several parts.
+__global__ void k_fill_work(int nbins, const int* __restrict__ part_off, const int* __restrict__ tile_parts,
+                            int2* __restrict__ work, int* __restrict__ tile_slot, int* __restrict__ slot_ctr) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbins) return;
+  const int np = tile_parts[t], off = part_off[t];
+  for (int q = 0; q < np; ++q) work[off + q] = make_int2(t, q);
+  tile_slot[t] = np > 1 ? atomicAdd(slot_ctr, np) : -1;
+}
+
+// Sum the partial tiles of every split tile in part order and write it to the grid.
+template <typename T, int DIM, int NCH, bool CPLX>
+__global__ __launch_bounds__(kSpreadThreads) void k_merge_tiles(SpreadArgs<T> a) {
+  const int t = blockIdx.x;
+  const int np = a.tile_parts[t];
+  if (np <= 1) return;
+  const int tr = blockIdx.y;
+  const int tcoord[3] = {t % a.nt[0], (t / a.nt[0]) % a.nt[1], DIM == 3 ? t / (a.nt[0] * a.nt[1]) : 0};
+  const int rows = a.tb[1] * (DIM == 3 ? a.tb[2] : 1);
+  const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
+  const T* src = a.scratch + ((int64_t)tr * a.slots + a.tile_slot[t]) * NCH * kMaxTileCells;
+  for (int i = threadIdx.x; i < kTileX * rows; i += kSpreadThreads) {
+    T v[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) v[ch] = (T)0;
+    for (int q = 0; q < np; ++q)
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) v[ch] += src[((int64_t)q * NCH + ch) * kMaxTileCells + i];
+    const int lx = i % kTileX, rw = i / kTileX;
+    const int ly = rw % a.tb[1], lz = DIM == 3 ? rw / a.tb[1] : 0;
+    const int gz = DIM == 3 ? tcoord[2] * a.tb[2] + lz : 0;
+    const int64_t g = ((int64_t)gz * a.nf[1] + tcoord[1] * a.tb[1] + ly) * a.nf[0] + tcoord[0] * kTileX + lx;
+    if (CPLX) {
+      reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = mk(v[0], v[1]);
+    } else {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = v[ch];
     }
   }
 }
@@ -264,12 +391,28 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
     a.nf[d] = (int)p.nf[d];
     a.tb[d] = (int)p.tb[d];
     a.nt[d] = (int)p.nt[d];
-    int q = (int)((W - 1 + p.tb[d] - 1) / p.tb[d]);
-    if (q > p.nt[d] - 1) q = (int)p.nt[d] - 1;
-    a.q[d] = d < DIM ? q : 0;
+    a.q[d] = (int)p.qn[d];
   }
-  hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX>), dim3((unsigned)p.nbins, (unsigned)ntr), dim3(kSpreadThreads),
-                     0, st, a);
+  a.part_off = p.part_off;
+  a.work = (const int2*)p.work;
+  a.tile_parts = p.tile_parts;
+  a.tile_slot = p.tile_slot;
+  a.scratch = (T*)p.split_scratch;
+  a.slots = p.split_slots;
+  const unsigned nb = (unsigned)p.nbins;
+  hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, DIM, a.nt[0], a.nt[1], a.nt[2], a.q[0],
+                     a.q[1], a.q[2], (const int*)p.offsets, p.tile_parts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_scan(p.nbins, p.tile_parts, p.part_off, st)) != hipSuccess) return e;
+  if ((e = launch_fill_zero(p.slot_ctr, 4, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, (int)p.nbins, (const int*)p.part_off,
+                     (const int*)p.tile_parts, (int2*)p.work, p.tile_slot, p.slot_ctr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX>), dim3((unsigned)p.work_blocks, (unsigned)ntr),
+                     dim3(kSpreadThreads), 0, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_merge_tiles<T, DIM, NCH, CPLX>), dim3(nb, (unsigned)ntr), dim3(kSpreadThreads), 0, st, a);
   return hipGetLastError();
 }
 
