@@ -31,6 +31,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=128, help="modes per axis")
     ap.add_argument("--rings", type=int, default=200)
+    ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 form and the NUFFT timings")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 512 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -66,12 +69,14 @@ def reset(s):
     s["uh"].zero_()
 
 
-def time_steps(torch, s, steps, warmup):
+def time_steps(torch, s, steps, warmup, prof_class=None):
     plan, force, params = s["plan"], s["force"], s["params"]
     s["Xinit"] = s["X"].clone()
     for _ in range(warmup):
         plan.step(params, force, s["X"], s["U"], s["uh"])
     reset(s)
+    if prof_class:
+        plan.profile(prof_class, max_launches=64 * steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -80,12 +85,16 @@ def time_steps(torch, s, steps, warmup):
         plan.step(params, force, s["X"], s["U"], s["uh"])
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
+    prof = None
+    if prof_class:
+        prof = plan.profile_read()
+        plan.profile(None)
     # state after ROUND steps from the initial state, for the FP32-vs-FP64 comparison
     reset(s)
     for _ in range(ROUND):
         plan.step(params, force, s["X"], s["U"], s["uh"])
     torch.cuda.synchronize()
-    return el
+    return (el, prof) if prof_class else el
 
 
 def time_nufft(torch, s, reps=20):
@@ -155,6 +164,23 @@ def cpu_baseline(N, rings, sample_points=2048):
             "seconds_per_step": t_step}
 
 
+ROOFLINE_CLASS = "fft_strided"
+ROOFLINE_KERNEL = "fsib::k_fft_c2c<double, false>"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def roofline(ms, n, nbytes):
+    """Achieved algorithmic bandwidth of the dominant kernel from the event timings."""
+    if n == 0 or ms <= 0:
+        return None
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": ROOFLINE_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": n,
+            "avg_launch_us": ms * 1e3 / n, "algorithmic_bytes_per_launch": nbytes / n,
+            "method": "HIP events around each launch on its stream over the timed steps; bytes = every input "
+                      "and output element of the pass once"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -168,13 +194,26 @@ def main():
     log("setup FP64")
     s64 = setup(F, torch, "f64", a.tol, a.n, a.rings)
     log(f"plan f64: {s64['plan'].info()}")
-    t64 = time_steps(torch, s64, a.steps, a.warmup)
-    log(f"f64 {t64 * 1e3:.3f} ms/step")
+    # the dominant kernel (batched FFT passes along y and z) is timed with HIP events on its own
+    # launch stream inside the timed region
+    t64, (prof_ms, prof_n, prof_bytes) = time_steps(torch, s64, a.steps, a.warmup, ROOFLINE_CLASS)
+    log(f"f64 {t64 * 1e3:.3f} ms/step; {ROOFLINE_CLASS}: {prof_n} launches, {prof_ms:.3f} ms")
     X64 = s64["X"].cpu().numpy()
     U64max = float(s64["U"].abs().max().item())
-    nu64 = time_nufft(torch, s64)
+    nu64 = None if a.fp64_only else time_nufft(torch, s64)
     s64["plan"].close()
     del s64
+    if a.calibrate_copy:
+        src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if a.fp64_only:
+        out = {"metric": "FSIB steps/sec, FP64 only (profiling run)", "value": 1.0 / t64, "unit": "steps/s",
+               "ms_per_step": t64 * 1e3, "roofline": roofline(prof_ms, prof_n, prof_bytes)}
+        print(json.dumps(out), flush=True)
+        return
     log("setup FP32")
     s32 = setup(F, torch, "f32", a.tol, a.n, a.rings)
     t32 = time_steps(torch, s32, a.steps, a.warmup)
@@ -212,7 +251,7 @@ def main():
         "fp32": {"steps_per_s": 1.0 / t32, "ms_per_step": t32 * 1e3,
                  "rel_err_displacement_vs_fp64": err32, "steps_compared": ROUND},
         "nufft_at_128": {"f64": nu64, "f32": nu32},
-        "roofline": None,
+        "roofline": roofline(prof_ms, prof_n, prof_bytes),
     }
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")

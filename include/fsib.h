@@ -118,6 +118,25 @@ fsib_status fsib_plan_info(fsib_plan plan, fsib_plan_info_t* info /* host */);
  * last check saw a non-finite position (such points are treated as x = 0), else FSIB_OK. */
 fsib_status fsib_plan_check(fsib_plan plan, void* stream);
 
+/* Kernel timing with HIP events (for roofline measurement): while enabled, every launch of the
+ * chosen kernel class by this plan is bracketed by an event pair on its stream, for at most
+ * max_launches launches, and its algorithmic bytes (each input and output element of the launch
+ * counted once; for spreading the grid written once plus the point records and strengths; for
+ * interpolation the point records plus w^d cells per point) are accumulated.
+ * fsib_plan_profile synchronises the device and (re)creates the events; kernel_class -1 disables.
+ * fsib_plan_profile_read waits for the recorded launches, returns the summed elapsed time (ms),
+ * the launch count and the bytes (host outputs), and starts a new tally. */
+typedef enum {
+  FSIB_PROF_FFT_STRIDED = 1,  /* batched FFT passes along y and z */
+  FSIB_PROF_SPREAD = 2,       /* spreading onto the fine grid */
+  FSIB_PROF_INTERP = 3,       /* interpolation from the fine grid */
+  FSIB_PROF_FFT_X = 4,        /* real-data FFT passes along x */
+  FSIB_PROF_NL_X = 5          /* fused x pass of the dealiased products */
+} fsib_prof_class;
+fsib_status fsib_plan_profile(fsib_plan plan, int kernel_class, int max_launches);
+fsib_status fsib_plan_profile_read(fsib_plan plan, double* total_ms /* host */, int64_t* launches /* host */,
+                                   double* bytes /* host */);
+
 /* ---- nonuniform transforms (App. A) --------------------------------------------------------- */
 /* Type-1 (App. A, eq. type1; with scale = L^-d it is eq. force_spreading_quad):
  *   fhat[t][k] = scale * sum_j c[t][j] exp(-i k.X_j),  k in K_N,  t < ntrans.

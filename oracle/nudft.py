@@ -123,6 +123,24 @@ def type2(X, fhat, Ns, L=1.0):
     return out[0] if single else out
 
 
+def type1_at_modes(X, c, modes, L=1.0, scale=1.0):
+    """Type-1 sum at selected integer mode vectors: out[q] = scale * sum_j c_j exp(-i 2 pi m_q.x_j / L).
+
+    modes: (K, d) integers in physical-axis order.  Direct sum, one phase per (point, mode); for
+    checking sampled outputs of a transform too large to evaluate in full.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    m = np.asarray(modes, dtype=np.float64)
+    xf = np.mod(X, L) / L
+    out = np.zeros(m.shape[0], dtype=np.complex128)
+    c = np.asarray(c, dtype=np.complex128)
+    blk = max(1, _BLOCK_ELEMS // max(1, m.shape[0]))
+    for j0 in range(0, X.shape[0], blk):
+        ang = (2.0 * np.pi) * (xf[j0:j0 + blk] @ m.T)
+        out += c[j0:j0 + blk] @ (np.cos(ang) - 1j * np.sin(ang))
+    return scale * out
+
+
 def _all_wavevectors(Ns, L):
     """(n_modes, d) array of k = 2*pi*m/L for every mode of K_N, in C order of spectral_shape."""
     d = len(Ns)

@@ -51,6 +51,9 @@ _SIGS = {
     "fsib_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "fsib_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
     "fsib_plan_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "fsib_plan_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "fsib_spread": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_double, ctypes.c_void_p]),
     "fsib_interp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -219,6 +222,20 @@ class Plan:
 
     def check(self):
         _check(self._lib.fsib_plan_check(self._h, _stream()), "fsib_plan_check")
+
+    PROF_CLASSES = {"fft_strided": 1, "spread": 2, "interp": 3, "fft_x": 4, "nl_x": 5}
+
+    def profile(self, kernel_class, max_launches=4096):
+        """Time every launch of one kernel class with HIP events (None disables)."""
+        cls = -1 if kernel_class is None else self.PROF_CLASSES[kernel_class]
+        _check(self._lib.fsib_plan_profile(self._h, cls, int(max_launches)), "fsib_plan_profile")
+
+    def profile_read(self):
+        """(total_ms, launches, algorithmic_bytes) of the launches recorded since the last read."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(self._lib.fsib_plan_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
+               "fsib_plan_profile_read")
+        return ms.value, n.value, b.value
 
     def _X(self, X):
         _need(X, "X", torch.float64)

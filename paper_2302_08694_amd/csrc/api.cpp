@@ -65,6 +65,8 @@ void free_plan(Plan& p) {
   auto fr = [](void* q) {
     if (q) (void)hipFree(q);
   };
+  for (hipEvent_t e : p.prof_ev) (void)hipEventDestroy(e);
+  p.prof_ev.clear();
   fr(p.coef);
   for (int a = 0; a < 3; ++a) fr(p.fac[a]);
   for (auto& kv : p.tw) fr(kv.second);
@@ -537,6 +539,43 @@ fsib_status fsib_plan_check(fsib_plan plan, void* stream) {
     FSIB_HIP(hipStreamSynchronize(S(stream)));
     return fail(FSIB_ERR_NONFINITE, "a non-finite position was seen (treated as x = 0)");
   }
+  return FSIB_OK;
+}
+
+fsib_status fsib_plan_profile(fsib_plan plan, int kernel_class, int max_launches) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (kernel_class != -1 && (kernel_class < FSIB_PROF_FFT_STRIDED || kernel_class > FSIB_PROF_NL_X))
+    return fail(FSIB_ERR_ARG, "unknown kernel class");
+  if (max_launches < 0 || max_launches > (1 << 20)) return fail(FSIB_ERR_ARG, "max_launches out of range");
+  FSIB_HIP(hipDeviceSynchronize());
+  for (hipEvent_t e : p.prof_ev) (void)hipEventDestroy(e);
+  p.prof_ev.clear();
+  p.prof_used = 0;
+  p.prof_bytes = 0.0;
+  p.prof_class = -1;
+  if (kernel_class == -1 || max_launches == 0) return FSIB_OK;
+  p.prof_ev.resize(2 * (size_t)max_launches);
+  for (auto& e : p.prof_ev) FSIB_HIP(hipEventCreate(&e));
+  p.prof_class = kernel_class;
+  return FSIB_OK;
+}
+
+fsib_status fsib_plan_profile_read(fsib_plan plan, double* total_ms, int64_t* launches, double* bytes) {
+  if (!plan || !total_ms || !launches || !bytes) return fail(FSIB_ERR_ARG, "NULL argument");
+  Plan& p = plan->p;
+  double tot = 0.0;
+  for (int i = 0; i < p.prof_used; ++i) {
+    FSIB_HIP(hipEventSynchronize(p.prof_ev[2 * (size_t)i + 1]));
+    float ms = 0.f;
+    FSIB_HIP(hipEventElapsedTime(&ms, p.prof_ev[2 * (size_t)i], p.prof_ev[2 * (size_t)i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = p.prof_used;
+  *bytes = p.prof_bytes;
+  p.prof_used = 0;
+  p.prof_bytes = 0.0;
   return FSIB_OK;
 }
 

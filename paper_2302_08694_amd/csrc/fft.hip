@@ -271,12 +271,16 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
   a.nb = lines_per_block<T>(n, contig ? outer : inner);
   const int nthr = n * a.nb / kEPT;
   const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  const bool prof = !contig && prof_on(p, PROF_FFT_STRIDED);
+  if (prof) prof_start(p, st);
   if (contig)
     hipLaunchKernelGGL((k_fft_c2c<T, true>), dim3((unsigned)((outer + a.nb - 1) / a.nb)), dim3(nthr), lds, st,
                        (const cplx<T>*)in, (cplx<T>*)out, a);
   else
     hipLaunchKernelGGL((k_fft_c2c<T, false>), dim3((unsigned)((inner + a.nb - 1) / a.nb), (unsigned)outer), dim3(nthr),
                        lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
+  // algorithmic bytes: every input entry read once, every output entry written once
+  if (prof) prof_stop(p, (double)(nin + nout) * inner * outer * sizeof(cplx<T>), st);
   return hipGetLastError();
 }
 
@@ -305,8 +309,11 @@ static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int6
   a.nb = lines_per_block<T>(n, pairs);
   const int nthr = n * a.nb / kEPT;
   const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  const bool prof = prof_on(p, PROF_FFT_X);
+  if (prof) prof_start(p, st);
   hipLaunchKernelGGL(k_fft_r2c_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(nthr), lds, st, (const T*)in,
                      (cplx<T>*)out, a);
+  if (prof) prof_stop(p, (double)rows * (n * sizeof(T) + nout * sizeof(cplx<T>)), st);
   return hipGetLastError();
 }
 
@@ -326,8 +333,11 @@ static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int6
   a.nb = lines_per_block<T>(n, pairs);
   const int nthr = n * a.nb / kEPT;
   const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  const bool prof = prof_on(p, PROF_FFT_X);
+  if (prof) prof_start(p, st);
   hipLaunchKernelGGL(k_fft_c2r_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(nthr), lds, st,
                      (const cplx<T>*)in, (T*)out, a);
+  if (prof) prof_stop(p, (double)rows * (nin * sizeof(cplx<T>) + n * sizeof(T)), st);
   return hipGetLastError();
 }
 

@@ -153,12 +153,16 @@ static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t 
   const size_t lds = (size_t)(fl * pp + 1) * n * sizeof(cplx<T>);
   const unsigned nblk = (unsigned)((pairs + pp - 1) / pp);
   const T inv = (T)(1.0 / (double)p.dealias_cells());
+  const bool prof = prof_on(p, PROF_NL_X);
+  if (prof) prof_start(p, st);
   if (p.dim == 3)
     hipLaunchKernelGGL((k_nl_xpass<T, 3>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a, rows,
                        (int)p.Hx, pp, inv);
   else
     hipLaunchKernelGGL((k_nl_xpass<T, 2>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a, rows,
                        (int)p.Hx, pp, inv);
+  // algorithmic bytes: dim velocity half-spectrum rows in, nprod product rows out
+  if (prof) prof_stop(p, (double)(p.dim + p.nprod()) * rows * p.Hx * sizeof(cplx<T>), st);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 
 #include <map>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "../../include/fsib.h"
@@ -81,6 +82,11 @@ struct Plan {
   double* part = nullptr;  // reduction partials
   int npart = 0;
   int64_t ws_bytes = 0;
+  // optional timing of one kernel class with HIP events on the launch stream
+  int prof_class = -1;
+  std::vector<hipEvent_t> prof_ev;  // start/stop pairs
+  mutable int prof_used = 0;
+  mutable double prof_bytes = 0.0;
 
   int64_t fine_cells() const { return nf[0] * nf[1] * nf[2]; }
   int64_t modes_full() const { return N[0] * N[1] * N[2]; }
@@ -119,6 +125,19 @@ hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const d
 hipError_t launch_diag(const Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M,
                        const double* F, const void* Uh, const void* uhat, const double* X, double* diag,
                        hipStream_t st);
+
+// Kernel classes that fsib_plan_profile can time (values of fsib_prof_class).
+enum { PROF_FFT_STRIDED = 1, PROF_SPREAD = 2, PROF_INTERP = 3, PROF_FFT_X = 4, PROF_NL_X = 5 };
+
+inline bool prof_on(const Plan& p, int cls) {
+  return p.prof_class == cls && 2 * (size_t)p.prof_used + 1 < p.prof_ev.size();
+}
+inline void prof_start(const Plan& p, hipStream_t st) { (void)hipEventRecord(p.prof_ev[2 * p.prof_used], st); }
+inline void prof_stop(const Plan& p, double bytes, hipStream_t st) {
+  (void)hipEventRecord(p.prof_ev[2 * p.prof_used + 1], st);
+  ++p.prof_used;
+  p.prof_bytes += bytes;
+}
 
 // fluid update modes
 enum { FLUID_STOKES = 0, FLUID_NS_HALF = 1, FLUID_NS_FULL = 2 };

@@ -409,8 +409,14 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, (int)p.nbins, (const int*)p.part_off,
                      (const int*)p.tile_parts, (int2*)p.work, p.tile_slot, p.slot_ctr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  const bool prof = prof_on(p, PROF_SPREAD);
+  if (prof) prof_start(p, st);
   hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX>), dim3((unsigned)p.work_blocks, (unsigned)ntr),
                      dim3(kSpreadThreads), 0, st, a);
+  // algorithmic bytes: the grid written once, per point its sorted record and its strengths read
+  if (prof)
+    prof_stop(p, (double)ntr * p.fine_cells() * NCH * sizeof(T) + (double)M * (8 + DIM * sizeof(T)) +
+                     (double)ntr * M * NCH * sizeof(T), st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((k_merge_tiles<T, DIM, NCH, CPLX>), dim3(nb, (unsigned)ntr), dim3(kSpreadThreads), 0, st, a);
   return hipGetLastError();
@@ -429,8 +435,16 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   a.M = M;
   for (int d = 0; d < 3; ++d) a.nf[d] = (int)p.nf[d];
   if (M == 0) return hipSuccess;
+  const bool prof = prof_on(p, PROF_INTERP);
+  if (prof) prof_start(p, st);
   hipLaunchKernelGGL((k_interp<T, DIM, W, NCH, CPLX>), dim3((unsigned)((M + 255) / 256), (unsigned)ntr), dim3(256), 0,
                      st, a);
+  // algorithmic bytes: per point its sorted record, w^d grid cells per channel, the result
+  if (prof) {
+    double cellsper = 1;
+    for (int d = 0; d < DIM; ++d) cellsper *= W;
+    prof_stop(p, (double)M * (8 + DIM * sizeof(T)) + (double)ntr * M * (cellsper + 1) * NCH * sizeof(T), st);
+  }
   return hipGetLastError();
 }
 

@@ -166,3 +166,19 @@ def test_empty_point_set():
     f = nudft.type1(np.zeros((0, 2)), np.zeros(0, complex), (4, 4))
     assert f.shape == (4, 4) and not np.any(f)
     assert nudft.type2(np.zeros((0, 2)), f, (4, 4)).shape == (0,)
+
+
+def test_type1_at_modes_matches_bruteforce_and_full():
+    rng = np.random.default_rng(19)
+    Ns = (5, 4, 6)
+    X = rng.uniform(-1, 2, (11, 3))
+    c = rng.standard_normal(11) + 1j * rng.standard_normal(11)
+    full = nudft.type1(X, c, Ns, 1.3, scale=0.5)
+    brute = nudft.type1_bruteforce(X, c, Ns, 1.3, scale=0.5)
+    ms = [mode_numbers(n) for n in Ns]
+    picks = [(0, 0, 0), (1, 2, 3), (4, 3, 5), (2, 0, 1)]  # FFT-order indices (ix, iy, iz)
+    modes = np.array([[ms[0][i], ms[1][j], ms[2][k]] for (i, j, k) in picks])
+    got = nudft.type1_at_modes(X, c, modes, 1.3, scale=0.5)
+    for q, (i, j, k) in enumerate(picks):
+        assert abs(got[q] - brute[k, j, i]) < 1e-13 * np.max(np.abs(brute))
+        assert abs(got[q] - full[k, j, i]) < 1e-13 * np.max(np.abs(full))
