@@ -167,6 +167,10 @@ def cpu_baseline(N, rings, sample_points=2048):
 ROOFLINE_CLASS = "fft_strided"
 ROOFLINE_KERNEL = "fsib::k_fft_c2c<double, false>"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, factors from a plain 512 MiB copy); None once the kernel changes after the counters
+TRAFFIC_BYTES_PER_LAUNCH = 308.1e6
+TRAFFIC_SOURCE = "profiles/fft_strided_ns128_f64_hbm_counters.md"
 
 
 def roofline(ms, n, nbytes):
@@ -175,7 +179,8 @@ def roofline(ms, n, nbytes):
         return None
     achieved = nbytes / (ms * 1e-3) / 1e9
     return {"kernel": ROOFLINE_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": n,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+            "traffic_unit": "bytes per launch", "traffic_source": TRAFFIC_SOURCE, "launches": n,
             "avg_launch_us": ms * 1e3 / n, "algorithmic_bytes_per_launch": nbytes / n,
             "method": "HIP events around each launch on its stream over the timed steps; bytes = every input "
                       "and output element of the pass once"}
