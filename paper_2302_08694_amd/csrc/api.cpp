@@ -78,7 +78,10 @@ void free_plan(Plan& p) {
   fr(p.s_idx);
   fr(p.s_i0);
   fr(p.s_y);
+  fr(p.s_str);
   fr(p.flag);
+  fr(p.rowmask);
+  fr(p.zmask);
   fr(p.tile_parts);
   fr(p.part_off);
   fr(p.work);
@@ -211,7 +214,10 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   A.get(p.s_idx, Mx * 4);
   A.get(p.s_i0, Mx * 4);
   A.get(p.s_y, Mx * d * rs);
+  A.get(p.s_str, Mx * (2 * p.ntrans > d ? 2 * p.ntrans : d) * rs);
   A.get(p.flag, 256);
+  A.get(p.rowmask, p.nt[1] * p.nt[2]);
+  A.get(p.zmask, p.nt[2]);
   // spreading work list: part bound = tiles + visits / kSplit, visits <= M * prod(q + 1)
   {
     int64_t reach = 1;
@@ -296,6 +302,32 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
 
 hipStream_t S(void* s) { return (hipStream_t)s; }
 
+// Occupancy masks of the fine grid for the passes of the nonuniform transforms (rows of the x
+// passes; entries y and lines z of the y passes; entries z of the z passes).
+fsib::PassMasks mask_x(const Plan& p) {
+  fsib::PassMasks m;
+  m.rows = {p.rowmask, (int)p.nf[1], (int)p.nf[2], (int)p.tb[1], (int)p.tb[2], (int)p.nt[1]};
+  return m;
+}
+fsib::PassMasks mask_y(const Plan& p, bool forward) {
+  fsib::PassMasks m;
+  if (p.dim == 3) {
+    m.line = {p.zmask, (int)p.nf[2], (int)p.tb[2], 1, 0};
+    const fsib::StrideMask e{p.rowmask, (int)p.nf[2], (int)p.tb[2], (int)p.nt[1], (int)p.tb[1]};
+    (forward ? m.ld : m.st) = e;
+  } else {
+    const fsib::StrideMask e{p.rowmask, 1, 1, 0, (int)p.tb[1]};
+    (forward ? m.ld : m.st) = e;
+  }
+  return m;
+}
+fsib::PassMasks mask_z(const Plan& p, bool forward) {
+  fsib::PassMasks m;
+  const fsib::StrideMask e{p.zmask, 1, 1, 0, (int)p.tb[2]};
+  (forward ? m.ld : m.st) = e;
+  return m;
+}
+
 fsib_status check_points(const Plan& p, int64_t M, const void* X) {
   if (M < 0 || M > p.max_points) return fail(FSIB_ERR_ARG, "M must be in [0, max_points]");
   if (M > 0 && !X) return fail(FSIB_ERR_ARG, "X is NULL");
@@ -309,16 +341,17 @@ fsib_status type1_complex(Plan& p, int64_t M, const double* X, const void* c, vo
   const int64_t T = p.ntrans;
   if (p.dim == 3) {
     FSIB_HIP(fsib::launch_fft_c2c(p, p.grid, p.B1, (int)p.nf[0], -1, 1, T * p.nf[2] * p.nf[1], (int)p.nf[0],
-                                  (int)p.nf[0], (int)p.N[0], (int)ceil_half(p.N[0]), nullptr, p.fac[0], 1.0, st));
+                                  (int)p.nf[0], (int)p.N[0], (int)ceil_half(p.N[0]), nullptr, p.fac[0], 1.0, st,
+                                  mask_x(p)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, p.B2, (int)p.nf[1], -1, p.N[0], T * p.nf[2], (int)p.nf[1], (int)p.nf[1],
-                                  (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, p.fac[1], 1.0, st));
+                                  (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, p.fac[1], 1.0, st, mask_y(p, true)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B2, fhat, (int)p.nf[2], -1, p.N[1] * p.N[0], T, (int)p.nf[2], (int)p.nf[2],
-                                  (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, p.fac[2], scale, st));
+                                  (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, p.fac[2], scale, st, mask_z(p, true)));
   } else {
     FSIB_HIP(fsib::launch_fft_c2c(p, p.grid, p.B1, (int)p.nf[0], -1, 1, T * p.nf[1], (int)p.nf[0], (int)p.nf[0],
-                                  (int)p.N[0], (int)ceil_half(p.N[0]), nullptr, p.fac[0], 1.0, st));
+                                  (int)p.N[0], (int)ceil_half(p.N[0]), nullptr, p.fac[0], 1.0, st, mask_x(p)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, fhat, (int)p.nf[1], -1, p.N[0], T, (int)p.nf[1], (int)p.nf[1], (int)p.N[1],
-                                  (int)ceil_half(p.N[1]), nullptr, p.fac[1], scale, st));
+                                  (int)ceil_half(p.N[1]), nullptr, p.fac[1], scale, st, mask_y(p, true)));
   }
   return FSIB_OK;
 }
@@ -328,16 +361,20 @@ fsib_status type2_complex(Plan& p, int64_t M, const double* X, const void* fhat,
   const int64_t T = p.ntrans;
   if (p.dim == 3) {
     FSIB_HIP(fsib::launch_fft_c2c(p, fhat, p.B2, (int)p.nf[2], +1, p.N[1] * p.N[0], T, (int)p.N[2],
-                                  (int)ceil_half(p.N[2]), (int)p.nf[2], (int)p.nf[2], p.fac[2], nullptr, 1.0, st));
+                                  (int)ceil_half(p.N[2]), (int)p.nf[2], (int)p.nf[2], p.fac[2], nullptr, 1.0, st,
+                                  mask_z(p, false)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B2, p.B1, (int)p.nf[1], +1, p.N[0], T * p.nf[2], (int)p.N[1],
-                                  (int)ceil_half(p.N[1]), (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st));
+                                  (int)ceil_half(p.N[1]), (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st,
+                                  mask_y(p, false)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, p.grid, (int)p.nf[0], +1, 1, T * p.nf[2] * p.nf[1], (int)p.N[0],
-                                  (int)ceil_half(p.N[0]), (int)p.nf[0], (int)p.nf[0], p.fac[0], nullptr, 1.0, st));
+                                  (int)ceil_half(p.N[0]), (int)p.nf[0], (int)p.nf[0], p.fac[0], nullptr, 1.0, st,
+                                  mask_x(p)));
   } else {
     FSIB_HIP(fsib::launch_fft_c2c(p, fhat, p.B1, (int)p.nf[1], +1, p.N[0], T, (int)p.N[1], (int)ceil_half(p.N[1]),
-                                  (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st));
+                                  (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st, mask_y(p, false)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, p.grid, (int)p.nf[0], +1, 1, T * p.nf[1], (int)p.N[0],
-                                  (int)ceil_half(p.N[0]), (int)p.nf[0], (int)p.nf[0], p.fac[0], nullptr, 1.0, st));
+                                  (int)ceil_half(p.N[0]), (int)p.nf[0], (int)p.nf[0], p.fac[0], nullptr, 1.0, st,
+                                  mask_x(p)));
   }
   FSIB_HIP(fsib::launch_interp(p, M, c, 0, st));
   return FSIB_OK;
@@ -348,15 +385,17 @@ fsib_status force_spread_sorted(Plan& p, int64_t M, const void* S_, void* fhat, 
   FSIB_HIP(fsib::launch_spread(p, M, S_, p.dim, st));
   const int64_t d = p.dim;
   if (p.dim == 3) {
-    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.grid, p.B1, (int)p.nf[0], d * p.nf[2] * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st));
+    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.grid, p.B1, (int)p.nf[0], d * p.nf[2] * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st,
+                                    mask_x(p)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, p.B2, (int)p.nf[1], -1, p.Hx, d * p.nf[2], (int)p.nf[1], (int)p.nf[1],
-                                  (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, p.fac[1], 1.0, st));
+                                  (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, p.fac[1], 1.0, st, mask_y(p, true)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B2, fhat, (int)p.nf[2], -1, p.N[1] * p.Hx, d, (int)p.nf[2], (int)p.nf[2],
-                                  (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, p.fac[2], scale, st));
+                                  (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, p.fac[2], scale, st, mask_z(p, true)));
   } else {
-    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.grid, p.B1, (int)p.nf[0], d * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st));
+    FSIB_HIP(fsib::launch_fft_r2c_x(p, p.grid, p.B1, (int)p.nf[0], d * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st,
+                                    mask_x(p)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B1, fhat, (int)p.nf[1], -1, p.Hx, d, (int)p.nf[1], (int)p.nf[1], (int)p.N[1],
-                                  (int)ceil_half(p.N[1]), nullptr, p.fac[1], scale, st));
+                                  (int)ceil_half(p.N[1]), nullptr, p.fac[1], scale, st, mask_y(p, true)));
   }
   return FSIB_OK;
 }
@@ -366,14 +405,18 @@ fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U
   const int64_t d = p.dim;
   if (p.dim == 3) {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.B2, (int)p.nf[2], +1, p.N[1] * p.Hx, d, (int)p.N[2],
-                                  (int)ceil_half(p.N[2]), (int)p.nf[2], (int)p.nf[2], p.fac[2], nullptr, 1.0, st));
+                                  (int)ceil_half(p.N[2]), (int)p.nf[2], (int)p.nf[2], p.fac[2], nullptr, 1.0, st,
+                                  mask_z(p, false)));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.B2, p.B1, (int)p.nf[1], +1, p.Hx, d * p.nf[2], (int)p.N[1],
-                                  (int)ceil_half(p.N[1]), (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.B1, p.grid, (int)p.nf[0], d * p.nf[2] * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st));
+                                  (int)ceil_half(p.N[1]), (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st,
+                                  mask_y(p, false)));
+    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.B1, p.grid, (int)p.nf[0], d * p.nf[2] * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st,
+                                    mask_x(p)));
   } else {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.B1, (int)p.nf[1], +1, p.Hx, d, (int)p.N[1], (int)ceil_half(p.N[1]),
-                                  (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.B1, p.grid, (int)p.nf[0], d * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st));
+                                  (int)p.nf[1], (int)p.nf[1], p.fac[1], nullptr, 1.0, st, mask_y(p, false)));
+    FSIB_HIP(fsib::launch_fft_c2r_x(p, p.B1, p.grid, (int)p.nf[0], d * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st,
+                                    mask_x(p)));
   }
   FSIB_HIP(fsib::launch_interp(p, M, U, p.dim, st));
   return FSIB_OK;

@@ -46,6 +46,35 @@ struct KernelPoly {
   double beta;
 };
 
+// Occupancy masks of the fine grid (one byte per block of tile_y x tile_z grid lines along x):
+// lines that no point's kernel support reaches are neither computed nor stored, and read as zero.
+// For a strided pass the byte of entry i of line o is m[((o % omod) / odiv) * ostride + i / idiv]
+// (idiv = 0: one byte per line).
+struct StrideMask {
+  const uint8_t* m;  // nullptr: no mask
+  int omod, odiv, ostride, idiv;
+};
+// For a pass along x over rows r (= ((c * nz + z) * ny + y)): m[((r / ny) % nz / tbz) * nt1 + (r % ny) / tby].
+struct RowMask {
+  const uint8_t* m;  // nullptr: no mask
+  int ny, nz, tby, tbz, nt1;
+};
+
+__host__ __device__ __forceinline__ int mask_index(const StrideMask& k, int64_t o, int i) {
+  return (int)(((o % k.omod) / k.odiv) * k.ostride) + (k.idiv > 0 ? i / k.idiv : 0);
+}
+__host__ __device__ __forceinline__ bool row_needed(const RowMask& k, int64_t r) {
+  if (!k.m) return true;
+  return k.m[(int)((r / k.ny) % k.nz / k.tbz) * k.nt1 + (int)(r % k.ny) / k.tby] != 0;
+}
+
+struct PassMasks {
+  StrideMask line{nullptr, 1, 1, 0, 0};
+  StrideMask ld{nullptr, 1, 1, 0, 0};
+  StrideMask st{nullptr, 1, 1, 0, 0};
+  RowMask rows{nullptr, 1, 1, 1, 1, 1};
+};
+
 // FFT pass description: a batch of 1-D transforms of length n along one axis of a
 // [outer][len][inner] array; the input holds `nin` entries of that axis (zero-padded to n: entries
 // i < pin sit at t = i, the rest at t = n - (nin - i)), the output keeps `nout` entries the same
@@ -63,6 +92,10 @@ struct FftArgs {
   const T* fac_out;
   T scale;
   int nb;             // transforms (columns) per workgroup
+  StrideMask line;    // strided passes: skip whole lines (masks on o only)
+  StrideMask ld;      // strided passes: entries read as zero
+  StrideMask st;      // strided passes: entries not stored
+  RowMask rows;       // x passes: rows neither read nor stored
 };
 
 }  // namespace fsib

@@ -18,6 +18,8 @@
 
 namespace fsib {
 
+constexpr int kFlagBytes = 4096;  // >= lines (x passes: 2 * pairs) and entries (<= n) of a workgroup
+
 template <typename T, bool CONTIG>
 __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __restrict__ in,
                                                             cplx<T>* __restrict__ out, FftArgs<T> a) {
@@ -26,16 +28,29 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
   const int n = a.n, nb = a.nb, nthr = blockDim.x;
   cplx<T>* twl = buf + n * nb;
   stage_twiddles(a.tw, twl, n);
+  // occupancy flags of this workgroup's rows (x passes) or of the entries it loads and stores
+  // (strided passes), fetched once; the workgroup leaves when nothing it owns is reached by a point
+  __shared__ uint8_t fld[kFlagBytes];
   int64_t o0 = 0, q0 = 0;
   int ncol;
+  int need = 0;
   if (CONTIG) {
     o0 = (int64_t)blockIdx.x * nb;
     ncol = (int)(a.outer - o0 < nb ? a.outer - o0 : nb);
+    for (int b = threadIdx.x; b < nb; b += nthr) {
+      const uint8_t f = b < ncol && row_needed(a.rows, o0 + b);
+      fld[b] = f;
+      need |= f;
+    }
   } else {
     q0 = (int64_t)blockIdx.x * nb;
     o0 = blockIdx.y;
     ncol = (int)(a.inner - q0 < nb ? a.inner - q0 : nb);
+    const bool line = !a.line.m || a.line.m[mask_index(a.line, o0, 0)];
+    for (int i = threadIdx.x; i < a.nin; i += nthr) fld[i] = line && (!a.ld.m || a.ld.m[mask_index(a.ld, o0, i)]);
+    need = line;
   }
+  if (!__syncthreads_or(need)) return;
   // zero the padding gap [pin, n - (nin - pin))
   const int g0 = a.pin, gl = n - a.nin;
   for (int it = threadIdx.x; it < gl * nb; it += nthr) {
@@ -69,7 +84,8 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
       }
       const int t = i < a.pin ? i : n - (a.nin - i);
       li[j] = lidx<CONTIG>(t, b, n, nb);
-      if (b < ncol) {
+      const bool use = b < ncol && (CONTIG ? fld[b] : fld[i]);
+      if (use) {
         const int64_t gi = CONTIG ? (o0 + b) * a.nin + i : (o0 * a.nin + i) * a.inner + q0 + b;
         v[j] = in[gi];
         if (a.fac_in) v[j] = v[j] * a.fac_in[i];
@@ -79,9 +95,17 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
 #pragma unroll
   for (int j = 0; j < kEPT; ++j)
     if (li[j] >= 0) buf[li[j]] = v[j];
+  // store flags of this thread's output entries (strided passes), fetched before the stages
+  const int nstore = a.nout * nb;
+  bool sf[kEPT];
+#pragma unroll
+  for (int j = 0; j < kEPT; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    sf[j] = true;
+    if (!CONTIG && a.st.m && e < nstore) sf[j] = a.st.m[mask_index(a.st, o0, e / nb)] != 0;
+  }
   __syncthreads();
   stockham<T, CONTIG>(a, buf, twl, a.nb, a.sign);
-  const int nstore = a.nout * nb;
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
     const int e = threadIdx.x + j * nthr;
@@ -95,6 +119,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
       b = e - i * nb;
     }
     if (b >= ncol) continue;
+    if (CONTIG ? !fld[b] : !sf[j]) continue;
     const int t = i < a.pout ? i : n - (a.nout - i);
     T f = a.scale;
     if (a.fac_out) f *= a.fac_out[i];
@@ -112,8 +137,17 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = a.n, nb = a.nb, nthr = blockDim.x;
   cplx<T>* twl = buf + n * nb;
-  stage_twiddles(a.tw, twl, n);
   const int64_t pair0 = (int64_t)blockIdx.x * nb;
+  __shared__ uint8_t fl[kFlagBytes];  // rows of this workgroup reached by a point
+  int need = 0;
+  for (int b = threadIdx.x; b < 2 * nb; b += nthr) {
+    const int64_t r = 2 * pair0 + b;
+    const uint8_t f = r < a.outer && row_needed(a.rows, r);
+    fl[b] = f;
+    need |= f;
+  }
+  if (!__syncthreads_or(need)) return;
+  stage_twiddles(a.tw, twl, n);
   cplx<T> v[kEPT];
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
@@ -122,8 +156,8 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
     if (e < n * nb) {
       const int b = e / n, t = e - b * n;
       const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
-      if (r0 < a.outer) v[j].x = in[r0 * n + t];
-      if (r1 < a.outer) v[j].y = in[r1 * n + t];
+      if (fl[2 * b]) v[j].x = in[r0 * n + t];
+      if (fl[2 * b + 1]) v[j].y = in[r1 * n + t];
     }
   }
 #pragma unroll
@@ -145,8 +179,8 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
     T f = a.scale * (T)0.5;
     if (a.fac_out) f *= a.fac_out[m];
     const cplx<T> s = Z + Zc, d = Z - Zc;
-    out[r0 * a.nout + m] = s * f;
-    if (r1 < a.outer) out[r1 * a.nout + m] = mk(d.y * f, -d.x * f);
+    if (fl[2 * b]) out[r0 * a.nout + m] = s * f;
+    if (fl[2 * b + 1]) out[r1 * a.nout + m] = mk(d.y * f, -d.x * f);
   }
 }
 
@@ -160,8 +194,17 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = a.n, nb = a.nb, nthr = blockDim.x;
   cplx<T>* twl = buf + n * nb;
-  stage_twiddles(a.tw, twl, n);
   const int64_t pair0 = (int64_t)blockIdx.x * nb;
+  __shared__ uint8_t fl[kFlagBytes];  // rows of this workgroup reached by a point
+  int need = 0;
+  for (int b = threadIdx.x; b < 2 * nb; b += nthr) {
+    const int64_t r = 2 * pair0 + b;
+    const uint8_t f = r < a.outer && row_needed(a.rows, r);
+    fl[b] = f;
+    need |= f;
+  }
+  if (!__syncthreads_or(need)) return;
+  stage_twiddles(a.tw, twl, n);
   cplx<T> A[kEPT], B[kEPT];
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
@@ -173,8 +216,8 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
       const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
       const int m = 2 * t <= n ? t : n - t;
       if (m < a.nin) {
-        if (r0 < a.outer) A[j] = in[r0 * a.nin + m];
-        if (r1 < a.outer) B[j] = in[r1 * a.nin + m];
+        if (fl[2 * b]) A[j] = in[r0 * a.nin + m];
+        if (fl[2 * b + 1]) B[j] = in[r1 * a.nin + m];
       }
     }
   }
@@ -210,14 +253,18 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
     const int b = e / n, t = e - b * n;
     const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
     const cplx<T> z = buf[e];
-    if (r0 < a.outer) out[r0 * n + t] = z.x * a.scale;
-    if (r1 < a.outer) out[r1 * n + t] = z.y * a.scale;
+    if (fl[2 * b]) out[r0 * n + t] = z.x * a.scale;
+    if (fl[2 * b + 1]) out[r1 * n + t] = z.y * a.scale;
   }
 }
 
 template <typename T>
-static FftArgs<T> base_args(const Plan& p, int n, int sign) {
+static FftArgs<T> base_args(const Plan& p, int n, int sign, const PassMasks& mk) {
   FftArgs<T> a;
+  a.line = mk.line;
+  a.ld = mk.ld;
+  a.st = mk.st;
+  a.rows = mk.rows;
   a.n = n;
   a.nst = radix_plan(n, a.radix);
   a.tw = (const cplx<T>*)p.tw.at(n);
@@ -256,8 +303,8 @@ static int lines_per_block(int n, int64_t cap) {
 template <typename T>
 static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int sign, int64_t inner, int64_t outer,
                            int nin, int pin, int nout, int pout, const void* fin, const void* fout, double scale,
-                           hipStream_t st) {
-  FftArgs<T> a = base_args<T>(p, n, sign);
+                           hipStream_t st, const PassMasks& mk) {
+  FftArgs<T> a = base_args<T>(p, n, sign, mk);
   a.inner = inner;
   a.outer = outer;
   a.nin = nin;
@@ -286,17 +333,17 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
 
 hipError_t launch_fft_c2c(const Plan& p, const void* in, void* out, int n, int sign, int64_t inner, int64_t outer,
                           int nin, int pin, int nout, int pout, const void* fac_in, const void* fac_out, double scale,
-                          hipStream_t st) {
+                          hipStream_t st, const PassMasks& mk) {
   if (outer <= 0 || inner <= 0) return hipSuccess;
   return p.prec == FSIB_F64
-             ? c2c_impl<double>(p, in, out, n, sign, inner, outer, nin, pin, nout, pout, fac_in, fac_out, scale, st)
-             : c2c_impl<float>(p, in, out, n, sign, inner, outer, nin, pin, nout, pout, fac_in, fac_out, scale, st);
+             ? c2c_impl<double>(p, in, out, n, sign, inner, outer, nin, pin, nout, pout, fac_in, fac_out, scale, st, mk)
+             : c2c_impl<float>(p, in, out, n, sign, inner, outer, nin, pin, nout, pout, fac_in, fac_out, scale, st, mk);
 }
 
 template <typename T>
 static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int64_t rows, int nout, const void* fout,
-                           double scale, hipStream_t st) {
-  FftArgs<T> a = base_args<T>(p, n, -1);
+                           double scale, hipStream_t st, const PassMasks& mk) {
+  FftArgs<T> a = base_args<T>(p, n, -1, mk);
   a.inner = 1;
   a.outer = rows;
   a.nin = n;
@@ -319,8 +366,8 @@ static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int6
 
 template <typename T>
 static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int64_t rows, int nin, const void* fin,
-                           double scale, hipStream_t st) {
-  FftArgs<T> a = base_args<T>(p, n, +1);
+                           double scale, hipStream_t st, const PassMasks& mk) {
+  FftArgs<T> a = base_args<T>(p, n, +1, mk);
   a.inner = 1;
   a.outer = rows;
   a.nin = nin;
@@ -342,17 +389,17 @@ static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int6
 }
 
 hipError_t launch_fft_r2c_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nout,
-                            const void* fac_out, double scale, hipStream_t st) {
+                            const void* fac_out, double scale, hipStream_t st, const PassMasks& mk) {
   if (rows <= 0) return hipSuccess;
-  return p.prec == FSIB_F64 ? r2c_impl<double>(p, in, out, n, rows, nout, fac_out, scale, st)
-                            : r2c_impl<float>(p, in, out, n, rows, nout, fac_out, scale, st);
+  return p.prec == FSIB_F64 ? r2c_impl<double>(p, in, out, n, rows, nout, fac_out, scale, st, mk)
+                            : r2c_impl<float>(p, in, out, n, rows, nout, fac_out, scale, st, mk);
 }
 
 hipError_t launch_fft_c2r_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nin,
-                            const void* fac_in, double scale, hipStream_t st) {
+                            const void* fac_in, double scale, hipStream_t st, const PassMasks& mk) {
   if (rows <= 0) return hipSuccess;
-  return p.prec == FSIB_F64 ? c2r_impl<double>(p, in, out, n, rows, nin, fac_in, scale, st)
-                            : c2r_impl<float>(p, in, out, n, rows, nin, fac_in, scale, st);
+  return p.prec == FSIB_F64 ? c2r_impl<double>(p, in, out, n, rows, nin, fac_in, scale, st, mk)
+                            : c2r_impl<float>(p, in, out, n, rows, nin, fac_in, scale, st, mk);
 }
 
 }  // namespace fsib

@@ -131,6 +131,11 @@ template <typename T>
 static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t st) {
   const int n = (int)p.nd[0];
   FftArgs<T> a;
+  const PassMasks none;
+  a.line = none.line;
+  a.ld = none.ld;
+  a.st = none.st;
+  a.rows = none.rows;
   a.n = n;
   a.nst = radix_plan(n, a.radix);
   a.tw = (const cplx<T>*)p.tw.at(n);

@@ -53,7 +53,10 @@ struct Plan {
   int* s_idx = nullptr;    // M: original index of sorted point
   uint32_t* s_i0 = nullptr;  // M: packed first support cell (10 bits per axis)
   void* s_y = nullptr;     // M*dim prec: sub-cell position in [-1, 1]
+  void* s_str = nullptr;   // strengths in sorted order: max(2 ntrans, dim) * M prec
   int* flag = nullptr;     // non-finite position seen
+  uint8_t* rowmask = nullptr;  // nt[2] x nt[1]: a point's support reaches this block of x lines
+  uint8_t* zmask = nullptr;    // nt[2]: some line of this block of z planes is reached
   // spreading work list (heavy tiles split into parts of at most kSplit points)
   int64_t qn[3] = {0, 0, 0};   // bins before a tile, per axis, whose points can reach it
   int* tile_parts = nullptr;   // nbins
@@ -103,17 +106,18 @@ hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const doub
                                  double a, hipStream_t st);  // Y = X + a*U
 hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, hipStream_t st);  // exclusive, n+1 outputs
+hipError_t launch_row_masks(Plan& p, hipStream_t st);  // from the sorted bins
 // spread_interp.hip
 hipError_t launch_spread(Plan& p, int64_t M, const void* strengths, int real_comps, hipStream_t st);
 hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st);
 // fft.hip
 hipError_t launch_fft_c2c(const Plan& p, const void* in, void* out, int n, int sign, int64_t inner,
                           int64_t outer, int nin, int pin, int nout, int pout, const void* fac_in,
-                          const void* fac_out, double scale, hipStream_t st);
+                          const void* fac_out, double scale, hipStream_t st, const PassMasks& mk = PassMasks());
 hipError_t launch_fft_r2c_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nout,
-                            const void* fac_out, double scale, hipStream_t st);
+                            const void* fac_out, double scale, hipStream_t st, const PassMasks& mk = PassMasks());
 hipError_t launch_fft_c2r_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nin,
-                            const void* fac_in, double scale, hipStream_t st);
+                            const void* fac_in, double scale, hipStream_t st, const PassMasks& mk = PassMasks());
 // fluid.hip
 hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, hipStream_t st);  // nonlinear.hip
 hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,

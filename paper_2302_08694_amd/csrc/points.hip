@@ -138,6 +138,42 @@ hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Block (yb, zb) of x lines is needed when a point of some bin (any bx, by in [yb-qy, yb],
+// bz in [zb-qz, zb]) has a kernel support reaching it.
+__global__ void k_row_masks(int nt0, int nt1, int nt2, int qy, int qz, const int* __restrict__ counts,
+                            uint8_t* __restrict__ rowmask) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt1 * nt2) return;
+  const int yb = t % nt1, zb = t / nt1;
+  int any = 0;
+  for (int dz = 0; dz <= qz && !any; ++dz)
+    for (int dy = 0; dy <= qy && !any; ++dy) {
+      const int by = (yb - dy + nt1) % nt1, bz = (zb - dz + nt2) % nt2;
+      const int* c = counts + (int64_t)(bz * nt1 + by) * nt0;
+      for (int bx = 0; bx < nt0; ++bx) any |= c[bx];
+    }
+  rowmask[t] = any ? 1 : 0;
+}
+
+__global__ void k_plane_masks(int nt1, int nt2, const uint8_t* __restrict__ rowmask, uint8_t* __restrict__ zmask) {
+  const int zb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (zb >= nt2) return;
+  uint8_t any = 0;
+  for (int yb = 0; yb < nt1; ++yb) any |= rowmask[zb * nt1 + yb];
+  zmask[zb] = any;
+}
+
+hipError_t launch_row_masks(Plan& p, hipStream_t st) {
+  const int nrb = (int)(p.nt[1] * p.nt[2]);
+  hipLaunchKernelGGL(k_row_masks, dim3((nrb + 255) / 256), dim3(256), 0, st, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2],
+                     (int)p.qn[1], (int)p.qn[2], (const int*)p.counts, p.rowmask);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_plane_masks, dim3((unsigned)((p.nt[2] + 255) / 256)), dim3(256), 0, st, (int)p.nt[1],
+                     (int)p.nt[2], (const uint8_t*)p.rowmask, p.zmask);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, hipStream_t st) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, n, counts, offsets);
   return hipGetLastError();
@@ -153,6 +189,7 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_scan(p.nbins, p.counts, p.offsets, st)) != hipSuccess) return e;
+  if ((e = launch_row_masks(p, st)) != hipSuccess) return e;
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     if (p.prec == FSIB_F64)

@@ -29,6 +29,7 @@ struct SpreadArgs {
   const uint32_t* s_i0;
   const T* s_y;
   const T* str;         // strengths: real (M, nch) or complex (ntrans, M)
+  T* sstr;              // the strengths in sorted order, [ntrans][M][NCH]
   T* grid;              // real: nch planes; complex: ntrans interleaved complex grids
   int64_t M;
   int nf[3];
@@ -42,6 +43,7 @@ struct SpreadArgs {
   const int* tile_slot; // first scratch slot of a split tile
   T* scratch;           // split tiles: [ntrans][slots][NCH][kMaxTileCells] partial tiles
   int64_t slots;        // scratch slots per transform
+  const uint8_t* rowmask;  // blocks of x lines reached by some point (lines elsewhere stay unwritten)
 };
 
 template <typename T, int W>
@@ -73,6 +75,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   constexpr int RS = kTileX + 1;  // padded LDS row stride
   __shared__ T accs[NCH][kMaxTileCells / kTileX][RS];
   __shared__ T wts[kChunk][DIM][W];
+  __shared__ T wxr[kChunk][kTileX];  // x weights of the point on this tile's 16 columns (0 outside)
   __shared__ T sv[kChunk][NCH];
   __shared__ int vstart[kChunk][DIM];
   __shared__ int rbeg[27], rlen[27];
@@ -92,6 +95,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
     tcoord[1] = (int)(tile % a.nt[1]);
     tcoord[2] = DIM == 3 ? (int)(tile / a.nt[1]) : 0;
   }
+  // no point reaches this tile's block of x lines: those lines are neither read nor written
+  if (!a.rowmask[tcoord[2] * a.nt[1] + tcoord[1]]) return;
   const int rows = a.tb[1] * (DIM == 3 ? a.tb[2] : 1);
   const int tcells = kTileX * rows;
   int base[3] = {0, 0, 0};
@@ -127,7 +132,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   for (int r = 0; r < nrange; ++r) total += rlen[r];
   const int cbeg = part * kSplit;
   const int cend = total < cbeg + kSplit ? total : cbeg + kSplit;
-  if (total == 0) {  // no point reaches this tile: write zeros
+  if (total == 0) {  // no point reaches this tile, but some reach its lines: zeros
     for (int i = tid; i < tcells; i += kSpreadThreads) {
       const int lx = i % kTileX;
       const int ly = (i / kTileX) % a.tb[1];
@@ -169,13 +174,17 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
       if (s < 0) s += a.nf[d];
       vstart[pl][d] = s;
       if (d == 0) {
-        const int64_t j0 = a.s_idx[pos];
-        if (CPLX) {
-          sv[pl][0] = a.str[((int64_t)tr * a.M + j0) * 2 + 0];
-          sv[pl][1] = a.str[((int64_t)tr * a.M + j0) * 2 + 1];
-        } else {
+        // strengths in sorted order (gathered after the sort)
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) sv[pl][ch] = a.str[j0 * NCH + ch];
+        for (int ch = 0; ch < NCH; ++ch) sv[pl][ch] = a.sstr[((int64_t)tr * a.M + pos) * NCH + ch];
+#pragma unroll
+        for (int x = 0; x < kTileX; ++x) {
+          int dx = x - s;
+          if (dx < 0) dx += a.nf[0];
+          T wv = (T)0;
+#pragma unroll
+          for (int j = 0; j < W; ++j) wv = dx == j ? v[j] : wv;
+          wxr[pl][x] = wv;
         }
       }
     }
@@ -196,16 +205,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
         T s[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) s[ch] = wyz * sv[pl][ch];
-        const int vx = vstart[pl][0];
 #pragma unroll
         for (int x = 0; x < kTileX; ++x) {
-          int dx = x - vx;
-          if (dx < 0) dx += a.nf[0];
-          if (dx < W) {
-            const T wx = wts[pl][0][dx];
+          const T wx = wxr[pl][x];
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) acc[x][ch] += wx * s[ch];
-          }
+          for (int ch = 0; ch < NCH; ++ch) acc[x][ch] += wx * s[ch];
         }
       }
     }
@@ -246,6 +250,19 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
       for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = accs[ch][rw][lx];
     }
   }
+}
+
+// Strengths permuted into the sorted point order, so that the spreading stages read them contiguously.
+template <typename T, int NCH, bool CPLX>
+__global__ void k_sort_strengths(int64_t M, const int* __restrict__ s_idx, const T* __restrict__ str,
+                                 T* __restrict__ sstr) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= M) return;
+  const int tr = blockIdx.y;
+  const int64_t j = s_idx[pos];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+    sstr[((int64_t)tr * M + pos) * NCH + ch] = CPLX ? str[((int64_t)tr * M + j) * 2 + ch] : str[j * NCH + ch];
 }
 
 // Points reaching each tile (its bin and the q bins before it per axis) and the parts it splits into.
@@ -319,30 +336,44 @@ struct InterpArgs {
   int nf[3];
 };
 
+// Several lanes per point (kInterpLanes): each lane gathers a share of the point's w^(d-1) grid
+// lines along x and the partial sums are combined with cross-lane shuffles.
+template <int DIM>
+__host__ __device__ constexpr int interp_lanes() { return DIM == 3 ? 16 : 4; }
+
 template <typename T, int DIM, int W, int NCH, bool CPLX>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
-  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos >= a.M) return;
+  constexpr int TPP = interp_lanes<DIM>();
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pos = gid / TPP;
+  const int lane = (int)(gid % TPP);
+  const bool valid = pos < a.M;
   const int tr = blockIdx.y;
-  const uint32_t pk = a.s_i0[pos];
-  T wx[W], wy[W], wz[W];
-  kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 0], wx);
-  kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 1], wy);
-  if (DIM == 3) kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 2], wz);
-  const int ix = unpack_i0<DIM>(pk, 0), iy = unpack_i0<DIM>(pk, 1), iz = DIM == 3 ? unpack_i0<DIM>(pk, 2) : 0;
-  const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
   T acc[NCH];
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) acc[ch] = (T)0;
-  const int nz = DIM == 3 ? W : 1;
-  for (int jz = 0; jz < nz; ++jz) {
-    int z = iz + jz;
-    if (DIM == 3 && z >= a.nf[2]) z -= a.nf[2];
-    const T wzz = DIM == 3 ? wz[jz] : (T)1;
-    for (int jy = 0; jy < W; ++jy) {
+  if (valid) {
+    const uint32_t pk = a.s_i0[pos];
+    T wx[W], wy[W], wz[W];
+    kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 0], wx);
+    kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 1], wy);
+    if (DIM == 3) kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 2], wz);
+    const int ix = unpack_i0<DIM>(pk, 0), iy = unpack_i0<DIM>(pk, 1), iz = DIM == 3 ? unpack_i0<DIM>(pk, 2) : 0;
+    const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
+    constexpr int LINES = DIM == 3 ? W * W : W;
+    for (int l = lane; l < LINES; l += TPP) {
+      const int jy = l % W, jz = DIM == 3 ? l / W : 0;
       int y = iy + jy;
       if (y >= a.nf[1]) y -= a.nf[1];
-      const T wyz = wzz * wy[jy];
+      int z = iz + jz;
+      if (DIM == 3 && z >= a.nf[2]) z -= a.nf[2];
+      T wyz = wy[0], wzz = DIM == 3 ? wz[0] : (T)1;
+#pragma unroll
+      for (int j = 1; j < W; ++j) {
+        wyz = jy == j ? wy[j] : wyz;
+        if (DIM == 3) wzz = jz == j ? wz[j] : wzz;
+      }
+      wyz *= wzz;
       const int64_t row = ((int64_t)z * a.nf[1] + y) * a.nf[0];
       T racc[NCH];
 #pragma unroll
@@ -364,13 +395,20 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
       for (int ch = 0; ch < NCH; ++ch) acc[ch] += wyz * racc[ch];
     }
   }
-  const int64_t j = a.s_idx[pos];
-  if (CPLX) {
-    a.out[((int64_t)tr * a.M + j) * 2 + 0] = acc[0];
-    a.out[((int64_t)tr * a.M + j) * 2 + 1] = acc[1];
-  } else {
+  // combine the lanes of each point (TPP consecutive lanes of one wavefront)
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) a.out[j * NCH + ch] = acc[ch];
+  for (int off = TPP / 2; off > 0; off >>= 1)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] += __shfl_xor(acc[ch], off, TPP);
+  if (valid && lane == 0) {
+    const int64_t j = a.s_idx[pos];
+    if (CPLX) {
+      a.out[((int64_t)tr * a.M + j) * 2 + 0] = acc[0];
+      a.out[((int64_t)tr * a.M + j) * 2 + 1] = acc[1];
+    } else {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) a.out[j * NCH + ch] = acc[ch];
+    }
   }
 }
 
@@ -399,7 +437,15 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   a.tile_slot = p.tile_slot;
   a.scratch = (T*)p.split_scratch;
   a.slots = p.split_slots;
+  a.rowmask = p.rowmask;
+  a.sstr = (T*)p.s_str;
   const unsigned nb = (unsigned)p.nbins;
+  if (M > 0) {
+    hipLaunchKernelGGL((k_sort_strengths<T, NCH, CPLX>), dim3((unsigned)((M + 255) / 256), (unsigned)ntr), dim3(256), 0,
+                       st, M, (const int*)p.s_idx, (const T*)str, a.sstr);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+  }
   hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, DIM, a.nt[0], a.nt[1], a.nt[2], a.q[0],
                      a.q[1], a.q[2], (const int*)p.offsets, p.tile_parts);
   hipError_t e = hipGetLastError();
@@ -437,8 +483,9 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   if (M == 0) return hipSuccess;
   const bool prof = prof_on(p, PROF_INTERP);
   if (prof) prof_start(p, st);
-  hipLaunchKernelGGL((k_interp<T, DIM, W, NCH, CPLX>), dim3((unsigned)((M + 255) / 256), (unsigned)ntr), dim3(256), 0,
-                     st, a);
+  const int64_t threads = M * interp_lanes<DIM>();
+  hipLaunchKernelGGL((k_interp<T, DIM, W, NCH, CPLX>), dim3((unsigned)((threads + 255) / 256), (unsigned)ntr),
+                     dim3(256), 0, st, a);
   // algorithmic bytes: per point its sorted record, w^d grid cells per channel, the result
   if (prof) {
     double cellsper = 1;
