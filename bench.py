@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="modes per axis")
     ap.add_argument("--rings", type=int, default=200)
     ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 form and the NUFFT timings")
+    ap.add_argument("--no-nufft-micro", action="store_true", help="skip the NUFFT micro-benchmark legs")
+    ap.add_argument("--nufft-only", action="store_true", help="run only the NUFFT micro-benchmark legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -121,6 +123,96 @@ def time_nufft(torch, s, reps=20):
                 spread_ms=ts * 1e3, interp_ms=ti * 1e3)
 
 
+def touched_cells(torch, X, nf, w):
+    """Fine-grid cells inside at least one point's w^3 kernel support (counted on the device)."""
+    dev = X.device
+    occ = torch.zeros(nf ** 3, dtype=torch.bool, device=dev)
+    xf = torch.remainder(X, 1.0) * nf
+    i0 = torch.ceil(xf - w / 2.0).to(torch.int64)  # first cell of the support along each axis
+    off = torch.arange(w, device=dev)
+    ix = torch.remainder(i0[:, 0:1] + off, nf)  # (M, w)
+    for dz in range(w):
+        iz = torch.remainder(i0[:, 2] + dz, nf)
+        for dy in range(w):
+            iy = torch.remainder(i0[:, 1] + dy, nf)
+            occ[((iz * nf + iy) * nf)[:, None] + ix] = True
+    n = int(occ.sum().item())
+    del occ
+    return n
+
+
+def time_nufft_micro(F, torch, N, M, prec, tol, reps=10):
+    """Type-1 and type-2 of M complex strengths at N^3 modes with the NUFFT micro-benchmark's point law.
+
+    Returns points/s of the full transforms (sort + spread + FFT + deconvolution and the reverse)
+    and, from HIP events around the spreading and interpolation kernels alone, their time and
+    fraction of HBM bandwidth: spreading writes the fine grid once and reads each point's record
+    (24 B of coordinates + its strength); interpolation reads each touched fine cell once and each
+    point's record, and writes one value per point.
+    """
+    import workloads
+    dev = "cuda:0"
+    X0, c0 = workloads.nufft_points(M, seed=3, dim=3)
+    plan = F.Plan(3, (N, N, N), prec=prec, tol=tol, max_points=M)
+    info = plan.info()
+    nf, w = info["n_fine"][0], info["w"]
+    X = torch.as_tensor(X0).to(dev)
+    c = torch.as_tensor(c0).to(dev).to(plan.cdtype)
+    fh = torch.as_tensor(workloads.random_modes((N, N, N), 38)).to(dev).to(plan.cdtype)
+    out1 = plan.spread(X, c)
+    out2 = plan.interp(X, fh)
+    torch.cuda.synchronize()
+    res = {"N": N, "M": M, "prec": prec, "tol": tol, "w": w, "n_fine": nf}
+    for kind, call, cls in (("type1", lambda: plan.spread(X, c, out=out1), "spread"),
+                            ("type2", lambda: plan.interp(X, fh, out=out2), "interp")):
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        plan.profile(cls, max_launches=4 * reps)
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        ms, n, _ = plan.profile_read()
+        plan.profile(None)
+        res[f"{kind}_pts_per_s"] = M / t
+        res[f"{kind}_ms"] = t * 1e3
+        res[f"{cls}_kernel_us"] = ms * 1e3 / max(n, 1)
+    sc = 4 if prec == "f32" else 8
+    touched = touched_cells(torch, X, nf, w)
+    b_spread = M * (24 + 2 * sc) + nf ** 3 * 2 * sc
+    b_interp = M * (24 + 2 * sc) + touched * 2 * sc
+    res["spread_kernel_frac_hbm"] = b_spread / (res["spread_kernel_us"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
+    res["interp_kernel_frac_hbm"] = b_interp / (res["interp_kernel_us"] * 1e-6) / (HBM_PEAK_GBS * 1e9)
+    res["touched_cell_fraction"] = touched / nf ** 3
+    res["spread_interp_pts_per_s"] = M / ((res["type1_ms"] + res["type2_ms"]) * 1e-3)
+    plan.close()
+    del X, c, fh, out1, out2
+    torch.cuda.empty_cache()
+    return res
+
+
+# (N, M, prec, tol): the micro-benchmark's point law (half uniform, half on a sphere of radius 0.2)
+# at 256^3 with 2e6 points, and scaled to 128^3 with 2.5e5 points (same points per fine cell)
+NUFFT_MICRO = [(128, 250_000, "f32", 1e-5), (128, 250_000, "f64", 1e-5),
+               (256, 2_000_000, "f32", 1e-5), (256, 2_000_000, "f64", 1e-5), (256, 2_000_000, "f64", 1e-10)]
+
+
+def nufft_micro(F, torch):
+    res = []
+    for N, M, prec, tol in NUFFT_MICRO:
+        log(f"nufft micro N={N} M={M} {prec} tol {tol:g}")
+        r = time_nufft_micro(F, torch, N, M, prec, tol)
+        log(f"  type1 {r['type1_ms']:.3f} ms type2 {r['type2_ms']:.3f} ms spread kernel {r['spread_kernel_us']:.1f} us "
+            f"({r['spread_kernel_frac_hbm']:.2f} HBM) interp kernel {r['interp_kernel_us']:.1f} us "
+            f"({r['interp_kernel_frac_hbm']:.2f} HBM)")
+        res.append(r)
+    return res
+
+
 def cpu_baseline(N, rings, sample_points=2048):
     """The FP64 oracle on a bounded sample of one step, extrapolated to steps/s.
 
@@ -196,6 +288,10 @@ def main():
     import paper_2302_08694_amd as F
     if F.device_count() < 1:
         raise SystemExit("no HIP device visible")
+    if a.nufft_only:
+        print(json.dumps({"metric": "NUFFT micro-benchmark only (profiling run)", "nufft_micro": nufft_micro(F, torch)}),
+              flush=True)
+        return
     log("setup FP64")
     s64 = setup(F, torch, "f64", a.tol, a.n, a.rings)
     log(f"plan f64: {s64['plan'].info()}")
@@ -258,6 +354,8 @@ def main():
         "nufft_at_128": {"f64": nu64, "f32": nu32},
         "roofline": roofline(prof_ms, prof_n, prof_bytes),
     }
+    if not a.no_nufft_micro:
+        out["nufft_micro"] = nufft_micro(F, torch)
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.n, a.rings)

@@ -80,6 +80,7 @@ void free_plan(Plan& p) {
   fr(p.s_y);
   fr(p.s_str);
   fr(p.flag);
+  fr(p.scan_part);
   fr(p.rowmask);
   fr(p.zmask);
   fr(p.tile_parts);
@@ -216,6 +217,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   A.get(p.s_y, Mx * d * rs);
   A.get(p.s_str, Mx * (2 * p.ntrans > d ? 2 * p.ntrans : d) * rs);
   A.get(p.flag, 256);
+  A.get(p.scan_part, fsib::scan_segments(p.nbins) * 4);
   A.get(p.rowmask, p.nt[1] * p.nt[2]);
   A.get(p.zmask, p.nt[2]);
   // spreading work list: part bound = tiles + visits / kSplit, visits <= M * prod(q + 1)

@@ -55,6 +55,7 @@ struct Plan {
   void* s_y = nullptr;     // M*dim prec: sub-cell position in [-1, 1]
   void* s_str = nullptr;   // strengths in sorted order: max(2 ntrans, dim) * M prec
   int* flag = nullptr;     // non-finite position seen
+  int* scan_part = nullptr;  // segment sums of the exclusive scans over bins
   uint8_t* rowmask = nullptr;  // nt[2] x nt[1]: a point's support reaches this block of x lines
   uint8_t* zmask = nullptr;    // nt[2]: some line of this block of z planes is reached
   // spreading work list (heavy tiles split into parts of at most kSplit points)
@@ -105,7 +106,9 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
 hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const double* X, const void* U,
                                  double a, hipStream_t st);  // Y = X + a*U
 hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
-hipError_t launch_scan(int64_t n, const int* counts, int* offsets, hipStream_t st);  // exclusive, n+1 outputs
+hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum,
+                       hipStream_t st);  // exclusive, n+1 outputs; seg_sum: scan_segments(n) ints
+int64_t scan_segments(int64_t n);
 hipError_t launch_row_masks(Plan& p, hipStream_t st);  // from the sorted bins
 // spread_interp.hip
 hipError_t launch_spread(Plan& p, int64_t M, const void* strengths, int real_comps, hipStream_t st);

@@ -41,48 +41,113 @@ __device__ __forceinline__ void locate(double x, double L, int64_t nf, int w, in
   y = yy;
 }
 
+// Bin of every point and its rank inside the bin.  Neighbouring points of a mesh usually share a
+// bin, so the lanes of a wavefront form runs of equal bins and the first lane of each run claims
+// the whole run with one atomic add.  (The order of the runs inside a bin follows the order of the
+// atomics.)  Needs blockDim.x a multiple of 64.
 __global__ void k_bin_count(int64_t M, const double* __restrict__ X, Geo g, int* __restrict__ counts,
                             int* __restrict__ pt_bin, int* __restrict__ pt_rank, int* __restrict__ flag) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= M) return;
-  bool bad = false;
-  int64_t bin = 0, stride = 1;
-  for (int a = 0; a < g.dim; ++a) {
-    int i0;
-    double y;
-    locate(X[j * g.dim + a], g.L, g.nf[a], g.w, i0, y, bad);
-    bin += (i0 / g.tb[a]) * stride;
-    stride *= g.nt[a];
+  const bool valid = j < M;
+  int bin = -1;
+  if (valid) {
+    bool bad = false;
+    int64_t b = 0, stride = 1;
+    for (int a = 0; a < g.dim; ++a) {
+      int i0;
+      double y;
+      locate(X[j * g.dim + a], g.L, g.nf[a], g.w, i0, y, bad);
+      b += (i0 / g.tb[a]) * stride;
+      stride *= g.nt[a];
+    }
+    if (bad) flag[0] = 1;
+    bin = (int)b;
   }
-  if (bad) flag[0] = 1;
-  pt_bin[j] = (int)bin;
-  pt_rank[j] = atomicAdd(&counts[bin], 1);
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(bin, 1, 64);
+  const bool head = lane == 0 || prev != bin;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes <= lane
+  const int h = 63 - __clzll(heads & upto);                                       // head of my run
+  const unsigned long long after = heads & ~upto;
+  const int end = after ? __ffsll((long long)after) - 1 : 64;                     // next run's head
+  int base = 0;
+  if (valid && head) base = atomicAdd(&counts[bin], end - lane);
+  base = __shfl(base, h, 64);
+  if (valid) {
+    pt_bin[j] = bin;
+    pt_rank[j] = base + (lane - h);
+  }
 }
 
-// Exclusive scan of counts[0..n) into offsets[0..n] by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(int64_t n, const int* __restrict__ counts, int* __restrict__ offsets) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t b = t * chunk;
-  const int64_t e = b + chunk < n ? b + chunk : n;
-  int s = 0;
-  for (int64_t i = b; i < e; ++i) s += counts[i];
-  part[t] = s;
+// Exclusive scan of counts[0..n) into offsets[0..n] (offsets[n] = total).  Segments of
+// kScanSeg = 1024 threads x kScanEpt consecutive entries: each thread loads its run of kScanEpt
+// entries at once, the runs' sums are scanned across the workgroup (wavefront shuffles, then the
+// wavefront totals), and each thread writes its run.  With more than one segment, a first launch
+// stores the segment sums and a second one scans every segment after the sum of the segments
+// before it.
+constexpr int kScanThreads = 1024;
+constexpr int kScanEpt = 16;
+constexpr int64_t kScanSeg = (int64_t)kScanThreads * kScanEpt;
+
+// exclusive prefix of v over the workgroup; *total = sum over the workgroup
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += u;
+  }
+  if (lane == 63) wsum[wv] = inc;
   __syncthreads();
-  // Hillis-Steele inclusive scan of the 1024 chunk sums
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  if (wv == 0) {
+    const int nw = blockDim.x >> 6;
+    int x = lane < nw ? wsum[lane] : 0;
+    int xi = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(xi, off, 64);
+      if (lane >= off) xi += u;
+    }
+    if (lane < nw) wsum[lane] = xi - x;  // exclusive prefix of the wavefront totals
+    if (lane == nw - 1) wsum[64] = xi;
   }
-  int run = t > 0 ? part[t - 1] : 0;
-  for (int64_t i = b; i < e; ++i) {
-    offsets[i] = run;
-    run += counts[i];
+  __syncthreads();
+  *total = wsum[64];
+  return wsum[wv] + inc - v;
+}
+
+template <bool FINAL>
+__global__ __launch_bounds__(kScanThreads) void k_scan(int64_t n, const int* __restrict__ counts,
+                                                       int* __restrict__ offsets, int* __restrict__ seg_sum) {
+  __shared__ int wsum[65];
+  __shared__ int seg_base;
+  const int64_t first = (int64_t)blockIdx.x * kScanSeg + (int64_t)threadIdx.x * kScanEpt;
+  int v[kScanEpt];
+  int run = 0;
+#pragma unroll
+  for (int k = 0; k < kScanEpt; ++k) {
+    v[k] = first + k < n ? counts[first + k] : 0;
+    run += v[k];
   }
-  if (t == 1023) offsets[n] = part[1023];
+  if (FINAL && threadIdx.x == 0) {
+    int b = 0;
+    for (unsigned s = 0; s < blockIdx.x; ++s) b += seg_sum[s];
+    seg_base = b;
+  }
+  int total;
+  int excl = block_exclusive_scan(run, wsum, &total);
+  if (!FINAL) {
+    if (threadIdx.x == 0) seg_sum[blockIdx.x] = total;
+    return;
+  }
+  excl += seg_base;
+#pragma unroll
+  for (int k = 0; k < kScanEpt; ++k) {
+    if (first + k <= n) offsets[first + k] = excl;
+    excl += v[k];
+  }
 }
 
 template <typename T>
@@ -174,8 +239,16 @@ hipError_t launch_row_masks(Plan& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan(int64_t n, const int* counts, int* offsets, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, n, counts, offsets);
+int64_t scan_segments(int64_t n) { return n / kScanSeg + 1; }
+
+hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum, hipStream_t st) {
+  const int64_t nseg = scan_segments(n);
+  if (nseg > 1) {
+    hipLaunchKernelGGL(k_scan<false>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, n, counts, offsets, seg_sum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_scan<true>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, n, counts, offsets, seg_sum);
   return hipGetLastError();
 }
 
@@ -188,7 +261,7 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
     hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st, M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = launch_scan(p.nbins, p.counts, p.offsets, st)) != hipSuccess) return e;
+  if ((e = launch_scan(p.nbins, p.counts, p.offsets, p.scan_part, st)) != hipSuccess) return e;
   if ((e = launch_row_masks(p, st)) != hipSuccess) return e;
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);

@@ -450,7 +450,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
                      a.q[1], a.q[2], (const int*)p.offsets, p.tile_parts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = launch_scan(p.nbins, p.tile_parts, p.part_off, st)) != hipSuccess) return e;
+  if ((e = launch_scan(p.nbins, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
   if ((e = launch_fill_zero(p.slot_ctr, 4, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, (int)p.nbins, (const int*)p.part_off,
                      (const int*)p.tile_parts, (int2*)p.work, p.tile_slot, p.slot_ctr);
