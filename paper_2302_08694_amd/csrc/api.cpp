@@ -144,6 +144,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   p.fluid = o->fluid ? 1 : 0;
   p.ns = o->navier_stokes ? 1 : 0;
   FSIB_HIP(hipGetDevice(&p.device));
+  FSIB_HIP(hipDeviceGetAttribute(&p.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
   // kernel (App. A.3): width from tol, Kaiser-Bessel shape, polynomial degree
   p.w = fsib::choose_width(p.tol, p.dim);
   p.beta = fsib::choose_beta(p.w);

@@ -34,6 +34,12 @@ __host__ __device__ __forceinline__ cplx<T> conj(cplx<T> a) { return mk(a.x, -a.
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> mul_i(cplx<T> a, T s) { return mk(-a.y * s, a.x * s); }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, then for every
+// wave, but leaves global loads in flight (__syncthreads also waits for them), so loads issued
+// for the next block of work overlap the current one.  The memory clobber keeps the compiler from
+// moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 constexpr int kMaxW = 16;       // largest kernel width (fine cells)
 constexpr int kMaxDeg = 19;     // largest polynomial degree of the kernel pieces
 constexpr int kMaxStages = 16;  // FFT stages

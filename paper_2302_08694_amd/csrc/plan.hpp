@@ -31,6 +31,7 @@ struct Plan {
   int64_t max_points = 0;
   int fluid = 0, ns = 0;
   int device = 0;
+  int lds_max = 65536;  // LDS bytes one workgroup may allocate on this device
   // kernel
   int w = 0, deg = 0;
   double beta = 0.0;

@@ -64,20 +64,42 @@ __device__ __forceinline__ int unpack_i0(uint32_t p, int a) {
 // NCH channels per point: real vector strengths (NCH = components, planar grids) or one complex
 // strength (NCH = 2, interleaved complex grid, transform index = blockIdx.y).
 //
-// Inside a tile every thread owns one row of kTileX cells along x (rows = tile_y * tile_z) and
-// accumulates it in registers for a 1/TPR share of the tile's points; the lanes of a wavefront
-// hold different rows and visit the same point together, so point data are LDS broadcasts and no
-// atomics are needed.  The TPR partial rows are then summed in a fixed order through LDS and the
-// tile is written once.  Dense clusters (e.g. the poles of a lat-long mesh, where thousands of
-// points share a few cells) cost the same per point as isolated points.
+// Inside a tile every lane owns CW consecutive cells of one row along x (3D: 64 rows x 4 groups of
+// 4 cells; 2D: 16 rows x 16 single cells) and accumulates them in registers.  The tile's points are
+// staged 64 at a time: their kernel values along each axis are expanded over the tile's
+// coordinates (zero outside the support), and one ballot per tile coordinate gives the 64-bit set
+// of staged points whose support covers it.  A lane's points are the AND of the sets of its row's
+// y and z and of its x group; every lane walks its own set, lowest point first, so lanes stay busy
+// with different points and no lane visits a point that misses its cells.  Each cell is summed by
+// one lane in point order (deterministic for a given sorted order), no atomics; the tile is staged
+// through LDS and written once with coalesced stores.
+template <typename T, int DIM>
+struct SpreadTile {
+  static constexpr int TY = DIM == 3 ? 8 : 16;               // tile rows along y
+  static constexpr int TZ = DIM == 3 ? 8 : 1;                // tile rows along z
+  static constexpr int ROWS = TY * TZ;
+  static constexpr int CW = kTileX * ROWS / kSpreadThreads;  // cells per lane along x
+  static constexpr int NXG = kTileX / CW;                    // x groups
+  static constexpr int XS = kTileX + (sizeof(T) == 4 ? 4 : 2);  // padded LDS strides
+  static constexpr int YS = TY + 1;
+  static constexpr int ZS = TZ + 1;
+  static constexpr int NMASK = TY + (DIM == 3 ? TZ : 0) + NXG;
+};
+
 template <typename T, int DIM, int W, int NCH, bool CPLX>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
-  constexpr int RS = kTileX + 1;  // padded LDS row stride
-  __shared__ T accs[NCH][kMaxTileCells / kTileX][RS];
-  __shared__ T wts[kChunk][DIM][W];
-  __shared__ T wxr[kChunk][kTileX];  // x weights of the point on this tile's 16 columns (0 outside)
+  using G = SpreadTile<T, DIM>;
+  constexpr int TY = G::TY, TZ = G::TZ, ROWS = G::ROWS, CW = G::CW, NXG = G::NXG;
+  constexpr int WTS = kChunk * DIM * W;                 // kernel values of the staged points
+  constexpr int OUT = NCH * ROWS * (kTileX + 1);        // the finished tile
+  __shared__ T big[WTS > OUT ? WTS : OUT];
+  __shared__ T wxr[kChunk][G::XS];
+  __shared__ T wyr[kChunk][G::YS];
+  __shared__ T wzr[DIM == 3 ? kChunk : 1][G::ZS];
   __shared__ T sv[kChunk][NCH];
+  __shared__ T cf[(kMaxDeg + 1) * W];
   __shared__ int vstart[kChunk][DIM];
+  __shared__ unsigned long long msk[G::NMASK];
   __shared__ int rbeg[27], rlen[27];
   __shared__ int nrange;
 
@@ -97,10 +119,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   }
   // no point reaches this tile's block of x lines: those lines are neither read nor written
   if (!a.rowmask[tcoord[2] * a.nt[1] + tcoord[1]]) return;
-  const int rows = a.tb[1] * (DIM == 3 ? a.tb[2] : 1);
-  const int tcells = kTileX * rows;
+  constexpr int tcells = kTileX * ROWS;
   int base[3] = {0, 0, 0};
-  for (int d = 0; d < DIM; ++d) base[d] = tcoord[d] * a.tb[d];
+  base[0] = tcoord[0] * kTileX;
+  base[1] = tcoord[1] * TY;
+  if (DIM == 3) base[2] = tcoord[2] * TZ;
   const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
   // bins that can reach this tile: this one and up to q before it along each axis, read in parallel
   {
@@ -115,6 +138,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
       rbeg[tid] = s0;
       rlen[tid] = e0 - s0;
     }
+    for (int i = tid; i < (a.deg + 1) * W; i += kSpreadThreads) cf[i] = a.coef[i];
     __syncthreads();
     if (tid == 0) {
       int nr = 0;
@@ -135,8 +159,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   if (total == 0) {  // no point reaches this tile, but some reach its lines: zeros
     for (int i = tid; i < tcells; i += kSpreadThreads) {
       const int lx = i % kTileX;
-      const int ly = (i / kTileX) % a.tb[1];
-      const int lz = DIM == 3 ? i / (kTileX * a.tb[1]) : 0;
+      const int ly = (i / kTileX) % TY;
+      const int lz = DIM == 3 ? i / (kTileX * TY) : 0;
       const int gz = DIM == 3 ? base[2] + lz : 0;
       const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + ly) * a.nf[0] + base[0] + lx;
       if (CPLX) {
@@ -148,90 +172,135 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
     }
     return;
   }
-  const int tpr = kSpreadThreads / rows;  // threads per row
-  const int row = tid % rows, sub = tid / rows;
-  const int ly = row % a.tb[1];
-  const int lz = DIM == 3 ? row / a.tb[1] : 0;
-  T acc[kTileX][NCH];
+  const int row = tid % ROWS, xg = tid / ROWS;
+  const int ly = row % TY, lz = DIM == 3 ? row / TY : 0;
+  const int lane = tid & 63, wave = tid >> 6;
+  T acc[CW][NCH];
 #pragma unroll
-  for (int x = 0; x < kTileX; ++x)
+  for (int c = 0; c < CW; ++c)
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) acc[x][ch] = (T)0;
+    for (int ch = 0; ch < NCH; ++ch) acc[c][ch] = (T)0;
+  T(*wts)[DIM][W] = reinterpret_cast<T(*)[DIM][W]>(big);
 
   for (int c0 = cbeg; c0 < cend; c0 += kChunk) {
     const int cnt = cend - c0 < kChunk ? cend - c0 : kChunk;
-    // stage: kernel values per axis, start offset relative to the tile, strengths
+    // (1) kernel values per axis, support start relative to the tile, strengths
     for (int it = tid; it < cnt * DIM; it += kSpreadThreads) {
-      const int pl = it / DIM, d = it % DIM;
+      const int pl = it / DIM, d = it - pl * DIM;
       int vi = c0 + pl, r = 0;
       while (vi >= rlen[r]) vi -= rlen[r++];
       const int64_t pos = (int64_t)rbeg[r] + vi;
+      const T y = a.s_y[pos * DIM + d];
       T v[W];
-      kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + d], v);
+#pragma unroll
+      for (int j = 0; j < W; ++j) v[j] = cf[a.deg * W + j];
+      for (int i = a.deg - 1; i >= 0; --i) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) v[j] = v[j] * y + cf[i * W + j];
+      }
 #pragma unroll
       for (int j = 0; j < W; ++j) wts[pl][d][j] = v[j];
-      int s = unpack_i0<DIM>(a.s_i0[pos], d) - base[d];
-      if (s < 0) s += a.nf[d];
-      vstart[pl][d] = s;
+      int st = unpack_i0<DIM>(a.s_i0[pos], d) - base[d];
+      if (st < 0) st += a.nf[d];
+      vstart[pl][d] = st;
       if (d == 0) {
-        // strengths in sorted order (gathered after the sort)
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) sv[pl][ch] = a.sstr[((int64_t)tr * a.M + pos) * NCH + ch];
-#pragma unroll
-        for (int x = 0; x < kTileX; ++x) {
-          int dx = x - s;
-          if (dx < 0) dx += a.nf[0];
-          T wv = (T)0;
-#pragma unroll
-          for (int j = 0; j < W; ++j) wv = dx == j ? v[j] : wv;
-          wxr[pl][x] = wv;
-        }
       }
     }
     __syncthreads();
-    if (sub < tpr) {
-      for (int pl = sub; pl < cnt; pl += tpr) {
-        // offset of this thread's row inside the point's support (cells (v + j) mod n_f, j < w)
-        int dy = ly - vstart[pl][1];
-        if (dy < 0) dy += a.nf[1];
-        if (dy >= W) continue;
-        T wyz = wts[pl][1][dy];
-        if (DIM == 3) {
-          int dz = lz - vstart[pl][2];
-          if (dz < 0) dz += a.nf[2];
-          if (dz >= W) continue;
-          wyz *= wts[pl][2][dz];
+    // (2) kernel values expanded over the tile's x, y, z coordinates; coverage sets by ballot
+    constexpr int EPP = kTileX + TY + (DIM == 3 ? TZ : 0);  // expanded entries per point
+    for (int e = tid; e < cnt * EPP; e += kSpreadThreads) {
+      const int pl = e / EPP, k = e - pl * EPP;
+      int d, c;
+      if (k < kTileX) {
+        d = 0;
+        c = k;
+      } else if (k < kTileX + TY) {
+        d = 1;
+        c = k - kTileX;
+      } else {
+        d = 2;
+        c = k - kTileX - TY;
+      }
+      int off = c - vstart[pl][d];
+      if (off < 0) off += a.nf[d];
+      const T val = off < W ? wts[pl][d][off] : (T)0;
+      if (d == 0)
+        wxr[pl][c] = val;
+      else if (d == 1)
+        wyr[pl][c] = val;
+      else
+        wzr[DIM == 3 ? pl : 0][c] = val;
+    }
+    {
+      int sx = 0, sy = 0, sz = 0;
+      if (lane < cnt) {
+        sx = vstart[lane][0];
+        sy = vstart[lane][1];
+        if (DIM == 3) sz = vstart[lane][2];
+      }
+      for (int k = wave; k < G::NMASK; k += kSpreadThreads / 64) {
+        bool hit = false;
+        if (lane < cnt) {
+          if (k < TY) {  // row coordinate y = k
+            int off = k - sy;
+            if (off < 0) off += a.nf[1];
+            hit = off < W;
+          } else if (DIM == 3 && k < TY + TZ) {  // z = k - TY
+            int off = k - TY - sz;
+            if (off < 0) off += a.nf[2];
+            hit = off < W;
+          } else {  // x group: cells [g CW, (g + 1) CW)
+            const int g = k - TY - (DIM == 3 ? TZ : 0);
+            int off = g * CW - sx;
+            if (off < 0) off += a.nf[0];
+            // covered when the support [sx, sx + W) meets the group (periodic distances)
+            int back = sx - g * CW;
+            if (back < 0) back += a.nf[0];
+            hit = off < W || back < CW;
+          }
         }
-        T s[NCH];
+        const unsigned long long bm = __ballot(hit);
+        if (lane == 0) msk[k] = bm;
+      }
+    }
+    __syncthreads();
+    // (3) every lane walks the staged points that cover its cells
+    unsigned long long m = msk[ly] & msk[TY + (DIM == 3 ? TZ : 0) + xg];
+    if (DIM == 3) m &= msk[TY + lz];
+    while (m) {
+      const int pl = __ffsll((long long)m) - 1;
+      m &= m - 1ull;
+      T wyz = wyr[pl][ly];
+      if (DIM == 3) wyz *= wzr[DIM == 3 ? pl : 0][lz];
+      T sw[NCH];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) s[ch] = wyz * sv[pl][ch];
+      for (int ch = 0; ch < NCH; ++ch) sw[ch] = sv[pl][ch] * wyz;
 #pragma unroll
-        for (int x = 0; x < kTileX; ++x) {
-          const T wx = wxr[pl][x];
+      for (int c = 0; c < CW; ++c) {
+        const T wx = wxr[pl][xg * CW + c];
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) acc[x][ch] += wx * s[ch];
-        }
+        for (int ch = 0; ch < NCH; ++ch) acc[c][ch] += wx * sw[ch];
       }
     }
     __syncthreads();
   }
-  // fixed-order sum of the partial rows through LDS
-  for (int sidx = 0; sidx < tpr; ++sidx) {
-    if (sub == sidx) {
+  // the finished tile through LDS: [ch][row][x]
+  T(*outt)[ROWS][kTileX + 1] = reinterpret_cast<T(*)[ROWS][kTileX + 1]>(big);
 #pragma unroll
-      for (int x = 0; x < kTileX; ++x)
+  for (int c = 0; c < CW; ++c)
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) accs[ch][row][x] = (sidx == 0 ? (T)0 : accs[ch][row][x]) + acc[x][ch];
-    }
-    __syncthreads();
-  }
+    for (int ch = 0; ch < NCH; ++ch) outt[ch][row][xg * CW + c] = acc[c][ch];
+  __syncthreads();
   if (nparts > 1) {  // one part of a split tile: partial tile to scratch, summed by k_merge_tiles
     T* dst = a.scratch + ((int64_t)tr * a.slots + a.tile_slot[tile_id] + part) * NCH * kMaxTileCells;
     for (int i = tid; i < tcells; i += kSpreadThreads) {
       const int lx = i % kTileX;
       const int rw = i / kTileX;
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) dst[ch * kMaxTileCells + i] = accs[ch][rw][lx];
+      for (int ch = 0; ch < NCH; ++ch) dst[ch * kMaxTileCells + i] = outt[ch][rw][lx];
     }
     return;
   }
@@ -239,15 +308,15 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   for (int i = tid; i < tcells; i += kSpreadThreads) {
     const int lx = i % kTileX;
     const int rw = i / kTileX;
-    const int lyy = rw % a.tb[1];
-    const int lzz = DIM == 3 ? rw / a.tb[1] : 0;
+    const int lyy = rw % TY;
+    const int lzz = DIM == 3 ? rw / TY : 0;
     const int gz = DIM == 3 ? base[2] + lzz : 0;
     const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + lyy) * a.nf[0] + base[0] + lx;
     if (CPLX) {
-      reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = mk(accs[0][rw][lx], accs[1][rw][lx]);
+      reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = mk(outt[0][rw][lx], outt[1][rw][lx]);
     } else {
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = accs[ch][rw][lx];
+      for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = outt[ch][rw][lx];
     }
   }
 }
@@ -336,78 +405,189 @@ struct InterpArgs {
   int nf[3];
 };
 
-// Several lanes per point (kInterpLanes): each lane gathers a share of the point's w^(d-1) grid
-// lines along x and the partial sums are combined with cross-lane shuffles.
-template <int DIM>
-__host__ __device__ constexpr int interp_lanes() { return DIM == 3 ? 16 : 4; }
+// One wavefront per point (a few points at a time).  The lanes cover an XL x YL patch of the
+// point's support in one z-plane (XL >= w lanes along x, YL = 64/XL along y), so one load
+// instruction reads YL short runs of consecutive cells; the planes jz = 0..w-1 (and, when w > YL,
+// the chunks of YL rows) are walked in turn.  Lanes 16a + j (axis a, j < w) evaluate the kernel value
+// j along axis a (Horner, with the coefficient column j held in registers); every lane takes its x
+// and y values by lane permute and the plane's z value by readlane.  The wavefront sum is a
+// butterfly reduction.  Consecutive sorted points go to the same wavefront, so their shared cells
+// hit in the L1 cache, and the next group of points' records is loaded one group ahead.
+constexpr int kIpPointsPerWave = 8;
+
+// Lane permutes and readlanes run with every lane of the wavefront active: the source lane of a
+// permute must be active for its value to be read.
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int src) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+  } else {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(u & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(u >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T uniform_lane_value(T v, int src) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+  } else {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  }
+}
+
+template <int W>
+__host__ __device__ constexpr int interp_xlanes() { return W <= 2 ? 2 : (W <= 4 ? 4 : (W <= 8 ? 8 : 16)); }
 
 template <typename T, int DIM, int W, int NCH, bool CPLX>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
-  constexpr int TPP = interp_lanes<DIM>();
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t pos = gid / TPP;
-  const int lane = (int)(gid % TPP);
-  const bool valid = pos < a.M;
+  constexpr int XL = interp_xlanes<W>();
+  constexpr int YL = 64 / XL;
+  constexpr int YCH = (W + YL - 1) / YL;  // chunks of YL rows along y
+  constexpr int NZ = DIM == 3 ? W : 1;
+  constexpr int SC = CPLX ? 2 : NCH;
+  constexpr int RPP = YCH * NZ * SC * (int)sizeof(T) / 4;  // registers of one point's cells
+  constexpr int PB = RPP <= 16 ? 4 : (RPP <= 32 ? 2 : 1);   // points summed together
+  constexpr int GMAX = (PB == 1 ? 32 : 64) / (PB * SC * (int)sizeof(T) / 4);
+  constexpr int G = NZ < GMAX ? NZ : GMAX;                  // planes loaded together
+  const int lane = threadIdx.x & 63;
+  const int xl = lane % XL, yl = lane / XL;
+  const int axis = lane >> 4, jk = lane & 15;  // kernel value jk along axis (lanes 16a + j)
   const int tr = blockIdx.y;
-  T acc[NCH];
+  const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
+  // coefficient column jk of the kernel pieces
+  T cfr[kMaxDeg + 1];
 #pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) acc[ch] = (T)0;
-  if (valid) {
-    const uint32_t pk = a.s_i0[pos];
-    T wx[W], wy[W], wz[W];
-    kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 0], wx);
-    kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 1], wy);
-    if (DIM == 3) kernel_values<T, W>(a.coef, a.deg, a.s_y[pos * DIM + 2], wz);
-    const int ix = unpack_i0<DIM>(pk, 0), iy = unpack_i0<DIM>(pk, 1), iz = DIM == 3 ? unpack_i0<DIM>(pk, 2) : 0;
-    const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
-    constexpr int LINES = DIM == 3 ? W * W : W;
-    for (int l = lane; l < LINES; l += TPP) {
-      const int jy = l % W, jz = DIM == 3 ? l / W : 0;
-      int y = iy + jy;
-      if (y >= a.nf[1]) y -= a.nf[1];
-      int z = iz + jz;
-      if (DIM == 3 && z >= a.nf[2]) z -= a.nf[2];
-      T wyz = wy[0], wzz = DIM == 3 ? wz[0] : (T)1;
+  for (int i = 0; i <= kMaxDeg; ++i) cfr[i] = (i <= a.deg && jk < W) ? a.coef[i * W + jk] : (T)0;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t first = wave * kIpPointsPerWave;
+  uint32_t pkn[PB];
+  T yn[PB];
+  auto records = [&](int k0) {
 #pragma unroll
-      for (int j = 1; j < W; ++j) {
-        wyz = jy == j ? wy[j] : wyz;
-        if (DIM == 3) wzz = jz == j ? wz[j] : wzz;
+    for (int b = 0; b < PB; ++b) {
+      int64_t pq = first + k0 + b;
+      if (pq >= a.M) pq = a.M - 1;
+      pkn[b] = a.s_i0[pq];
+      yn[b] = a.s_y[pq * DIM + (axis < DIM ? axis : 0)];
+    }
+  };
+  if (first < a.M) records(0);
+  for (int k0 = 0; k0 < kIpPointsPerWave; k0 += PB) {
+    if (first + k0 >= a.M) break;
+    uint32_t pkc[PB];
+    T yc[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      pkc[b] = pkn[b];
+      yc[b] = yn[b];
+    }
+    if (k0 + PB < kIpPointsPerWave && first + k0 + PB < a.M) records(k0 + PB);
+    T v[PB];
+    int iz[PB], gxb[PB], gyb[PB][YCH];
+    T wxy[PB][YCH];
+    bool ok[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      ok[b] = first + k0 + b < a.M;
+      T u = (T)0;
+#pragma unroll
+      for (int i = kMaxDeg; i >= 0; --i)
+        if (i <= a.deg) u = u * yc[b] + cfr[i];
+      v[b] = u;
+      const int ix = unpack_i0<DIM>(pkc[b], 0), iy = unpack_i0<DIM>(pkc[b], 1);
+      iz[b] = DIM == 3 ? unpack_i0<DIM>(pkc[b], 2) : 0;
+      const T wxa = lane_value(v[b], xl < W ? xl : 0);
+      const T wx = xl < W ? wxa : (T)0;
+      gxb[b] = ix + xl;
+      if (gxb[b] >= a.nf[0]) gxb[b] -= a.nf[0];
+#pragma unroll
+      for (int ch = 0; ch < YCH; ++ch) {
+        const int jy = yl + YL * ch;
+        const bool act = ok[b] && xl < W && jy < W;
+        const T wya = lane_value(v[b], 16 + (jy < W ? jy : 0));
+        wxy[b][ch] = act ? wx * wya : (T)0;
+        int gy = iy + (jy < W ? jy : 0);
+        if (gy >= a.nf[1]) gy -= a.nf[1];
+        gyb[b][ch] = act ? gy : -1;
       }
-      wyz *= wzz;
-      const int64_t row = ((int64_t)z * a.nf[1] + y) * a.nf[0];
-      T racc[NCH];
+    }
+    T acc[PB][SC];
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) racc[ch] = (T)0;
+    for (int b = 0; b < PB; ++b)
 #pragma unroll
-      for (int jx = 0; jx < W; ++jx) {
-        int x = ix + jx;
-        if (x >= a.nf[0]) x -= a.nf[0];
+      for (int c = 0; c < SC; ++c) acc[b][c] = (T)0;
+#pragma unroll
+    for (int ch = 0; ch < YCH; ++ch) {
+      // planes jz0 .. jz0+G-1 of this chunk (a rolled loop when the support has more planes)
+#pragma unroll 1
+      for (int jz0 = 0; jz0 < NZ; jz0 += G) {
+        T cv[PB][G][SC];
+#pragma unroll
+        for (int b = 0; b < PB; ++b)
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            const int jz = jz0 + t;
+#pragma unroll
+            for (int c = 0; c < SC; ++c) cv[b][t][c] = (T)0;
+            int gz = iz[b] + jz;
+            if (DIM == 3 && gz >= a.nf[2]) gz -= a.nf[2];
+            if (jz < NZ && gyb[b][ch] >= 0) {
+              const int64_t g = ((int64_t)gz * a.nf[1] + gyb[b][ch]) * a.nf[0] + gxb[b];
+              if (CPLX) {
+                const cplx<T> z = reinterpret_cast<const cplx<T>*>(a.grid)[(int64_t)tr * cells + g];
+                cv[b][t][0] = z.x;
+                cv[b][t][SC - 1] = z.y;
+              } else {
+#pragma unroll
+                for (int c = 0; c < SC; ++c) cv[b][t][c] = a.grid[c * cells + g];
+              }
+            }
+          }
+#pragma unroll
+        for (int b = 0; b < PB; ++b)
+#pragma unroll
+          for (int t = 0; t < G; ++t) {
+            const int jz = jz0 + t;
+            const T wz = DIM == 3 ? uniform_lane_value(v[b], 32 + (jz < NZ ? jz : 0)) : (T)1;
+            if (jz < NZ) {
+              const T w = wxy[b][ch] * wz;
+#pragma unroll
+              for (int c = 0; c < SC; ++c) acc[b][c] += w * cv[b][t][c];
+            }
+          }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int b = 0; b < PB; ++b)
+#pragma unroll
+        for (int c = 0; c < SC; ++c) acc[b][c] += __shfl_xor(acc[b][c], off, 64);
+    if (lane < PB) {  // lane b writes point b
+      T res[SC];
+#pragma unroll
+      for (int c = 0; c < SC; ++c) res[c] = acc[0][c];
+#pragma unroll
+      for (int b = 1; b < PB; ++b)
+        if (lane == b)
+#pragma unroll
+          for (int c = 0; c < SC; ++c) res[c] = acc[b][c];
+      const int64_t pos = first + k0 + lane;
+      if (pos < a.M) {
+        const int64_t j = a.s_idx[pos];
         if (CPLX) {
-          const cplx<T> v = reinterpret_cast<const cplx<T>*>(a.grid)[(int64_t)tr * cells + row + x];
-          racc[0] += wx[jx] * v.x;
-          racc[1] += wx[jx] * v.y;
+          a.out[((int64_t)tr * a.M + j) * 2 + 0] = res[0];
+          a.out[((int64_t)tr * a.M + j) * 2 + 1] = res[SC - 1];
         } else {
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) racc[ch] += wx[jx] * a.grid[ch * cells + row + x];
+          for (int c = 0; c < SC; ++c) a.out[j * NCH + c] = res[c];
         }
       }
-#pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) acc[ch] += wyz * racc[ch];
-    }
-  }
-  // combine the lanes of each point (TPP consecutive lanes of one wavefront)
-#pragma unroll
-  for (int off = TPP / 2; off > 0; off >>= 1)
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) acc[ch] += __shfl_xor(acc[ch], off, TPP);
-  if (valid && lane == 0) {
-    const int64_t j = a.s_idx[pos];
-    if (CPLX) {
-      a.out[((int64_t)tr * a.M + j) * 2 + 0] = acc[0];
-      a.out[((int64_t)tr * a.M + j) * 2 + 1] = acc[1];
-    } else {
-#pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) a.out[j * NCH + ch] = acc[ch];
     }
   }
 }
@@ -470,6 +650,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
 
 template <typename T, int DIM, int NCH, bool CPLX, int W>
 static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t st) {
+  if (M == 0) return hipSuccess;
   InterpArgs<T> a;
   a.coef = (const T*)p.coef;
   a.deg = p.deg;
@@ -480,11 +661,10 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   a.out = (T*)out;
   a.M = M;
   for (int d = 0; d < 3; ++d) a.nf[d] = (int)p.nf[d];
-  if (M == 0) return hipSuccess;
   const bool prof = prof_on(p, PROF_INTERP);
   if (prof) prof_start(p, st);
-  const int64_t threads = M * interp_lanes<DIM>();
-  hipLaunchKernelGGL((k_interp<T, DIM, W, NCH, CPLX>), dim3((unsigned)((threads + 255) / 256), (unsigned)ntr),
+  const int64_t per_wg = 4 * kIpPointsPerWave;  // four wavefronts per workgroup
+  hipLaunchKernelGGL((k_interp<T, DIM, W, NCH, CPLX>), dim3((unsigned)((M + per_wg - 1) / per_wg), (unsigned)ntr),
                      dim3(256), 0, st, a);
   // algorithmic bytes: per point its sorted record, w^d grid cells per channel, the result
   if (prof) {
