@@ -36,7 +36,7 @@ struct SpreadArgs {
   int tb[3];
   int nt[3];
   int q[3];             // neighbour bins to visit per axis (0..q)
-  // work list: part b of the launch spreads points [q*kSplit, (q+1)*kSplit) of tile t
+  // work list: entry e = (t, q), q >= 1: workgroup nbins + e spreads points [q*kSplit, (q+1)*kSplit) of tile t
   const int* part_off;  // nbins+1 (exclusive scan of tile_parts)
   const int2* work;     // (t, q) per part
   const int* tile_parts;
@@ -66,13 +66,17 @@ __device__ __forceinline__ int unpack_i0(uint32_t p, int a) {
 //
 // Inside a tile every lane owns CW consecutive cells of one row along x (3D: 64 rows x 4 groups of
 // 4 cells; 2D: 16 rows x 16 single cells) and accumulates them in registers.  The tile's points are
-// staged 64 at a time: their kernel values along each axis are expanded over the tile's
-// coordinates (zero outside the support), and one ballot per tile coordinate gives the 64-bit set
-// of staged points whose support covers it.  A lane's points are the AND of the sets of its row's
-// y and z and of its x group; every lane walks its own set, lowest point first, so lanes stay busy
-// with different points and no lane visits a point that misses its cells.  Each cell is summed by
-// one lane in point order (deterministic for a given sorted order), no atomics; the tile is staged
-// through LDS and written once with coalesced stores.
+// staged 64 at a time, one wavefront per axis with one lane per point: the lane evaluates the
+// point's w kernel values along its axis (Horner), writes them expanded over the tile's
+// coordinates of that axis (zero outside the support), and one ballot per tile coordinate gives the
+// 64-bit set of staged points whose support covers it.  A lane's points are the AND of the sets of
+// its row's y and z and of its x group; every lane walks its own set, lowest point first, so lanes
+// stay busy with different points and no lane visits a point that misses its cells.  Each cell is
+// summed by one lane in point order (deterministic for a given sorted order), no atomics, and each
+// lane writes its cells once.
+//
+// Workgroup b < nbins spreads (the first part of) tile b; workgroups past nbins take the further
+// parts of heavy tiles from the work list.
 template <typename T, int DIM>
 struct SpreadTile {
   static constexpr int TY = DIM == 3 ? 8 : 16;               // tile rows along y
@@ -90,35 +94,36 @@ template <typename T, int DIM, int W, int NCH, bool CPLX>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   using G = SpreadTile<T, DIM>;
   constexpr int TY = G::TY, TZ = G::TZ, ROWS = G::ROWS, CW = G::CW, NXG = G::NXG;
-  constexpr int WTS = kChunk * DIM * W;                 // kernel values of the staged points
-  constexpr int OUT = NCH * ROWS * (kTileX + 1);        // the finished tile
-  __shared__ T big[WTS > OUT ? WTS : OUT];
   __shared__ T wxr[kChunk][G::XS];
   __shared__ T wyr[kChunk][G::YS];
   __shared__ T wzr[DIM == 3 ? kChunk : 1][G::ZS];
   __shared__ T sv[kChunk][NCH];
   __shared__ T cf[(kMaxDeg + 1) * W];
-  __shared__ int vstart[kChunk][DIM];
   __shared__ unsigned long long msk[G::NMASK];
   __shared__ int rbeg[27], rlen[27];
   __shared__ int nrange;
 
   const int tid = threadIdx.x;
   const int tr = blockIdx.y;
-  if ((int)blockIdx.x >= a.part_off[a.nt[0] * a.nt[1] * a.nt[2]]) return;  // beyond the work list
-  const int2 wk = a.work[blockIdx.x];
-  const int tile_id = wk.x, part = wk.y;
-  const int nparts = a.tile_parts[tile_id];
-  int tcoord[3];
-  {
-    int64_t tile = tile_id;
-    tcoord[0] = (int)(tile % a.nt[0]);
-    tile /= a.nt[0];
-    tcoord[1] = (int)(tile % a.nt[1]);
-    tcoord[2] = DIM == 3 ? (int)(tile / a.nt[1]) : 0;
+  const int nbins = a.nt[0] * a.nt[1] * (DIM == 3 ? a.nt[2] : 1);
+  int tile_id, part;
+  if ((int)blockIdx.x < nbins) {
+    tile_id = blockIdx.x;
+    part = 0;
+  } else {
+    const int e = (int)blockIdx.x - nbins;
+    if (e >= a.part_off[nbins] - nbins) return;  // beyond the further parts
+    const int2 wk = a.work[e];
+    tile_id = wk.x;
+    part = wk.y;
   }
+  int tcoord[3];
+  tcoord[0] = tile_id % a.nt[0];
+  tcoord[1] = (tile_id / a.nt[0]) % a.nt[1];
+  tcoord[2] = DIM == 3 ? tile_id / (a.nt[0] * a.nt[1]) : 0;
   // no point reaches this tile's block of x lines: those lines are neither read nor written
   if (!a.rowmask[tcoord[2] * a.nt[1] + tcoord[1]]) return;
+  const int nparts = a.tile_parts[tile_id];
   constexpr int tcells = kTileX * ROWS;
   int base[3] = {0, 0, 0};
   base[0] = tcoord[0] * kTileX;
@@ -156,22 +161,6 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   for (int r = 0; r < nrange; ++r) total += rlen[r];
   const int cbeg = part * kSplit;
   const int cend = total < cbeg + kSplit ? total : cbeg + kSplit;
-  if (total == 0) {  // no point reaches this tile, but some reach its lines: zeros
-    for (int i = tid; i < tcells; i += kSpreadThreads) {
-      const int lx = i % kTileX;
-      const int ly = (i / kTileX) % TY;
-      const int lz = DIM == 3 ? i / (kTileX * TY) : 0;
-      const int gz = DIM == 3 ? base[2] + lz : 0;
-      const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + ly) * a.nf[0] + base[0] + lx;
-      if (CPLX) {
-        reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = mk((T)0, (T)0);
-      } else {
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = (T)0;
-      }
-    }
-    return;
-  }
   const int row = tid % ROWS, xg = tid / ROWS;
   const int ly = row % TY, lz = DIM == 3 ? row / TY : 0;
   const int lane = tid & 63, wave = tid >> 6;
@@ -180,94 +169,71 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   for (int c = 0; c < CW; ++c)
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) acc[c][ch] = (T)0;
-  T(*wts)[DIM][W] = reinterpret_cast<T(*)[DIM][W]>(big);
 
   for (int c0 = cbeg; c0 < cend; c0 += kChunk) {
     const int cnt = cend - c0 < kChunk ? cend - c0 : kChunk;
-    // (1) kernel values per axis, support start relative to the tile, strengths
-    for (int it = tid; it < cnt * DIM; it += kSpreadThreads) {
-      const int pl = it / DIM, d = it - pl * DIM;
-      int vi = c0 + pl, r = 0;
-      while (vi >= rlen[r]) vi -= rlen[r++];
-      const int64_t pos = (int64_t)rbeg[r] + vi;
-      const T y = a.s_y[pos * DIM + d];
-      T v[W];
-#pragma unroll
-      for (int j = 0; j < W; ++j) v[j] = cf[a.deg * W + j];
-      for (int i = a.deg - 1; i >= 0; --i) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) v[j] = v[j] * y + cf[i * W + j];
+    // (1) wavefront d < DIM: axis d of the staged points, lane = point; wavefront DIM: strengths
+    {
+      const int pl = lane;
+      const bool valid = pl < cnt;
+      int64_t pos = 0;
+      if (valid) {
+        int vi = c0 + pl, r = 0;
+        while (vi >= rlen[r]) vi -= rlen[r++];
+        pos = (int64_t)rbeg[r] + vi;
       }
+      if (wave < DIM) {
+        const int d = wave;
+        const int nfd = a.nf[d];
+        int st = 0;
+        if (valid) {
+          const T y = a.s_y[pos * DIM + d];
+          T v[W];
 #pragma unroll
-      for (int j = 0; j < W; ++j) wts[pl][d][j] = v[j];
-      int st = unpack_i0<DIM>(a.s_i0[pos], d) - base[d];
-      if (st < 0) st += a.nf[d];
-      vstart[pl][d] = st;
-      if (d == 0) {
+          for (int j = 0; j < W; ++j) v[j] = cf[a.deg * W + j];
+          for (int i = a.deg - 1; i >= 0; --i) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) v[j] = v[j] * y + cf[i * W + j];
+          }
+          st = unpack_i0<DIM>(a.s_i0[pos], d) - base[d];  // support start relative to the tile
+          if (st < 0) st += nfd;
+          // kernel values expanded over the tile's coordinates along d (zero outside the support)
+          const int L = d == 0 ? kTileX : (d == 1 ? TY : TZ);
+          T* rowp = d == 0 ? &wxr[pl][0] : (d == 1 ? &wyr[pl][0] : &wzr[DIM == 3 ? pl : 0][0]);
+          for (int c = 0; c < L; ++c) rowp[c] = (T)0;
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            int c = st + j;
+            if (c >= nfd) c -= nfd;
+            if (c < L) rowp[c] = v[j];
+          }
+        }
+        // coverage sets of this axis' tile coordinates
+        if (d == 0) {
+          for (int g = 0; g < NXG; ++g) {
+            int off = g * CW - st;
+            if (off < 0) off += nfd;
+            int back = st - g * CW;
+            if (back < 0) back += nfd;
+            const unsigned long long bm = __ballot(valid && (off < W || back < CW));
+            if (lane == 0) msk[TY + (DIM == 3 ? TZ : 0) + g] = bm;
+          }
+        } else {
+          const int L = d == 1 ? TY : TZ;
+          for (int k = 0; k < L; ++k) {
+            int off = k - st;
+            if (off < 0) off += nfd;
+            const unsigned long long bm = __ballot(valid && off < W);
+            if (lane == 0) msk[(d == 1 ? 0 : TY) + k] = bm;
+          }
+        }
+      } else if (wave == DIM && valid) {
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) sv[pl][ch] = a.sstr[((int64_t)tr * a.M + pos) * NCH + ch];
       }
     }
     __syncthreads();
-    // (2) kernel values expanded over the tile's x, y, z coordinates; coverage sets by ballot
-    constexpr int EPP = kTileX + TY + (DIM == 3 ? TZ : 0);  // expanded entries per point
-    for (int e = tid; e < cnt * EPP; e += kSpreadThreads) {
-      const int pl = e / EPP, k = e - pl * EPP;
-      int d, c;
-      if (k < kTileX) {
-        d = 0;
-        c = k;
-      } else if (k < kTileX + TY) {
-        d = 1;
-        c = k - kTileX;
-      } else {
-        d = 2;
-        c = k - kTileX - TY;
-      }
-      int off = c - vstart[pl][d];
-      if (off < 0) off += a.nf[d];
-      const T val = off < W ? wts[pl][d][off] : (T)0;
-      if (d == 0)
-        wxr[pl][c] = val;
-      else if (d == 1)
-        wyr[pl][c] = val;
-      else
-        wzr[DIM == 3 ? pl : 0][c] = val;
-    }
-    {
-      int sx = 0, sy = 0, sz = 0;
-      if (lane < cnt) {
-        sx = vstart[lane][0];
-        sy = vstart[lane][1];
-        if (DIM == 3) sz = vstart[lane][2];
-      }
-      for (int k = wave; k < G::NMASK; k += kSpreadThreads / 64) {
-        bool hit = false;
-        if (lane < cnt) {
-          if (k < TY) {  // row coordinate y = k
-            int off = k - sy;
-            if (off < 0) off += a.nf[1];
-            hit = off < W;
-          } else if (DIM == 3 && k < TY + TZ) {  // z = k - TY
-            int off = k - TY - sz;
-            if (off < 0) off += a.nf[2];
-            hit = off < W;
-          } else {  // x group: cells [g CW, (g + 1) CW)
-            const int g = k - TY - (DIM == 3 ? TZ : 0);
-            int off = g * CW - sx;
-            if (off < 0) off += a.nf[0];
-            // covered when the support [sx, sx + W) meets the group (periodic distances)
-            int back = sx - g * CW;
-            if (back < 0) back += a.nf[0];
-            hit = off < W || back < CW;
-          }
-        }
-        const unsigned long long bm = __ballot(hit);
-        if (lane == 0) msk[k] = bm;
-      }
-    }
-    __syncthreads();
-    // (3) every lane walks the staged points that cover its cells
+    // (2) every lane walks the staged points that cover its cells
     unsigned long long m = msk[ly] & msk[TY + (DIM == 3 ? TZ : 0) + xg];
     if (DIM == 3) m &= msk[TY + lz];
     while (m) {
@@ -287,38 +253,28 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
     }
     __syncthreads();
   }
-  // the finished tile through LDS: [ch][row][x]
-  T(*outt)[ROWS][kTileX + 1] = reinterpret_cast<T(*)[ROWS][kTileX + 1]>(big);
-#pragma unroll
-  for (int c = 0; c < CW; ++c)
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) outt[ch][row][xg * CW + c] = acc[c][ch];
-  __syncthreads();
+  // each lane writes its CW cells (zeros when no point reaches the tile but some reach its lines)
   if (nparts > 1) {  // one part of a split tile: partial tile to scratch, summed by k_merge_tiles
     T* dst = a.scratch + ((int64_t)tr * a.slots + a.tile_slot[tile_id] + part) * NCH * kMaxTileCells;
-    for (int i = tid; i < tcells; i += kSpreadThreads) {
-      const int lx = i % kTileX;
-      const int rw = i / kTileX;
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) dst[ch * kMaxTileCells + i] = outt[ch][rw][lx];
-    }
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int c = 0; c < CW; ++c) dst[ch * kMaxTileCells + row * kTileX + xg * CW + c] = acc[c][ch];
     return;
   }
-  // write the tile once
-  for (int i = tid; i < tcells; i += kSpreadThreads) {
-    const int lx = i % kTileX;
-    const int rw = i / kTileX;
-    const int lyy = rw % TY;
-    const int lzz = DIM == 3 ? rw / TY : 0;
-    const int gz = DIM == 3 ? base[2] + lzz : 0;
-    const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + lyy) * a.nf[0] + base[0] + lx;
-    if (CPLX) {
-      reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = mk(outt[0][rw][lx], outt[1][rw][lx]);
-    } else {
+  const int gz = DIM == 3 ? base[2] + lz : 0;
+  const int64_t g = ((int64_t)gz * a.nf[1] + base[1] + ly) * a.nf[0] + base[0] + xg * CW;
+  if (CPLX) {
+    cplx<T>* dst = reinterpret_cast<cplx<T>*>(a.grid) + (int64_t)tr * cells + g;
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = outt[ch][rw][lx];
-    }
+    for (int c = 0; c < CW; ++c) dst[c] = mk(acc[c][0], acc[c][1]);
+  } else {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int c = 0; c < CW; ++c) a.grid[ch * cells + g + c] = acc[c][ch];
   }
+  (void)tcells;
 }
 
 // Strengths permuted into the sorted point order, so that the spreading stages read them contiguously.
@@ -351,13 +307,15 @@ __global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1,
   tile_parts[t] = total <= kSplit ? 1 : (total + kSplit - 1) / kSplit;
 }
 
-// Work list (tile, part) in tile order, and scratch slots for tiles split into several parts.
+// Work list of the further parts (tile, part >= 1) in tile order, and scratch slots for tiles split
+// into several parts.
 __global__ void k_fill_work(int nbins, const int* __restrict__ part_off, const int* __restrict__ tile_parts,
                             int2* __restrict__ work, int* __restrict__ tile_slot, int* __restrict__ slot_ctr) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nbins) return;
-  const int np = tile_parts[t], off = part_off[t];
-  for (int q = 0; q < np; ++q) work[off + q] = make_int2(t, q);
+  // parts 1.. of tile t: entries part_off[t] - t .. (parts before t, less one per tile)
+  const int np = tile_parts[t], off = part_off[t] - t;
+  for (int q = 1; q < np; ++q) work[off + q - 1] = make_int2(t, q);
   tile_slot[t] = np > 1 ? atomicAdd(slot_ctr, np) : -1;
 }
 
