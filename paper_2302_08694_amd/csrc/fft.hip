@@ -18,7 +18,16 @@
 
 namespace fsib {
 
-constexpr int kFlagBytes = 4096;  // >= lines (x passes: 2 * pairs) and entries (<= n) of a workgroup
+// Occupancy flags live in dynamic LDS after the lines and the twiddles: one byte per line of the
+// workgroup (x passes: 2 per pair) or per loaded entry (strided passes).
+template <typename T>
+__device__ __forceinline__ uint8_t* flag_area(cplx<T>* twl, int n) {
+  return reinterpret_cast<uint8_t*>(twl + n);
+}
+static size_t flag_bytes(int nflags) { return (size_t)((nflags + 15) / 16 * 16); }
+// workgroup size of the passes: 2048 complex entries in LDS (256 threads of kEPT entries) in both
+// precisions (measured at 128^3: 1024 or 4096 entries are slower in FP64, 4096 is slower in FP32)
+constexpr int kFftWgEntries = 2048;
 
 template <typename T, bool CONTIG>
 __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __restrict__ in,
@@ -30,7 +39,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
   stage_twiddles(a.tw, twl, n);
   // occupancy flags of this workgroup's rows (x passes) or of the entries it loads and stores
   // (strided passes), fetched once; the workgroup leaves when nothing it owns is reached by a point
-  __shared__ uint8_t fld[kFlagBytes];
+  uint8_t* fld = flag_area(twl, n);
   int64_t o0 = 0, q0 = 0;
   int ncol;
   int need = 0;
@@ -138,7 +147,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
   const int n = a.n, nb = a.nb, nthr = blockDim.x;
   cplx<T>* twl = buf + n * nb;
   const int64_t pair0 = (int64_t)blockIdx.x * nb;
-  __shared__ uint8_t fl[kFlagBytes];  // rows of this workgroup reached by a point
+  uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
   int need = 0;
   for (int b = threadIdx.x; b < 2 * nb; b += nthr) {
     const int64_t r = 2 * pair0 + b;
@@ -195,7 +204,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
   const int n = a.n, nb = a.nb, nthr = blockDim.x;
   cplx<T>* twl = buf + n * nb;
   const int64_t pair0 = (int64_t)blockIdx.x * nb;
-  __shared__ uint8_t fl[kFlagBytes];  // rows of this workgroup reached by a point
+  uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
   int need = 0;
   for (int b = threadIdx.x; b < 2 * nb; b += nthr) {
     const int64_t r = 2 * pair0 + b;
@@ -288,7 +297,7 @@ static int gcd_int(int a, int b) {
 // owns kEPT elements), preferring whole wavefronts; `cap` bounds nb (columns that exist).
 template <typename T>
 static int lines_per_block(int n, int64_t cap) {
-  const int budget = (int)(32768 / sizeof(cplx<T>));
+  const int budget = kFftWgEntries;
   const int step = kEPT / gcd_int(n, kEPT);  // nb multiple of step -> n*nb multiple of kEPT
   int nb = budget / n;
   if (cap > 0 && nb > cap) nb = (int)cap;
@@ -317,7 +326,7 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
   const bool contig = inner == 1;
   a.nb = lines_per_block<T>(n, contig ? outer : inner);
   const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(contig ? a.nb : nin);
   const bool prof = !contig && prof_on(p, PROF_FFT_STRIDED);
   if (prof) prof_start(p, st);
   if (contig)
@@ -355,7 +364,7 @@ static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int6
   const int64_t pairs = (rows + 1) / 2;
   a.nb = lines_per_block<T>(n, pairs);
   const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
   const bool prof = prof_on(p, PROF_FFT_X);
   if (prof) prof_start(p, st);
   hipLaunchKernelGGL(k_fft_r2c_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(nthr), lds, st, (const T*)in,
@@ -379,7 +388,7 @@ static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int6
   const int64_t pairs = (rows + 1) / 2;
   a.nb = lines_per_block<T>(n, pairs);
   const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>);
+  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
   const bool prof = prof_on(p, PROF_FFT_X);
   if (prof) prof_start(p, st);
   hipLaunchKernelGGL(k_fft_c2r_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(nthr), lds, st,

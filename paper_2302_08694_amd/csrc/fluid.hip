@@ -143,13 +143,18 @@ __global__ void k_force_curve(int64_t M, const double* __restrict__ X, double K,
 
 // Surface tension, Sec. 6.2.3: F_i = -(gamma/2) sum over incident triangles (i, j, k) (in the
 // triangle's cyclic order starting at i) of (X_j - X_k) x n, n the unit normal of (X_i, X_j, X_k).
-__global__ void k_force_surface(int64_t M, const double* __restrict__ X, double gamma, const int32_t* __restrict__ tris,
-                                const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
-                                double* __restrict__ F) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
+// One wavefront per vertex: lane l takes the incident triangles l, l + 64, ... of the vertex (a
+// polar fan vertex of a lat-long mesh has hundreds) and the lanes are summed by a fixed butterfly.
+__global__ __launch_bounds__(256) void k_force_surface(int64_t M, const double* __restrict__ X, double gamma,
+                                                       const int32_t* __restrict__ tris,
+                                                       const int32_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ idx, double* __restrict__ F) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= M) return;  // uniform per wavefront
   double f0 = 0, f1 = 0, f2 = 0;
-  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+  const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
+  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 64) {
     const int t = idx[e];
     const int v0 = tris[3 * t], v1 = tris[3 * t + 1], v2 = tris[3 * t + 2];
     int j, k;
@@ -163,8 +168,8 @@ __global__ void k_force_surface(int64_t M, const double* __restrict__ X, double 
       j = v0;
       k = v1;
     }
-    const double ax = X[3 * j] - X[3 * i], ay = X[3 * j + 1] - X[3 * i + 1], az = X[3 * j + 2] - X[3 * i + 2];
-    const double bx = X[3 * k] - X[3 * i], by = X[3 * k + 1] - X[3 * i + 1], bz = X[3 * k + 2] - X[3 * i + 2];
+    const double ax = X[3 * j] - xi, ay = X[3 * j + 1] - yi, az = X[3 * j + 2] - zi;
+    const double bx = X[3 * k] - xi, by = X[3 * k + 1] - yi, bz = X[3 * k + 2] - zi;
     double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
     const double nn = sqrt(nx * nx + ny * ny + nz * nz);
     if (nn > 0) {
@@ -177,9 +182,17 @@ __global__ void k_force_surface(int64_t M, const double* __restrict__ X, double 
     f1 += dz * nx - dx * nz;
     f2 += dx * ny - dy * nx;
   }
-  F[3 * i] = -0.5 * gamma * f0;
-  F[3 * i + 1] = -0.5 * gamma * f1;
-  F[3 * i + 2] = -0.5 * gamma * f2;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    f0 += __shfl_xor(f0, off, 64);
+    f1 += __shfl_xor(f1, off, 64);
+    f2 += __shfl_xor(f2, off, 64);
+  }
+  if (lane == 0) {
+    F[3 * i] = -0.5 * gamma * f0;
+    F[3 * i + 1] = -0.5 * gamma * f1;
+    F[3 * i + 2] = -0.5 * gamma * f2;
+  }
 }
 
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F, hipStream_t st) {
@@ -188,7 +201,8 @@ hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X
   if (f.kind == FSIB_FORCE_CURVE_TENSION)
     hipLaunchKernelGGL(k_force_curve, dim3(nblk), dim3(256), 0, st, M, X, f.K, F);
   else
-    hipLaunchKernelGGL(k_force_surface, dim3(nblk), dim3(256), 0, st, M, X, f.K, f.tris, f.v2t_ptr, f.v2t_idx, F);
+    hipLaunchKernelGGL(k_force_surface, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, M, X, f.K, f.tris, f.v2t_ptr,
+                       f.v2t_idx, F);  // four vertices (wavefronts) per workgroup
   return hipGetLastError();
 }
 

@@ -148,8 +148,9 @@ static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t 
   a.nb = 0;
   const int64_t rows = p.dim == 3 ? p.nd[2] * p.nd[1] : p.nd[1];
   const int fl = p.dim == 3 ? 6 : 3;
-  // row pairs per workgroup: the forward lines fit 36 KiB of LDS and 1024 threads
-  int pp = (int)(36864 / ((size_t)fl * n * sizeof(cplx<T>)));
+  // row pairs per workgroup: the forward lines fit 2304 complex entries (36 KiB in FP64) and 1024
+  // threads
+  int pp = (int)(2304 / ((size_t)fl * n));
   if (pp < 1) pp = 1;
   while (pp > 1 && (fl * pp * n + kEPT - 1) / kEPT > 1024) --pp;
   const int64_t pairs = (rows + 1) / 2;

@@ -81,13 +81,13 @@ __global__ void k_bin_count(int64_t M, const double* __restrict__ X, Geo g, int*
 }
 
 // Exclusive scan of counts[0..n) into offsets[0..n] (offsets[n] = total).  Segments of
-// kScanSeg = 1024 threads x kScanEpt consecutive entries: each thread loads its run of kScanEpt
+// kScanSeg = 1024 threads x kScanEpt (32) consecutive entries: each thread loads its run of kScanEpt
 // entries at once, the runs' sums are scanned across the workgroup (wavefront shuffles, then the
 // wavefront totals), and each thread writes its run.  With more than one segment, a first launch
 // stores the segment sums and a second one scans every segment after the sum of the segments
 // before it.
 constexpr int kScanThreads = 1024;
-constexpr int kScanEpt = 16;
+constexpr int kScanEpt = 32;
 constexpr int64_t kScanSeg = (int64_t)kScanThreads * kScanEpt;
 
 // exclusive prefix of v over the workgroup; *total = sum over the workgroup
