@@ -29,12 +29,14 @@ static size_t flag_bytes(int nflags) { return (size_t)((nflags + 15) / 16 * 16);
 // precisions (measured at 128^3: 1024 or 4096 entries are slower in FP64, 4096 is slower in FP32)
 constexpr int kFftWgEntries = 2048;
 
-template <typename T, bool CONTIG>
+// N > 0: a pass of length N with NB lines per workgroup known at compile time (N * NB / kEPT
+// threads); N = 0: any length, from the arguments.
+template <typename T, bool CONTIG, int N = 0, int NB = 0>
 __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __restrict__ in,
                                                             cplx<T>* __restrict__ out, FftArgs<T> a) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int n = a.n, nb = a.nb, nthr = blockDim.x;
+  const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
   cplx<T>* twl = buf + n * nb;
   stage_twiddles(a.tw, twl, n);
   // occupancy flags of this workgroup's rows (x passes) or of the entries it loads and stores
@@ -114,7 +116,10 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
     if (!CONTIG && a.st.m && e < nstore) sf[j] = a.st.m[mask_index(a.st, o0, e / nb)] != 0;
   }
   __syncthreads();
-  stockham<T, CONTIG>(a, buf, twl, a.nb, a.sign);
+  if constexpr (N > 0)
+    stockham_ct<T, CONTIG, N, NB>(buf, twl, a.sign);
+  else
+    stockham<T, CONTIG>(a, buf, twl, a.nb, a.sign);
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
     const int e = threadIdx.x + j * nthr;
@@ -329,12 +334,31 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
   const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(contig ? a.nb : nin);
   const bool prof = !contig && prof_on(p, PROF_FFT_STRIDED);
   if (prof) prof_start(p, st);
-  if (contig)
-    hipLaunchKernelGGL((k_fft_c2c<T, true>), dim3((unsigned)((outer + a.nb - 1) / a.nb)), dim3(nthr), lds, st,
-                       (const cplx<T>*)in, (cplx<T>*)out, a);
-  else
-    hipLaunchKernelGGL((k_fft_c2c<T, false>), dim3((unsigned)((inner + a.nb - 1) / a.nb), (unsigned)outer), dim3(nthr),
-                       lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
+  const dim3 grid = contig ? dim3((unsigned)((outer + a.nb - 1) / a.nb))
+                           : dim3((unsigned)((inner + a.nb - 1) / a.nb), (unsigned)outer);
+  // lengths with compile-time specialisations (when the line count is the standard one for n)
+#define FSIB_C2C_CT(N_, NB_)                                                                               \
+  if (n == N_ && a.nb == NB_) {                                                                           \
+    if (contig)                                                                                           \
+      hipLaunchKernelGGL((k_fft_c2c<T, true, N_, NB_>), grid, dim3(nthr), lds, st, (const cplx<T>*)in,   \
+                         (cplx<T>*)out, a);                                                               \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_fft_c2c<T, false, N_, NB_>), grid, dim3(nthr), lds, st, (const cplx<T>*)in,  \
+                         (cplx<T>*)out, a);                                                               \
+  } else
+  FSIB_C2C_CT(64, 32)
+  FSIB_C2C_CT(96, 16)
+  FSIB_C2C_CT(128, 16)
+  FSIB_C2C_CT(192, 8)
+  FSIB_C2C_CT(256, 8)
+  FSIB_C2C_CT(384, 4)
+  FSIB_C2C_CT(512, 4) {
+    if (contig)
+      hipLaunchKernelGGL((k_fft_c2c<T, true>), grid, dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
+    else
+      hipLaunchKernelGGL((k_fft_c2c<T, false>), grid, dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
+  }
+#undef FSIB_C2C_CT
   // algorithmic bytes: every input entry read once, every output entry written once
   if (prof) prof_stop(p, (double)(nin + nout) * inner * outer * sizeof(cplx<T>), st);
   return hipGetLastError();

@@ -155,4 +155,96 @@ __device__ __forceinline__ void stockham(const FftArgs<T>& a, cplx<T>* buf, cons
   }
 }
 
+// ---- the same stages with the length and the line count known at compile time ----
+// For the lengths of the hot passes the index arithmetic of every stage (divisions by the line
+// count, the butterfly count and the twiddle stride) folds into shifts and constant multiplies.
+// The radix order is the host's (8s, then 4, 2, 3, 5).
+constexpr int kCtRadices[5] = {8, 4, 2, 3, 5};
+constexpr int ct_nstages(int n) {
+  int m = n, k = 0;
+  for (int r = 0; r < 5; ++r)
+    while (m % kCtRadices[r] == 0) {
+      m /= kCtRadices[r];
+      ++k;
+    }
+  return m == 1 ? k : -1;
+}
+constexpr int ct_radix_at(int n, int s) {
+  int m = n, k = 0;
+  for (int r = 0; r < 5; ++r)
+    while (m % kCtRadices[r] == 0) {
+      if (k == s) return kCtRadices[r];
+      m /= kCtRadices[r];
+      ++k;
+    }
+  return 1;
+}
+constexpr int ct_p_before(int n, int s) {
+  int p = 1;
+  for (int t = 0; t < s; ++t) p *= ct_radix_at(n, t);
+  return p;
+}
+
+template <typename T, bool CONTIG, int N, int NB, int R, int P>
+__device__ __forceinline__ void stage_ct(cplx<T>* buf, const cplx<T>* twl, int sign) {
+  constexpr int M = N / R;
+  constexpr int TOTAL = M * NB;
+  constexpr int NTHR = N * NB / kEPT;  // blockDim.x of the specialised passes
+  constexpr int NBF = (TOTAL + NTHR - 1) / NTHR;
+  constexpr int TWS = N / (P * R);
+  const T sg = (T)sign;
+  cplx<T> u[NBF][R];
+  int ii[NBF], bb[NBF];
+#pragma unroll
+  for (int j = 0; j < NBF; ++j) {
+    const int bf = threadIdx.x + j * NTHR;
+    ii[j] = -1;
+    bb[j] = 0;
+    if (TOTAL % NTHR == 0 || bf < TOTAL) {
+      int i, b;
+      if (CONTIG) {
+        b = bf / M;
+        i = bf - b * M;
+      } else {
+        i = bf / NB;
+        b = bf - i * NB;
+      }
+      ii[j] = i;
+      bb[j] = b;
+#pragma unroll
+      for (int q = 0; q < R; ++q) u[j][q] = buf[lidx<CONTIG>(i + q * M, b, N, NB)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NBF; ++j) {
+    const int i = ii[j];
+    if (TOTAL % NTHR == 0 || i >= 0) {
+      const int b = bb[j];
+      const int k = i % P;
+      if (P > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          cplx<T> w = twl[q * k * TWS];
+          if (sign > 0) w.y = -w.y;
+          u[j][q] = cmul(u[j][q], w);
+        }
+      }
+      bfly<T, R>(u[j], sg);
+      const int j0 = (i - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[lidx<CONTIG>(j0 + q * P, b, N, NB)] = u[j][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, bool CONTIG, int N, int NB, int S = 0>
+__device__ __forceinline__ void stockham_ct(cplx<T>* buf, const cplx<T>* twl, int sign) {
+  if constexpr (S < ct_nstages(N)) {
+    stage_ct<T, CONTIG, N, NB, ct_radix_at(N, S), ct_p_before(N, S)>(buf, twl, sign);
+    stockham_ct<T, CONTIG, N, NB, S + 1>(buf, twl, sign);
+  }
+}
+
 }  // namespace fsib
