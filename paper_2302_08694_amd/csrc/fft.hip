@@ -144,12 +144,12 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
 
 // Real lines along x -> half spectra: lines 2b and 2b+1 form z = a + i b; A_m = (Z_m + conj Z_{n-m})/2,
 // B_m = (Z_m - conj Z_{n-m})/(2i) for m < nout.  a.outer = number of real lines, a.nb = pairs per block.
-template <typename T>
+template <typename T, int N = 0, int NB = 0>
 __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restrict__ in, cplx<T>* __restrict__ out,
                                                               FftArgs<T> a) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int n = a.n, nb = a.nb, nthr = blockDim.x;
+  const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
   cplx<T>* twl = buf + n * nb;
   const int64_t pair0 = (int64_t)blockIdx.x * nb;
   uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
@@ -180,7 +180,10 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
     if (e < n * nb) buf[e] = v[j];  // [b][t] layout: e = b*n + t
   }
   __syncthreads();
-  stockham<T, true>(a, buf, twl, a.nb, a.sign);
+  if constexpr (N > 0)
+    stockham_ct<T, true, N, NB>(buf, twl, a.sign);
+  else
+    stockham<T, true>(a, buf, twl, a.nb, a.sign);
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
     const int e = threadIdx.x + j * nthr;
@@ -201,12 +204,12 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
 // Half spectra along x (nin entries m = 0..nin-1, the rest zero) -> real lines of length n; two
 // lines per complex transform: Z_t = A_t + i B_t with A_{n-m} = conj A_m, then Re/Im of the
 // inverse transform.  a.outer = number of real lines, a.nb = pairs per block.
-template <typename T>
+template <typename T, int N = 0, int NB = 0>
 __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __restrict__ in, T* __restrict__ out,
                                                               FftArgs<T> a) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int n = a.n, nb = a.nb, nthr = blockDim.x;
+  const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
   cplx<T>* twl = buf + n * nb;
   const int64_t pair0 = (int64_t)blockIdx.x * nb;
   uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
@@ -259,7 +262,10 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
     }
   }
   __syncthreads();
-  stockham<T, true>(a, buf, twl, a.nb, a.sign);
+  if constexpr (N > 0)
+    stockham_ct<T, true, N, NB>(buf, twl, a.sign);
+  else
+    stockham<T, true>(a, buf, twl, a.nb, a.sign);
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
     const int e = threadIdx.x + j * nthr;
@@ -391,8 +397,20 @@ static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int6
   const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
   const bool prof = prof_on(p, PROF_FFT_X);
   if (prof) prof_start(p, st);
-  hipLaunchKernelGGL(k_fft_r2c_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(nthr), lds, st, (const T*)in,
-                     (cplx<T>*)out, a);
+  const dim3 grid((unsigned)((pairs + a.nb - 1) / a.nb));
+#define FSIB_R2C_CT(N_, NB_)                                                                                   \
+  if (n == N_ && a.nb == NB_)                                                                                 \
+    hipLaunchKernelGGL((k_fft_r2c_x<T, N_, NB_>), grid, dim3(nthr), lds, st, (const T*)in, (cplx<T>*)out, a); \
+  else
+  FSIB_R2C_CT(64, 32)
+  FSIB_R2C_CT(96, 16)
+  FSIB_R2C_CT(128, 16)
+  FSIB_R2C_CT(192, 8)
+  FSIB_R2C_CT(256, 8)
+  FSIB_R2C_CT(384, 4)
+  FSIB_R2C_CT(512, 4)
+  hipLaunchKernelGGL(k_fft_r2c_x<T>, grid, dim3(nthr), lds, st, (const T*)in, (cplx<T>*)out, a);
+#undef FSIB_R2C_CT
   if (prof) prof_stop(p, (double)rows * (n * sizeof(T) + nout * sizeof(cplx<T>)), st);
   return hipGetLastError();
 }
@@ -415,8 +433,20 @@ static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int6
   const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
   const bool prof = prof_on(p, PROF_FFT_X);
   if (prof) prof_start(p, st);
-  hipLaunchKernelGGL(k_fft_c2r_x<T>, dim3((unsigned)((pairs + a.nb - 1) / a.nb)), dim3(nthr), lds, st,
-                     (const cplx<T>*)in, (T*)out, a);
+  const dim3 grid((unsigned)((pairs + a.nb - 1) / a.nb));
+#define FSIB_C2R_CT(N_, NB_)                                                                                   \
+  if (n == N_ && a.nb == NB_)                                                                                 \
+    hipLaunchKernelGGL((k_fft_c2r_x<T, N_, NB_>), grid, dim3(nthr), lds, st, (const cplx<T>*)in, (T*)out, a); \
+  else
+  FSIB_C2R_CT(64, 32)
+  FSIB_C2R_CT(96, 16)
+  FSIB_C2R_CT(128, 16)
+  FSIB_C2R_CT(192, 8)
+  FSIB_C2R_CT(256, 8)
+  FSIB_C2R_CT(384, 4)
+  FSIB_C2R_CT(512, 4)
+  hipLaunchKernelGGL(k_fft_c2r_x<T>, grid, dim3(nthr), lds, st, (const cplx<T>*)in, (T*)out, a);
+#undef FSIB_C2R_CT
   if (prof) prof_stop(p, (double)rows * (nin * sizeof(cplx<T>) + n * sizeof(T)), st);
   return hipGetLastError();
 }

@@ -185,11 +185,12 @@ constexpr int ct_p_before(int n, int s) {
   return p;
 }
 
-template <typename T, bool CONTIG, int N, int NB, int R, int P>
+// NTHR = blockDim.x (N * NB / kEPT for the passes; the fused nonlinear kernel runs fewer lines
+// than threads in its inverse half)
+template <typename T, bool CONTIG, int N, int NB, int NTHR, int R, int P>
 __device__ __forceinline__ void stage_ct(cplx<T>* buf, const cplx<T>* twl, int sign) {
   constexpr int M = N / R;
   constexpr int TOTAL = M * NB;
-  constexpr int NTHR = N * NB / kEPT;  // blockDim.x of the specialised passes
   constexpr int NBF = (TOTAL + NTHR - 1) / NTHR;
   constexpr int TWS = N / (P * R);
   const T sg = (T)sign;
@@ -239,11 +240,11 @@ __device__ __forceinline__ void stage_ct(cplx<T>* buf, const cplx<T>* twl, int s
   __syncthreads();
 }
 
-template <typename T, bool CONTIG, int N, int NB, int S = 0>
+template <typename T, bool CONTIG, int N, int NB, int NTHR = N * NB / kEPT, int S = 0>
 __device__ __forceinline__ void stockham_ct(cplx<T>* buf, const cplx<T>* twl, int sign) {
   if constexpr (S < ct_nstages(N)) {
-    stage_ct<T, CONTIG, N, NB, ct_radix_at(N, S), ct_p_before(N, S)>(buf, twl, sign);
-    stockham_ct<T, CONTIG, N, NB, S + 1>(buf, twl, sign);
+    stage_ct<T, CONTIG, N, NB, NTHR, ct_radix_at(N, S), ct_p_before(N, S)>(buf, twl, sign);
+    stockham_ct<T, CONTIG, N, NB, NTHR, S + 1>(buf, twl, sign);
   }
 }
 

@@ -13,14 +13,16 @@
 
 namespace fsib {
 
-template <typename T, int DIM>
+// N > 0: length N and PP row pairs per workgroup known at compile time; N = 0: from the arguments.
+template <typename T, int DIM, int N = 0, int PP = 0>
 __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                                   FftArgs<T> a, int64_t rows, int hx, int pp, T inv_cells) {
+                                                   FftArgs<T> a, int64_t rows, int hx, int pp_arg, T inv_cells) {
   constexpr int IL = DIM == 3 ? 3 : 2;  // inverse lines per row pair
   constexpr int FL = DIM == 3 ? 6 : 3;  // forward lines per row pair (products)
+  constexpr int NTHR = (FL * PP * N + kEPT - 1) / kEPT;
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int n = a.n, nthr = blockDim.x;
+  const int n = N > 0 ? N : a.n, nthr = N > 0 ? NTHR : (int)blockDim.x, pp = N > 0 ? PP : pp_arg;
   cplx<T>* twl = buf + FL * pp * n;
   stage_twiddles(a.tw, twl, n);
   const int64_t pair0 = (int64_t)blockIdx.x * pp;
@@ -73,7 +75,10 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
     }
   }
   __syncthreads();
-  stockham<T, true>(a, buf, twl, IL * pp, +1);
+  if constexpr (N > 0)
+    stockham_ct<T, true, N, IL * PP, NTHR>(buf, twl, +1);
+  else
+    stockham<T, true>(a, buf, twl, IL * pp, +1);
   // ---- products, packed two rows per complex line: line (q, f) = prod_f(row a) + i prod_f(row b) ----
   constexpr int PPT = (kEPT + FL - 1) / FL;  // (pair, t) positions per thread
   T pa[PPT][FL], pb[PPT][FL];
@@ -110,7 +115,10 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
     }
   }
   __syncthreads();
-  stockham<T, true>(a, buf, twl, FL * pp, -1);
+  if constexpr (N > 0)
+    stockham_ct<T, true, N, FL * PP, NTHR>(buf, twl, -1);
+  else
+    stockham<T, true>(a, buf, twl, FL * pp, -1);
   // ---- unpack the two rows of each line, keep m < Hx ----
   const int nst = FL * pp * hx;
   for (int e = threadIdx.x; e < nst; e += nthr) {
@@ -161,7 +169,16 @@ static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t 
   const T inv = (T)(1.0 / (double)p.dealias_cells());
   const bool prof = prof_on(p, PROF_NL_X);
   if (prof) prof_start(p, st);
-  if (p.dim == 3)
+  if (p.dim == 3 && n == 192 && pp == 2)
+    hipLaunchKernelGGL((k_nl_xpass<T, 3, 192, 2>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out,
+                       a, rows, (int)p.Hx, pp, inv);
+  else if (p.dim == 3 && n == 96 && pp == 4)
+    hipLaunchKernelGGL((k_nl_xpass<T, 3, 96, 4>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out,
+                       a, rows, (int)p.Hx, pp, inv);
+  else if (p.dim == 3 && n == 384 && pp == 1)
+    hipLaunchKernelGGL((k_nl_xpass<T, 3, 384, 1>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out,
+                       a, rows, (int)p.Hx, pp, inv);
+  else if (p.dim == 3)
     hipLaunchKernelGGL((k_nl_xpass<T, 3>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a, rows,
                        (int)p.Hx, pp, inv);
   else
