@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--rings", type=int, default=200)
     ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 form and the NUFFT timings")
     ap.add_argument("--no-nufft-micro", action="store_true", help="skip the NUFFT micro-benchmark legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 2D Stokes leg")
     ap.add_argument("--nufft-only", action="store_true", help="run only the NUFFT micro-benchmark legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (reference for hardware byte counters)")
@@ -192,6 +193,47 @@ def time_nufft_micro(F, torch, N, M, prec, tol, reps=10):
     plan.close()
     del X, c, fh, out1, out2
     torch.cuda.empty_cache()
+    return res
+
+
+def batched_stokes(F, torch, steps=50, graph_steps=10):
+    """64 independent 2D Stokes instances (uneven N and M), FP32 batched under a HIP graph, against
+    the same batch launched eagerly and the plain FP64 path; instance-steps per second.  The stream
+    count of each batch is picked by the batch's autotuner from timed probes."""
+    import workloads
+    from paper_2302_08694_amd.batch import StokesBatch
+    cases = workloads.batched_stokes2d(count=64, seed=4)
+    res = {"instances": len(cases), "steps": steps, "points": int(sum(c["X"].shape[0] for c in cases)),
+           "n_modes": sorted(set(int(c["N"][0]) for c in cases))}
+    finals = {}
+    for prec, tol in (("f32", 1e-5), ("f64", 1e-5)):
+        b = StokesBatch(cases, prec=prec, tol=tol)
+        tune = b.autotune()
+        res[f"{prec}_streams"] = len(b.streams)
+        res[f"{prec}_autotune_ms_per_batch_step"] = {str(k): v * 1e3 for k, v in tune.items()}
+        b.step(1)
+        b.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t0
+        res[f"{prec}_eager_instance_steps_per_s"] = len(cases) * steps / te
+        if prec == "f32":
+            b.reset()
+            b.capture(graph_steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps // graph_steps):
+                b.replay()
+            torch.cuda.synchronize()
+            tg = time.perf_counter() - t0
+            res["f32_graph_instance_steps_per_s"] = len(cases) * steps / tg
+        finals[prec] = [(it["X"].cpu().numpy(), it["X0"].cpu().numpy()) for it in b.items]
+        b.close()
+    num = sum(float(np.sum((x32 - x64) ** 2)) for (x32, _), (x64, _) in zip(finals["f32"], finals["f64"]))
+    den = sum(float(np.sum((x64 - x0) ** 2)) for (x64, x0) in finals["f64"])
+    res["f32_rel_err_displacement_vs_f64"] = (num / max(den, 1e-300)) ** 0.5
     return res
 
 
@@ -356,6 +398,10 @@ def main():
     }
     if not a.no_nufft_micro:
         out["nufft_micro"] = nufft_micro(F, torch)
+    if not a.no_batch:
+        log("batched 2D Stokes (64 instances)")
+        out["batched_2d_stokes"] = batched_stokes(F, torch)
+        log(f"  {out['batched_2d_stokes']}")
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.n, a.rings)

@@ -1,0 +1,105 @@
+"""Many independent 2D Stokes FSIB simulations advanced together.
+
+Each instance has its own plan (its own N, M and workspace); a step of the batch is one fsib_step
+per instance.  Instances are spread over `streams` HIP streams forked from the current one (and
+joined back after each batch step), so the small kernels of different instances run concurrently
+on the chip's XCDs.  `capture(steps)` records `steps` batch steps into one HIP graph
+(torch.cuda.CUDAGraph on ROCm; the stream fork/join becomes parallel branches of the graph), so a
+replay launches every kernel of every instance with no host work in between.  The library calls
+allocate nothing and synchronise nothing while stepping, so they are capturable as they are.
+Streams keep the default priority.
+"""
+
+import torch
+
+from ._binding import FluidParams, Force, Plan
+
+
+class StokesBatch:
+    def __init__(self, cases, prec="f32", tol=1e-5, device="cuda", streams=8):
+        self.prec = prec
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, streams))]
+        self.items = []
+        for c in cases:
+            X0 = torch.as_tensor(c["X"], dtype=torch.float64, device=device).contiguous()
+            M = X0.shape[0]
+            plan = Plan(2, c["N"], L=c.get("L", 1.0), prec=prec, tol=tol, max_points=M, fluid=True)
+            params = FluidParams("stokes", mu=c["mu"], dt=c["dt"])
+            force = Force("tension2d", c["K"])
+            uh = torch.zeros((2,) + plan.half_shape, dtype=plan.cdtype, device=device)
+            U = plan.velocity(params, force, X0, uh)  # U^0 = U(X^0)
+            self.items.append(dict(plan=plan, params=params, force=force, X=X0.clone(), U=U, uh=uh,
+                                   X0=X0, U0=U.clone(), uh0=uh.clone(), M=M))
+        self.graph = None
+        self.graph_steps = 0
+
+    def reset(self):
+        for it in self.items:
+            it["X"].copy_(it["X0"])
+            it["U"].copy_(it["U0"])
+            it["uh"].copy_(it["uh0"])
+
+    def step(self, n=1):
+        main = torch.cuda.current_stream()
+        for _ in range(n):
+            for s in self.streams:
+                s.wait_stream(main)
+            for i, it in enumerate(self.items):
+                with torch.cuda.stream(self.streams[i % len(self.streams)]):
+                    it["plan"].step(it["params"], it["force"], it["X"], it["U"], it["uh"])
+            for s in self.streams:
+                main.wait_stream(s)
+
+    def autotune(self, candidates=(1, 4, 8, 16), steps=2):
+        """Pick the stream count by timing `steps` eager batch steps per candidate (the state is
+        restored afterwards); returns {candidate: seconds per batch step}."""
+        import time
+        saved = [(it["X"].clone(), it["U"].clone(), it["uh"].clone()) for it in self.items]
+        times = {}
+        for c in candidates:
+            self.streams = [torch.cuda.Stream() for _ in range(c)]
+            self.step(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            self.step(steps)
+            torch.cuda.synchronize()
+            times[c] = (time.perf_counter() - t0) / steps
+        best = min(times, key=times.get)
+        self.streams = [torch.cuda.Stream() for _ in range(best)]
+        for it, (X, U, uh) in zip(self.items, saved):
+            it["X"].copy_(X)
+            it["U"].copy_(U)
+            it["uh"].copy_(uh)
+        torch.cuda.synchronize()
+        return times
+
+    def capture(self, steps):
+        """Record `steps` batch steps into a graph; the state is left as it was."""
+        saved = [(it["X"].clone(), it["U"].clone(), it["uh"].clone()) for it in self.items]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):  # warm-up outside the capture
+            self.step(1)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(steps)
+        for it, (X, U, uh) in zip(self.items, saved):
+            it["X"].copy_(X)
+            it["U"].copy_(U)
+            it["uh"].copy_(uh)
+        torch.cuda.synchronize()
+        self.graph, self.graph_steps = g, steps
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def close(self):
+        self.graph = None
+        for it in self.items:
+            it["plan"].close()
+        self.items = []

@@ -159,3 +159,14 @@ def test_divergence_free_and_area_conserved_continuous_limit():
         X, U, uh = step.ns_step(X, U, uh, force, Ns, L, rho, mu, dt)
     assert diagnostics.divergence_residual(uh, Ns, L) < 1e-13
     assert abs(diagnostics.enclosed_area(X) - A0) < 1e-7 * A0
+
+
+def test_batched_stokes2d_workload_is_seeded():
+    import workloads
+    a = workloads.batched_stokes2d(count=64, seed=4)
+    b = workloads.batched_stokes2d(count=64, seed=4)
+    assert len(a) == 64
+    for x, y in zip(a, b):
+        assert x["N"] == y["N"] and np.array_equal(x["X"], y["X"])
+        assert x["N"][0] in (64, 128, 256, 512)
+        assert 256 <= x["X"].shape[0] <= 8192

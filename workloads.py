@@ -83,6 +83,23 @@ def stokes2d_case(seed=1, M=128, N=32):
                 force="tension2d")
 
 
+def batched_stokes2d(count=64, seed=4, sizes=(64, 128, 256, 512), m_range=(256, 8192)):
+    """Independent 2D Stokes instances: N_i from `sizes`, M_i log-uniform in m_range, ellipses of
+    semi-major axis 0.3 and aspect ratio U[1, 3] with a random centre and rotation; K = 1, mu = 1,
+    dt = 1e-3.  Draw order per instance: N, M, aspect, centre (2), rotation."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for _ in range(count):
+        n = int(rng.choice(sizes))
+        m = int(np.floor(np.exp(rng.uniform(np.log(m_range[0]), np.log(m_range[1])))))
+        aspect = rng.uniform(1.0, 3.0)
+        c = rng.random(2)
+        rot = rng.uniform(0.0, np.pi)
+        X = ellipse_2d(m, center=c, a=0.3, b=0.3 / aspect, rotation=rot)
+        cases.append(dict(X=X, N=(n, n), L=1.0, K=1.0, mu=1.0, dt=1e-3, force="tension2d"))
+    return cases
+
+
 def ns3d_case(n_rings=200, n_lon=200, N=128):
     """3D Navier-Stokes: sphere of radius 0.25 stretched by (1.2, 1, 0.8) about (1/2,1/2,1/2);
     surface tension K = 1, rho = 1, mu = 0.01, dt = 5e-4, uhat^0 = 0."""
