@@ -174,3 +174,58 @@ def type2_bruteforce(X, fhat, Ns, L=1.0):
             acc += f[q] * np.exp(1j * float(np.dot(K[q], X[j])))
         out[j] = acc
     return out
+
+
+# ---- gradients of the sums (for the adjoint of the transforms) ----
+#
+# Convention: for a real loss L and complex arrays, the gradient is dL/dRe + i dL/dIm (the
+# conjugate-Wirtinger convention of torch.autograd); positions are real.  For a linear map the
+# gradient of the input is the adjoint applied to the gradient of the output.
+
+
+def _ik_weighted(f, Ns, L, axis):
+    """i k_axis f(k) on the FFT-ordered spectrum (physical axis `axis`)."""
+    shp = spectral_shape(Ns)
+    d = len(Ns)
+    k = (2.0 * np.pi / L) * mode_numbers(Ns[axis]).astype(np.float64)
+    bshape = [1] * d
+    bshape[d - 1 - axis] = Ns[axis]
+    f = np.asarray(f, dtype=np.complex128)
+    return f * (1j * k.reshape(bshape)) if f.shape == shp else f * (1j * k.reshape([1] + bshape))
+
+
+def type1_grad(X, c, g, Ns, L=1.0, scale=1.0):
+    """Gradients of type1 given the output gradient g (same shape as the output).
+
+    grad_c_j = scale * sum_k g(k) exp(+i k.x_j)                        (the adjoint: a type-2 sum)
+    grad_X[j, a] = Re( scale * c_j * conj( sum_k i k_a g(k) exp(+i k.x_j) ) )
+    (the phase derivative d/dx_a exp(-i k.x) = -i k_a exp(-i k.x)).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    M, d = X.shape
+    c, single = _as_trans(c, M)
+    g = np.asarray(g, dtype=np.complex128).reshape((c.shape[0],) + spectral_shape(Ns))
+    gc = scale * type2(X, g, Ns, L)
+    gX = np.zeros((M, d))
+    for a in range(d):
+        h = type2(X, _ik_weighted(g, Ns, L, a), Ns, L)
+        gX[:, a] = np.sum(np.real(scale * c * np.conj(h)), axis=0)
+    return (gc[0] if single else gc), gX
+
+
+def type2_grad(X, fhat, g, Ns, L=1.0):
+    """Gradients of type2 given the output gradient g ((M,) or (T, M)).
+
+    grad_fhat(k) = sum_j g_j exp(-i k.x_j)                             (the adjoint: a type-1 sum)
+    grad_X[j, a] = Re( conj(g_j) * sum_k i k_a fhat(k) exp(+i k.x_j) )
+    """
+    X = np.asarray(X, dtype=np.float64)
+    M, d = X.shape
+    g, single = _as_trans(g, M)
+    f = np.asarray(fhat, dtype=np.complex128).reshape((g.shape[0],) + spectral_shape(Ns))
+    gf = type1(X, g, Ns, L)
+    gX = np.zeros((M, d))
+    for a in range(d):
+        dv = type2(X, _ik_weighted(f, Ns, L, a), Ns, L)
+        gX[:, a] = np.sum(np.real(np.conj(g) * dv), axis=0)
+    return (gf[0] if single else gf), gX
