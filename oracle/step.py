@@ -95,3 +95,30 @@ def ns_step(X, U, uhat, force, Ns, L, rho, mu, dt, npad=None, return_mid=False):
     if return_mid:
         return Xn, Un, un, dict(Xh=Xh, F=F, w=w, fhat=fhat, uhat_half=uh, U_half=Uh)
     return Xn, Un, un
+
+
+def stokes_map(X, S, Ns, L, mu):
+    """Velocity at X of point strengths S (M, d) at X: U = interp(Stokeslet(spread(S)), X), Nyquist
+    modes zeroed (Sec. 6.1 with the strengths given instead of a force law).  Returns (U, uhat)."""
+    uhat = fluid.stokeslet(spread_force(X, S, 1.0, Ns, L), Ns, L, mu)
+    uhat[:, nyquist_mask(Ns)] = 0.0
+    return interp_velocity(X, uhat, Ns, L), uhat
+
+
+def stokes_map_grad(X, S, GU, Ns, L, mu):
+    """Gradients of a loss of U = stokes_map(X, S) given GU = dL/dU.
+
+    U_j = sum_l K(X_j - X_l) S_l with K(r) = L^-d sum_k G(k) exp(i k.r), G the Stokeslet: K is
+    even and symmetric, so grad_S = stokes_map(X, GU) and
+    grad_X[j, b] = sum_a GU[j, a] d_b u_a(X_j) + S[j, a] d_b v_a(X_j), with u the flow of S and v
+    the flow of GU; d_b of a field is the type-2 sum of i k_b times its coefficients.
+    """
+    d = X.shape[1]
+    _, uh = stokes_map(X, S, Ns, L, mu)
+    V, vh = stokes_map(X, GU, Ns, L, mu)
+    gX = np.zeros_like(X)
+    for b in range(d):
+        du = interp_velocity(X, nudft._ik_weighted(uh, Ns, L, b), Ns, L)
+        dv = interp_velocity(X, nudft._ik_weighted(vh, Ns, L, b), Ns, L)
+        gX[:, b] = np.sum(GU * du + S * dv, axis=1)
+    return V, gX

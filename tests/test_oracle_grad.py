@@ -83,3 +83,28 @@ def test_position_gradients_of_a_shift_sum_to_a_translation_derivative():
     for a in range(2):
         shift = float(np.real(np.vdot(w, -nudft._ik_weighted(f, Ns, L, a))))
         assert abs(gX[:, a].sum() - shift) < 1e-10 * max(1.0, abs(shift))
+
+
+@pytest.mark.parametrize("Ns", [(8, 6), (6, 5, 4)])
+def test_stokes_map_grad_matches_finite_differences(Ns):
+    from oracle import step
+    rng = np.random.default_rng(54)
+    d, M, L, mu = len(Ns), 5, 1.0, 0.7
+    X = rng.random((M, d))
+    S = rng.standard_normal((M, d))
+    W = rng.standard_normal((M, d))
+    loss = lambda X_, S_: float(np.sum(W * step.stokes_map(X_, S_, Ns, L, mu)[0]))
+    gS, gX = step.stokes_map_grad(X, S, W, Ns, L, mu)
+    h = 1e-6
+    for j in range(M):
+        for a in range(d):
+            Sp, Sm = S.copy(), S.copy()
+            Sp[j, a] += h
+            Sm[j, a] -= h
+            fd = (loss(X, Sp) - loss(X, Sm)) / (2 * h)
+            assert abs(fd - gS[j, a]) < 1e-7 * max(1.0, abs(gS[j, a]))
+            Xp, Xm = X.copy(), X.copy()
+            Xp[j, a] += h
+            Xm[j, a] -= h
+            fd = (loss(Xp, S) - loss(Xm, S)) / (2 * h)
+            assert abs(fd - gX[j, a]) < 1e-6 * max(1.0, abs(gX[j, a]))
