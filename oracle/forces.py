@@ -59,3 +59,38 @@ def surface_area(X, tris):
 
 def surface_tension_energy_3d(X, tris, gamma):
     return gamma * surface_area(X, tris)
+
+
+def tension_force_2d_jvp(V, K):
+    """Directional derivative dF(X)[V] of the closed-curve tension force (Sec. 6.2.1): the force is
+    linear in X, so it is the same second difference applied to V.  The Jacobian is symmetric (the
+    force is minus the gradient of a quadratic energy), so this is also the transpose product."""
+    return tension_force_2d(V, K)
+
+
+def surface_tension_force_3d_jvp(X, tris, gamma, V):
+    """Directional derivative dF(X)[V] of the surface-tension force (Sec. 6.2.3).
+
+    Per triangle (i, j, k) the force on i is -(gamma/2) (X_j - X_k) x n with n = m/|m|,
+    m = (X_j - X_i) x (X_k - X_i).  Differentiating along V:
+      d(X_j - X_k) = V_j - V_k,   dm = (V_j - V_i) x (X_k - X_i) + (X_j - X_i) x (V_k - V_i),
+      dn = (dm - n (n . dm)) / |m|.
+    F = -gamma grad(area), so the Jacobian is minus gamma times the Hessian of the area: symmetric,
+    and this is also the transpose product used by the adjoint.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    out = np.zeros_like(X)
+    for r in range(3):  # the three cyclic rotations (i, j, k) of each triangle
+        i, j, k = tris[:, r], tris[:, (r + 1) % 3], tris[:, (r + 2) % 3]
+        a, b = X[j] - X[i], X[k] - X[i]
+        da, db = V[j] - V[i], V[k] - V[i]
+        m = np.cross(a, b)
+        nm = np.linalg.norm(m, axis=1)[:, None]
+        n = m / nm
+        dm = np.cross(da, b) + np.cross(a, db)
+        dn = (dm - n * np.sum(n * dm, axis=1)[:, None]) / nm
+        df = np.cross(da - db, n) + np.cross(a - b, dn)
+        np.add.at(out, i, -0.5 * gamma * df)
+    return out

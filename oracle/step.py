@@ -122,3 +122,65 @@ def stokes_map_grad(X, S, GU, Ns, L, mu):
         dv = interp_velocity(X, nudft._ik_weighted(vh, Ns, L, b), Ns, L)
         gX[:, b] = np.sum(GU * du + S * dv, axis=1)
     return V, gX
+
+
+def _force_jvp(force, X, V):
+    """dF(X)[V] of the force law (also its transpose product: the Jacobians are symmetric)."""
+    if force.kind == "tension2d":
+        return forces.tension_force_2d_jvp(V, force.K)
+    return forces.surface_tension_force_3d_jvp(X, force.tris, force.K, V)
+
+
+def stokes_trajectory(X0, force, Ns, L, mu, dt, steps):
+    """X after `steps` midpoint steps of the Stokes variant from X0 (stokes_step, U^0 = U(X0))."""
+    X = np.array(X0, dtype=np.float64)
+    for _ in range(steps):
+        U, _ = stokes_velocity(X, force, Ns, L, mu)
+        Xh = X + 0.5 * dt * U
+        Uh, _ = stokes_velocity(Xh, force, Ns, L, mu)
+        X = X + dt * Uh
+    return X
+
+
+def trajectory_loss(XT, target):
+    """Squared distance of the final positions to their targets, sum_j |X_j(T) - Xtarget_j|^2."""
+    D = XT - target
+    return float(np.sum(D * D))
+
+
+def stokes_trajectory_grad(X0, force, Ns, L, mu, dt, steps, target):
+    """Loss of stokes_trajectory and its gradients with respect to X0 and the stiffness K.
+
+    Reverse sweep over the steps (each step: U0 = U(X), Xh = X + dt/2 U0, Xn = X + dt U(Xh)), with
+    U(X) = stokes_map(X, w F(X; K)).  The adjoint of one velocity evaluation, given GU = dL/dU:
+    (gS, gX) from stokes_map_grad, then gX += w dF(X)^T gS (symmetric Jacobian) and
+    gK += w <gS, F(X; 1)> (F is linear in K).  The forward positions are stored per step.
+    Returns (loss, gX0, gK).
+    """
+    unit = ForceLaw(force.kind, 1.0, force.tris)
+    Xs = [np.array(X0, dtype=np.float64)]
+    Xhs = []
+    for _ in range(steps):
+        X = Xs[-1]
+        U, _ = stokes_velocity(X, force, Ns, L, mu)
+        Xh = X + 0.5 * dt * U
+        Uh, _ = stokes_velocity(Xh, force, Ns, L, mu)
+        Xhs.append(Xh)
+        Xs.append(X + dt * Uh)
+    loss = trajectory_loss(Xs[-1], target)
+
+    def velocity_vjp(X, GU):
+        F, w = force(X)
+        gS, gX = stokes_map_grad(X, w * F, GU, Ns, L, mu)
+        gX = gX + w * _force_jvp(force, X, gS)
+        F1, _ = unit(X)
+        return gX, w * float(np.sum(gS * F1))
+
+    g = 2.0 * (Xs[-1] - target)
+    gK = 0.0
+    for s in range(steps - 1, -1, -1):
+        gXh, k1 = velocity_vjp(Xhs[s], dt * g)
+        gX0, k0 = velocity_vjp(Xs[s], 0.5 * dt * gXh)
+        g = g + gXh + gX0
+        gK += k1 + k0
+    return loss, g, gK
