@@ -150,6 +150,28 @@ fsib_status fsib_spread(fsib_plan plan, int64_t M, const double* X, const void* 
 fsib_status fsib_interp(fsib_plan plan, int64_t M, const double* X, const void* fhat, void* c,
                         void* stream);
 
+/* ---- Adjoint building blocks (gradients of the transforms) ------------------------------------
+ * For a real loss, the gradient of the strengths of type-1 is a type-2 sum of the gradient of its
+ * output (and vice versa), and the gradient of the positions needs the phase derivative
+ * d/dx_a exp(+-i k.x) = +-i k_a exp(+-i k.x) (App. A, eqs. type1 and type2).  Gradients of complex
+ * arrays are dL/dRe + i dL/dIm. */
+/* out = scale * in (axis = -1) or out = scale * i k_axis * in (axis in [0, dim)), k_a = 2 pi m_a / L,
+ * elementwise on spectral arrays (device, complex prec, in place allowed):
+ *   layout 0: ntrans full spectral arrays (FFT order, x fastest), as fsib_spread / fsib_interp;
+ *   layout 1: dim half spectral arrays of real fields (fluid plans), as fsib_velocity_interp --
+ *             i k_a uhat is the half spectrum of the derivative d/dx_a of the field.
+ * Errors: FSIB_ERR_ARG for a bad layout or axis, NULL arrays, a non-finite scale; FSIB_ERR_STATE for
+ * layout 1 on a plan without fluid. */
+fsib_status fsib_spectral_scale(fsib_plan plan, int layout, int axis, double scale, const void* in, void* out,
+                                void* stream);
+/* Per-point combination of gradient terms into column `axis` of gX ((M, dim) double, device):
+ *   kind 0: gX[j][axis] = scale * sum_{t < ntrans} Re( conj(u[t][j]) v[t][j] ),  u, v: ntrans x M complex;
+ *   kind 1: gX[j][axis] = scale * sum_a ( u[j][a] v[j][a] + u2[j][a] v2[j][a] ),  u, v, u2, v2: (M, dim)
+ *           real prec; u2 and v2 may both be NULL.
+ * Errors: FSIB_ERR_ARG for M outside [0, max_points], a bad kind or axis, NULL arrays, non-finite scale. */
+fsib_status fsib_grad_combine(fsib_plan plan, int64_t M, int kind, const void* u, const void* v, const void* u2,
+                              const void* v2, double scale, double* gX, int axis, void* stream);
+
 /* ---- FSIB coupling (Sec. 3.1); plans created with fluid = 1 ---------------------------------- */
 /* Force spreading of real vector strengths S (M, dim) prec (S_j = w_j F_j):
  *   fhat[a][k] = scale * sum_j S[j][a] exp(-i k.X_j)   (eq. force_spreading_quad, scale = L^-d),
@@ -180,6 +202,13 @@ fsib_status fsib_fluid_step(fsib_plan plan, const fsib_fluid_params* params, con
  *    weight 1).  Needs tris and the vertex->triangle CSR. */
 fsib_status fsib_compute_force(const fsib_force* force, int dim, int64_t M, const double* X,
                                double* F, void* stream);
+/* Directional derivative out = dF(X)[V] of the force law ((M, dim) double arrays, device).  Both
+ * laws are minus the gradient of an energy (Sec. 6.2.1: (K/2) sum |X_{j+1} - X_j|^2 / dtheta;
+ * Sec. 6.2.3: K times the surface area), so the Jacobian is symmetric and out is also the transpose
+ * product dF(X)^T V that the adjoint of a time step needs.  CURVE_TENSION is linear in X: out = F(V).
+ * out must not alias X or V.  Errors as fsib_compute_force. */
+fsib_status fsib_force_jvp(const fsib_force* force, int dim, int64_t M, const double* X, const double* V,
+                           double* out, void* stream);
 /* Boundary velocity at X for the current state:  NAVIER_STOKES: U = interp(uhat, X) (uhat is
  * input).  STOKES: uhat <- Stokeslet(spread(w F(X))), U = interp(uhat, X) (uhat is output).
  * This gives U^0 for the first fsib_step. */

@@ -18,6 +18,11 @@ Entry points (same names as the C ABI):
     plan.velocity(params, force, X, uhat)   U at X (U^0 for the first step)
     plan.step(params, force, X, U, uhat)    one Alg. 1 step
     compute_force(force, X)                 built-in force laws
+    force_jvp(force, X, V)                  their Jacobian products (adjoint)
+    plan.spectral_scale / plan.grad_combine adjoint building blocks
+
+Differentiable wrappers (torch.autograd) are in ``paper_2302_08694_amd.autograd``; batched
+independent 2D Stokes simulations in ``paper_2302_08694_amd.batch``.
 """
 
 from ._binding import (  # noqa: F401
@@ -26,6 +31,7 @@ from ._binding import (  # noqa: F401
     FluidParams,
     Force,
     compute_force,
+    force_jvp,
     device_count,
     library_path,
     load_library,

@@ -58,6 +58,11 @@ _SIGS = {
                                    ctypes.c_double, ctypes.c_void_p]),
     "fsib_interp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p]),
+    "fsib_spectral_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_grad_combine": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                         ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "fsib_force_spread": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
     "fsib_velocity_interp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
@@ -66,6 +71,8 @@ _SIGS = {
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "fsib_compute_force": (ctypes.c_int, [ctypes.POINTER(_Force), ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_force_jvp": (ctypes.c_int, [ctypes.POINTER(_Force), ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fsib_velocity": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fsib_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
@@ -171,6 +178,18 @@ def compute_force(force, X):
     return F
 
 
+def force_jvp(force, X, V):
+    """dF(X)[V] (double, same shape as X) of a built-in force law; also dF(X)^T V (symmetric)."""
+    lib = load_library()
+    dim = X.shape[1]
+    _need(X, "X", torch.float64)
+    _need(V, "V", torch.float64, X.shape)
+    out = torch.empty_like(X)
+    _check(lib.fsib_force_jvp(ctypes.byref(force._s), dim, X.shape[0], _ptr(X), _ptr(V), _ptr(out), _stream()),
+           "fsib_force_jvp")
+    return out
+
+
 class Plan:
     def __init__(self, dim, n_modes, L=1.0, prec="f64", tol=1e-6, ntrans=1, max_points=1 << 16, fluid=False,
                  navier_stokes=False):
@@ -262,6 +281,38 @@ class Plan:
         out = torch.empty(shp, dtype=self.cdtype, device=X.device) if out is None else _need(out, "c", self.cdtype, shp)
         _check(self._lib.fsib_interp(self._h, M, _ptr(X), _ptr(fhat), _ptr(out), _stream()), "fsib_interp")
         return out
+
+    def spectral_scale(self, fhat, axis=-1, scale=1.0, out=None, half=False):
+        """scale * fhat (axis = -1) or scale * i k_axis * fhat (fsib_spectral_scale); full spectra
+        (ntrans arrays) or, with half=True, the dim half spectra of real fields."""
+        fhat = _need(fhat, "fhat", self.cdtype)
+        if half:
+            _need(fhat, "fhat", self.cdtype, (self.dim,) + self.half_shape)
+        out = torch.empty_like(fhat) if out is None else _need(out, "out", self.cdtype, tuple(fhat.shape))
+        _check(self._lib.fsib_spectral_scale(self._h, 1 if half else 0, int(axis), float(scale), _ptr(fhat), _ptr(out),
+                                             _stream()), "fsib_spectral_scale")
+        return out
+
+    def grad_combine(self, u, v, gX, axis, scale=1.0, u2=None, v2=None):
+        """gX[:, axis] = scale * sum_t Re(conj(u) v) for complex (ntrans, M) u, v, or
+        scale * sum_a (u v + u2 v2) for real (M, dim) u, v (u2, v2 optional) (fsib_grad_combine)."""
+        M = gX.shape[0]
+        _need(gX, "gX", torch.float64, (M, self.dim))
+        real = not u.is_complex()
+        dt = self.rdtype if real else self.cdtype
+        u = _need(u, "u", dt)
+        v = _need(v, "v", dt)
+        n = M * self.dim if real else M * self.ntrans
+        if u.numel() != n or v.numel() != n:
+            raise ValueError("u and v must hold (M, dim) real or ntrans x M complex values")
+        if (u2 is None) != (v2 is None) or (u2 is not None and not real):
+            raise ValueError("u2 and v2 go together, for real u, v only")
+        if u2 is not None:
+            _need(u2, "u2", dt, tuple(u.shape))
+            _need(v2, "v2", dt, tuple(u.shape))
+        _check(self._lib.fsib_grad_combine(self._h, M, 1 if real else 0, _ptr(u), _ptr(v), _ptr(u2), _ptr(v2),
+                                           float(scale), _ptr(gX), int(axis), _stream()), "fsib_grad_combine")
+        return gX
 
     def force_spread(self, X, S, scale, out=None):
         M = self._X(X)

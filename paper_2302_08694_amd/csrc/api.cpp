@@ -645,6 +645,34 @@ fsib_status fsib_interp(fsib_plan plan, int64_t M, const double* X, const void* 
   return type2_complex(p, M, X, fhat, c, S(stream));
 }
 
+fsib_status fsib_spectral_scale(fsib_plan plan, int layout, int axis, double scale, const void* in, void* out,
+                                void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (layout != 0 && layout != 1) return fail(FSIB_ERR_ARG, "layout must be 0 (full spectra) or 1 (half spectra)");
+  if (layout == 1 && !p.fluid) return fail(FSIB_ERR_STATE, "half spectra need a plan created with fluid = 1");
+  if (axis < -1 || axis >= p.dim) return fail(FSIB_ERR_ARG, "axis must be -1 or in [0, dim)");
+  if (!in || !out) return fail(FSIB_ERR_ARG, "in / out is NULL");
+  if (!std::isfinite(scale)) return fail(FSIB_ERR_ARG, "scale must be finite");
+  FSIB_HIP(fsib::launch_spectral_scale(p, layout, axis, scale, in, out, S(stream)));
+  return FSIB_OK;
+}
+
+fsib_status fsib_grad_combine(fsib_plan plan, int64_t M, int kind, const void* u, const void* v, const void* u2,
+                              const void* v2, double scale, double* gX, int axis, void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (M < 0 || M > p.max_points) return fail(FSIB_ERR_ARG, "M out of range [0, max_points]");
+  if (kind != 0 && kind != 1) return fail(FSIB_ERR_ARG, "kind must be 0 (complex) or 1 (real)");
+  if (axis < 0 || axis >= p.dim) return fail(FSIB_ERR_ARG, "axis must be in [0, dim)");
+  if (M > 0 && (!u || !v || !gX)) return fail(FSIB_ERR_ARG, "u / v / gX is NULL");
+  if (M > 0 && kind == 1 && (!u2) != (!v2)) return fail(FSIB_ERR_ARG, "u2 and v2 must both be given or both NULL");
+  if (!std::isfinite(scale)) return fail(FSIB_ERR_ARG, "scale must be finite");
+  FSIB_HIP(fsib::launch_grad_combine(p, M, kind, u, v, kind == 1 ? u2 : nullptr, kind == 1 ? v2 : nullptr, scale, gX,
+                                     axis, S(stream)));
+  return FSIB_OK;
+}
+
 fsib_status fsib_force_spread(fsib_plan plan, int64_t M, const double* X, const void* S_, void* fhat_half, double scale,
                               void* stream) {
   if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
@@ -685,6 +713,17 @@ fsib_status fsib_compute_force(const fsib_force* force, int dim, int64_t M, cons
   FSIB_TRY(check_force(force, dim, M));
   if (M > 0 && (!X || !F)) return fail(FSIB_ERR_ARG, "X and F must not be NULL");
   FSIB_HIP(fsib::launch_force(*force, dim, M, X, F, S(stream)));
+  return FSIB_OK;
+}
+
+fsib_status fsib_force_jvp(const fsib_force* force, int dim, int64_t M, const double* X, const double* V, double* out,
+                          void* stream) {
+  if (dim != 2 && dim != 3) return fail(FSIB_ERR_ARG, "dim must be 2 or 3");
+  if (M < 0) return fail(FSIB_ERR_ARG, "M must be >= 0");
+  FSIB_TRY(check_force(force, dim, M));
+  if (M > 0 && (!X || !V || !out)) return fail(FSIB_ERR_ARG, "X, V and out must not be NULL");
+  if (M > 0 && (out == X || out == V)) return fail(FSIB_ERR_ARG, "out must not alias X or V");
+  FSIB_HIP(fsib::launch_force_jvp(*force, dim, M, X, V, out, S(stream)));
   return FSIB_OK;
 }
 

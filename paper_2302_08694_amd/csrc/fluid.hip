@@ -206,6 +206,80 @@ hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X
   return hipGetLastError();
 }
 
+// Directional derivative dF(X)[V] of the surface-tension force (Sec. 6.2.3), one wavefront per vertex
+// as k_force_surface.  Per incident triangle (i, j, k): a = X_j - X_i, b = X_k - X_i, m = a x b,
+// n = m/|m|; d(a - b) = V_j - V_k, dm = da x b + a x db, dn = (dm - n (n.dm))/|m|, and the force term
+// (a - b) x n changes by d(a - b) x n + (a - b) x dn.  F is minus gamma times the gradient of the area,
+// so its Jacobian is symmetric and this is also the transpose product the adjoint needs.
+__global__ __launch_bounds__(256) void k_force_surface_jvp(int64_t M, const double* __restrict__ X,
+                                                           const double* __restrict__ V, double gamma,
+                                                           const int32_t* __restrict__ tris,
+                                                           const int32_t* __restrict__ ptr,
+                                                           const int32_t* __restrict__ idx, double* __restrict__ out) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= M) return;  // uniform per wavefront
+  double f0 = 0, f1 = 0, f2 = 0;
+  const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
+  const double vxi = V[3 * i], vyi = V[3 * i + 1], vzi = V[3 * i + 2];
+  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 64) {
+    const int t = idx[e];
+    const int v0 = tris[3 * t], v1 = tris[3 * t + 1], v2 = tris[3 * t + 2];
+    int j, k;
+    if (v0 == i) {
+      j = v1;
+      k = v2;
+    } else if (v1 == i) {
+      j = v2;
+      k = v0;
+    } else {
+      j = v0;
+      k = v1;
+    }
+    const double ax = X[3 * j] - xi, ay = X[3 * j + 1] - yi, az = X[3 * j + 2] - zi;
+    const double bx = X[3 * k] - xi, by = X[3 * k + 1] - yi, bz = X[3 * k + 2] - zi;
+    const double dax = V[3 * j] - vxi, day = V[3 * j + 1] - vyi, daz = V[3 * j + 2] - vzi;
+    const double dbx = V[3 * k] - vxi, dby = V[3 * k + 1] - vyi, dbz = V[3 * k + 2] - vzi;
+    const double mx = ay * bz - az * by, my = az * bx - ax * bz, mz = ax * by - ay * bx;
+    const double mm = sqrt(mx * mx + my * my + mz * mz);
+    if (!(mm > 0)) continue;  // degenerate triangle: its force term is zero, so is the derivative
+    const double nx = mx / mm, ny = my / mm, nz = mz / mm;
+    // dm = da x b + a x db
+    const double dmx = (day * bz - daz * by) + (ay * dbz - az * dby);
+    const double dmy = (daz * bx - dax * bz) + (az * dbx - ax * dbz);
+    const double dmz = (dax * by - day * bx) + (ax * dby - ay * dbx);
+    const double nd = nx * dmx + ny * dmy + nz * dmz;
+    const double dnx = (dmx - nx * nd) / mm, dny = (dmy - ny * nd) / mm, dnz = (dmz - nz * nd) / mm;
+    const double ex = ax - bx, ey = ay - by, ez = az - bz;          // X_j - X_k
+    const double dex = dax - dbx, dey = day - dby, dez = daz - dbz;  // V_j - V_k
+    f0 += (dey * nz - dez * ny) + (ey * dnz - ez * dny);
+    f1 += (dez * nx - dex * nz) + (ez * dnx - ex * dnz);
+    f2 += (dex * ny - dey * nx) + (ex * dny - ey * dnx);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    f0 += __shfl_xor(f0, off, 64);
+    f1 += __shfl_xor(f1, off, 64);
+    f2 += __shfl_xor(f2, off, 64);
+  }
+  if (lane == 0) {
+    out[3 * i] = -0.5 * gamma * f0;
+    out[3 * i + 1] = -0.5 * gamma * f1;
+    out[3 * i + 2] = -0.5 * gamma * f2;
+  }
+}
+
+hipError_t launch_force_jvp(const fsib_force& f, int dim, int64_t M, const double* X, const double* V, double* out,
+                            hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  if (f.kind == FSIB_FORCE_CURVE_TENSION)  // the curve force is linear in X: dF(X)[V] = F(V)
+    hipLaunchKernelGGL(k_force_curve, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, V, f.K, out);
+  else
+    hipLaunchKernelGGL(k_force_surface_jvp, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, M, X, V, f.K, f.tris,
+                       f.v2t_ptr, f.v2t_idx, out);
+  return hipGetLastError();
+}
+
 // Strengths S_j = w_j F_j in the plan precision (quadrature weights of eq. force_spreading_quad).
 template <typename T>
 __global__ void k_strengths(int64_t n, const double* __restrict__ F, double w, T* __restrict__ S) {

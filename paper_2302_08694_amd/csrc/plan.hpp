@@ -104,6 +104,10 @@ struct Plan {
 // ---- launchers (all asynchronous on `st`) ----
 // points.hip
 hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st);
+hipError_t launch_spectral_scale(const Plan& p, int layout, int axis, double scale, const void* in, void* out,
+                                 hipStream_t st);  // layout 0: ntrans full spectra; 1: dim half spectra
+hipError_t launch_grad_combine(const Plan& p, int64_t M, int kind, const void* u, const void* v, const void* u2,
+                               const void* v2, double scale, double* gX, int axis, hipStream_t st);
 hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const double* X, const void* U,
                                  double a, hipStream_t st);  // Y = X + a*U
 hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
@@ -128,6 +132,8 @@ hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params&
                                const void* uin, void* uout, hipStream_t st);
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F,
                         hipStream_t st);
+hipError_t launch_force_jvp(const fsib_force& f, int dim, int64_t M, const double* X, const double* V, double* out,
+                            hipStream_t st);
 hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S,
                                      hipStream_t st);
 hipError_t launch_diag(const Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M,

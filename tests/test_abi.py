@@ -72,3 +72,20 @@ def test_no_device_reported():
     assert lib.fsib_device_count() == 0
     h = ctypes.c_void_p()
     assert lib.fsib_plan_create(ctypes.byref(_opts()), ctypes.byref(h)) == 3
+
+
+def test_adjoint_helpers_reject_null_plan():
+    lib = B.load_library()
+    assert lib.fsib_spectral_scale(None, 0, 0, 1.0, None, None, None) == 1
+    assert lib.fsib_grad_combine(None, 0, 0, None, None, None, None, 1.0, None, 0, None) == 1
+
+
+def test_force_jvp_rejects_bad_arguments():
+    lib = B.load_library()
+    f = B._Force(99, 1.0, None, 0, None, None)
+    assert lib.fsib_force_jvp(ctypes.byref(f), 3, 10, None, None, None, None) == 1
+    g = B._Force(B.FSIB_FORCE_CURVE_TENSION, 1.0, None, 0, None, None)
+    assert lib.fsib_force_jvp(ctypes.byref(g), 2, 10, None, None, None, None) == 1
+    assert lib.fsib_force_jvp(ctypes.byref(g), 4, 10, None, None, None, None) == 1
+    assert lib.fsib_force_jvp(ctypes.byref(g), 2, -1, None, None, None, None) == 1
+    assert lib.fsib_force_jvp(ctypes.byref(g), 2, 0, None, None, None, None) == 0  # nothing to do

@@ -11,6 +11,8 @@ Workloads (L = 1 throughout):
                       counter-clockwise seen from outside.
 * ``stokes2d_case``   2D Stokes ellipse, N = 32^2, M = 128, centre drawn from seed 1.
 * ``ns3d_case``       3D Navier-Stokes ellipsoid, N = 128^3, lat-long 200 x 200 = 40,000 points.
+* ``diff_stokes3d_case`` differentiable 3D Stokes, N = 64^3, lat-long 100 x 100 = 10,000 points,
+                      20 steps, target ellipsoid with semi-axes drawn from seed 5.
 * ``nufft_points``    half uniform in the unit torus, half on a sphere of radius 0.2
                       (the NUFFT micro-benchmark point law), complex N(0,1) strengths.
 """
@@ -106,6 +108,19 @@ def ns3d_case(n_rings=200, n_lon=200, N=128):
     X, tris = latlong_sphere(n_rings, n_lon, radius=0.25, center=(0.5, 0.5, 0.5), scale=(1.2, 1.0, 0.8))
     return dict(X=X, tris=tris, N=(N, N, N), L=1.0, K=1.0, mu=0.01, rho=1.0, dt=5e-4,
                 force="surface3d")
+
+
+def diff_stokes3d_case(seed=5, n_rings=100, n_lon=100, N=64, steps=20):
+    """Differentiable 3D Stokes: lat-long sphere of radius 0.25 about (1/2,1/2,1/2), surface tension
+    K = 1, mu = 1, dt = 1e-3, `steps` steps; target = the same vertices on an ellipsoid with semi-axes
+    drawn U[0.2, 0.3] (three draws), i.e. c + axes * (X0 - c) / 0.25."""
+    rng = np.random.default_rng(seed)
+    axes = rng.uniform(0.2, 0.3, 3)
+    c = np.array([0.5, 0.5, 0.5])
+    X, tris = latlong_sphere(n_rings, n_lon, radius=0.25, center=tuple(c))
+    target = c[None, :] + axes[None, :] * (X - c[None, :]) / 0.25
+    return dict(X=X, tris=tris, target=target, axes=axes, N=(N, N, N), L=1.0, K=1.0, mu=1.0, dt=1e-3,
+                steps=steps, force="surface3d")
 
 
 def nufft_points(M, seed=3, dim=3, cluster_radius=0.2):
