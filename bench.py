@@ -9,7 +9,9 @@ Inputs are synthetic and resident on the device before timing starts.
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu-baseline]
 
 Prints one JSON line: FSIB steps/s in FP64 at NUFFT tolerance 1e-5 (value), with the FP32 form,
-the NUFFT spread+interp points/s at 128^3, the roofline of the dominant kernel and the CPU oracle
+the NUFFT spread+interp points/s at 128^3, the NUFFT micro-benchmark (256^3, 2e6 points), the
+batched 2D Stokes form (64 uneven instances, HIP graph), the differentiable 3D Stokes form (64^3,
+10,000 points, 20 checkpointed steps), the roofline of the dominant kernel and the CPU oracle
 timed on the host.
 """
 
@@ -34,6 +36,7 @@ def parse():
     ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 form and the NUFFT timings")
     ap.add_argument("--no-nufft-micro", action="store_true", help="skip the NUFFT micro-benchmark legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2D Stokes leg")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiable 3D Stokes leg")
     ap.add_argument("--nufft-only", action="store_true", help="run only the NUFFT micro-benchmark legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (reference for hardware byte counters)")
@@ -237,6 +240,52 @@ def batched_stokes(F, torch, steps=50, graph_steps=10):
     return res
 
 
+def differentiable_stokes(F, torch, reps=3):
+    """Loss and gradients (initial positions, stiffness) of 20 checkpointed Stokes steps at 64^3 modes
+    with 10,000 surface-tension points: FP32 and FP64 forward + adjoint, wall time per gradient
+    evaluation next to the forward alone, and the FP32 gradients' error against the FP64 ones."""
+    import workloads
+    from paper_2302_08694_amd.autograd import ForceLaw, stokes_trajectory
+    c = workloads.diff_stokes3d_case()
+    X0, tris, M = c["X"], c["tris"], c["X"].shape[0]
+    ptr, idx = workloads.vertex_triangle_csr(tris, M)
+    d = lambda a: torch.as_tensor(a).to("cuda:0")
+    law = ForceLaw("surface3d", d(tris), d(ptr), d(idx))
+    tgt = d(c["target"])
+    res = {"n_modes": c["N"][0], "points": M, "steps": c["steps"], "dt": c["dt"], "checkpointed": True}
+    grads = {}
+    for prec, tol in (("f32", 1e-6), ("f64", 1e-10)):
+        plan = F.Plan(3, c["N"], prec=prec, tol=tol, max_points=M, fluid=True)
+
+        def evaluate(grad):
+            X = d(X0).requires_grad_(grad)
+            K = torch.tensor(c["K"], dtype=torch.float64, device="cuda:0", requires_grad=grad)
+            XT = stokes_trajectory(plan, X, K, law, c["mu"], c["dt"], c["steps"], checkpoint=True)
+            loss = torch.sum((XT - tgt) ** 2)
+            if grad:
+                loss.backward()
+                return loss, X.grad, K.grad
+            return loss, None, None
+
+        for grad in (False, True):
+            evaluate(grad)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out = evaluate(grad)
+            torch.cuda.synchronize()
+            res[f"{prec}_tol"] = tol
+            res[f"{prec}_{'forward_backward' if grad else 'forward'}_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        grads[prec] = (float(out[0].detach()), out[1].cpu().numpy(), float(out[2]))
+        plan.close()
+    (l32, g32, k32), (l64, g64, k64) = grads["f32"], grads["f64"]
+    res["loss_f64"] = l64
+    res["f32_rel_err_loss"] = abs(l32 - l64) / abs(l64)
+    res["f32_rel_err_grad_X0"] = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    res["f32_rel_err_grad_K"] = abs(k32 - k64) / abs(k64)
+    return res
+
+
 # (N, M, prec, tol): the micro-benchmark's point law (half uniform, half on a sphere of radius 0.2)
 # at 256^3 with 2e6 points, and scaled to 128^3 with 2.5e5 points (same points per fine cell)
 NUFFT_MICRO = [(128, 250_000, "f32", 1e-5), (128, 250_000, "f64", 1e-5),
@@ -402,6 +451,10 @@ def main():
         log("batched 2D Stokes (64 instances)")
         out["batched_2d_stokes"] = batched_stokes(F, torch)
         log(f"  {out['batched_2d_stokes']}")
+    if not a.no_diff:
+        log("differentiable 3D Stokes (64^3, 10,000 points, 20 checkpointed steps)")
+        out["differentiable_stokes"] = differentiable_stokes(F, torch)
+        log(f"  {out['differentiable_stokes']}")
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.n, a.rings)
