@@ -50,6 +50,20 @@ def stokes_pressure(fhat, Ns, L):
     return np.where(nz, kdotf / (1j * np.where(nz, k2, 1.0)), 0.0)
 
 
+def pressure(fhat, uhat, Ns, L, rho, npad=None):
+    """phat = -i k.(fhat - rho shat(uhat)) / |k|^2, phat(0) = 0 (Sec. 3, eq. pressure_poisson_k), shat the
+    advective nonlinear term of eq. nonlinear_physical (three-halves rule); uhat = None gives the
+    Stokes pressure -i k.fhat / |k|^2."""
+    k = wavevector(Ns, L)
+    k2 = ksquared(Ns, L)
+    nz = k2 != 0.0
+    g = np.array(fhat, dtype=np.complex128)
+    if uhat is not None:
+        g = g - rho * nonlinear(uhat, Ns, L, npad)
+    kg = sum(k[a] * g[a] for a in range(len(Ns)))
+    return np.where(nz, -1j * kg / np.where(nz, k2, 1.0), 0.0)
+
+
 def _embed(a, Ns, npad):
     """Zero-pad a K_N array (FFT order) into a K_Npad array (centred padding, Sec. 3.1)."""
     d = len(Ns)

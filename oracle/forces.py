@@ -94,3 +94,70 @@ def surface_tension_force_3d_jvp(X, tris, gamma, V):
         df = np.cross(da - db, n) + np.cross(a - b, dn)
         np.add.at(out, i, -0.5 * gamma * df)
     return out
+
+
+def mesh_edges(tris):
+    """Undirected edges (E, 2) of a triangulation, each once with i < j, sorted."""
+    tris = np.asarray(tris, dtype=np.int64)
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    e = np.sort(e, axis=1)
+    return np.unique(e, axis=0)
+
+
+def spring_stiffness(X0, tris, sigma):
+    """Edge stiffness of the elastic sphere (Sec. 6.2.3): for edge AB, the sum over the two triangles
+    ABC that share it of (sigma/8)(a0^2 + b0^2 - c0^2)/S0, with c0 = |AB|, a0 = |BC|, b0 = |AC| and S0 the
+    triangle's area, all in the reference configuration X0.  Returns (edges (E,2), K (E,))."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    tris = np.asarray(tris, dtype=np.int64)
+    edges = mesh_edges(tris)
+    index = {(int(i), int(j)): n for n, (i, j) in enumerate(edges)}
+    K = np.zeros(len(edges))
+    for t in tris:
+        for r in range(3):
+            A, B, C = t[r], t[(r + 1) % 3], t[(r + 2) % 3]  # edge AB, opposite vertex C
+            c2 = np.sum((X0[A] - X0[B]) ** 2)
+            a2 = np.sum((X0[B] - X0[C]) ** 2)
+            b2 = np.sum((X0[A] - X0[C]) ** 2)
+            S0 = 0.5 * np.linalg.norm(np.cross(X0[B] - X0[A], X0[C] - X0[A]))
+            K[index[(min(A, B), max(A, B))]] += sigma / 8.0 * (a2 + b2 - c2) / S0
+    return edges, K
+
+
+def spring_force(X, edges, K):
+    """F_i = sum_{j linked with i} K_ij (X_j - X_i) (Sec. 6.2.3)."""
+    X = np.asarray(X, dtype=np.float64)
+    F = np.zeros_like(X)
+    i, j = edges[:, 0], edges[:, 1]
+    D = K[:, None] * (X[j] - X[i])
+    np.add.at(F, i, D)
+    np.add.at(F, j, -D)
+    return F
+
+
+def spring_energy(X, edges, K):
+    """sum over edges of (K_ij / 2) |X_i - X_j|^2, whose negative gradient is spring_force."""
+    X = np.asarray(X, dtype=np.float64)
+    D = X[edges[:, 0]] - X[edges[:, 1]]
+    return 0.5 * float(np.sum(K * np.sum(D * D, axis=1)))
+
+
+def elastic_energy(X, X0, tris, sigma):
+    """The elastic energy of eq. total_elastic_energy, per triangle: (sigma/2) sum over the cyclic
+    permutations of a^2 (b0^2 + c0^2 - a0^2) / (8 S0)."""
+    X = np.asarray(X, dtype=np.float64)
+    X0 = np.asarray(X0, dtype=np.float64)
+    E = 0.0
+    for t in np.asarray(tris, dtype=np.int64):
+        P, P0 = X[t], X0[t]
+        sq = [np.sum((P[(r + 1) % 3] - P[(r + 2) % 3]) ** 2) for r in range(3)]    # side opposite vertex r
+        sq0 = [np.sum((P0[(r + 1) % 3] - P0[(r + 2) % 3]) ** 2) for r in range(3)]
+        S0 = 0.5 * np.linalg.norm(np.cross(P0[1] - P0[0], P0[2] - P0[0]))
+        for r in range(3):
+            E += sq[r] * (sq0[(r + 1) % 3] + sq0[(r + 2) % 3] - sq0[r]) / (8.0 * S0)
+    return 0.5 * sigma * E
+
+
+def target_force(X, target, K):
+    """Target points (Sec. 6.2.2): F_i = K (Xtarget_i - X_i)."""
+    return K * (np.asarray(target, dtype=np.float64) - np.asarray(X, dtype=np.float64))

@@ -9,6 +9,7 @@ Workloads (L = 1 throughout):
 * ``ellipse_2d``      closed curve X_j = c + (a cos th_j, b sin th_j), th_j = 2 pi j / M.
 * ``latlong_sphere``  triangulated sphere (rings x longitudes, polar fans),
                       counter-clockwise seen from outside.
+* ``icosphere``       icosahedral sphere refined by 4-splits (10 4^level + 2 vertices).
 * ``stokes2d_case``   2D Stokes ellipse, N = 32^2, M = 128, centre drawn from seed 1.
 * ``ns3d_case``       3D Navier-Stokes ellipsoid, N = 128^3, lat-long 200 x 200 = 40,000 points.
 * ``diff_stokes3d_case`` differentiable 3D Stokes, N = 64^3, lat-long 100 x 100 = 10,000 points,
@@ -75,6 +76,48 @@ def vertex_triangle_csr(tris, M):
     ptr = np.zeros(M + 1, dtype=np.int64)
     ptr[1:] = np.cumsum(counts)
     return ptr.astype(np.int32), tid[order].astype(np.int32)
+
+
+def icosphere(level, radius=1.0, center=(0.0, 0.0, 0.0)):
+    """Icosahedral sphere (Sec. 6.2.3): the regular icosahedron refined `level` times, each triangle
+    split into four through its edge midpoints, which are pushed out to the sphere.  10 4^level + 2
+    vertices, triangles counter-clockwise seen from outside.  Returns (X (M,3) float64, tris int32)."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    V = [np.array(v, dtype=np.float64) / np.linalg.norm(v) for v in V]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+         (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(int(level)):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                mid[key] = len(V) - 1
+            return mid[key]
+
+        G = []
+        for a, b, c in F:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            G += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = G
+    X = np.asarray(center, dtype=np.float64)[None, :] + radius * np.array(V)
+    return X, np.asarray(F, dtype=np.int32)
+
+
+def vertex_neighbor_csr(tris, M):
+    """Vertex -> linked-vertex lists (the mesh edges, both directions) in CSR form, int32, sorted."""
+    tris = np.asarray(tris, dtype=np.int64)
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    e = np.unique(np.concatenate([e, e[:, ::-1]]), axis=0)  # sorted by (i, j)
+    counts = np.bincount(e[:, 0], minlength=M)
+    ptr = np.zeros(M + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum(counts)
+    return ptr.astype(np.int32), e[:, 1].astype(np.int32)
 
 
 def stokes2d_case(seed=1, M=128, N=32):
