@@ -87,9 +87,17 @@ typedef enum { FSIB_STOKES = 0, FSIB_NAVIER_STOKES = 1 } fsib_model;
 typedef struct {
   int model;            /* fsib_model */
   double rho, mu, dt;   /* density, viscosity (> 0), time step */
+  double body[3];       /* NAVIER_STOKES: uniform body force density f0 added to the zero mode of fhat
+                           (the channel-flow driving force of Sec. 6.2.2); 0 for none.  STOKES
+                           ignores it (its zero mode is 0). */
 } fsib_fluid_params;
 
-typedef enum { FSIB_FORCE_CURVE_TENSION = 0, FSIB_FORCE_SURFACE_TENSION = 1 } fsib_force_kind;
+typedef enum {
+  FSIB_FORCE_CURVE_TENSION = 0,
+  FSIB_FORCE_SURFACE_TENSION = 1,
+  FSIB_FORCE_EDGE_SPRINGS = 2,
+  FSIB_FORCE_TARGET = 3
+} fsib_force_kind;
 
 typedef struct {
   int kind;                 /* fsib_force_kind */
@@ -97,8 +105,11 @@ typedef struct {
   const int32_t* tris;      /* SURFACE_TENSION: device (ntris, 3) vertex indices, counter-clockwise
                                seen from outside */
   int64_t ntris;
-  const int32_t* v2t_ptr;   /* device CSR (M+1) offsets: triangles incident to each vertex */
-  const int32_t* v2t_idx;   /* device CSR (3*ntris) triangle ids */
+  const int32_t* v2t_ptr;   /* device CSR (M+1) offsets: triangles incident to each vertex
+                               (EDGE_SPRINGS: the neighbours of each vertex) */
+  const int32_t* v2t_idx;   /* device CSR (3*ntris) triangle ids (EDGE_SPRINGS: neighbour ids) */
+  const double* aux;        /* EDGE_SPRINGS: device stiffness per CSR entry (K_ij, both directions);
+                               TARGET: device (M, dim) target positions.  NULL otherwise. */
 } fsib_force;
 
 /* ---- library ------------------------------------------------------------------------------- */
@@ -199,7 +210,12 @@ fsib_status fsib_fluid_step(fsib_plan plan, const fsib_fluid_params* params, con
  *  CURVE_TENSION (dim 2, Sec. 6.2.1 eq. elstic_force_2d): F_j = K (X_{j+1}+X_{j-1}-2X_j)/dtheta^2,
  *    dtheta = 2 pi / M (force per unit theta; quadrature weight dtheta).
  *  SURFACE_TENSION (dim 3, Sec. 6.2.3): F_i = -(K/2) sum_{(i,j,k)} (X_j - X_k) x n_ijk (nodal force,
- *    weight 1).  Needs tris and the vertex->triangle CSR. */
+ *    weight 1).  Needs tris and the vertex->triangle CSR.
+ *  EDGE_SPRINGS (dim 2 or 3, Sec. 6.2.3 elastic sphere): F_i = K sum_{j linked with i} K_ij (X_j - X_i)
+ *    (nodal force, weight 1); the CSR lists each vertex's neighbours, aux the K_ij of each entry (the
+ *    cotangent stiffness of the reference triangulation for sigma = 1, K = sigma).
+ *  TARGET (dim 2 or 3, Sec. 6.2.2 channel walls): F_i = K (Xtarget_i - X_i), aux = Xtarget (nodal
+ *    force, weight 1). */
 fsib_status fsib_compute_force(const fsib_force* force, int dim, int64_t M, const double* X,
                                double* F, void* stream);
 /* Directional derivative out = dF(X)[V] of the force law ((M, dim) double arrays, device).  Both
@@ -209,6 +225,26 @@ fsib_status fsib_compute_force(const fsib_force* force, int dim, int64_t M, cons
  * out must not alias X or V.  Errors as fsib_compute_force. */
 fsib_status fsib_force_jvp(const fsib_force* force, int dim, int64_t M, const double* X, const double* V,
                            double* out, void* stream);
+/* Stiffness of the elastic sphere's edge springs from the reference configuration X0 (Sec. 6.2.3),
+ * for sigma = 1 (the EDGE_SPRINGS force takes sigma as K): entry e = (i -> j) of the neighbour CSR
+ * (nbr_ptr (M+1), nbr_idx) receives sum over the triangles holding edge ij of
+ * (a0^2 + b0^2 - c0^2) / (8 S0) = (cot C1 + cot C2) / 2.  X0 (M, 3) double, tris (T, 3), the
+ * vertex->triangle CSR and the neighbour CSR are device arrays; kij (device, nbr_ptr[M] doubles) is
+ * written.  A set-up call: it allocates 4 bytes and synchronises the device.  Errors: FSIB_ERR_ARG for
+ * NULL arrays or a triangle edge absent from the neighbour lists. */
+fsib_status fsib_spring_stiffness(int64_t M, const double* X0, const int32_t* tris, const int32_t* v2t_ptr,
+                                  const int32_t* v2t_idx, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                                  double* kij);
+/* Pressure (Sec. 3, eq. pressure_poisson_k; Stokes: Sec. 6.1, eq. stokeslet), half spectrum of one real
+ * field (prec, device, N_z x N_y x H_x):
+ *   NAVIER_STOKES: phat = -i k.(fhat - rho shat(uhat)) / |k|^2, shat the dealiased nonlinear term of
+ *                  uhat (as in fsib_fluid_step);
+ *   STOKES:        phat = -i k.fhat / |k|^2.
+ * phat(0) = 0 (the pressure has zero mean) and the modes with some m_a = -N_a/2 are zero.  fhat as for
+ * fsib_fluid_step; uhat_half may be NULL for STOKES.  Errors: FSIB_ERR_STATE without fluid,
+ * FSIB_ERR_ARG for NULL arrays or bad params. */
+fsib_status fsib_pressure(fsib_plan plan, const fsib_fluid_params* params, const void* fhat_half,
+                          const void* uhat_half, void* phat_half, void* stream);
 /* Boundary velocity at X for the current state:  NAVIER_STOKES: U = interp(uhat, X) (uhat is
  * input).  STOKES: uhat <- Stokeslet(spread(w F(X))), U = interp(uhat, X) (uhat is output).
  * This gives U^0 for the first fsib_step. */

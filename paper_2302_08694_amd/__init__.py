@@ -19,6 +19,8 @@ Entry points (same names as the C ABI):
     plan.step(params, force, X, U, uhat)    one Alg. 1 step
     compute_force(force, X)                 built-in force laws
     force_jvp(force, X, V)                  their Jacobian products (adjoint)
+    spring_stiffness(X0, tris, ...)         edge springs of the elastic sphere (set-up)
+    plan.pressure(params, fhat, uhat)       pressure half spectrum
     plan.spectral_scale / plan.grad_combine adjoint building blocks
 
 Differentiable wrappers (torch.autograd) are in ``paper_2302_08694_amd.autograd``; batched
@@ -32,6 +34,7 @@ from ._binding import (  # noqa: F401
     Force,
     compute_force,
     force_jvp,
+    spring_stiffness,
     device_count,
     library_path,
     load_library,

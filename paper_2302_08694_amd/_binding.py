@@ -11,7 +11,7 @@ DIAG_COUNT = 11
 
 FSIB_F64, FSIB_F32 = 0, 1
 FSIB_STOKES, FSIB_NAVIER_STOKES = 0, 1
-FSIB_FORCE_CURVE_TENSION, FSIB_FORCE_SURFACE_TENSION = 0, 1
+FSIB_FORCE_CURVE_TENSION, FSIB_FORCE_SURFACE_TENSION, FSIB_FORCE_EDGE_SPRINGS, FSIB_FORCE_TARGET = 0, 1, 2, 3
 
 
 class FSIBError(RuntimeError):
@@ -34,12 +34,13 @@ class _Info(ctypes.Structure):
 
 
 class _Params(ctypes.Structure):
-    _fields_ = [("model", ctypes.c_int), ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("dt", ctypes.c_double)]
+    _fields_ = [("model", ctypes.c_int), ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("dt", ctypes.c_double),
+                ("body", ctypes.c_double * 3)]
 
 
 class _Force(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("K", ctypes.c_double), ("tris", ctypes.c_void_p), ("ntris", ctypes.c_int64),
-                ("v2t_ptr", ctypes.c_void_p), ("v2t_idx", ctypes.c_void_p)]
+                ("v2t_ptr", ctypes.c_void_p), ("v2t_idx", ctypes.c_void_p), ("aux", ctypes.c_void_p)]
 
 
 _SIGS = {
@@ -73,6 +74,10 @@ _SIGS = {
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "fsib_force_jvp": (ctypes.c_int, [ctypes.POINTER(_Force), ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_spring_stiffness": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_pressure": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
     "fsib_velocity": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fsib_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
@@ -140,31 +145,55 @@ def _need(t, name, dtype, shape=None):
 
 
 class FluidParams:
-    def __init__(self, model="navier_stokes", rho=1.0, mu=1.0, dt=1e-3):
+    def __init__(self, model="navier_stokes", rho=1.0, mu=1.0, dt=1e-3, body=(0.0, 0.0, 0.0)):
         m = {"stokes": FSIB_STOKES, "navier_stokes": FSIB_NAVIER_STOKES}[model]
-        self._s = _Params(m, float(rho), float(mu), float(dt))
-        self.model, self.rho, self.mu, self.dt = model, rho, mu, dt
+        b = tuple(float(x) for x in body) + (0.0,) * (3 - len(body))
+        self._s = _Params(m, float(rho), float(mu), float(dt), (ctypes.c_double * 3)(*b[:3]))
+        self.model, self.rho, self.mu, self.dt, self.body = model, rho, mu, dt, b[:3]
 
 
 class Force:
-    """Built-in force law: kind "tension2d" (closed curve) or "surface3d" (triangulated surface).
+    """Built-in force law.
 
-    For "surface3d" give tris (T,3) and the vertex->triangle CSR (ptr, idx) as int32 device tensors.
+    kind "tension2d" (closed curve), "surface3d" (triangulated surface: tris (T,3) and the
+    vertex->triangle CSR (ptr, idx)), "springs" (edge springs: the vertex->neighbour CSR as (ptr, idx)
+    and the stiffness of every CSR entry as `aux`, double; tris optional, used by the volume
+    diagnostic) or "target" (target points: `aux` = targets, double (M, dim)).  Index arrays are int32
+    device tensors.
     """
 
-    def __init__(self, kind, K, tris=None, v2t_ptr=None, v2t_idx=None):
-        k = {"tension2d": FSIB_FORCE_CURVE_TENSION, "surface3d": FSIB_FORCE_SURFACE_TENSION}[kind]
+    KINDS = {"tension2d": FSIB_FORCE_CURVE_TENSION, "surface3d": FSIB_FORCE_SURFACE_TENSION,
+             "springs": FSIB_FORCE_EDGE_SPRINGS, "target": FSIB_FORCE_TARGET}
+
+    def __init__(self, kind, K, tris=None, v2t_ptr=None, v2t_idx=None, aux=None):
+        k = self.KINDS[kind]
         self.kind = kind
-        self._keep = (tris, v2t_ptr, v2t_idx)
+        self._keep = (tris, v2t_ptr, v2t_idx, aux)
         ntris = 0
         if kind == "surface3d":
             _need(tris, "tris", torch.int32)
+        if kind in ("surface3d", "springs"):
             _need(v2t_ptr, "v2t_ptr", torch.int32)
             _need(v2t_idx, "v2t_idx", torch.int32)
+        if kind in ("springs", "target"):
+            _need(aux, "aux", torch.float64)
+        if tris is not None:
+            _need(tris, "tris", torch.int32)
             ntris = tris.shape[0]
-        self._s = _Force(k, float(K), _ptr(tris).value if tris is not None else None, ntris,
-                         _ptr(v2t_ptr).value if v2t_ptr is not None else None,
-                         _ptr(v2t_idx).value if v2t_idx is not None else None)
+        p = lambda t: _ptr(t).value if t is not None else None
+        self._s = _Force(k, float(K), p(tris), ntris, p(v2t_ptr), p(v2t_idx), p(aux))
+
+
+def spring_stiffness(X0, tris, v2t_ptr, v2t_idx, nbr_ptr, nbr_idx):
+    """Edge-spring stiffness per neighbour-CSR entry (sigma = 1) of the reference mesh X0 (device)."""
+    lib = load_library()
+    _need(X0, "X0", torch.float64)
+    for t, n in ((tris, "tris"), (v2t_ptr, "v2t_ptr"), (v2t_idx, "v2t_idx"), (nbr_ptr, "nbr_ptr"), (nbr_idx, "nbr_idx")):
+        _need(t, n, torch.int32)
+    kij = torch.empty(nbr_idx.shape[0], dtype=torch.float64, device=X0.device)
+    _check(lib.fsib_spring_stiffness(X0.shape[0], _ptr(X0), _ptr(tris), _ptr(v2t_ptr), _ptr(v2t_idx), _ptr(nbr_ptr),
+                                     _ptr(nbr_idx), _ptr(kij)), "fsib_spring_stiffness")
+    return kij
 
 
 def compute_force(force, X):
@@ -341,6 +370,18 @@ class Plan:
         _check(self._lib.fsib_fluid_step(self._h, ctypes.byref(params._s), _ptr(fhat), _ptr(uhat), _ptr(uhat_mid),
                                          _stream()), "fsib_fluid_step")
         return uhat
+
+    def pressure(self, params, fhat, uhat=None, out=None):
+        """Half spectrum of the pressure (fsib_pressure); uhat is needed for Navier-Stokes."""
+        shp = (self.dim,) + self.half_shape
+        _need(fhat, "fhat", self.cdtype, shp)
+        if uhat is not None:
+            _need(uhat, "uhat", self.cdtype, shp)
+        out = torch.empty(self.half_shape, dtype=self.cdtype, device=fhat.device) if out is None else \
+            _need(out, "phat", self.cdtype, self.half_shape)
+        _check(self._lib.fsib_pressure(self._h, ctypes.byref(params._s), _ptr(fhat), _ptr(uhat), _ptr(out),
+                                       _stream()), "fsib_pressure")
+        return out
 
     def velocity(self, params, force, X, uhat, out=None):
         M = self._X(X)

@@ -159,10 +159,10 @@ class ForceLaw:
     """A built-in force law with its stiffness K as a separate (differentiable) factor:
     F(X; K) = K F(X; 1), quadrature weight w (2 pi / M for the closed curve, 1 for the surface)."""
 
-    def __init__(self, kind, tris=None, v2t_ptr=None, v2t_idx=None):
+    def __init__(self, kind, tris=None, v2t_ptr=None, v2t_idx=None, aux=None):
         from ._binding import Force
         self.kind = kind
-        self.unit = Force(kind, 1.0, tris, v2t_ptr, v2t_idx)
+        self.unit = Force(kind, 1.0, tris, v2t_ptr, v2t_idx, aux)
 
     def weight(self, M):
         return 2.0 * math.pi / M if self.kind == "tension2d" else 1.0

@@ -475,6 +475,8 @@ fsib_status check_fluid(const Plan& p, const fsib_fluid_params* prm) {
     if (!(prm->rho > 0) || !std::isfinite(prm->rho)) return fail(FSIB_ERR_ARG, "rho must be positive");
   }
   if (!std::isfinite(prm->dt)) return fail(FSIB_ERR_ARG, "dt must be finite");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(prm->body[a])) return fail(FSIB_ERR_ARG, "body force must be finite");
   return FSIB_OK;
 }
 
@@ -490,6 +492,15 @@ fsib_status check_force(const fsib_force* f, int dim, int64_t M) {
     if (dim != 3) return fail(FSIB_ERR_ARG, "surface tension needs dim = 3");
     if (M > 0 && (!f->tris || !f->v2t_ptr || !f->v2t_idx || f->ntris <= 0))
       return fail(FSIB_ERR_ARG, "surface tension needs tris and the vertex-triangle CSR");
+    return FSIB_OK;
+  }
+  if (f->kind == FSIB_FORCE_EDGE_SPRINGS) {
+    if (M > 0 && (!f->v2t_ptr || !f->v2t_idx || !f->aux))
+      return fail(FSIB_ERR_ARG, "edge springs need the neighbour CSR and the stiffness per entry (aux)");
+    return FSIB_OK;
+  }
+  if (f->kind == FSIB_FORCE_TARGET) {
+    if (M > 0 && !f->aux) return fail(FSIB_ERR_ARG, "target points need the targets (aux)");
     return FSIB_OK;
   }
   return fail(FSIB_ERR_ARG, "unknown force kind");
@@ -724,6 +735,40 @@ fsib_status fsib_force_jvp(const fsib_force* force, int dim, int64_t M, const do
   if (M > 0 && (!X || !V || !out)) return fail(FSIB_ERR_ARG, "X, V and out must not be NULL");
   if (M > 0 && (out == X || out == V)) return fail(FSIB_ERR_ARG, "out must not alias X or V");
   FSIB_HIP(fsib::launch_force_jvp(*force, dim, M, X, V, out, S(stream)));
+  return FSIB_OK;
+}
+
+fsib_status fsib_spring_stiffness(int64_t M, const double* X0, const int32_t* tris, const int32_t* v2t_ptr,
+                                  const int32_t* v2t_idx, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                                  double* kij) {
+  if (M < 0) return fail(FSIB_ERR_ARG, "M must be >= 0");
+  if (M == 0) return FSIB_OK;
+  if (!X0 || !tris || !v2t_ptr || !v2t_idx || !nbr_ptr || !nbr_idx || !kij)
+    return fail(FSIB_ERR_ARG, "arrays must not be NULL");
+  int* missing = nullptr;
+  FSIB_HIP(hipMalloc(&missing, sizeof(int)));
+  hipError_t e = hipMemset(missing, 0, sizeof(int));
+  if (e == hipSuccess) e = fsib::launch_spring_stiffness(M, X0, tris, v2t_ptr, v2t_idx, nbr_ptr, nbr_idx, kij, missing,
+                                                         nullptr);
+  int h = 0;
+  if (e == hipSuccess) e = hipMemcpy(&h, missing, sizeof(int), hipMemcpyDeviceToHost);
+  (void)hipFree(missing);
+  FSIB_HIP(e);
+  if (h) return fail(FSIB_ERR_ARG, "a triangle edge is missing from the neighbour lists");
+  return FSIB_OK;
+}
+
+fsib_status fsib_pressure(fsib_plan plan, const fsib_fluid_params* params, const void* fhat_half,
+                          const void* uhat_half, void* phat_half, void* stream) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  FSIB_TRY(check_fluid(p, params));
+  if (!fhat_half || !phat_half) return fail(FSIB_ERR_ARG, "fhat_half and phat_half must not be NULL");
+  const int ns = params->model == FSIB_NAVIER_STOKES ? 1 : 0;
+  if (ns && !uhat_half) return fail(FSIB_ERR_ARG, "uhat_half must not be NULL for NAVIER_STOKES");
+  const hipStream_t st = S(stream);
+  if (ns) FSIB_TRY(dealiased_products(p, uhat_half, st));
+  FSIB_HIP(fsib::launch_pressure(p, ns, params->rho, fhat_half, phat_half, st));
   return FSIB_OK;
 }
 

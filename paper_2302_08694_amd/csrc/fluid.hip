@@ -37,7 +37,7 @@ __device__ __forceinline__ int sym_index(int a, int b, int dim) {
 }
 
 template <typename T, int DIM>
-__global__ void k_fluid(ModeGeo g, int mode, T rho, T mu, T dt, const cplx<T>* __restrict__ fhat,
+__global__ void k_fluid(ModeGeo g, int mode, T rho, T mu, T dt, T b0, T b1, T b2, const cplx<T>* __restrict__ fhat,
                         const cplx<T>* __restrict__ pihat, const cplx<T>* uin, cplx<T>* uout) {
   const int64_t nm = g.Hx * g.N[1] * (DIM == 3 ? g.N[2] : 1);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,6 +83,7 @@ __global__ void k_fluid(ModeGeo g, int mode, T rho, T mu, T dt, const cplx<T>* _
     cplx<T> s = mk((T)0, (T)0);
     for (int b = 0; b < DIM; ++b) s = s + mul_i(pihat[sym_index(a, b, DIM) * nm + idx], k[b]);
     P[a] = fhat[a * nm + idx] * inv_rho - s;
+    if (k2 == (T)0) P[a].x += (a == 0 ? b0 : (a == 1 ? b1 : b2)) * inv_rho;  // uniform body force
     kP = kP + P[a] * k[a];
   }
   const T k2p = k2 == (T)0 ? (T)1 : k2;
@@ -113,18 +114,89 @@ hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params&
     using T = double;
     if (p.dim == 3)
       hipLaunchKernelGGL((k_fluid<T, 3>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
-                         (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+                         (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
+                         (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
     else
       hipLaunchKernelGGL((k_fluid<T, 2>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
-                         (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+                         (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
+                         (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
   } else {
     using T = float;
     if (p.dim == 3)
       hipLaunchKernelGGL((k_fluid<T, 3>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
-                         (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+                         (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
+                         (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
     else
       hipLaunchKernelGGL((k_fluid<T, 2>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
-                         (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+                         (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
+                         (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
+  }
+  return hipGetLastError();
+}
+
+// Pressure (eq. pressure_poisson_k; Stokes: eq. stokeslet): phat = -i k.(fhat - rho shat)/|k|^2 with
+// shat_a = sum_b i k_b (u_a u_b)^ (ns = 1, products in pihat) or shat = 0 (ns = 0); phat(0) = 0.
+template <typename T, int DIM>
+__global__ void k_pressure(ModeGeo g, int ns, T rho, const cplx<T>* __restrict__ fhat,
+                           const cplx<T>* __restrict__ pihat, cplx<T>* __restrict__ phat) {
+  const int64_t nm = g.Hx * g.N[1] * (DIM == 3 ? g.N[2] : 1);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nm) return;
+  const int64_t ix = idx % g.Hx;
+  const int64_t iy = (idx / g.Hx) % g.N[1];
+  const int64_t iz = DIM == 3 ? idx / (g.Hx * g.N[1]) : 0;
+  const int64_t m[3] = {ix, mode_of(iy, g.N[1]), DIM == 3 ? mode_of(iz, g.N[2]) : 0};
+  bool nyq = false;
+  for (int a = 0; a < DIM; ++a)
+    if (g.N[a] % 2 == 0 && (a == 0 ? ix == g.N[0] / 2 : m[a] == -g.N[a] / 2)) nyq = true;
+  const T twopi_L = (T)(6.283185307179586476925286766559 / g.L);
+  T k[3];
+  T k2 = 0;
+  for (int a = 0; a < DIM; ++a) {
+    k[a] = twopi_L * (T)m[a];
+    k2 += k[a] * k[a];
+  }
+  if (nyq || k2 == (T)0) {
+    phat[idx] = mk((T)0, (T)0);
+    return;
+  }
+  cplx<T> kg = mk((T)0, (T)0);
+  for (int a = 0; a < DIM; ++a) {
+    cplx<T> ga = fhat[a * nm + idx];
+    if (ns) {
+      cplx<T> s = mk((T)0, (T)0);
+      for (int b = 0; b < DIM; ++b) s = s + mul_i(pihat[sym_index(a, b, DIM) * nm + idx], k[b]);
+      ga = ga - s * rho;
+    }
+    kg = kg + ga * k[a];
+  }
+  phat[idx] = mul_i(kg, -(T)1 / k2);
+}
+
+hipError_t launch_pressure(const Plan& p, int ns, double rho, const void* fhat, void* phat, hipStream_t st) {
+  ModeGeo g;
+  g.dim = p.dim;
+  for (int a = 0; a < 3; ++a) g.N[a] = p.N[a];
+  g.Hx = p.Hx;
+  g.L = p.L;
+  const int64_t nm = p.modes_half();
+  const unsigned nblk = (unsigned)((nm + 255) / 256);
+  if (p.prec == FSIB_F64) {
+    using T = double;
+    if (p.dim == 3)
+      hipLaunchKernelGGL((k_pressure<T, 3>), dim3(nblk), dim3(256), 0, st, g, ns, (T)rho, (const cplx<T>*)fhat,
+                         (const cplx<T>*)p.pihat, (cplx<T>*)phat);
+    else
+      hipLaunchKernelGGL((k_pressure<T, 2>), dim3(nblk), dim3(256), 0, st, g, ns, (T)rho, (const cplx<T>*)fhat,
+                         (const cplx<T>*)p.pihat, (cplx<T>*)phat);
+  } else {
+    using T = float;
+    if (p.dim == 3)
+      hipLaunchKernelGGL((k_pressure<T, 3>), dim3(nblk), dim3(256), 0, st, g, ns, (T)rho, (const cplx<T>*)fhat,
+                         (const cplx<T>*)p.pihat, (cplx<T>*)phat);
+    else
+      hipLaunchKernelGGL((k_pressure<T, 2>), dim3(nblk), dim3(256), 0, st, g, ns, (T)rho, (const cplx<T>*)fhat,
+                         (const cplx<T>*)p.pihat, (cplx<T>*)phat);
   }
   return hipGetLastError();
 }
@@ -195,11 +267,96 @@ __global__ __launch_bounds__(256) void k_force_surface(int64_t M, const double* 
   }
 }
 
+// Edge springs (Sec. 6.2.3, elastic sphere): F_i = K sum_{j linked with i} K_ij (X_j - X_i) over the
+// vertex's neighbour list (CSR), K_ij stored per entry.  Linear in X, so it also serves as its own
+// Jacobian product.
+__global__ void k_force_springs(int64_t M, int dim, const double* __restrict__ X, double K,
+                                const int32_t* __restrict__ ptr, const int32_t* __restrict__ nbr,
+                                const double* __restrict__ kij, double* __restrict__ F) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  double f[3] = {0, 0, 0};
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+    const int64_t j = nbr[e];
+    const double k = kij[e];
+    for (int a = 0; a < dim; ++a) f[a] += k * (X[j * dim + a] - X[i * dim + a]);
+  }
+  for (int a = 0; a < dim; ++a) F[i * dim + a] = K * f[a];
+}
+
+// Edge stiffness of the elastic sphere from its reference configuration X0 (Sec. 6.2.3), for sigma = 1:
+// entry (i -> j) of the neighbour CSR receives, from every triangle (i, j, k) holding edge ij,
+// (a0^2 + b0^2 - c0^2) / (8 S0) with c0 = |X_i - X_j|, a0, b0 the other two sides and S0 the area
+// (the cotangent of the angle at k, halved).  One thread per vertex, over its incident triangles.
+__global__ void k_spring_stiffness(int64_t M, const double* __restrict__ X0, const int32_t* __restrict__ tris,
+                                   const int32_t* __restrict__ v2t_ptr, const int32_t* __restrict__ v2t_idx,
+                                   const int32_t* __restrict__ nptr, const int32_t* __restrict__ nbr,
+                                   double* __restrict__ kij, int* __restrict__ missing) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int e0 = nptr[i], e1 = nptr[i + 1];
+  for (int e = e0; e < e1; ++e) kij[e] = 0.0;
+  for (int q = v2t_ptr[i]; q < v2t_ptr[i + 1]; ++q) {
+    const int t = v2t_idx[q];
+    const int v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+    const int r = v[0] == i ? 0 : (v[1] == i ? 1 : 2);
+    const int j = v[(r + 1) % 3], k = v[(r + 2) % 3];
+    double dij[3], dik[3], djk[3];
+    for (int a = 0; a < 3; ++a) {
+      dij[a] = X0[3 * j + a] - X0[3 * i + a];
+      dik[a] = X0[3 * k + a] - X0[3 * i + a];
+      djk[a] = X0[3 * k + a] - X0[3 * j + a];
+    }
+    const double cx = dij[1] * dik[2] - dij[2] * dik[1], cy = dij[2] * dik[0] - dij[0] * dik[2],
+                 cz = dij[0] * dik[1] - dij[1] * dik[0];
+    const double S0 = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    const double lij = dij[0] * dij[0] + dij[1] * dij[1] + dij[2] * dij[2];
+    const double lik = dik[0] * dik[0] + dik[1] * dik[1] + dik[2] * dik[2];
+    const double ljk = djk[0] * djk[0] + djk[1] * djk[1] + djk[2] * djk[2];
+    const double kij_t = (ljk + lik - lij) / (8.0 * S0);  // edge ij, opposite k
+    const double kik_t = (ljk + lij - lik) / (8.0 * S0);  // edge ik, opposite j
+    bool fj = false, fk = false;
+    for (int e = e0; e < e1; ++e) {
+      if (nbr[e] == j) {
+        kij[e] += kij_t;
+        fj = true;
+      } else if (nbr[e] == k) {
+        kij[e] += kik_t;
+        fk = true;
+      }
+    }
+    if (!fj || !fk) missing[0] = 1;
+  }
+}
+
+hipError_t launch_spring_stiffness(int64_t M, const double* X0, const int32_t* tris, const int32_t* v2t_ptr,
+                                   const int32_t* v2t_idx, const int32_t* nptr, const int32_t* nbr, double* kij,
+                                   int* missing, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spring_stiffness, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, X0, tris, v2t_ptr,
+                     v2t_idx, nptr, nbr, kij, missing);
+  return hipGetLastError();
+}
+
+// Target points (Sec. 6.2.2, channel walls): F_i = K (Xtarget_i - X_i); sign = -1 with Xtarget = NULL
+// gives the Jacobian product -K V.
+__global__ void k_force_target(int64_t n, const double* __restrict__ X, const double* __restrict__ tgt, double K,
+                               double* __restrict__ F) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  F[e] = K * ((tgt ? tgt[e] : 0.0) - X[e]);
+}
+
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F, hipStream_t st) {
   if (M <= 0) return hipSuccess;
   const unsigned nblk = (unsigned)((M + 255) / 256);
   if (f.kind == FSIB_FORCE_CURVE_TENSION)
     hipLaunchKernelGGL(k_force_curve, dim3(nblk), dim3(256), 0, st, M, X, f.K, F);
+  else if (f.kind == FSIB_FORCE_EDGE_SPRINGS)
+    hipLaunchKernelGGL(k_force_springs, dim3(nblk), dim3(256), 0, st, M, dim, X, f.K, f.v2t_ptr, f.v2t_idx, f.aux, F);
+  else if (f.kind == FSIB_FORCE_TARGET)
+    hipLaunchKernelGGL(k_force_target, dim3((unsigned)((M * dim + 255) / 256)), dim3(256), 0, st, M * dim, X, f.aux,
+                       f.K, F);
   else
     hipLaunchKernelGGL(k_force_surface, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, M, X, f.K, f.tris, f.v2t_ptr,
                        f.v2t_idx, F);  // four vertices (wavefronts) per workgroup
@@ -274,6 +431,12 @@ hipError_t launch_force_jvp(const fsib_force& f, int dim, int64_t M, const doubl
   if (M <= 0) return hipSuccess;
   if (f.kind == FSIB_FORCE_CURVE_TENSION)  // the curve force is linear in X: dF(X)[V] = F(V)
     hipLaunchKernelGGL(k_force_curve, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, V, f.K, out);
+  else if (f.kind == FSIB_FORCE_EDGE_SPRINGS)  // linear too
+    hipLaunchKernelGGL(k_force_springs, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, dim, V, f.K, f.v2t_ptr,
+                       f.v2t_idx, f.aux, out);
+  else if (f.kind == FSIB_FORCE_TARGET)  // dF[V] = -K V
+    hipLaunchKernelGGL(k_force_target, dim3((unsigned)((M * dim + 255) / 256)), dim3(256), 0, st, M * dim, V,
+                       (const double*)nullptr, f.K, out);
   else
     hipLaunchKernelGGL(k_force_surface_jvp, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, M, X, V, f.K, f.tris,
                        f.v2t_ptr, f.v2t_idx, out);
@@ -463,7 +626,7 @@ hipError_t launch_diag(const Plan& p, const fsib_fluid_params& prm, const fsib_f
                        (const cplx<T>*)uhat, p.part);
   }
   hipLaunchKernelGGL(k_diag_volume, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, p.dim, M, X,
-                     f.kind == FSIB_FORCE_SURFACE_TENSION ? f.tris : nullptr, f.ntris, p.part);
+                     f.ntris > 0 ? f.tris : nullptr, f.ntris, p.part);
   if (p.prec == FSIB_F64)
     hipLaunchKernelGGL(k_diag_final<double>, dim3(1), dim3(kDiagThreads), 0, st, p.dim, prm.rho, prm.mu, Ld,
                        (const cplx<double>*)uhat, p.modes_half(), (const double*)p.part, diag);

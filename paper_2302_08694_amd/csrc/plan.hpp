@@ -132,6 +132,10 @@ hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params&
                                const void* uin, void* uout, hipStream_t st);
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F,
                         hipStream_t st);
+hipError_t launch_pressure(const Plan& p, int ns, double rho, const void* fhat, void* phat, hipStream_t st);
+hipError_t launch_spring_stiffness(int64_t M, const double* X0, const int32_t* tris, const int32_t* v2t_ptr,
+                                   const int32_t* v2t_idx, const int32_t* nptr, const int32_t* nbr, double* kij,
+                                   int* missing, hipStream_t st);
 hipError_t launch_force_jvp(const fsib_force& f, int dim, int64_t M, const double* X, const double* V, double* out,
                             hipStream_t st);
 hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S,

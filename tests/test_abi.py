@@ -89,3 +89,20 @@ def test_force_jvp_rejects_bad_arguments():
     assert lib.fsib_force_jvp(ctypes.byref(g), 4, 10, None, None, None, None) == 1
     assert lib.fsib_force_jvp(ctypes.byref(g), 2, -1, None, None, None, None) == 1
     assert lib.fsib_force_jvp(ctypes.byref(g), 2, 0, None, None, None, None) == 0  # nothing to do
+
+
+def test_new_force_kinds_and_pressure_reject_bad_arguments():
+    lib = B.load_library()
+    for kind in (B.FSIB_FORCE_EDGE_SPRINGS, B.FSIB_FORCE_TARGET):
+        f = B._Force(kind, 1.0, None, 0, None, None, None)  # no CSR / no targets
+        assert lib.fsib_compute_force(ctypes.byref(f), 3, 10, None, None, None) == 1
+        assert lib.fsib_force_jvp(ctypes.byref(f), 2, 10, None, None, None, None) == 1
+        assert lib.fsib_compute_force(ctypes.byref(f), 3, 0, None, None, None) == 0  # nothing to do
+    assert lib.fsib_pressure(None, None, None, None, None, None) == 1
+
+
+def test_fluid_params_layout():
+    # the C struct is {int; double rho, mu, dt; double body[3]}
+    assert ctypes.sizeof(B._Params) == 8 + 3 * 8 + 3 * 8
+    assert B._Params.body.offset == 32
+    assert ctypes.sizeof(B._Force) == 7 * 8
