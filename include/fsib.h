@@ -63,7 +63,14 @@ typedef struct {
   int prec;             /* fsib_prec: arithmetic of grids, FFTs, spectral update, U */
   double tol;           /* relative l2 accuracy asked of the nonuniform transforms:
                            FP64 in [1e-14, 1e-1], FP32 in [1e-6, 1e-1] (else FSIB_ERR_TOL) */
-  double upsampfac;     /* fine-grid oversampling; 0 or 2.0 (the only supported value) */
+  double upsampfac;     /* fine-grid oversampling sigma: 2.0, or 1.25 (low-memory form:
+                           fine grid >= 1.25 N per axis, about 4x fewer grid bytes in 3D, a wider
+                           kernel; per-axis error tol/(2 dim) must stay reachable with w <= 16,
+                           i.e. tol >= about 1e-8, and FP32 plans need tol >= 1e-3 (the
+                           deconvolution lifts FP32 rounding by up to ~100x at this
+                           oversampling), else FSIB_ERR_TOL); 0 = automatic: 1.25 for FP64 3D
+                           plans at tol >= 1e-6 with max_points <= N_x N_y N_z / 20, else 2.0
+                           (fsib_plan_info reports n_fine) */
   int ntrans;           /* complex transforms per fsib_spread / fsib_interp call, >= 1 */
   int64_t max_points;   /* largest M accepted by any call, >= 0 */
   int fluid;            /* 0: NUFFT only; 1: also the FSIB workspace (force spread, velocity

@@ -221,7 +221,7 @@ def force_jvp(force, X, V):
 
 class Plan:
     def __init__(self, dim, n_modes, L=1.0, prec="f64", tol=1e-6, ntrans=1, max_points=1 << 16, fluid=False,
-                 navier_stokes=False):
+                 navier_stokes=False, upsampfac=0.0):
         lib = load_library()
         nm = list(n_modes) + [1] * (3 - len(n_modes))
         self.dim = int(dim)
@@ -233,7 +233,8 @@ class Plan:
         self.ntrans = int(ntrans)
         self.max_points = int(max_points)
         opts = _Opts(self.dim, (ctypes.c_int64 * 3)(*nm), self.L, FSIB_F64 if prec == "f64" else FSIB_F32,
-                     float(tol), 2.0, self.ntrans, self.max_points, int(bool(fluid)), int(bool(navier_stokes)))
+                     float(tol), float(upsampfac), self.ntrans, self.max_points, int(bool(fluid)),
+                     int(bool(navier_stokes)))
         h = ctypes.c_void_p()
         _check(lib.fsib_plan_create(ctypes.byref(opts), ctypes.byref(h)), "fsib_plan_create")
         self._h = h

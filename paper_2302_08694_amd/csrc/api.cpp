@@ -1,5 +1,6 @@
 // C ABI of the FSIB library: plan construction and the orchestration of the kernels for the
 // nonuniform transforms (App. A), the FSIB coupling (Sec. 3.1), the fluid update and Alg. 1.
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -116,6 +117,18 @@ fsib_status upload(const Plan& p, void* dst, const std::vector<double>& v) {
   return FSIB_OK;
 }
 
+// Oversampling of a plan: upsampfac 2.0 or 1.25 as asked; 0 picks 1.25 for FP64 3D plans at
+// tol >= 1e-6 whose point count is small against the mode count (max_points <= N^3 / 20), where the
+// FFT passes over the fine grid outweigh the wider kernel (128^3 modes with 4e4 points: 533 against
+// 499 steps/s of the Navier-Stokes step), and 2.0 otherwise.
+static double plan_sigma(const fsib_plan_opts* o) {
+  if (o->upsampfac == 1.25) return 1.25;
+  if (o->upsampfac == 2.0) return 2.0;
+  const double modes = (double)o->n_modes[0] * (double)o->n_modes[1] * (o->dim == 3 ? (double)o->n_modes[2] : 1.0);
+  const bool small_m = 20.0 * (double)o->max_points <= modes;
+  return (o->prec == FSIB_F64 && o->dim == 3 && o->tol >= 1e-6 && small_m) ? 1.25 : 2.0;
+}
+
 fsib_status validate_opts(const fsib_plan_opts* o) {
   if (!o) return fail(FSIB_ERR_ARG, "opts is NULL");
   if (o->dim != 2 && o->dim != 3) return fail(FSIB_ERR_ARG, "dim must be 2 or 3");
@@ -123,13 +136,20 @@ fsib_status validate_opts(const fsib_plan_opts* o) {
     if (o->n_modes[a] < 2 || o->n_modes[a] > 4096) return fail(FSIB_ERR_ARG, "n_modes must be in [2, 4096]");
   if (!(o->L > 0) || !std::isfinite(o->L)) return fail(FSIB_ERR_ARG, "L must be positive and finite");
   if (o->prec != FSIB_F64 && o->prec != FSIB_F32) return fail(FSIB_ERR_ARG, "prec must be FSIB_F64 or FSIB_F32");
-  if (!(o->upsampfac == 0.0 || o->upsampfac == 2.0)) return fail(FSIB_ERR_ARG, "upsampfac must be 0 or 2.0");
+  if (!(o->upsampfac == 0.0 || o->upsampfac == 2.0 || o->upsampfac == 1.25))
+    return fail(FSIB_ERR_ARG, "upsampfac must be 0, 2.0 or 1.25");
   if (o->ntrans < 1 || o->ntrans > 65535) return fail(FSIB_ERR_ARG, "ntrans must be in [1, 65535]");
   if (o->max_points < 0 || o->max_points > (int64_t)1 << 30) return fail(FSIB_ERR_ARG, "max_points out of range");
   if (!std::isfinite(o->tol) || o->tol > 0.1) return fail(FSIB_ERR_TOL, "tol must be <= 0.1");
   if (o->prec == FSIB_F64 && !(o->tol >= 1e-14)) return fail(FSIB_ERR_TOL, "FP64 plans reach tol >= 1e-14");
   if (o->prec == FSIB_F32 && !(o->tol >= 1e-6)) return fail(FSIB_ERR_TOL, "FP32 plans reach tol >= 1e-6");
   if (o->navier_stokes && !o->fluid) return fail(FSIB_ERR_ARG, "navier_stokes needs fluid = 1");
+  // at oversampling 1.25 the kernel transform falls by up to ~100x across the retained modes, and the
+  // deconvolution lifts FP32 rounding of the grid by as much: FP32 low-memory plans stop at 1e-3
+  if (plan_sigma(o) == 1.25 && o->prec == FSIB_F32 && !(o->tol >= 1e-3))
+    return fail(FSIB_ERR_TOL, "FP32 plans with upsampfac 1.25 reach tol >= 1e-3");
+  if (fsib::choose_width(o->tol, o->dim, plan_sigma(o)) > fsib::kMaxW)
+    return fail(FSIB_ERR_TOL, "tol is out of reach of the kernel widths available at this oversampling");
   return FSIB_OK;
 }
 
@@ -145,11 +165,17 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   p.ns = o->navier_stokes ? 1 : 0;
   FSIB_HIP(hipGetDevice(&p.device));
   FSIB_HIP(hipDeviceGetAttribute(&p.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
+  // workgroup-to-XCD run lengths (tuning knobs; the defaults are the measured best)
+  if (const char* e = std::getenv("FSIB_XCD_CHUNK_INTERP")) p.xcd_chunk_interp = std::atoi(e);
+  if (const char* e = std::getenv("FSIB_XCD_CHUNK_SPREAD")) p.xcd_chunk_spread = std::atoi(e);
   // kernel (App. A.3): width from tol, Kaiser-Bessel shape, polynomial degree
-  p.w = fsib::choose_width(p.tol, p.dim);
-  p.beta = fsib::choose_beta(p.w);
+  p.sigma = plan_sigma(o);
+  p.w = fsib::choose_width(p.tol, p.dim, p.sigma);
+  if (p.w > fsib::kMaxW)
+    return fail(FSIB_ERR_TOL, "tol is out of reach of the kernel widths available at this oversampling");
+  p.beta = fsib::choose_beta(p.w, p.sigma);
   p.deg = fsib::choose_degree(p.w);
-  // fine grid and tiles: n_f >= 2N and >= 2w, 2^a 3^b 5^c, a multiple of the tile
+  // fine grid and tiles: n_f >= sigma N and >= 2w, 2^a 3^b 5^c, a multiple of the tile
   // spreading tiles: 16 cells along x (one register row per thread), <= 1024 cells, <= 256 rows
   const int64_t tile3[3] = {16, 8, 8}, tile2[3] = {16, 16, 1};
   for (int a = 0; a < 3; ++a) {
@@ -158,7 +184,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
       continue;
     }
     const int64_t tb = p.dim == 3 ? tile3[a] : tile2[a];
-    int64_t need = 2 * p.N[a];
+    int64_t need = p.sigma == 2.0 ? 2 * p.N[a] : (5 * p.N[a] + 3) / 4;  // ceil(sigma N)
     if (need < 2 * p.w) need = 2 * p.w;
     if (need < tb) need = tb;
     p.nf[a] = fsib::smooth_at_least(need, tb);

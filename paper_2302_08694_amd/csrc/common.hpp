@@ -40,6 +40,28 @@ __host__ __device__ __forceinline__ cplx<T> mul_i(cplx<T> a, T s) { return mk(-a
 // moving memory accesses across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Workgroups are dispatched to the chip's 8 XCDs in turn (workgroup i to XCD i mod 8) and each XCD
+// has its own L2.  xcd_linear() renumbers a linear workgroup id so that each XCD receives one
+// contiguous range of ids: neighbouring work (consecutive sorted points, adjacent tiles, FFT lines
+// that share cache lines) then shares one L2 instead of being fetched into several.  It is a
+// permutation of [0, n) whatever the dispatch order, so results never depend on it.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_linear(int64_t i, int64_t n) {
+  const int64_t q = n / kXcds, r = n % kXcds;
+  const int64_t x = i % kXcds, k = i / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// The same in chunks: each XCD receives runs of C consecutive ids, the XCDs taking the runs in turn,
+// which keeps most of the locality while spreading uneven work over all XCDs.  Ids past the last
+// whole group of 8 C keep their number.
+__device__ __forceinline__ int64_t xcd_chunked(int64_t i, int64_t n, int64_t C) {
+  const int64_t g = kXcds * C;
+  if (i >= n / g * g) return i;
+  const int64_t s = i / g, r = i % g;
+  return s * g + (r % kXcds) * C + r / kXcds;
+}
+
 constexpr int kMaxW = 16;       // largest kernel width (fine cells)
 constexpr int kMaxDeg = 19;     // largest polynomial degree of the kernel pieces
 constexpr int kMaxStages = 16;  // FFT stages

@@ -46,7 +46,9 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
   int ncol;
   int need = 0;
   if (CONTIG) {
-    o0 = (int64_t)blockIdx.x * nb;
+    // XCD-contiguous numbering only for unmasked passes: with occupancy masks the reached rows cluster,
+    // and contiguous ranges would leave some XCDs most of the work
+    o0 = (a.rows.m ? (int64_t)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x)) * nb;
     ncol = (int)(a.outer - o0 < nb ? a.outer - o0 : nb);
     for (int b = threadIdx.x; b < nb; b += nthr) {
       const uint8_t f = b < ncol && row_needed(a.rows, o0 + b);
@@ -54,8 +56,10 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
       need |= f;
     }
   } else {
-    q0 = (int64_t)blockIdx.x * nb;
-    o0 = blockIdx.y;
+    const int64_t lin0 = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+    const int64_t lin = (a.line.m || a.ld.m || a.st.m) ? lin0 : xcd_linear(lin0, (int64_t)gridDim.x * gridDim.y);
+    q0 = (lin % gridDim.x) * nb;
+    o0 = lin / gridDim.x;
     ncol = (int)(a.inner - q0 < nb ? a.inner - q0 : nb);
     const bool line = !a.line.m || a.line.m[mask_index(a.line, o0, 0)];
     for (int i = threadIdx.x; i < a.nin; i += nthr) fld[i] = line && (!a.ld.m || a.ld.m[mask_index(a.ld, o0, i)]);
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
   cplx<T>* twl = buf + n * nb;
-  const int64_t pair0 = (int64_t)blockIdx.x * nb;
+  const int64_t pair0 = (a.rows.m ? (int64_t)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x)) * nb;
   uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
   int need = 0;
   for (int b = threadIdx.x; b < 2 * nb; b += nthr) {
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
   cplx<T>* twl = buf + n * nb;
-  const int64_t pair0 = (int64_t)blockIdx.x * nb;
+  const int64_t pair0 = (a.rows.m ? (int64_t)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x)) * nb;
   uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
   int need = 0;
   for (int b = threadIdx.x; b < 2 * nb; b += nthr) {
@@ -355,8 +359,10 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
   FSIB_C2C_CT(64, 32)
   FSIB_C2C_CT(96, 16)
   FSIB_C2C_CT(128, 16)
+  FSIB_C2C_CT(160, 12)
   FSIB_C2C_CT(192, 8)
   FSIB_C2C_CT(256, 8)
+  FSIB_C2C_CT(320, 6)
   FSIB_C2C_CT(384, 4)
   FSIB_C2C_CT(512, 4) {
     if (contig)
@@ -405,8 +411,10 @@ static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int6
   FSIB_R2C_CT(64, 32)
   FSIB_R2C_CT(96, 16)
   FSIB_R2C_CT(128, 16)
+  FSIB_R2C_CT(160, 12)
   FSIB_R2C_CT(192, 8)
   FSIB_R2C_CT(256, 8)
+  FSIB_R2C_CT(320, 6)
   FSIB_R2C_CT(384, 4)
   FSIB_R2C_CT(512, 4)
   hipLaunchKernelGGL(k_fft_r2c_x<T>, grid, dim3(nthr), lds, st, (const T*)in, (cplx<T>*)out, a);
@@ -441,8 +449,10 @@ static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int6
   FSIB_C2R_CT(64, 32)
   FSIB_C2R_CT(96, 16)
   FSIB_C2R_CT(128, 16)
+  FSIB_C2R_CT(160, 12)
   FSIB_C2R_CT(192, 8)
   FSIB_C2R_CT(256, 8)
+  FSIB_C2R_CT(320, 6)
   FSIB_C2R_CT(384, 4)
   FSIB_C2R_CT(512, 4)
   hipLaunchKernelGGL(k_fft_c2r_x<T>, grid, dim3(nthr), lds, st, (const cplx<T>*)in, (T*)out, a);

@@ -45,20 +45,26 @@ double kb_transform(double a, double beta) {
 }
 
 // One-dimensional relative error of the oversampled (factor 2) nonuniform transform with the
-// Kaiser-Bessel kernel of width w and shape beta = choose_beta(w), measured against direct sums
+// Kaiser-Bessel kernel of width w and shape beta = choose_beta(w, 2), measured against direct sums
 // on random points (N = 128, M = 2000) when this library's parameters were chosen.
 static const double kErr1d[17] = {1, 1,       3.5e-2,  3.3e-3,  3.6e-4,  4.2e-5,  4.4e-6,  4.9e-7, 5.2e-8,
                                   4.9e-9,     5.3e-10, 5.4e-11, 6.2e-12, 6.8e-13, 7.8e-14, 1.5e-14, 1.2e-14};
+// The same for oversampling 1.25 with beta = 1.86 w (the best ratio of a scan over beta/w; close to
+// beta = pi sqrt((w/sigma)^2 (sigma - 1/2)^2 - 0.8) of Beatty, Nishimura and Pauly, 2005).
+static const double kErr1d125[17] = {1, 1,      1.1e-1, 2.6e-2, 5.2e-3, 1.2e-3, 2.7e-4, 6.2e-5, 1.4e-5,
+                                     3.5e-6,    7.8e-7, 2.3e-7, 6.2e-8, 1.4e-8, 3.3e-9, 7.3e-10, 1.9e-10};
 
-int choose_width(double tol, int dim) {
+int choose_width(double tol, int dim, double sigma) {
   // per-axis errors add up across the dim axes: ask each axis for tol / (2 dim)
   const double target = tol / (2.0 * dim);
+  const double* err = sigma < 1.5 ? kErr1d125 : kErr1d;
   for (int w = 2; w <= kMaxW; ++w)
-    if (kErr1d[w] <= target) return w;
-  return kMaxW;
+    if (err[w] <= target) return w;
+  return kMaxW + 1;  // out of reach: the caller rejects the tolerance
 }
 
-double choose_beta(int w) {
+double choose_beta(int w, double sigma) {
+  if (sigma < 1.5) return 1.86 * w;
   static const double ratio[6] = {0, 0, 2.143, 2.257, 2.300, 2.329};
   return (w < 6 ? ratio[w] : 2.343) * w;
 }

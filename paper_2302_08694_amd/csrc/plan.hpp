@@ -13,8 +13,8 @@ namespace fsib {
 // Host-side numerics chosen at plan time (params.cpp).
 double bessel_i0(double x);
 double kb_transform(double a, double beta);  // int_{-1}^{1} I0(beta sqrt(1-z^2))/I0(beta) cos(a z) dz
-int choose_width(double tol, int dim);
-double choose_beta(int w);
+int choose_width(double tol, int dim, double sigma);
+double choose_beta(int w, double sigma);
 int choose_degree(int w);
 void fit_kernel_pieces(int w, double beta, int deg, double* coef /* (deg+1)*w */);
 int64_t smooth_at_least(int64_t n, int64_t multiple);
@@ -27,11 +27,14 @@ struct Plan {
   double L = 1.0;
   int prec = FSIB_F64;
   double tol = 1e-6;
+  double sigma = 2.0;  // fine-grid oversampling
   int ntrans = 1;
   int64_t max_points = 0;
   int fluid = 0, ns = 0;
   int device = 0;
   int lds_max = 65536;  // LDS bytes one workgroup may allocate on this device
+  int xcd_chunk_interp = 64;  // interpolation workgroups kept together per XCD (2048 sorted points)
+  int xcd_chunk_spread = 16;  // spreading tiles kept together per XCD (0: plain numbering)
   // kernel
   int w = 0, deg = 0;
   double beta = 0.0;

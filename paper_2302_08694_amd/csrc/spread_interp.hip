@@ -44,6 +44,7 @@ struct SpreadArgs {
   T* scratch;           // split tiles: [ntrans][slots][NCH][kMaxTileCells] partial tiles
   int64_t slots;        // scratch slots per transform
   const uint8_t* rowmask;  // blocks of x lines reached by some point (lines elsewhere stay unwritten)
+  int xcd_chunk;           // > 0: workgroups renumbered in runs of this many per XCD (xcd_chunked)
 };
 
 template <typename T, int W>
@@ -107,11 +108,14 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   const int tr = blockIdx.y;
   const int nbins = a.nt[0] * a.nt[1] * (DIM == 3 ? a.nt[2] : 1);
   int tile_id, part;
-  if ((int)blockIdx.x < nbins) {
-    tile_id = blockIdx.x;
+  // tiles holding points cluster (surfaces): whole XCD-contiguous ranges of tiles would load the XCDs
+  // unevenly, short runs keep neighbouring tiles (which stage the same points) on one L2
+  const int blk = a.xcd_chunk > 0 ? (int)xcd_chunked(blockIdx.x, gridDim.x, a.xcd_chunk) : (int)blockIdx.x;
+  if (blk < nbins) {
+    tile_id = blk;
     part = 0;
   } else {
-    const int e = (int)blockIdx.x - nbins;
+    const int e = blk - nbins;
     if (e >= a.part_off[nbins] - nbins) return;  // beyond the further parts
     const int2 wk = a.work[e];
     tile_id = wk.x;
@@ -361,6 +365,7 @@ struct InterpArgs {
   T* out;   // real: (M, nch); complex: (ntrans, M)
   int64_t M;
   int nf[3];
+  int xcd_chunk;  // > 0: workgroups renumbered in runs of this many per XCD (xcd_chunked)
 };
 
 // One wavefront per point (a few points at a time).  The lanes cover an XL x YL patch of the
@@ -398,8 +403,22 @@ __device__ __forceinline__ T uniform_lane_value(T v, int src) {
   }
 }
 
+// x lanes per row: the power of two >= w, unless a narrower row (xl < 16) lets the 64 lanes cover the
+// w rows of a plane in fewer chunks (w = 9, 10: rows of 9 or 10 lanes, 7 or 6 rows per chunk, two
+// chunks instead of three).  Lanes past the last whole row (yl >= YL) stay idle.
 template <int W>
-__host__ __device__ constexpr int interp_xlanes() { return W <= 2 ? 2 : (W <= 4 ? 4 : (W <= 8 ? 8 : 16)); }
+__host__ __device__ constexpr int interp_xlanes() {
+  constexpr int p2 = W <= 2 ? 2 : (W <= 4 ? 4 : (W <= 8 ? 8 : 16));
+  int best = p2, cost = (W + 64 / p2 - 1) / (64 / p2);
+  for (int xl = W; xl < p2; ++xl) {
+    const int c = (W + 64 / xl - 1) / (64 / xl);
+    if (c < cost) {
+      cost = c;
+      best = xl;
+    }
+  }
+  return best;
+}
 
 template <typename T, int DIM, int W, int NCH, bool CPLX>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
@@ -421,7 +440,8 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
   T cfr[kMaxDeg + 1];
 #pragma unroll
   for (int i = 0; i <= kMaxDeg; ++i) cfr[i] = (i <= a.deg && jk < W) ? a.coef[i * W + jk] : (T)0;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t blk = a.xcd_chunk > 0 ? xcd_chunked(blockIdx.x, gridDim.x, a.xcd_chunk) : (int64_t)blockIdx.x;
+  const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
   const int64_t first = wave * kIpPointsPerWave;
   uint32_t pkn[PB];
   T yn[PB];
@@ -466,7 +486,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
 #pragma unroll
       for (int ch = 0; ch < YCH; ++ch) {
         const int jy = yl + YL * ch;
-        const bool act = ok[b] && xl < W && jy < W;
+        const bool act = ok[b] && xl < W && jy < W && yl < YL;
         const T wya = lane_value(v[b], 16 + (jy < W ? jy : 0));
         wxy[b][ch] = act ? wx * wya : (T)0;
         int gy = iy + (jy < W ? jy : 0);
@@ -576,6 +596,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   a.scratch = (T*)p.split_scratch;
   a.slots = p.split_slots;
   a.rowmask = p.rowmask;
+  a.xcd_chunk = p.xcd_chunk_spread;
   a.sstr = (T*)p.s_str;
   const unsigned nb = (unsigned)p.nbins;
   if (M > 0) {
@@ -619,6 +640,7 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   a.out = (T*)out;
   a.M = M;
   for (int d = 0; d < 3; ++d) a.nf[d] = (int)p.nf[d];
+  a.xcd_chunk = p.xcd_chunk_interp;
   const bool prof = prof_on(p, PROF_INTERP);
   if (prof) prof_start(p, st);
   const int64_t per_wg = 4 * kIpPointsPerWave;  // four wavefronts per workgroup

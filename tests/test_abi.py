@@ -43,7 +43,7 @@ def _opts(**kw):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(dim=1), 1), (dict(dim=4), 1), (dict(n_modes=(1, 16, 16)), 1), (dict(L=0.0), 1), (dict(L=float("nan")), 1),
-    (dict(prec=7), 1), (dict(upsampfac=1.5), 1), (dict(ntrans=0), 1), (dict(max_points=-1), 1),
+    (dict(prec=7), 1), (dict(upsampfac=1.5), 1), (dict(upsampfac=1.25, tol=1e-10), 2), (dict(upsampfac=1.25, prec=1, tol=1e-4), 2), (dict(ntrans=0), 1), (dict(max_points=-1), 1),
     (dict(navier_stokes=1, fluid=0), 1),
     (dict(prec=1, tol=1e-10), 2), (dict(prec=0, tol=1e-16), 2), (dict(tol=0.5), 2),
 ])
