@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
-  cplx<T>* twl = buf + n * nb;
+  cplx<T>* twl = buf + (CONTIG ? lpad_len(n * nb) : n * nb);
   stage_twiddles(a.tw, twl, n);
   // occupancy flags of this workgroup's rows (x passes) or of the entries it loads and stores
   // (strided passes), fetched once; the workgroup leaves when nothing it owns is reached by a point
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
-  cplx<T>* twl = buf + n * nb;
+  cplx<T>* twl = buf + lpad_len(n * nb);
   const int64_t pair0 = (a.rows.m ? (int64_t)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x)) * nb;
   uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
   int need = 0;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
     const int e = threadIdx.x + j * nthr;
-    if (e < n * nb) buf[e] = v[j];  // [b][t] layout: e = b*n + t
+    if (e < n * nb) buf[lpad(e)] = v[j];  // [b][t] layout: e = b*n + t
   }
   __syncthreads();
   if constexpr (N > 0)
@@ -195,8 +195,8 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
     const int b = e / a.nout, m = e - b * a.nout;
     const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
     if (r0 >= a.outer) continue;
-    const cplx<T> Z = buf[b * n + m];
-    const cplx<T> Zc = conj(buf[b * n + (m == 0 ? 0 : n - m)]);
+    const cplx<T> Z = buf[lpad(b * n + m)];
+    const cplx<T> Zc = conj(buf[lpad(b * n + (m == 0 ? 0 : n - m))]);
     T f = a.scale * (T)0.5;
     if (a.fac_out) f *= a.fac_out[m];
     const cplx<T> s = Z + Zc, d = Z - Zc;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
-  cplx<T>* twl = buf + n * nb;
+  cplx<T>* twl = buf + lpad_len(n * nb);
   const int64_t pair0 = (a.rows.m ? (int64_t)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x)) * nb;
   uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
   int need = 0;
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
           y = conj(y);
         }
       }
-      buf[e] = mk(x.x - y.y, x.y + y.x);
+      buf[lpad(e)] = mk(x.x - y.y, x.y + y.x);
     }
   }
   __syncthreads();
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
     if (e >= n * nb) continue;
     const int b = e / n, t = e - b * n;
     const int64_t r0 = 2 * (pair0 + b), r1 = r0 + 1;
-    const cplx<T> z = buf[e];
+    const cplx<T> z = buf[lpad(e)];
     if (fl[2 * b]) out[r0 * n + t] = z.x * a.scale;
     if (fl[2 * b + 1]) out[r1 * n + t] = z.y * a.scale;
   }
@@ -341,7 +341,8 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
   const bool contig = inner == 1;
   a.nb = lines_per_block<T>(n, contig ? outer : inner);
   const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(contig ? a.nb : nin);
+  const size_t lds = (size_t)((contig ? lpad_len(n * a.nb) : n * a.nb) + n) * sizeof(cplx<T>) +
+                     flag_bytes(contig ? a.nb : nin);
   const bool prof = !contig && prof_on(p, PROF_FFT_STRIDED);
   if (prof) prof_start(p, st);
   const dim3 grid = contig ? dim3((unsigned)((outer + a.nb - 1) / a.nb))
@@ -400,7 +401,7 @@ static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int6
   const int64_t pairs = (rows + 1) / 2;
   a.nb = lines_per_block<T>(n, pairs);
   const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
+  const size_t lds = (size_t)(lpad_len(n * a.nb) + n) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
   const bool prof = prof_on(p, PROF_FFT_X);
   if (prof) prof_start(p, st);
   const dim3 grid((unsigned)((pairs + a.nb - 1) / a.nb));
@@ -438,7 +439,7 @@ static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int6
   const int64_t pairs = (rows + 1) / 2;
   a.nb = lines_per_block<T>(n, pairs);
   const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)n * (a.nb + 1) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
+  const size_t lds = (size_t)(lpad_len(n * a.nb) + n) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
   const bool prof = prof_on(p, PROF_FFT_X);
   if (prof) prof_start(p, st);
   const dim3 grid((unsigned)((pairs + a.nb - 1) / a.nb));

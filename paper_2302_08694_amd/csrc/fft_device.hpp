@@ -68,10 +68,17 @@ __device__ __forceinline__ void bfly(cplx<T>* u, T sg) {
   }
 }
 
-// LDS index of entry t of line b: lines contiguous (x passes) or interleaved (strided passes).
+// Contiguous lines in LDS are padded by one entry per 8: a Stockham stage writes its outputs R
+// entries apart, and unpadded the lanes of a wavefront would hit the same few banks (measured
+// bank-conflict cycles above the kernel's busy cycles in the fused nonlinear pass).
+__host__ __device__ constexpr int lpad(int x) { return x + (x >> 3); }
+__host__ __device__ constexpr int lpad_len(int m) { return m + (m >> 3) + 1; }  // entries for m lines' worth
+
+// LDS index of entry t of line b: lines contiguous and padded (x passes) or interleaved (strided
+// passes, whose lanes already write whole 128-byte runs).
 template <bool CONTIG>
 __device__ __forceinline__ int lidx(int t, int b, int n, int nb) {
-  return CONTIG ? b * n + t : t * nb + b;
+  return CONTIG ? lpad(b * n + t) : t * nb + b;
 }
 
 // Copies the n twiddles into LDS (caller synchronises before the first stage).

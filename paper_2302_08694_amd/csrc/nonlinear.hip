@@ -23,7 +23,7 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nthr = N > 0 ? NTHR : (int)blockDim.x, pp = N > 0 ? PP : pp_arg;
-  cplx<T>* twl = buf + FL * pp * n;
+  cplx<T>* twl = buf + lpad_len(FL * pp * n);  // lines padded (lpad)
   stage_twiddles(a.tw, twl, n);
   const int64_t pair0 = (int64_t)blockIdx.x * pp;
   const int64_t cs = rows * hx;  // component stride of in/out
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
         x = conj(x);
         y = conj(y);
       }
-      buf[e] = mk(x.x - y.y, x.y + y.x);
+      buf[lpad(e)] = mk(x.x - y.y, x.y + y.x);
     }
   }
   __syncthreads();
@@ -90,10 +90,10 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
     if (e < pp * n) {
       const int q = e / n, t = e - q * n;
       pos[j] = e;
-      const cplx<T> l0 = buf[(q * IL + 0) * n + t], l1 = buf[(q * IL + 1) * n + t];
+      const cplx<T> l0 = buf[lpad((q * IL + 0) * n + t)], l1 = buf[lpad((q * IL + 1) * n + t)];
       const T uxa = l0.x, uya = l0.y, uxb = l1.x, uyb = l1.y;
       if constexpr (DIM == 3) {
-        const cplx<T> l2 = buf[(q * IL + 2) * n + t];
+        const cplx<T> l2 = buf[lpad((q * IL + 2) * n + t)];
         const T uza = l2.x, uzb = l2.y;
         pa[j][0] = uxa * uxa; pa[j][1] = uxa * uya; pa[j][2] = uxa * uza;
         pa[j][3] = uya * uya; pa[j][4] = uya * uza; pa[j][5] = uza * uza;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
     if (pos[j] >= 0) {
       const int q = pos[j] / n, t = pos[j] - q * n;
 #pragma unroll
-      for (int f = 0; f < FL; ++f) buf[(q * FL + f) * n + t] = mk(pa[j][f], pb[j][f]);
+      for (int f = 0; f < FL; ++f) buf[lpad((q * FL + f) * n + t)] = mk(pa[j][f], pb[j][f]);
     }
   }
   __syncthreads();
@@ -126,8 +126,8 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
     const int q = ln / FL, f = ln - q * FL;
     const int64_t ra = 2 * (pair0 + q), rb = ra + 1;
     if (ra >= rows) continue;
-    const cplx<T> Z = buf[ln * n + m];
-    const cplx<T> Zc = conj(buf[ln * n + (m == 0 ? 0 : n - m)]);
+    const cplx<T> Z = buf[lpad(ln * n + m)];
+    const cplx<T> Zc = conj(buf[lpad(ln * n + (m == 0 ? 0 : n - m))]);
     const T s = (T)0.5 * inv_cells;
     const cplx<T> su = Z + Zc, d = Z - Zc;
     out[f * cs + ra * hx + m] = su * s;
@@ -164,7 +164,7 @@ static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t 
   const int64_t pairs = (rows + 1) / 2;
   if (pp > pairs) pp = (int)pairs;
   const int nthr = (fl * pp * n + kEPT - 1) / kEPT;
-  const size_t lds = (size_t)(fl * pp + 1) * n * sizeof(cplx<T>);
+  const size_t lds = (size_t)(lpad_len(fl * pp * n) + n) * sizeof(cplx<T>);
   const unsigned nblk = (unsigned)((pairs + pp - 1) / pp);
   const T inv = (T)(1.0 / (double)p.dealias_cells());
   const bool prof = prof_on(p, PROF_NL_X);
