@@ -239,6 +239,32 @@ def batched_stokes(F, torch, steps=50, graph_steps=10):
     num = sum(float(np.sum((x32 - x64) ** 2)) for (x32, _), (x64, _) in zip(finals["f32"], finals["f64"]))
     den = sum(float(np.sum((x64 - x0) ** 2)) for (x64, x0) in finals["f64"])
     res["f32_rel_err_displacement_vs_f64"] = (num / max(den, 1e-300)) ** 0.5
+    # the same cases on multi-instance plans, one per group of equal N: every stage is one launch per
+    # group
+    from paper_2302_08694_amd.batch import StokesGroupBatch
+    for prec, tol in (("f32", 1e-5), ("f64", 1e-5)):
+        b = StokesGroupBatch(cases, prec=prec, tol=tol)
+        res["grouped_plans"] = len(b.groups)
+        b.step(1)
+        b.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        res[f"{prec}_grouped_eager_instance_steps_per_s"] = len(cases) * steps / (time.perf_counter() - t0)
+        Xg = [x.cpu().numpy() for x in b.positions()]
+        if prec == "f32":
+            b.reset()
+            b.capture(graph_steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps // graph_steps):
+                b.replay()
+            torch.cuda.synchronize()
+            res["f32_grouped_graph_instance_steps_per_s"] = len(cases) * steps / (time.perf_counter() - t0)
+        num = sum(float(np.sum((xg - x64) ** 2)) for xg, (x64, _) in zip(Xg, finals["f64"]))
+        res[f"{prec}_grouped_rel_err_displacement_vs_f64"] = (num / max(den, 1e-300)) ** 0.5
+        b.close()
     return res
 
 

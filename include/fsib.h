@@ -76,6 +76,11 @@ typedef struct {
   int fluid;            /* 0: NUFFT only; 1: also the FSIB workspace (force spread, velocity
                            interp, fluid step, time step) */
   int navier_stokes;    /* with fluid = 1: 1 also allocates the dealiasing workspace (Sec. 3.1) */
+  int ninst;            /* independent simulations held by the plan, all with these n_modes, L, prec
+                           and tol (0 or 1: one).  ninst > 1 needs fluid = 1, navier_stokes = 0 and
+                           ntrans = 1 (Stokes instances); every stage of a step then runs as one
+                           launch over all instances.  Points are given instance after instance
+                           (fsib_plan_set_instances), half spectra as [ninst][dim][...]. */
 } fsib_plan_opts;
 
 /* Read-only facts about a plan (host struct filled by fsib_plan_info). */
@@ -130,6 +135,12 @@ int fsib_device_count(void);        /* visible HIP devices (0 when none or no dr
  * 2^a 3^b 5^c multiple of the tile), twiddle and deconvolution tables, and allocates the workspace
  * on the current device.  *out is written only on success. */
 fsib_status fsib_plan_create(const fsib_plan_opts* opts, fsib_plan* out);
+/* Point ranges of the instances of a plan with ninst > 1: instance i owns points
+ * [offsets[i], offsets[i+1]) of X, U (host array of ninst + 1, offsets[0] = 0, non-decreasing,
+ * offsets[ninst] <= max_points).  A set-up call: copies to the device and synchronises.  Until it is
+ * made, fsib_step and fsib_velocity fail with FSIB_ERR_STATE on such plans; afterwards their M must
+ * be offsets[ninst].  Errors: FSIB_ERR_ARG for bad offsets, FSIB_ERR_STATE for ninst = 1 plans. */
+fsib_status fsib_plan_set_instances(fsib_plan plan, const int64_t* offsets);
 fsib_status fsib_plan_destroy(fsib_plan plan);  /* waits for the plan's work, frees the workspace */
 fsib_status fsib_plan_info(fsib_plan plan, fsib_plan_info_t* info /* host */);
 /* Synchronises `stream`; returns FSIB_ERR_NONFINITE (and clears the flag) if any call since the

@@ -24,7 +24,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_modes", ctypes.c_int64 * 3), ("L", ctypes.c_double),
                 ("prec", ctypes.c_int), ("tol", ctypes.c_double), ("upsampfac", ctypes.c_double),
                 ("ntrans", ctypes.c_int), ("max_points", ctypes.c_int64), ("fluid", ctypes.c_int),
-                ("navier_stokes", ctypes.c_int)]
+                ("navier_stokes", ctypes.c_int), ("ninst", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -50,6 +50,7 @@ _SIGS = {
     "fsib_device_count": (ctypes.c_int, []),
     "fsib_plan_create": (ctypes.c_int, [ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_void_p)]),
     "fsib_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fsib_plan_set_instances": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "fsib_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
     "fsib_plan_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fsib_plan_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
@@ -221,7 +222,7 @@ def force_jvp(force, X, V):
 
 class Plan:
     def __init__(self, dim, n_modes, L=1.0, prec="f64", tol=1e-6, ntrans=1, max_points=1 << 16, fluid=False,
-                 navier_stokes=False, upsampfac=0.0):
+                 navier_stokes=False, upsampfac=0.0, ninst=1):
         lib = load_library()
         nm = list(n_modes) + [1] * (3 - len(n_modes))
         self.dim = int(dim)
@@ -234,11 +235,29 @@ class Plan:
         self.max_points = int(max_points)
         opts = _Opts(self.dim, (ctypes.c_int64 * 3)(*nm), self.L, FSIB_F64 if prec == "f64" else FSIB_F32,
                      float(tol), float(upsampfac), self.ntrans, self.max_points, int(bool(fluid)),
-                     int(bool(navier_stokes)))
+                     int(bool(navier_stokes)), int(ninst))
+        self.ninst = max(1, int(ninst))
         h = ctypes.c_void_p()
         _check(lib.fsib_plan_create(ctypes.byref(opts), ctypes.byref(h)), "fsib_plan_create")
         self._h = h
         self._lib = lib
+
+    @property
+    def field_shape(self):
+        """Shape of the half spectra of the plan's real fields: (dim, ...) or (ninst, dim, ...)."""
+        return ((self.dim,) if self.ninst == 1 else (self.ninst, self.dim)) + self.half_shape
+
+    def set_instances(self, counts):
+        """Point counts of the instances of a multi-instance plan (fsib_plan_set_instances); points are
+        then passed instance after instance."""
+        counts = [int(c) for c in counts]
+        if len(counts) != self.ninst:
+            raise ValueError(f"need {self.ninst} counts, got {len(counts)}")
+        off = (ctypes.c_int64 * (self.ninst + 1))()
+        for i, c in enumerate(counts):
+            off[i + 1] = off[i] + c
+        _check(self._lib.fsib_plan_set_instances(self._h, off), "fsib_plan_set_instances")
+        self.instance_offsets = list(off)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -347,7 +366,7 @@ class Plan:
     def force_spread(self, X, S, scale, out=None):
         M = self._X(X)
         _need(S, "S", self.rdtype, (M, self.dim))
-        shp = (self.dim,) + self.half_shape
+        shp = self.field_shape
         out = torch.empty(shp, dtype=self.cdtype, device=X.device) if out is None else _need(out, "fhat", self.cdtype, shp)
         _check(self._lib.fsib_force_spread(self._h, M, _ptr(X), _ptr(S), _ptr(out), float(scale), _stream()),
                "fsib_force_spread")
@@ -355,7 +374,7 @@ class Plan:
 
     def velocity_interp(self, X, uhat, out=None):
         M = self._X(X)
-        _need(uhat, "uhat", self.cdtype, (self.dim,) + self.half_shape)
+        _need(uhat, "uhat", self.cdtype, self.field_shape)
         out = torch.empty((M, self.dim), dtype=self.rdtype, device=X.device) if out is None else \
             _need(out, "U", self.rdtype, (M, self.dim))
         _check(self._lib.fsib_velocity_interp(self._h, M, _ptr(X), _ptr(uhat), _ptr(out), _stream()),
@@ -363,7 +382,7 @@ class Plan:
         return out
 
     def fluid_step(self, params, fhat, uhat, uhat_mid=None):
-        shp = (self.dim,) + self.half_shape
+        shp = self.field_shape
         _need(fhat, "fhat", self.cdtype, shp)
         _need(uhat, "uhat", self.cdtype, shp)
         if uhat_mid is not None:
@@ -386,7 +405,7 @@ class Plan:
 
     def velocity(self, params, force, X, uhat, out=None):
         M = self._X(X)
-        _need(uhat, "uhat", self.cdtype, (self.dim,) + self.half_shape)
+        _need(uhat, "uhat", self.cdtype, self.field_shape)
         out = torch.empty((M, self.dim), dtype=self.rdtype, device=X.device) if out is None else \
             _need(out, "U", self.rdtype, (M, self.dim))
         _check(self._lib.fsib_velocity(self._h, ctypes.byref(params._s), ctypes.byref(force._s) if force else None, M,
@@ -396,7 +415,7 @@ class Plan:
     def step(self, params, force, X, U, uhat, diag=None):
         M = self._X(X)
         _need(U, "U", self.rdtype, (M, self.dim))
-        _need(uhat, "uhat", self.cdtype, (self.dim,) + self.half_shape)
+        _need(uhat, "uhat", self.cdtype, self.field_shape)
         if diag is not None:
             _need(diag, "diag", torch.float64, (DIAG_COUNT,))
         _check(self._lib.fsib_step(self._h, ctypes.byref(params._s), ctypes.byref(force._s), M, _ptr(X), _ptr(U),

@@ -103,3 +103,87 @@ class StokesBatch:
         for it in self.items:
             it["plan"].close()
         self.items = []
+
+
+class StokesGroupBatch:
+    """The same simulations with one multi-instance plan per group of cases that share N, L, mu, dt
+    and K (ninst > 1): each stage of a step is one launch over all instances of a group, so a batch
+    step costs a few launches per group instead of per instance.  Groups run on their own streams.
+    Same interface as StokesBatch; `positions()` returns each case's X in the order of `cases`."""
+
+    def __init__(self, cases, prec="f32", tol=1e-5, device="cuda"):
+        self.prec = prec
+        keys = {}
+        for i, c in enumerate(cases):
+            key = (tuple(c["N"]), c.get("L", 1.0), c["mu"], c["dt"], c["K"])
+            keys.setdefault(key, []).append(i)
+        self.groups = []
+        for (N, L, mu, dt, K), idx in keys.items():
+            Xs = [torch.as_tensor(cases[i]["X"], dtype=torch.float64) for i in idx]
+            counts = [x.shape[0] for x in Xs]
+            X0 = torch.cat(Xs).to(device).contiguous()
+            plan = Plan(2, N, L=L, prec=prec, tol=tol, max_points=X0.shape[0], fluid=True, ninst=len(idx))
+            plan.set_instances(counts)
+            params = FluidParams("stokes", mu=mu, dt=dt)
+            force = Force("tension2d", K)
+            uh = torch.zeros(plan.field_shape, dtype=plan.cdtype, device=device)
+            U = plan.velocity(params, force, X0, uh)
+            self.groups.append(dict(plan=plan, params=params, force=force, X=X0.clone(), U=U, uh=uh, X0=X0,
+                                    U0=U.clone(), uh0=uh.clone(), idx=idx, counts=counts))
+        self.streams = [torch.cuda.Stream() for _ in self.groups]
+        self.graph = None
+        self.graph_steps = 0
+
+    def reset(self):
+        for g in self.groups:
+            g["X"].copy_(g["X0"])
+            g["U"].copy_(g["U0"])
+            g["uh"].copy_(g["uh0"])
+
+    def step(self, n=1):
+        main = torch.cuda.current_stream()
+        for _ in range(n):
+            for s in self.streams:
+                s.wait_stream(main)
+            for g, s in zip(self.groups, self.streams):
+                with torch.cuda.stream(s):
+                    g["plan"].step(g["params"], g["force"], g["X"], g["U"], g["uh"])
+            for s in self.streams:
+                main.wait_stream(s)
+
+    def positions(self):
+        out = [None] * sum(len(g["idx"]) for g in self.groups)
+        for g in self.groups:
+            for i, X in zip(g["idx"], torch.split(g["X"], g["counts"])):
+                out[i] = X
+        return out
+
+    def capture(self, steps):
+        saved = [(g["X"].clone(), g["U"].clone(), g["uh"].clone()) for g in self.groups]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.step(1)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            self.step(steps)
+        for g, (X, U, uh) in zip(self.groups, saved):
+            g["X"].copy_(X)
+            g["U"].copy_(U)
+            g["uh"].copy_(uh)
+        torch.cuda.synchronize()
+        self.graph, self.graph_steps = gr, steps
+        return gr
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def close(self):
+        self.graph = None
+        for g in self.groups:
+            g["plan"].close()
+        self.groups = []

@@ -74,6 +74,7 @@ void free_plan(Plan& p) {
   p.tw.clear();
   fr(p.counts);
   fr(p.offsets);
+  fr(p.inst_off);
   fr(p.pt_bin);
   fr(p.pt_rank);
   fr(p.s_idx);
@@ -144,6 +145,9 @@ fsib_status validate_opts(const fsib_plan_opts* o) {
   if (o->prec == FSIB_F64 && !(o->tol >= 1e-14)) return fail(FSIB_ERR_TOL, "FP64 plans reach tol >= 1e-14");
   if (o->prec == FSIB_F32 && !(o->tol >= 1e-6)) return fail(FSIB_ERR_TOL, "FP32 plans reach tol >= 1e-6");
   if (o->navier_stokes && !o->fluid) return fail(FSIB_ERR_ARG, "navier_stokes needs fluid = 1");
+  if (o->ninst < 0 || o->ninst > 4096) return fail(FSIB_ERR_ARG, "ninst must be in [0, 4096]");
+  if (o->ninst > 1 && (!o->fluid || o->navier_stokes || o->ntrans != 1))
+    return fail(FSIB_ERR_ARG, "ninst > 1 needs fluid = 1, navier_stokes = 0 and ntrans = 1");
   // at oversampling 1.25 the kernel transform falls by up to ~100x across the retained modes, and the
   // deconvolution lifts FP32 rounding of the grid by as much: FP32 low-memory plans stop at 1e-3
   if (plan_sigma(o) == 1.25 && o->prec == FSIB_F32 && !(o->tol >= 1e-3))
@@ -195,6 +199,8 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
     return fail(FSIB_ERR_ARG, "3D fine grid above 1024 per axis (n_modes above 512) is not supported");
   if (p.dim == 2 && (p.nf[0] > 65535 || p.nf[1] > 65535)) return fail(FSIB_ERR_ARG, "2D fine grid too large");
   p.nbins = p.nt[0] * p.nt[1] * p.nt[2];
+  p.ninst = o->ninst > 1 ? o->ninst : 1;
+  p.nbt = p.nbins * p.ninst;
   p.Hx = p.N[0] / 2 + 1;
   if (p.ns) {
     for (int a = 0; a < 3; ++a) {
@@ -235,8 +241,9 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
     A.get(t, (int64_t)n * cs);
     if (t) p.tw[n] = t;
   }
-  A.get(p.counts, (p.nbins + 1) * 4);
-  A.get(p.offsets, (p.nbins + 1) * 4);
+  A.get(p.counts, (p.nbt + 1) * 4);
+  A.get(p.offsets, (p.nbt + 1) * 4);
+  A.get(p.inst_off, (int64_t)(p.ninst + 1) * 8);
   A.get(p.pt_bin, Mx * 4);
   A.get(p.pt_rank, Mx * 4);
   A.get(p.s_idx, Mx * 4);
@@ -244,7 +251,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   A.get(p.s_y, Mx * d * rs);
   A.get(p.s_str, Mx * (2 * p.ntrans > d ? 2 * p.ntrans : d) * rs);
   A.get(p.flag, 256);
-  A.get(p.scan_part, fsib::scan_segments(p.nbins) * 4);
+  A.get(p.scan_part, fsib::scan_segments(p.nbt) * 4);
   A.get(p.rowmask, p.nt[1] * p.nt[2]);
   A.get(p.zmask, p.nt[2]);
   // spreading work list: part bound = tiles + visits / kSplit, visits <= M * prod(q + 1)
@@ -257,14 +264,14 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
       reach *= q + 1;
     }
     const int64_t visits = Mx * reach;
-    p.work_blocks = p.nbins + visits / kSplitPoints + 1;
+    p.work_blocks = p.nbt + visits / kSplitPoints + 1;
     p.split_slots = 2 * visits / kSplitPoints + 2;
     const int64_t nch_bytes = 2 * rs > d * rs ? 2 * rs : d * rs;  // complex or dim real channels
     const int64_t tr = p.ntrans > 1 ? p.ntrans : 1;
-    A.get(p.tile_parts, p.nbins * 4);
-    A.get(p.part_off, (p.nbins + 1) * 4);
+    A.get(p.tile_parts, p.nbt * 4);
+    A.get(p.part_off, (p.nbt + 1) * 4);
     A.get(p.work, p.work_blocks * 8);
-    A.get(p.tile_slot, p.nbins * 4);
+    A.get(p.tile_slot, p.nbt * 4);
     A.get(p.slot_ctr, 256);
     A.get(p.split_scratch, tr * p.split_slots * 1024 * nch_bytes);
   }
@@ -273,9 +280,10 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   int64_t b1 = p.dim == 3 ? (int64_t)p.ntrans * p.nf[2] * p.nf[1] * p.N[0] * cs : (int64_t)p.ntrans * p.nf[1] * p.N[0] * cs;
   int64_t b2 = p.dim == 3 ? (int64_t)p.ntrans * p.nf[2] * p.N[1] * p.N[0] * cs : 0;
   if (p.fluid) {
-    const int64_t gr = d * nfc * rs;
-    const int64_t r1 = p.dim == 3 ? d * p.nf[2] * p.nf[1] * p.Hx * cs : d * p.nf[1] * p.Hx * cs;
-    const int64_t r2 = p.dim == 3 ? d * p.nf[2] * p.N[1] * p.Hx * cs : 0;
+    const int64_t dn = d * p.ninst;  // real fields of all instances
+    const int64_t gr = dn * nfc * rs;
+    const int64_t r1 = p.dim == 3 ? dn * p.nf[2] * p.nf[1] * p.Hx * cs : dn * p.nf[1] * p.Hx * cs;
+    const int64_t r2 = p.dim == 3 ? dn * p.nf[2] * p.N[1] * p.Hx * cs : 0;
     grid_b = grid_b > gr ? grid_b : gr;
     b1 = b1 > r1 ? b1 : r1;
     b2 = b2 > r2 ? b2 : r2;
@@ -288,8 +296,8 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
     A.get(p.F64, Mx * d * 8);
     A.get(p.S, Mx * d * rs);
     A.get(p.Uh, Mx * d * rs);
-    A.get(p.fhat, d * p.modes_half() * cs);
-    A.get(p.uhat_mid, d * p.modes_half() * cs);
+    A.get(p.fhat, d * p.ninst * p.modes_half() * cs);
+    A.get(p.uhat_mid, d * p.ninst * p.modes_half() * cs);
     A.get(p.part, 256 * 12 * 8);
   }
   if (p.ns) {
@@ -335,11 +343,13 @@ hipStream_t S(void* s) { return (hipStream_t)s; }
 // passes; entries y and lines z of the y passes; entries z of the z passes).
 fsib::PassMasks mask_x(const Plan& p) {
   fsib::PassMasks m;
+  if (p.ninst > 1) return m;  // occupancy masks are kept for single-instance plans only
   m.rows = {p.rowmask, (int)p.nf[1], (int)p.nf[2], (int)p.tb[1], (int)p.tb[2], (int)p.nt[1]};
   return m;
 }
 fsib::PassMasks mask_y(const Plan& p, bool forward) {
   fsib::PassMasks m;
+  if (p.ninst > 1) return m;
   if (p.dim == 3) {
     m.line = {p.zmask, (int)p.nf[2], (int)p.tb[2], 1, 0};
     const fsib::StrideMask e{p.rowmask, (int)p.nf[2], (int)p.tb[2], (int)p.nt[1], (int)p.tb[1]};
@@ -352,6 +362,7 @@ fsib::PassMasks mask_y(const Plan& p, bool forward) {
 }
 fsib::PassMasks mask_z(const Plan& p, bool forward) {
   fsib::PassMasks m;
+  if (p.ninst > 1) return m;
   const fsib::StrideMask e{p.zmask, 1, 1, 0, (int)p.tb[2]};
   (forward ? m.ld : m.st) = e;
   return m;
@@ -360,6 +371,23 @@ fsib::PassMasks mask_z(const Plan& p, bool forward) {
 fsib_status check_points(const Plan& p, int64_t M, const void* X) {
   if (M < 0 || M > p.max_points) return fail(FSIB_ERR_ARG, "M must be in [0, max_points]");
   if (M > 0 && !X) return fail(FSIB_ERR_ARG, "X is NULL");
+  return FSIB_OK;
+}
+
+// Calls that take one point set: not on multi-instance plans.
+fsib_status single_instance(const Plan& p) {
+  if (p.ninst > 1) return fail(FSIB_ERR_STATE, "this call takes one instance; the plan holds ninst > 1");
+  return FSIB_OK;
+}
+
+// Multi-instance plans: the instances are set, M covers them all, curve forces have >= 3 points each.
+fsib_status check_instances(const Plan& p, int64_t M, const fsib_force* f) {
+  if (p.ninst <= 1) return FSIB_OK;
+  if (p.inst_off_h.empty()) return fail(FSIB_ERR_STATE, "fsib_plan_set_instances has not been called");
+  if (M != p.inst_off_h[p.ninst]) return fail(FSIB_ERR_ARG, "M must equal the last instance offset");
+  if (f && f->kind == FSIB_FORCE_CURVE_TENSION)
+    for (int i = 0; i < p.ninst; ++i)
+      if (p.inst_off_h[i + 1] - p.inst_off_h[i] < 3) return fail(FSIB_ERR_ARG, "curve tension needs >= 3 points per instance");
   return FSIB_OK;
 }
 
@@ -412,7 +440,7 @@ fsib_status type2_complex(Plan& p, int64_t M, const double* X, const void* fhat,
 // real vector strengths (sorted point set already in place) -> dim half spectra
 fsib_status force_spread_sorted(Plan& p, int64_t M, const void* S_, void* fhat, double scale, hipStream_t st) {
   FSIB_HIP(fsib::launch_spread(p, M, S_, p.dim, st));
-  const int64_t d = p.dim;
+  const int64_t d = (int64_t)p.dim * p.ninst;  // real fields of all instances
   if (p.dim == 3) {
     FSIB_HIP(fsib::launch_fft_r2c_x(p, p.grid, p.B1, (int)p.nf[0], d * p.nf[2] * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st,
                                     mask_x(p)));
@@ -431,7 +459,7 @@ fsib_status force_spread_sorted(Plan& p, int64_t M, const void* S_, void* fhat, 
 
 // dim half spectra -> real vector velocity at the sorted point set
 fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U, hipStream_t st) {
-  const int64_t d = p.dim;
+  const int64_t d = (int64_t)p.dim * p.ninst;  // real fields of all instances
   if (p.dim == 3) {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.B2, (int)p.nf[2], +1, p.N[1] * p.Hx, d, (int)p.N[2],
                                   (int)ceil_half(p.N[2]), (int)p.nf[2], (int)p.nf[2], p.fac[2], nullptr, 1.0, st,
@@ -480,7 +508,8 @@ fsib_status fluid_impl(Plan& p, const fsib_fluid_params& prm, const void* fhat, 
   if (prm.model == FSIB_STOKES) {
     FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_STOKES, prm, fhat, nullptr, uhat, st));
     if (umid)
-      FSIB_HIP(hipMemcpyAsync(umid, uhat, (size_t)p.dim * p.modes_half() * 2 * p.real_size(), hipMemcpyDeviceToDevice, st));
+      FSIB_HIP(hipMemcpyAsync(umid, uhat, (size_t)p.dim * p.ninst * p.modes_half() * 2 * p.real_size(),
+                              hipMemcpyDeviceToDevice, st));
     return FSIB_OK;
   }
   void* mid = umid ? umid : p.uhat_mid;
@@ -536,7 +565,7 @@ fsib_status check_force(const fsib_force* f, int dim, int64_t M) {
 fsib_status stokes_velocity(Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M, const double* X,
                             void* U, void* uhat, hipStream_t st) {
   const double Ld = p.dim == 3 ? p.L * p.L * p.L : p.L * p.L;
-  FSIB_HIP(fsib::launch_force(f, p.dim, M, X, p.F64, st));
+  FSIB_HIP(fsib::launch_force_plan(p, f, M, X, p.F64, st));
   FSIB_HIP(fsib::launch_weighted_strengths(p, f.kind, M, p.F64, p.S, st));
   FSIB_HIP(fsib::launch_sort_points(p, M, X, st));
   FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, st));
@@ -586,6 +615,20 @@ fsib_status fsib_plan_create(const fsib_plan_opts* opts, fsib_plan* out) {
     return s;
   }
   *out = h;
+  return FSIB_OK;
+}
+
+fsib_status fsib_plan_set_instances(fsib_plan plan, const int64_t* offsets) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (p.ninst <= 1) return fail(FSIB_ERR_STATE, "the plan holds one instance");
+  if (!offsets) return fail(FSIB_ERR_ARG, "offsets is NULL");
+  if (offsets[0] != 0) return fail(FSIB_ERR_ARG, "offsets[0] must be 0");
+  for (int i = 0; i < p.ninst; ++i)
+    if (offsets[i + 1] < offsets[i]) return fail(FSIB_ERR_ARG, "offsets must be non-decreasing");
+  if (offsets[p.ninst] > p.max_points) return fail(FSIB_ERR_ARG, "offsets[ninst] exceeds max_points");
+  FSIB_HIP(hipMemcpy(p.inst_off, offsets, (size_t)(p.ninst + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  p.inst_off_h.assign(offsets, offsets + p.ninst + 1);
   return FSIB_OK;
 }
 
@@ -666,6 +709,7 @@ fsib_status fsib_spread(fsib_plan plan, int64_t M, const double* X, const void* 
                         void* stream) {
   if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
   Plan& p = plan->p;
+  FSIB_TRY(single_instance(p));
   FSIB_TRY(check_points(p, M, X));
   if (M > 0 && !c) return fail(FSIB_ERR_ARG, "c is NULL");
   if (!fhat) return fail(FSIB_ERR_ARG, "fhat is NULL");
@@ -676,6 +720,7 @@ fsib_status fsib_spread(fsib_plan plan, int64_t M, const double* X, const void* 
 fsib_status fsib_interp(fsib_plan plan, int64_t M, const double* X, const void* fhat, void* c, void* stream) {
   if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
   Plan& p = plan->p;
+  FSIB_TRY(single_instance(p));
   FSIB_TRY(check_points(p, M, X));
   if (!fhat) return fail(FSIB_ERR_ARG, "fhat is NULL");
   if (M > 0 && !c) return fail(FSIB_ERR_ARG, "c is NULL");
@@ -686,6 +731,7 @@ fsib_status fsib_spectral_scale(fsib_plan plan, int layout, int axis, double sca
                                 void* stream) {
   if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
   Plan& p = plan->p;
+  FSIB_TRY(single_instance(p));
   if (layout != 0 && layout != 1) return fail(FSIB_ERR_ARG, "layout must be 0 (full spectra) or 1 (half spectra)");
   if (layout == 1 && !p.fluid) return fail(FSIB_ERR_STATE, "half spectra need a plan created with fluid = 1");
   if (axis < -1 || axis >= p.dim) return fail(FSIB_ERR_ARG, "axis must be -1 or in [0, dim)");
@@ -716,6 +762,7 @@ fsib_status fsib_force_spread(fsib_plan plan, int64_t M, const double* X, const 
   Plan& p = plan->p;
   if (!p.fluid) return fail(FSIB_ERR_STATE, "plan was created without fluid = 1");
   FSIB_TRY(check_points(p, M, X));
+  FSIB_TRY(check_instances(p, M, nullptr));
   if (M > 0 && !S_) return fail(FSIB_ERR_ARG, "S is NULL");
   if (!fhat_half) return fail(FSIB_ERR_ARG, "fhat_half is NULL");
   if (!std::isfinite(scale)) return fail(FSIB_ERR_ARG, "scale must be finite");
@@ -729,6 +776,7 @@ fsib_status fsib_velocity_interp(fsib_plan plan, int64_t M, const double* X, con
   Plan& p = plan->p;
   if (!p.fluid) return fail(FSIB_ERR_STATE, "plan was created without fluid = 1");
   FSIB_TRY(check_points(p, M, X));
+  FSIB_TRY(check_instances(p, M, nullptr));
   if (!uhat_half) return fail(FSIB_ERR_ARG, "uhat_half is NULL");
   if (M > 0 && !U) return fail(FSIB_ERR_ARG, "U is NULL");
   FSIB_HIP(fsib::launch_sort_points(p, M, X, S(stream)));
@@ -788,6 +836,7 @@ fsib_status fsib_pressure(fsib_plan plan, const fsib_fluid_params* params, const
                           const void* uhat_half, void* phat_half, void* stream) {
   if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
   Plan& p = plan->p;
+  FSIB_TRY(single_instance(p));
   FSIB_TRY(check_fluid(p, params));
   if (!fhat_half || !phat_half) return fail(FSIB_ERR_ARG, "fhat_half and phat_half must not be NULL");
   const int ns = params->model == FSIB_NAVIER_STOKES ? 1 : 0;
@@ -804,6 +853,7 @@ fsib_status fsib_velocity(fsib_plan plan, const fsib_fluid_params* params, const
   Plan& p = plan->p;
   FSIB_TRY(check_fluid(p, params));
   FSIB_TRY(check_points(p, M, X));
+  FSIB_TRY(check_instances(p, M, force));
   if (M > 0 && !U) return fail(FSIB_ERR_ARG, "U is NULL");
   if (!uhat_half) return fail(FSIB_ERR_ARG, "uhat_half is NULL");
   if (params->model == FSIB_NAVIER_STOKES) {
@@ -821,6 +871,8 @@ fsib_status fsib_step(fsib_plan plan, const fsib_fluid_params* params, const fsi
   FSIB_TRY(check_fluid(p, params));
   FSIB_TRY(check_points(p, M, X));
   FSIB_TRY(check_force(force, p.dim, M));
+  FSIB_TRY(check_instances(p, M, force));
+  if (p.ninst > 1 && diag) return fail(FSIB_ERR_ARG, "diag is not available on multi-instance plans");
   if (M > 0 && !U) return fail(FSIB_ERR_ARG, "U is NULL");
   if (!uhat_half) return fail(FSIB_ERR_ARG, "uhat_half is NULL");
   const hipStream_t st = S(stream);

@@ -42,6 +42,11 @@ __global__ void k_fluid(ModeGeo g, int mode, T rho, T mu, T dt, T b0, T b1, T b2
   const int64_t nm = g.Hx * g.N[1] * (DIM == 3 ? g.N[2] : 1);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nm) return;
+  // instance blockIdx.y of a multi-instance (Stokes) plan: its dim half spectra follow the previous ones
+  const int64_t ib = (int64_t)blockIdx.y * DIM * nm;
+  fhat += ib;
+  uout += ib;
+  if (uin) uin += ib;
   const int64_t ix = idx % g.Hx;
   const int64_t iy = (idx / g.Hx) % g.N[1];
   const int64_t iz = DIM == 3 ? idx / (g.Hx * g.N[1]) : 0;
@@ -110,24 +115,25 @@ hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params&
   g.L = p.L;
   const int64_t nm = p.modes_half();
   const unsigned nblk = (unsigned)((nm + 255) / 256);
+  const dim3 grid(nblk, (unsigned)p.ninst);  // one row of blocks per instance
   if (p.prec == FSIB_F64) {
     using T = double;
     if (p.dim == 3)
-      hipLaunchKernelGGL((k_fluid<T, 3>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
+      hipLaunchKernelGGL((k_fluid<T, 3>), grid, dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
                          (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
                          (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
     else
-      hipLaunchKernelGGL((k_fluid<T, 2>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
+      hipLaunchKernelGGL((k_fluid<T, 2>), grid, dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
                          (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
                          (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
   } else {
     using T = float;
     if (p.dim == 3)
-      hipLaunchKernelGGL((k_fluid<T, 3>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
+      hipLaunchKernelGGL((k_fluid<T, 3>), grid, dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
                          (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
                          (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
     else
-      hipLaunchKernelGGL((k_fluid<T, 2>), dim3(nblk), dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
+      hipLaunchKernelGGL((k_fluid<T, 2>), grid, dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
                          (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
                          (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
   }
@@ -347,6 +353,41 @@ __global__ void k_force_target(int64_t n, const double* __restrict__ X, const do
   F[e] = K * ((tgt ? tgt[e] : 0.0) - X[e]);
 }
 
+// The closed-curve force for the instances of a multi-instance plan: point j belongs to instance i with
+// points [off[i], off[i+1]), whose curve closes on itself and has dtheta = 2 pi / (off[i+1] - off[i]).
+__global__ void k_force_curve_inst(int64_t M, const double* __restrict__ X, double K, const int64_t* __restrict__ off,
+                                   int ninst, double* __restrict__ F) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  const int64_t s = off[lo], e = off[lo + 1];
+  const int64_t jp = j + 1 == e ? s : j + 1, jm = j == s ? e - 1 : j - 1;
+  const double dth = 6.283185307179586476925286766559 / (double)(e - s);
+  const double c = K / (dth * dth);
+  for (int a = 0; a < 2; ++a) F[j * 2 + a] = c * (X[jp * 2 + a] + X[jm * 2 + a] - 2.0 * X[j * 2 + a]);
+}
+
+// Strengths S = w F per instance: w = 2 pi / M_i (closed curves), with M_i the instance's point count.
+template <typename T>
+__global__ void k_strengths_inst(int64_t M, int dim, const double* __restrict__ F, const int64_t* __restrict__ off,
+                                 int ninst, T* __restrict__ S) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  const double w = 6.283185307179586476925286766559 / (double)(off[lo + 1] - off[lo]);
+  for (int a = 0; a < dim; ++a) S[j * dim + a] = (T)(w * F[j * dim + a]);
+}
+
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F, hipStream_t st) {
   if (M <= 0) return hipSuccess;
   const unsigned nblk = (unsigned)((M + 255) / 256);
@@ -454,9 +495,29 @@ double force_weight(int kind, int64_t M) {
   return kind == FSIB_FORCE_CURVE_TENSION ? 6.283185307179586476925286766559 / (double)M : 1.0;
 }
 
+hipError_t launch_force_plan(const Plan& p, const fsib_force& f, int64_t M, const double* X, double* F, hipStream_t st) {
+  if (p.ninst > 1 && f.kind == FSIB_FORCE_CURVE_TENSION) {
+    if (M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_force_curve_inst, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, X, f.K,
+                       (const int64_t*)p.inst_off, p.ninst, F);
+    return hipGetLastError();
+  }
+  return launch_force(f, p.dim, M, X, F, st);  // the other laws index their mesh globally
+}
+
 hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S, hipStream_t st) {
   const int64_t n = M * p.dim;
   if (n <= 0) return hipSuccess;
+  if (p.ninst > 1 && kind == FSIB_FORCE_CURVE_TENSION) {
+    const unsigned nb = (unsigned)((M + 255) / 256);
+    if (p.prec == FSIB_F64)
+      hipLaunchKernelGGL(k_strengths_inst<double>, dim3(nb), dim3(256), 0, st, M, p.dim, F,
+                         (const int64_t*)p.inst_off, p.ninst, (double*)S);
+    else
+      hipLaunchKernelGGL(k_strengths_inst<float>, dim3(nb), dim3(256), 0, st, M, p.dim, F,
+                         (const int64_t*)p.inst_off, p.ninst, (float*)S);
+    return hipGetLastError();
+  }
   const double w = force_weight(kind, M);
   const unsigned nblk = (unsigned)((n + 255) / 256);
   if (p.prec == FSIB_F64)

@@ -43,7 +43,11 @@ struct Plan {
   int64_t nd[3] = {1, 1, 1};  // dealiasing grid
   int64_t tb[3] = {1, 1, 1};  // tile (bin) size
   int64_t nt[3] = {1, 1, 1};  // tiles per axis
-  int64_t nbins = 1;
+  int64_t nbins = 1;            // bins (tiles) of one instance
+  int ninst = 1;                // independent instances sharing the plan (Stokes)
+  int64_t nbt = 1;              // bins of all instances, nbins * ninst
+  int64_t* inst_off = nullptr;  // device: ninst + 1 point offsets of the instances
+  std::vector<int64_t> inst_off_h;  // host copy (empty until set)
   int64_t Hx = 1;             // half-spectrum length along x
   // device tables
   void* coef = nullptr;              // (deg+1)*w scalars of prec
@@ -139,6 +143,7 @@ hipError_t launch_pressure(const Plan& p, int ns, double rho, const void* fhat, 
 hipError_t launch_spring_stiffness(int64_t M, const double* X0, const int32_t* tris, const int32_t* v2t_ptr,
                                    const int32_t* v2t_idx, const int32_t* nptr, const int32_t* nbr, double* kij,
                                    int* missing, hipStream_t st);
+hipError_t launch_force_plan(const Plan& p, const fsib_force& f, int64_t M, const double* X, double* F, hipStream_t st);
 hipError_t launch_force_jvp(const fsib_force& f, int dim, int64_t M, const double* X, const double* V, double* out,
                             hipStream_t st);
 hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S,

@@ -17,7 +17,21 @@ struct Geo {
   int64_t nf[3];
   int64_t tb[3];
   int64_t nt[3];
+  int ninst;                  // instances of the plan; their bins follow one another
+  int64_t nbins;              // bins of one instance
+  const int64_t* inst_off;    // ninst + 1 point offsets (ninst > 1)
 };
+
+// Instance owning point j: the last i with inst_off[i] <= j (binary search; inst_off[0] = 0 <= j).
+__device__ __forceinline__ int point_instance(const int64_t* __restrict__ off, int ninst, int64_t j) {
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ void locate(double x, double L, int64_t nf, int w, int& i0, double& y, bool& bad) {
   if (!isfinite(x)) {
@@ -61,6 +75,7 @@ __global__ void k_bin_count(int64_t M, const double* __restrict__ X, Geo g, int*
       stride *= g.nt[a];
     }
     if (bad) flag[0] = 1;
+    if (g.ninst > 1) b += (int64_t)point_instance(g.inst_off, g.ninst, j) * g.nbins;
     bin = (int)b;
   }
   const int lane = threadIdx.x & 63;
@@ -193,6 +208,9 @@ static Geo make_geo(const Plan& p) {
     g.tb[a] = p.tb[a];
     g.nt[a] = p.nt[a];
   }
+  g.ninst = p.ninst;
+  g.nbins = p.nbins;
+  g.inst_off = p.inst_off;
   return g;
 }
 
@@ -254,15 +272,15 @@ hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum,
 
 hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st) {
   Geo g = make_geo(p);
-  hipError_t e = launch_fill_zero(p.counts, (p.nbins + 1) * (int64_t)sizeof(int), st);
+  hipError_t e = launch_fill_zero(p.counts, (p.nbt + 1) * (int64_t)sizeof(int), st);
   if (e != hipSuccess) return e;
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st, M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = launch_scan(p.nbins, p.counts, p.offsets, p.scan_part, st)) != hipSuccess) return e;
-  if ((e = launch_row_masks(p, st)) != hipSuccess) return e;
+  if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st)) != hipSuccess) return e;
+  if (p.ninst == 1 && (e = launch_row_masks(p, st)) != hipSuccess) return e;  // masks: one instance only
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     if (p.prec == FSIB_F64)

@@ -45,6 +45,8 @@ struct SpreadArgs {
   int64_t slots;        // scratch slots per transform
   const uint8_t* rowmask;  // blocks of x lines reached by some point (lines elsewhere stay unwritten)
   int xcd_chunk;           // > 0: workgroups renumbered in runs of this many per XCD (xcd_chunked)
+  int ninst;               // instances: tile t of the whole plan is tile t % nbins of instance t / nbins,
+                           // whose real grids follow one another ([inst][ch][cells])
 };
 
 template <typename T, int W>
@@ -107,26 +109,28 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   const int tid = threadIdx.x;
   const int tr = blockIdx.y;
   const int nbins = a.nt[0] * a.nt[1] * (DIM == 3 ? a.nt[2] : 1);
+  const int nbt = nbins * a.ninst;  // tiles of all instances
   int tile_id, part;
   // tiles holding points cluster (surfaces): whole XCD-contiguous ranges of tiles would load the XCDs
   // unevenly, short runs keep neighbouring tiles (which stage the same points) on one L2
   const int blk = a.xcd_chunk > 0 ? (int)xcd_chunked(blockIdx.x, gridDim.x, a.xcd_chunk) : (int)blockIdx.x;
-  if (blk < nbins) {
+  if (blk < nbt) {
     tile_id = blk;
     part = 0;
   } else {
-    const int e = blk - nbins;
-    if (e >= a.part_off[nbins] - nbins) return;  // beyond the further parts
+    const int e = blk - nbt;
+    if (e >= a.part_off[nbt] - nbt) return;  // beyond the further parts
     const int2 wk = a.work[e];
     tile_id = wk.x;
     part = wk.y;
   }
+  const int inst = tile_id / nbins, lt = tile_id - inst * nbins;  // instance, tile within it
   int tcoord[3];
-  tcoord[0] = tile_id % a.nt[0];
-  tcoord[1] = (tile_id / a.nt[0]) % a.nt[1];
-  tcoord[2] = DIM == 3 ? tile_id / (a.nt[0] * a.nt[1]) : 0;
+  tcoord[0] = lt % a.nt[0];
+  tcoord[1] = (lt / a.nt[0]) % a.nt[1];
+  tcoord[2] = DIM == 3 ? lt / (a.nt[0] * a.nt[1]) : 0;
   // no point reaches this tile's block of x lines: those lines are neither read nor written
-  if (!a.rowmask[tcoord[2] * a.nt[1] + tcoord[1]]) return;
+  if (a.rowmask && !a.rowmask[tcoord[2] * a.nt[1] + tcoord[1]]) return;
   const int nparts = a.tile_parts[tile_id];
   constexpr int tcells = kTileX * ROWS;
   int base[3] = {0, 0, 0};
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
       const int bx = (tcoord[0] - dx + a.nt[0]) % a.nt[0];
       const int by = (tcoord[1] - dy + a.nt[1]) % a.nt[1];
       const int bz = DIM == 3 ? (tcoord[2] - dz + a.nt[2]) % a.nt[2] : 0;
-      const int b = bx + a.nt[0] * (by + a.nt[1] * bz);
+      const int b = bx + a.nt[0] * (by + a.nt[1] * bz) + inst * nbins;
       const int s0 = a.offsets[b], e0 = a.offsets[b + 1];
       rbeg[tid] = s0;
       rlen[tid] = e0 - s0;
@@ -276,7 +280,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-      for (int c = 0; c < CW; ++c) a.grid[ch * cells + g + c] = acc[c][ch];
+      for (int c = 0; c < CW; ++c) a.grid[((int64_t)inst * NCH + ch) * cells + g + c] = acc[c][ch];
   }
   (void)tcells;
 }
@@ -295,20 +299,22 @@ __global__ void k_sort_strengths(int64_t M, const int* __restrict__ s_idx, const
 }
 
 // Points reaching each tile (its bin and the q bins before it per axis) and the parts it splits into.
-__global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1, int q2, const int* __restrict__ offsets,
-                             int* __restrict__ tile_parts) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nt0 * nt1 * nt2) return;
+__global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1, int q2, int ninst,
+                             const int* __restrict__ offsets, int* __restrict__ tile_parts) {
+  const int tg = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nbins = nt0 * nt1 * nt2;
+  if (tg >= nbins * ninst) return;
+  const int inst = tg / nbins, t = tg - inst * nbins;
   const int tx = t % nt0, ty = (t / nt0) % nt1, tz = t / (nt0 * nt1);
   int total = 0;
   for (int dz = 0; dz <= (dim == 3 ? q2 : 0); ++dz)
     for (int dy = 0; dy <= q1; ++dy)
       for (int dx = 0; dx <= q0; ++dx) {
         const int bx = (tx - dx + nt0) % nt0, by = (ty - dy + nt1) % nt1, bz = dim == 3 ? (tz - dz + nt2) % nt2 : 0;
-        const int b = bx + nt0 * (by + nt1 * bz);
+        const int b = bx + nt0 * (by + nt1 * bz) + inst * nbins;
         total += offsets[b + 1] - offsets[b];
       }
-  tile_parts[t] = total <= kSplit ? 1 : (total + kSplit - 1) / kSplit;
+  tile_parts[tg] = total <= kSplit ? 1 : (total + kSplit - 1) / kSplit;
 }
 
 // Work list of the further parts (tile, part >= 1) in tile order, and scratch slots for tiles split
@@ -330,7 +336,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_merge_tiles(SpreadArgs<T> a)
   const int np = a.tile_parts[t];
   if (np <= 1) return;
   const int tr = blockIdx.y;
-  const int tcoord[3] = {t % a.nt[0], (t / a.nt[0]) % a.nt[1], DIM == 3 ? t / (a.nt[0] * a.nt[1]) : 0};
+  const int nbins = a.nt[0] * a.nt[1] * (DIM == 3 ? a.nt[2] : 1);
+  const int inst = t / nbins, lt = t - inst * nbins;
+  const int tcoord[3] = {lt % a.nt[0], (lt / a.nt[0]) % a.nt[1], DIM == 3 ? lt / (a.nt[0] * a.nt[1]) : 0};
   const int rows = a.tb[1] * (DIM == 3 ? a.tb[2] : 1);
   const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
   const T* src = a.scratch + ((int64_t)tr * a.slots + a.tile_slot[t]) * NCH * kMaxTileCells;
@@ -349,7 +357,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_merge_tiles(SpreadArgs<T> a)
       reinterpret_cast<cplx<T>*>(a.grid)[(int64_t)tr * cells + g] = mk(v[0], v[1]);
     } else {
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) a.grid[ch * cells + g] = v[ch];
+      for (int ch = 0; ch < NCH; ++ch) a.grid[((int64_t)inst * NCH + ch) * cells + g] = v[ch];
     }
   }
 }
@@ -366,7 +374,23 @@ struct InterpArgs {
   int64_t M;
   int nf[3];
   int xcd_chunk;  // > 0: workgroups renumbered in runs of this many per XCD (xcd_chunked)
+  // instances (ninst > 1): sorted positions [offsets[i nbins], offsets[(i+1) nbins]) belong to
+  // instance i, whose real grids start at channel i * NCH
+  const int* offsets;
+  int nbins;
+  int ninst;
 };
+
+// Instance of sorted position pos: the last i with offsets[i * nbins] <= pos.
+__device__ __forceinline__ int sorted_instance(const int* __restrict__ offsets, int nbins, int ninst, int64_t pos) {
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offsets[(int64_t)mid * nbins] <= pos) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
 
 // One wavefront per point (a few points at a time).  The lanes cover an XL x YL patch of the
 // point's support in one z-plane (XL >= w lanes along x, YL = 64/XL along y), so one load
@@ -467,11 +491,13 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
     if (k0 + PB < kIpPointsPerWave && first + k0 + PB < a.M) records(k0 + PB);
     T v[PB];
     int iz[PB], gxb[PB], gyb[PB][YCH];
+    int64_t gin[PB];  // first grid channel of the point's instance
     T wxy[PB][YCH];
     bool ok[PB];
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
       ok[b] = first + k0 + b < a.M;
+      gin[b] = a.ninst > 1 && ok[b] ? (int64_t)sorted_instance(a.offsets, a.nbins, a.ninst, first + k0 + b) * NCH : 0;
       T u = (T)0;
 #pragma unroll
       for (int i = kMaxDeg; i >= 0; --i)
@@ -522,7 +548,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
                 cv[b][t][SC - 1] = z.y;
               } else {
 #pragma unroll
-                for (int c = 0; c < SC; ++c) cv[b][t][c] = a.grid[c * cells + g];
+                for (int c = 0; c < SC; ++c) cv[b][t][c] = a.grid[(gin[b] + c) * cells + g];
               }
             }
           }
@@ -595,10 +621,11 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   a.tile_slot = p.tile_slot;
   a.scratch = (T*)p.split_scratch;
   a.slots = p.split_slots;
-  a.rowmask = p.rowmask;
+  a.rowmask = p.ninst > 1 ? nullptr : p.rowmask;  // occupancy masks: single-instance plans only
   a.xcd_chunk = p.xcd_chunk_spread;
+  a.ninst = p.ninst;
   a.sstr = (T*)p.s_str;
-  const unsigned nb = (unsigned)p.nbins;
+  const unsigned nb = (unsigned)p.nbt;
   if (M > 0) {
     hipLaunchKernelGGL((k_sort_strengths<T, NCH, CPLX>), dim3((unsigned)((M + 255) / 256), (unsigned)ntr), dim3(256), 0,
                        st, M, (const int*)p.s_idx, (const T*)str, a.sstr);
@@ -606,12 +633,12 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
     if (e0 != hipSuccess) return e0;
   }
   hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, DIM, a.nt[0], a.nt[1], a.nt[2], a.q[0],
-                     a.q[1], a.q[2], (const int*)p.offsets, p.tile_parts);
+                     a.q[1], a.q[2], p.ninst, (const int*)p.offsets, p.tile_parts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = launch_scan(p.nbins, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
+  if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
   if ((e = launch_fill_zero(p.slot_ctr, 4, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, (int)p.nbins, (const int*)p.part_off,
+  hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, (int)p.nbt, (const int*)p.part_off,
                      (const int*)p.tile_parts, (int2*)p.work, p.tile_slot, p.slot_ctr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const bool prof = prof_on(p, PROF_SPREAD);
@@ -620,7 +647,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
                      dim3(kSpreadThreads), 0, st, a);
   // algorithmic bytes: the grid written once, per point its sorted record and its strengths read
   if (prof)
-    prof_stop(p, (double)ntr * p.fine_cells() * NCH * sizeof(T) + (double)M * (8 + DIM * sizeof(T)) +
+    prof_stop(p, (double)ntr * p.ninst * p.fine_cells() * NCH * sizeof(T) + (double)M * (8 + DIM * sizeof(T)) +
                      (double)ntr * M * NCH * sizeof(T), st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((k_merge_tiles<T, DIM, NCH, CPLX>), dim3(nb, (unsigned)ntr), dim3(kSpreadThreads), 0, st, a);
@@ -641,6 +668,9 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   a.M = M;
   for (int d = 0; d < 3; ++d) a.nf[d] = (int)p.nf[d];
   a.xcd_chunk = p.xcd_chunk_interp;
+  a.offsets = p.offsets;
+  a.nbins = (int)p.nbins;
+  a.ninst = p.ninst;
   const bool prof = prof_on(p, PROF_INTERP);
   if (prof) prof_start(p, st);
   const int64_t per_wg = 4 * kIpPointsPerWave;  // four wavefronts per workgroup

@@ -35,16 +35,18 @@ def test_version_and_status_strings():
 
 def _opts(**kw):
     o = dict(dim=3, n_modes=(16, 16, 16), L=1.0, prec=0, tol=1e-6, upsampfac=2.0, ntrans=1, max_points=100,
-             fluid=0, navier_stokes=0)
+             fluid=0, navier_stokes=0, ninst=0)
     o.update(kw)
     return B._Opts(o["dim"], (ctypes.c_int64 * 3)(*o["n_modes"]), o["L"], o["prec"], o["tol"], o["upsampfac"],
-                   o["ntrans"], o["max_points"], o["fluid"], o["navier_stokes"])
+                   o["ntrans"], o["max_points"], o["fluid"], o["navier_stokes"], o["ninst"])
 
 
 @pytest.mark.parametrize("kw,status", [
     (dict(dim=1), 1), (dict(dim=4), 1), (dict(n_modes=(1, 16, 16)), 1), (dict(L=0.0), 1), (dict(L=float("nan")), 1),
     (dict(prec=7), 1), (dict(upsampfac=1.5), 1), (dict(upsampfac=1.25, tol=1e-10), 2), (dict(upsampfac=1.25, prec=1, tol=1e-4), 2), (dict(ntrans=0), 1), (dict(max_points=-1), 1),
     (dict(navier_stokes=1, fluid=0), 1),
+    (dict(ninst=2), 1), (dict(ninst=2, fluid=1, navier_stokes=1), 1), (dict(ninst=2, fluid=1, ntrans=2), 1),
+    (dict(ninst=5000, fluid=1), 1), (dict(ninst=-1), 1),
     (dict(prec=1, tol=1e-10), 2), (dict(prec=0, tol=1e-16), 2), (dict(tol=0.5), 2),
 ])
 def test_plan_argument_errors_come_before_device_use(kw, status):
@@ -106,3 +108,8 @@ def test_fluid_params_layout():
     assert ctypes.sizeof(B._Params) == 8 + 3 * 8 + 3 * 8
     assert B._Params.body.offset == 32
     assert ctypes.sizeof(B._Force) == 7 * 8
+
+
+def test_set_instances_rejects_null_plan():
+    lib = B.load_library()
+    assert lib.fsib_plan_set_instances(None, None) == 1
