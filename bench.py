@@ -79,7 +79,9 @@ def reset(s):
 
 def time_steps(torch, s, steps, warmup, prof_class=None):
     plan, force, params = s["plan"], s["force"], s["params"]
-    s["Xinit"] = s["X"].clone()
+    if "Xinit" not in s:  # the initial state (every call starts from it)
+        s["Xinit"] = s["X"].clone()
+    reset(s)
     for _ in range(warmup):
         plan.step(params, force, s["X"], s["U"], s["uh"])
     reset(s)
@@ -332,7 +334,7 @@ def nufft_micro(F, torch):
     return res
 
 
-def cpu_baseline(N, rings, sample_points=2048):
+def cpu_baseline(N, rings, sample_points=16384):
     """The FP64 oracle on a bounded sample of one step, extrapolated to steps/s.
 
     Sample: the oracle's force spreading and one velocity interpolation of `sample_points` of the

@@ -59,6 +59,11 @@ __device__ __forceinline__ void kernel_values(const T* __restrict__ coef, int de
   }
 }
 
+// Degree of the kernel pieces for width W (choose_degree), known at compile time: the Horner loops
+// unroll, and interpolation lanes keep only the W + 3 coefficients of their column in registers.
+template <int W>
+__host__ __device__ constexpr int interp_degree() { return W + 2 < kMaxDeg ? W + 2 : kMaxDeg; }
+
 template <int DIM>
 __device__ __forceinline__ int unpack_i0(uint32_t p, int a) {
   return DIM == 3 ? (int)((p >> (10 * a)) & 1023u) : (int)((p >> (16 * a)) & 65535u);
@@ -197,6 +202,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
         if (valid) {
           const T y = a.s_y[pos * DIM + d];
           T v[W];
+          // runtime degree: a fully unrolled Horner loop here lifts the kernel's VGPRs (68 -> 105 in FP32)
 #pragma unroll
           for (int j = 0; j < W; ++j) v[j] = cf[a.deg * W + j];
           for (int i = a.deg - 1; i >= 0; --i) {
@@ -461,9 +467,10 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
   const int tr = blockIdx.y;
   const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
   // coefficient column jk of the kernel pieces
-  T cfr[kMaxDeg + 1];
+  constexpr int DEG = interp_degree<W>();  // the plan's degree for this width (checked on the host)
+  T cfr[DEG + 1];
 #pragma unroll
-  for (int i = 0; i <= kMaxDeg; ++i) cfr[i] = (i <= a.deg && jk < W) ? a.coef[i * W + jk] : (T)0;
+  for (int i = 0; i <= DEG; ++i) cfr[i] = jk < W ? a.coef[i * W + jk] : (T)0;
   const int64_t blk = a.xcd_chunk > 0 ? xcd_chunked(blockIdx.x, gridDim.x, a.xcd_chunk) : (int64_t)blockIdx.x;
   const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
   const int64_t first = wave * kIpPointsPerWave;
@@ -500,8 +507,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
       gin[b] = a.ninst > 1 && ok[b] ? (int64_t)sorted_instance(a.offsets, a.nbins, a.ninst, first + k0 + b) * NCH : 0;
       T u = (T)0;
 #pragma unroll
-      for (int i = kMaxDeg; i >= 0; --i)
-        if (i <= a.deg) u = u * yc[b] + cfr[i];
+      for (int i = DEG; i >= 0; --i) u = u * yc[b] + cfr[i];
       v[b] = u;
       const int ix = unpack_i0<DIM>(pkc[b], 0), iy = unpack_i0<DIM>(pkc[b], 1);
       iz[b] = DIM == 3 ? unpack_i0<DIM>(pkc[b], 2) : 0;
@@ -657,6 +663,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
 template <typename T, int DIM, int NCH, bool CPLX, int W>
 static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t st) {
   if (M == 0) return hipSuccess;
+  if (p.deg != interp_degree<W>()) return hipErrorInvalidValue;  // the kernel's compile-time degree
   InterpArgs<T> a;
   a.coef = (const T*)p.coef;
   a.deg = p.deg;
