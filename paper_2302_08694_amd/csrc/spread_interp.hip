@@ -110,6 +110,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   __shared__ unsigned long long msk[G::NMASK];
   __shared__ int rbeg[27], rlen[27];
   __shared__ int nrange;
+  __shared__ int sel[kSpreadThreads];  // candidates of the current window whose support meets the tile
+  __shared__ int wcnt[kSpreadThreads / 64 + 1];
 
   const int tid = threadIdx.x;
   const int tr = blockIdx.y;
@@ -183,18 +185,50 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) acc[c][ch] = (T)0;
 
-  for (int c0 = cbeg; c0 < cend; c0 += kChunk) {
-    const int cnt = cend - c0 < kChunk ? cend - c0 : kChunk;
+  // Candidates are taken kSpreadThreads at a time: each thread tests one (support meets the tile
+  // along every axis, from the packed first cell alone) and the hits are compacted, in order, into
+  // sel[]; only those are staged, kChunk at a time.  (With the reach of ceil((w-1)/tile) bins per
+  // axis, about half of the candidates miss the tile.)
+  for (int w0 = cbeg; w0 < cend; w0 += kSpreadThreads) {
+  {
+    const int ci = w0 + tid;
+    bool hit = false;
+    int cpos = 0;
+    if (ci < cend) {
+      int vi = ci, r = 0;
+      while (vi >= rlen[r]) vi -= rlen[r++];
+      cpos = rbeg[r] + vi;
+      const uint32_t pk = a.s_i0[cpos];
+      hit = true;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int L = d == 0 ? kTileX : (d == 1 ? TY : TZ);
+        int st = unpack_i0<DIM>(pk, d) - base[d];
+        if (st < 0) st += a.nf[d];
+        hit = hit && (st < L || st + W > a.nf[d]);  // starts inside, or wraps round into the tile
+      }
+    }
+    const unsigned long long hb = __ballot(hit);
+    const int before = __popcll(hb & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wave] = __popcll(hb);
+    __syncthreads();
+    int wbase = 0, nsel = 0;
+    for (int v = 0; v < kSpreadThreads / 64; ++v) {
+      if (v < wave) wbase += wcnt[v];
+      nsel += wcnt[v];
+    }
+    if (hit) sel[wbase + before] = cpos;
+    if (tid == 0) wcnt[kSpreadThreads / 64] = nsel;
+    __syncthreads();
+  }
+  const int nsel = wcnt[kSpreadThreads / 64];
+  for (int c0 = 0; c0 < nsel; c0 += kChunk) {
+    const int cnt = nsel - c0 < kChunk ? nsel - c0 : kChunk;
     // (1) wavefront d < DIM: axis d of the staged points, lane = point; wavefront DIM: strengths
     {
       const int pl = lane;
       const bool valid = pl < cnt;
-      int64_t pos = 0;
-      if (valid) {
-        int vi = c0 + pl, r = 0;
-        while (vi >= rlen[r]) vi -= rlen[r++];
-        pos = (int64_t)rbeg[r] + vi;
-      }
+      const int64_t pos = valid ? (int64_t)sel[c0 + pl] : 0;
       if (wave < DIM) {
         const int d = wave;
         const int nfd = a.nf[d];
@@ -266,6 +300,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
       }
     }
     __syncthreads();
+  }
   }
   // each lane writes its CW cells (zeros when no point reaches the tile but some reach its lines)
   if (nparts > 1) {  // one part of a split tile: partial tile to scratch, summed by k_merge_tiles
