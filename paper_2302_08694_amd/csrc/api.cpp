@@ -39,7 +39,6 @@ fsib_status fail(fsib_status s, const std::string& msg) {
 
 using fsib::Plan;
 
-constexpr int64_t kSplitPoints = 1024;  // points per part of a heavy spreading tile (kSplit)
 
 int64_t ceil_half(int64_t n) { return (n + 1) / 2; }
 
@@ -172,6 +171,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   // workgroup-to-XCD run lengths (tuning knobs; the defaults are the measured best)
   if (const char* e = std::getenv("FSIB_XCD_CHUNK_INTERP")) p.xcd_chunk_interp = std::atoi(e);
   if (const char* e = std::getenv("FSIB_XCD_CHUNK_SPREAD")) p.xcd_chunk_spread = std::atoi(e);
+  if (const char* e = std::getenv("FSIB_SPREAD_SPLIT")) p.split = std::atoi(e) >= 64 ? std::atoi(e) : 64;
   // kernel (App. A.3): width from tol, Kaiser-Bessel shape, polynomial degree
   p.sigma = plan_sigma(o);
   p.w = fsib::choose_width(p.tol, p.dim, p.sigma);
@@ -254,7 +254,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   A.get(p.scan_part, fsib::scan_segments(p.nbt) * 4);
   A.get(p.rowmask, p.nt[1] * p.nt[2]);
   A.get(p.zmask, p.nt[2]);
-  // spreading work list: part bound = tiles + visits / kSplit, visits <= M * prod(q + 1)
+  // spreading work list: part bound = tiles + visits / split, visits <= M * prod(q + 1)
   {
     int64_t reach = 1;
     for (int a = 0; a < p.dim; ++a) {
@@ -264,8 +264,8 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
       reach *= q + 1;
     }
     const int64_t visits = Mx * reach;
-    p.work_blocks = p.nbt + visits / kSplitPoints + 1;
-    p.split_slots = 2 * visits / kSplitPoints + 2;
+    p.work_blocks = p.nbt + visits / p.split + 1;
+    p.split_slots = 2 * visits / p.split + 2;
     const int64_t nch_bytes = 2 * rs > d * rs ? 2 * rs : d * rs;  // complex or dim real channels
     const int64_t tr = p.ntrans > 1 ? p.ntrans : 1;
     A.get(p.tile_parts, p.nbt * 4);

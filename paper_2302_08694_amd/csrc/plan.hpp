@@ -35,6 +35,7 @@ struct Plan {
   int lds_max = 65536;  // LDS bytes one workgroup may allocate on this device
   int xcd_chunk_interp = 64;  // interpolation workgroups kept together per XCD (2048 sorted points)
   int xcd_chunk_spread = 16;  // spreading tiles kept together per XCD (0: plain numbering)
+  int split = 512;            // candidates per part of a heavy spreading tile (sweep: 1024, 512, 256, 128)
   // kernel
   int w = 0, deg = 0;
   double beta = 0.0;
@@ -66,7 +67,7 @@ struct Plan {
   int* scan_part = nullptr;  // segment sums of the exclusive scans over bins
   uint8_t* rowmask = nullptr;  // nt[2] x nt[1]: a point's support reaches this block of x lines
   uint8_t* zmask = nullptr;    // nt[2]: some line of this block of z planes is reached
-  // spreading work list (heavy tiles split into parts of at most kSplit points)
+  // spreading work list (heavy tiles split into parts of at most `split` candidates)
   int64_t qn[3] = {0, 0, 0};   // bins before a tile, per axis, whose points can reach it
   int* tile_parts = nullptr;   // nbins
   int* part_off = nullptr;     // nbins+1

@@ -18,7 +18,6 @@ constexpr int kChunk = 64;           // points staged per round
 constexpr int kMaxTileCells = 1024;  // cells of one tile
 constexpr int kTileX = 16;           // tile extent along x (one register row per thread)
 
-constexpr int kSplit = 1024;         // points per part of a heavy tile
 
 template <typename T>
 struct SpreadArgs {
@@ -36,7 +35,7 @@ struct SpreadArgs {
   int tb[3];
   int nt[3];
   int q[3];             // neighbour bins to visit per axis (0..q)
-  // work list: entry e = (t, q), q >= 1: workgroup nbins + e spreads points [q*kSplit, (q+1)*kSplit) of tile t
+  // work list: entry e = (t, q), q >= 1: workgroup nbins + e spreads candidates [q*split, (q+1)*split) of tile t
   const int* part_off;  // nbins+1 (exclusive scan of tile_parts)
   const int2* work;     // (t, q) per part
   const int* tile_parts;
@@ -45,6 +44,7 @@ struct SpreadArgs {
   int64_t slots;        // scratch slots per transform
   const uint8_t* rowmask;  // blocks of x lines reached by some point (lines elsewhere stay unwritten)
   int xcd_chunk;           // > 0: workgroups renumbered in runs of this many per XCD (xcd_chunked)
+  int split;               // candidates per part of a heavy tile
   int ninst;               // instances: tile t of the whole plan is tile t % nbins of instance t / nbins,
                            // whose real grids follow one another ([inst][ch][cells])
 };
@@ -174,8 +174,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   }
   int total = 0;
   for (int r = 0; r < nrange; ++r) total += rlen[r];
-  const int cbeg = part * kSplit;
-  const int cend = total < cbeg + kSplit ? total : cbeg + kSplit;
+  const int cbeg = part * a.split;
+  const int cend = total < cbeg + a.split ? total : cbeg + a.split;
   const int row = tid % ROWS, xg = tid / ROWS;
   const int ly = row % TY, lz = DIM == 3 ? row / TY : 0;
   const int lane = tid & 63, wave = tid >> 6;
@@ -340,7 +340,7 @@ __global__ void k_sort_strengths(int64_t M, const int* __restrict__ s_idx, const
 }
 
 // Points reaching each tile (its bin and the q bins before it per axis) and the parts it splits into.
-__global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1, int q2, int ninst,
+__global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1, int q2, int ninst, int split,
                              const int* __restrict__ offsets, int* __restrict__ tile_parts) {
   const int tg = blockIdx.x * blockDim.x + threadIdx.x;
   const int nbins = nt0 * nt1 * nt2;
@@ -355,7 +355,7 @@ __global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1,
         const int b = bx + nt0 * (by + nt1 * bz) + inst * nbins;
         total += offsets[b + 1] - offsets[b];
       }
-  tile_parts[tg] = total <= kSplit ? 1 : (total + kSplit - 1) / kSplit;
+  tile_parts[tg] = total <= split ? 1 : (total + split - 1) / split;
 }
 
 // Work list of the further parts (tile, part >= 1) in tile order, and scratch slots for tiles split
@@ -665,6 +665,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   a.rowmask = p.ninst > 1 ? nullptr : p.rowmask;  // occupancy masks: single-instance plans only
   a.xcd_chunk = p.xcd_chunk_spread;
   a.ninst = p.ninst;
+  a.split = p.split;
   a.sstr = (T*)p.s_str;
   const unsigned nb = (unsigned)p.nbt;
   if (M > 0) {
@@ -674,7 +675,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
     if (e0 != hipSuccess) return e0;
   }
   hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, DIM, a.nt[0], a.nt[1], a.nt[2], a.q[0],
-                     a.q[1], a.q[2], p.ninst, (const int*)p.offsets, p.tile_parts);
+                     a.q[1], a.q[2], p.ninst, a.split, (const int*)p.offsets, p.tile_parts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
