@@ -321,3 +321,32 @@ def test_circle_navier_stokes_conserves_area(F):
           f"max {drift.max():.2e}; final radius spread {rad.max() - rad.min():.2e}")
     assert drift.max() < 1e-3
     plan.close()
+
+
+def test_temporal_second_order_2d_navier_stokes(F):
+    """Sec. 5 / Alg. 1 temporal convergence (the 2D circle with sine flow of Sec. 6.2.1, N = 64,
+    202 points): dt = 0.002 halved three times to t = 0.1; successive differences of the positions
+    and of the velocity field shrink by about 4 (second order)."""
+    announce("temporal convergence 2D NS")
+    N, Nb, T = 64, 202, 0.1
+    X0 = wl.circle_2d(Nb, center=(0.5, 0.5), r=0.25)
+    outs = []
+    for dt in (2e-3, 1e-3, 5e-4, 2.5e-4):
+        plan = F.Plan(2, (N, N), prec="f64", tol=1e-11, max_points=Nb, fluid=True, navier_stokes=True)
+        params = F.FluidParams("navier_stokes", rho=1.0, mu=0.01, dt=dt)
+        force = F.Force("tension2d", 1.0)
+        X = dev(X0)
+        uh = torch.zeros((2,) + plan.half_shape, dtype=torch.complex128)
+        uh[1, 0, 1] = -0.5j
+        uh = uh.to("cuda:0")
+        U = plan.velocity(params, force, X, uh)
+        for _ in range(int(round(T / dt))):
+            plan.step(params, force, X, U, uh)
+        outs.append((host(X), host(uh)))
+        plan.close()
+    dX = [np.linalg.norm(outs[i + 1][0] - outs[i][0]) for i in range(3)]
+    dU = [np.linalg.norm(outs[i + 1][1] - outs[i][1]) for i in range(3)]
+    rX = [dX[i] / dX[i + 1] for i in range(2)]
+    rU = [dU[i] / dU[i + 1] for i in range(2)]
+    print(f"temporal convergence: position ratios {rX[0]:.2f} {rX[1]:.2f}; velocity ratios {rU[0]:.2f} {rU[1]:.2f}")
+    assert all(3.5 < r < 4.5 for r in rX + rU)
