@@ -247,6 +247,7 @@ def batched_stokes(F, torch, steps=50, graph_steps=10):
     for prec, tol in (("f32", 1e-5), ("f64", 1e-5)):
         b = StokesGroupBatch(cases, prec=prec, tol=tol)
         res["grouped_plans"] = len(b.groups)
+        res[f"{prec}_grouped_tuning"] = {str(k): v for k, v in b.autotune().items()}
         b.step(1)
         b.reset()
         torch.cuda.synchronize()

@@ -94,6 +94,13 @@ typedef struct {
   int64_t workspace_bytes;
 } fsib_plan_info_t;
 
+/* Launch-shape knobs of a plan (results do not depend on them, only speed). */
+typedef struct {
+  int xcd_chunk_interp;  /* interpolation workgroups kept together on one XCD (0: plain order) */
+  int xcd_chunk_spread;  /* spreading tiles kept together on one XCD (0: plain order) */
+  int split;             /* candidate points per part of a heavy spreading tile */
+} fsib_tuning;
+
 typedef enum { FSIB_STOKES = 0, FSIB_NAVIER_STOKES = 1 } fsib_model;
 
 typedef struct {
@@ -163,6 +170,11 @@ typedef enum {
   FSIB_PROF_NL_X = 5          /* fused x pass of the dealiased products */
 } fsib_prof_class;
 fsib_status fsib_plan_profile(fsib_plan plan, int kernel_class, int max_launches);
+/* Read (get = 1) or set (get = 0) the launch-shape knobs, e.g. for a timed autotuning search.
+ * Results are identical up to the summation order of spreading.  split may not go below the value
+ * the plan was created with (its scratch is sized for it; the creation value is 512).  Errors:
+ * FSIB_ERR_ARG for NULL or out-of-range values (chunks in [0, 4096], split in [creation, 1 << 20]). */
+fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* tuning, int get);
 fsib_status fsib_plan_profile_read(fsib_plan plan, double* total_ms /* host */, int64_t* launches /* host */,
                                    double* bytes /* host */);
 

@@ -38,6 +38,10 @@ class _Params(ctypes.Structure):
                 ("body", ctypes.c_double * 3)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("xcd_chunk_interp", ctypes.c_int), ("xcd_chunk_spread", ctypes.c_int), ("split", ctypes.c_int)]
+
+
 class _Force(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("K", ctypes.c_double), ("tris", ctypes.c_void_p), ("ntris", ctypes.c_int64),
                 ("v2t_ptr", ctypes.c_void_p), ("v2t_idx", ctypes.c_void_p), ("aux", ctypes.c_void_p)]
@@ -50,6 +54,7 @@ _SIGS = {
     "fsib_device_count": (ctypes.c_int, []),
     "fsib_plan_create": (ctypes.c_int, [ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_void_p)]),
     "fsib_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fsib_plan_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Tuning), ctypes.c_int]),
     "fsib_plan_set_instances": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "fsib_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Info)]),
     "fsib_plan_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -246,6 +251,17 @@ class Plan:
     def field_shape(self):
         """Shape of the half spectra of the plan's real fields: (dim, ...) or (ninst, dim, ...)."""
         return ((self.dim,) if self.ninst == 1 else (self.ninst, self.dim)) + self.half_shape
+
+    def tuning(self, **changes):
+        """Launch-shape knobs (fsib_plan_tuning): with no arguments returns them as a dict; keyword
+        arguments (xcd_chunk_interp, xcd_chunk_spread, split) set them and return the new dict."""
+        t = _Tuning()
+        _check(self._lib.fsib_plan_tuning(self._h, ctypes.byref(t), 1), "fsib_plan_tuning")
+        if changes:
+            for k, v in changes.items():
+                setattr(t, k, int(v))
+            _check(self._lib.fsib_plan_tuning(self._h, ctypes.byref(t), 0), "fsib_plan_tuning")
+        return {k: getattr(t, k) for k, _ in _Tuning._fields_}
 
     def set_instances(self, counts):
         """Point counts of the instances of a multi-instance plan (fsib_plan_set_instances); points are

@@ -151,6 +151,21 @@ class StokesGroupBatch:
             for s in self.streams:
                 main.wait_stream(s)
 
+    def autotune(self, reps=3):
+        """Tune each group's plan knobs (paper_2302_08694_amd.tune) on timed steps of that group;
+        the state is restored afterwards.  Returns {N: chosen knobs}."""
+        from .tune import autotune
+        chosen = {}
+        for g in self.groups:
+            saved = (g["X"].clone(), g["U"].clone(), g["uh"].clone())
+            run = lambda g=g: g["plan"].step(g["params"], g["force"], g["X"], g["U"], g["uh"])
+            chosen[g["plan"].n_modes[0]] = autotune(g["plan"], run, reps=reps)["best"]
+            g["X"].copy_(saved[0])
+            g["U"].copy_(saved[1])
+            g["uh"].copy_(saved[2])
+        torch.cuda.synchronize()
+        return chosen
+
     def positions(self):
         out = [None] * sum(len(g["idx"]) for g in self.groups)
         for g in self.groups:

@@ -264,6 +264,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
       reach *= q + 1;
     }
     const int64_t visits = Mx * reach;
+    p.split_alloc = p.split;
     p.work_blocks = p.nbt + visits / p.split + 1;
     p.split_slots = 2 * visits / p.split + 2;
     const int64_t nch_bytes = 2 * rs > d * rs ? 2 * rs : d * rs;  // complex or dim real channels
@@ -665,6 +666,26 @@ fsib_status fsib_plan_check(fsib_plan plan, void* stream) {
     FSIB_HIP(hipStreamSynchronize(S(stream)));
     return fail(FSIB_ERR_NONFINITE, "a non-finite position was seen (treated as x = 0)");
   }
+  return FSIB_OK;
+}
+
+fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  if (!t) return fail(FSIB_ERR_ARG, "tuning is NULL");
+  Plan& p = plan->p;
+  if (get) {
+    t->xcd_chunk_interp = p.xcd_chunk_interp;
+    t->xcd_chunk_spread = p.xcd_chunk_spread;
+    t->split = p.split;
+    return FSIB_OK;
+  }
+  if (t->xcd_chunk_interp < 0 || t->xcd_chunk_interp > 4096 || t->xcd_chunk_spread < 0 || t->xcd_chunk_spread > 4096)
+    return fail(FSIB_ERR_ARG, "XCD chunks must be in [0, 4096]");
+  if (t->split < p.split_alloc || t->split > (1 << 20))
+    return fail(FSIB_ERR_ARG, "split must be in [the creation value, 1 << 20]");
+  p.xcd_chunk_interp = t->xcd_chunk_interp;
+  p.xcd_chunk_spread = t->xcd_chunk_spread;
+  p.split = t->split;
   return FSIB_OK;
 }
 

@@ -113,3 +113,9 @@ def test_fluid_params_layout():
 def test_set_instances_rejects_null_plan():
     lib = B.load_library()
     assert lib.fsib_plan_set_instances(None, None) == 1
+
+
+def test_tuning_rejects_null_arguments():
+    lib = B.load_library()
+    t = B._Tuning(0, 0, 512)
+    assert lib.fsib_plan_tuning(None, ctypes.byref(t), 1) == 1

@@ -178,3 +178,30 @@ def test_group_batch_matches_per_instance_batch(F):
     a.close()
     b.close()
     assert worst < 1e-11
+
+
+def test_tuning_knobs_keep_results(F):
+    """Changing the launch-shape knobs (fsib_plan_tuning) changes speed only: a 3D NUFFT pair and a
+    2D multi-instance step agree to rounding across settings; the autotuner leaves a valid setting."""
+    import workloads as wl
+    from oracle.modes import spectral_shape
+    from paper_2302_08694_amd.tune import autotune
+    announce("tuning knobs")
+    X0, c0 = wl.nufft_points(3000, seed=7, dim=3)
+    f0 = wl.random_modes(spectral_shape((24, 24, 24)), 8)
+    plan = F.Plan(3, (24, 24, 24), prec="f64", tol=1e-10, max_points=3000)
+    X, c, f = dev(X0), dev(c0), dev(f0)
+    base = plan.tuning()
+    assert base["split"] == 512
+    r0 = (host(plan.spread(X, c)), host(plan.interp(X, f)))
+    for knobs in ({"xcd_chunk_spread": 0, "xcd_chunk_interp": 0}, {"xcd_chunk_spread": 64, "split": 2048},
+                  {"xcd_chunk_interp": 256, "split": 600}):
+        plan.tuning(**{**base, **knobs})
+        r = (host(plan.spread(X, c)), host(plan.interp(X, f)))
+        assert rel_l2(r[0], r0[0]) < 1e-13 and rel_l2(r[1], r0[1]) < 1e-15
+    with pytest.raises(F.FSIBError):
+        plan.tuning(split=256)  # below the creation value
+    res = autotune(plan, lambda: (plan.spread(X, c), plan.interp(X, f)), reps=1)
+    assert res["best"] == plan.tuning()
+    print(f"autotune chose {res['best']} ({len(res['trials'])} trials)")
+    plan.close()
