@@ -116,3 +116,36 @@ def test_circle_pressure_has_zero_mean_and_the_laplace_jump():
     p1, p2 = validation.circle_pressure_jump(F, r, L)
     assert p1 * (L * L - np.pi * r * r) + p2 * np.pi * r * r == pytest.approx(0.0, abs=1e-15)
     assert p1 - p2 == pytest.approx(F / r)
+
+
+def test_steady_wall_system_satisfies_no_slip_and_force_balance():
+    # a symmetric matrix with a null direction, as the wall's Stokes matrix has: the solve must still
+    # meet every equation it states
+    rng = np.random.default_rng(7)
+    Nb = 6
+    B = rng.standard_normal((2 * Nb, 2 * Nb - 1))
+    A = B @ B.T
+    S, ubar = validation.steady_wall_system(A, Nb, 3.0, 1.0)
+    assert np.abs(A @ S.ravel() + np.tile(ubar, Nb)).max() < 1e-11
+    assert S.sum(axis=0) == pytest.approx([-3.0, 0.0], abs=1e-12)
+
+
+def test_steady_channel_converges_first_order_and_three_halves_against_the_effective_width():
+    """Sec. 6.2.2, steady channel with D = L: the relative velocity error is first order against the
+    channel width D and faster (3/2 order reported) against the effective width D_e; the effective
+    boundary width tends to about 0.4 h."""
+    f0, mu, L = 100.0, 0.1, 1.0
+    res = []
+    for N in (8, 16, 32):
+        S, ubar, uhat, ux = validation.steady_channel(N, f0, mu, L)
+        assert S.sum(axis=0) == pytest.approx([-f0, 0.0], abs=1e-9 * f0)
+        # the grid mean of a trigonometric polynomial is its k = 0 mode: the mean flow
+        assert ux.mean() == pytest.approx(ubar[0], rel=1e-12)
+        # mirror symmetry about the wall: u(y) = u(L - y)
+        assert np.abs(ux[1:] - ux[:0:-1]).max() < 1e-9 * np.abs(ux).max()
+        res.append(validation.steady_channel_errors(ux, ubar[0], N, f0, mu, L) + (N,))
+    for (e0, d0, _, _), (e1, d1, _, _) in zip(res, res[1:]):
+        assert 0.8 < np.log2(e0 / e1) < 1.3
+        assert np.log2(d0 / d1) > 1.4
+    De, N = res[-1][2], res[-1][3]
+    assert 0.35 < (L - De) * N / L < 0.5
