@@ -350,3 +350,56 @@ def test_temporal_second_order_2d_navier_stokes(F):
     rU = [dU[i] / dU[i + 1] for i in range(2)]
     print(f"temporal convergence: position ratios {rX[0]:.2f} {rX[1]:.2f}; velocity ratios {rU[0]:.2f} {rU[1]:.2f}")
     assert all(3.5 < r < 4.5 for r in rX + rU)
+
+
+def _steady_channel_gpu(F, N, f0, mu, L=1.0):
+    """The steady channel with D = L through the HIP path: the wall's Stokes matrix is assembled one
+    column per launch sequence (spread of a unit strength, Stokes solve, interpolation at the wall),
+    the small bordered system is solved on the host, and the strengths' flow is computed once more on
+    the GPU.  Returns (S, ubar, ux[y][x] with the mean flow)."""
+    X = dev(validation.wall_points(N, L))
+    plan = F.Plan(2, (N, N), prec="f64", tol=1e-11, max_points=N, fluid=True)
+    params = F.FluidParams("stokes", mu=mu)
+    A = np.zeros((2 * N, 2 * N))
+    for j in range(N):
+        for a in range(2):
+            S = torch.zeros((N, 2), dtype=torch.float64, device="cuda:0")
+            S[j, a] = 1.0
+            fh = plan.force_spread(X, S, 1.0)
+            uh = torch.zeros_like(fh)
+            plan.fluid_step(params, fh, uh)
+            A[:, 2 * j + a] = host(plan.velocity_interp(X, uh)).ravel()
+    S, ubar = validation.steady_wall_system(A, N, f0, L)
+    fh = plan.force_spread(X, dev(S), 1.0)
+    uh = torch.zeros_like(fh)
+    plan.fluid_step(params, fh, uh)
+    ux = _grid_values(host(uh)[0], N) + ubar[0]
+    plan.close()
+    return S, ubar, ux
+
+
+def test_steady_channel_matches_oracle_and_converges(F):
+    """Sec. 6.2.2, steady channel with D = L (one wall at y = 0), N_b = N, f0 = 100, mu = 0.1.
+    Parity of the strengths, mean flow and velocity field with the oracle (the bordered solve
+    amplifies the FP64 transform error by the wall matrix's condition number, a few hundred, so the
+    bar is 1e-8); then the paper's orders up to N = 512: first order against D, faster than 1.4
+    against the effective width D_e, and D - D_e about 0.4 h."""
+    f0, mu, L = 100.0, 0.1, 1.0
+    for N in (16, 64):
+        announce(f"steady channel parity N={N}")
+        S, ubar, ux = _steady_channel_gpu(F, N, f0, mu, L)
+        So, ubo, _, uxo = validation.steady_channel(N, f0, mu, L)
+        assert rel_l2(S, So) < 1e-8
+        assert np.abs(ubar - ubo).max() < 1e-8 * np.abs(ubo).max()
+        assert rel_l2(ux, uxo) < 1e-8
+    res = []
+    for N in (32, 64, 128, 256, 512):
+        announce(f"steady channel N={N}")
+        S, ubar, ux = _steady_channel_gpu(F, N, f0, mu, L)
+        e, d, De = validation.steady_channel_errors(ux, ubar[0], N, f0, mu, L)
+        print(f"steady channel N={N}: err(D) {e:.3e} err(D_e) {d:.3e} (L - D_e)/h {(L - De) * N:.3f}")
+        res.append((e, d, De, N))
+    for (e0, d0, _, _), (e1, d1, _, _) in zip(res, res[1:]):
+        assert 0.8 < np.log2(e0 / e1) < 1.3
+        assert np.log2(d0 / d1) > 1.4
+    assert all(0.35 < (L - De) * N < 0.5 for _, _, De, N in res)
