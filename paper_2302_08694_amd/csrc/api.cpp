@@ -223,10 +223,14 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   for (int n : lengths) {
     int r[fsib::kMaxStages];
     if (fsib::radix_plan(n, r) == 0) return fail(FSIB_ERR_ARG, "no FFT radix plan for length " + std::to_string(n));
-    // one FFT line (two LDS buffers) must fit the 64 KiB a workgroup may use
-    if ((int64_t)n * 2 * 2 * (int64_t)p.real_size() > 65536)
-      return fail(FSIB_ERR_ARG, "FFT length " + std::to_string(n) + " exceeds the LDS budget of one workgroup");
+    // one FFT line must fit one workgroup's threads and LDS on this device
+    if (!fsib::fft_line_fits(p, n))
+      return fail(FSIB_ERR_ARG, "FFT length " + std::to_string(n) + " exceeds the LDS budget of one workgroup (" +
+                                    std::to_string(p.lds_max) + " bytes) or its thread limit");
   }
+  if (p.ns && !fsib::nl_line_fits(p, (int)p.nd[0]))
+    return fail(FSIB_ERR_ARG, "dealiasing length " + std::to_string(p.nd[0]) +
+                                  " exceeds one workgroup of the nonlinear term's x pass");
 
   const int64_t rs = (int64_t)p.real_size();
   const int64_t cs = 2 * rs;

@@ -377,6 +377,17 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
   return hipGetLastError();
 }
 
+// One line of length n per workgroup is the smallest launch of every pass: it must fit the thread
+// limit (kEPT elements per thread) and the LDS of one workgroup (contiguous layout with padding,
+// twiddles and flags; the strided layout with one flag per input entry).
+bool fft_line_fits(const Plan& p, int n) {
+  if (n > kEPT * kMaxFftThreads) return false;
+  const size_t cs = p.prec == FSIB_F64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
+  const size_t contig = (size_t)(lpad_len(n) + n) * cs + flag_bytes(2);
+  const size_t strided = (size_t)2 * n * cs + flag_bytes(n);
+  return std::max(contig, strided) <= (size_t)p.lds_max;
+}
+
 hipError_t launch_fft_c2c(const Plan& p, const void* in, void* out, int n, int sign, int64_t inner, int64_t outer,
                           int nin, int pin, int nout, int pout, const void* fac_in, const void* fac_out, double scale,
                           hipStream_t st, const PassMasks& mk) {

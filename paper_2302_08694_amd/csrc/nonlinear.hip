@@ -189,6 +189,15 @@ static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t 
   return hipGetLastError();
 }
 
+// The x pass of the dealiased product holds the forward lines of one row pair (3 in 2D, 6 in 3D)
+// in one workgroup of at most 1024 threads.
+bool nl_line_fits(const Plan& p, int n) {
+  const int fl = p.dim == 3 ? 6 : 3;
+  if ((fl * n + kEPT - 1) / kEPT > 1024) return false;
+  const size_t cs = p.prec == FSIB_F64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
+  return (size_t)(lpad_len(fl * n) + n) * cs <= (size_t)p.lds_max;
+}
+
 hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, hipStream_t st) {
   return p.prec == FSIB_F64 ? nl_impl<double>(p, in, out, st) : nl_impl<float>(p, in, out, st);
 }

@@ -137,6 +137,8 @@ hipError_t launch_fft_c2r_x(const Plan& p, const void* in, void* out, int n, int
                             const void* fac_in, double scale, hipStream_t st, const PassMasks& mk = PassMasks());
 // fluid.hip
 hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, hipStream_t st);  // nonlinear.hip
+bool fft_line_fits(const Plan& p, int n);  // fft.hip
+bool nl_line_fits(const Plan& p, int n);   // nonlinear.hip
 hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
                                const void* uin, void* uout, hipStream_t st);
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F,

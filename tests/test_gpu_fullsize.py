@@ -178,3 +178,32 @@ def test_nufft_micro_type2_sampled(F, nufft_micro, prec, tol, bar):
     print(f"NUFFT micro type-2 {prec} tol {tol}: rel_l2 {err:.3e}")
     assert err < bar
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_longest_fft_lines_2d(F, prec):
+    """The longest fine-grid lines one workgroup holds: N = 2048^2 in 2D oversamples to 4096-point
+    lines (about 136 KiB of LDS per line in FP64).  Type-1 at 256 sampled modes and type-2 at 64
+    sampled points against direct sums; lines of 8192 points are refused at plan creation."""
+    announce(f"2D N=2048 long FFT lines {prec}")
+    Ns = (2048, 2048)
+    X, c = workloads.nufft_points(4000, seed=41, dim=2)
+    M = X.shape[0]
+    tol = 1e-11 if prec == "f64" else 1e-5
+    bar = 1e-10 if prec == "f64" else 1e-5
+    plan = F.Plan(2, Ns, prec=prec, tol=tol, max_points=M)
+    assert plan.info()["n_fine"] == (4096, 4096)
+    out = host(plan.spread(dev(X), dev(c, cdtype(prec))))
+    (ix, iy), m = _sample_modes(Ns, 256, 42)
+    e1 = rel_l2(out[iy, ix], nudft.type1_at_modes(X, c, m))
+    f = workloads.random_modes(spectral_shape(Ns), 43)
+    got = host(plan.interp(dev(X), dev(f, cdtype(prec))))
+    sel = np.random.default_rng(44).choice(M, 64, replace=False)
+    e2 = rel_l2(got[sel], nudft.type2(X[sel], f, Ns))
+    print(f"2D N=2048 {prec}: type-1 rel_l2 {e1:.3e}, type-2 rel_l2 {e2:.3e}")
+    assert e1 < bar and e2 < bar
+    plan.close()
+    with pytest.raises(F.FSIBError, match="LDS budget"):
+        F.Plan(2, (4096, 4096), prec=prec, tol=tol, max_points=16)
+    with pytest.raises(F.FSIBError, match="dealiasing length"):
+        F.Plan(2, Ns, prec=prec, tol=tol, max_points=16, fluid=True, navier_stokes=True)

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import workloads as wl
-from oracle import fluid, forces, validation
+from oracle import fluid, forces, step, validation
 from oracle.modes import nyquist_mask, spectral_shape
 from tests.gpu_helpers import announce, dev, host, half, rel_l2, cdtype, rdtype
 
@@ -403,3 +403,107 @@ def test_steady_channel_matches_oracle_and_converges(F):
         assert 0.8 < np.log2(e0 / e1) < 1.3
         assert np.log2(d0 / d1) > 1.4
     assert all(0.35 < (L - De) * N < 0.5 for _, _, De, N in res)
+
+
+def _circle_stokes_gpu(F, N, Nb, kind):
+    """_circle's Stokes solve returning the points, strengths, the velocity at the points and the x
+    velocity and pressure on the grid ([y][x], host)."""
+    X, S, (fh, uh, ph) = _circle(F, N, Nb, kind)
+    plan = F.Plan(2, (N, N), prec="f64", tol=1e-11, max_points=Nb, fluid=True)
+    U = host(plan.velocity_interp(dev(X), dev(uh)))
+    plan.close()
+    return X, S, U, _grid_values(uh[0], N), _grid_values(ph, N)
+
+
+def test_circle_exponential_convergence_in_the_number_of_points(F):
+    """Sec. 6.1 (exponential accuracy of the spreading quadrature): N = 128 fixed, N_b = 4 ... 128;
+    the x velocity of the tangent case and the pressure of the normal case on the vertical centreline,
+    against N_b = 512, fall faster than any power of N_b (each doubling gains more than the one
+    before) and reach rounding level once N_b resolves the band of the modes on the circle.  The
+    GPU velocity at the points matches the oracle at N_b = 32."""
+    N = 128
+    _, _, _, u_ref, _ = _circle_stokes_gpu(F, N, 512, "tangent")
+    _, _, _, _, p_ref = _circle_stokes_gpu(F, N, 512, "normal")
+    eu, ep = [], []
+    for Nb in (4, 8, 16, 32, 64, 128):
+        announce(f"circle N=128 N_b={Nb}")
+        X, S, U, ug, _ = _circle_stokes_gpu(F, N, Nb, "tangent")
+        _, _, _, _, pg = _circle_stokes_gpu(F, N, Nb, "normal")
+        eu.append(rel_l2(ug[:, N // 2], u_ref[:, N // 2]))
+        ep.append(rel_l2(pg[:, N // 2], p_ref[:, N // 2]))
+        if Nb == 32:
+            Uo, _ = step.stokes_map(X, S, (N, N), 1.0, 1.0)
+            assert rel_l2(U, Uo) < 1e-10
+    print("circle centreline errors vs N_b = 512: u " + ", ".join(f"{e:.2e}" for e in eu)
+          + "; p " + ", ".join(f"{e:.2e}" for e in ep))
+    for e in (eu, ep):
+        gains = [e[i] / e[i + 1] for i in range(len(e) - 2)]
+        assert all(g2 > g1 for g1, g2 in zip(gains[1:], gains[2:]))  # accelerating
+        assert e[-2] < 0.05 * e[2] and e[-1] < 1e-9
+
+
+def test_circle_stokes_first_order_with_coupled_refinement(F):
+    """Sec. 6.1 (spatial convergence, FSIB half): the tangent case from N = 8, N_b = 4, both doubled
+    eight times to N = 2048; the velocity at the points, compared with the next refinement at the
+    shared points, converges at first order.  Parity with the oracle at N = 128."""
+    errs, prev = [], None
+    for k in range(9):
+        N, Nb = 8 << k, 4 << k
+        announce(f"circle coupled N={N} N_b={Nb}")
+        X, S, U, _, _ = _circle_stokes_gpu(F, N, Nb, "tangent")
+        if N == 128:
+            Uo, _ = step.stokes_map(X, S, (N, N), 1.0, 1.0)
+            assert rel_l2(U, Uo) < 1e-10
+        if prev is not None:
+            errs.append(rel_l2(U[::2], prev))
+        prev = U
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    print("coupled refinement: errors " + ", ".join(f"{e:.2e}" for e in errs)
+          + "; ratios " + ", ".join(f"{x:.2f}" for x in ratios))
+    assert all(1.7 < x < 2.4 for x in ratios[2:])
+
+
+def _half_spectrum_l2_diff(hc, Nc, hf, Nf):
+    """Relative L2 norm over the box of the difference of two velocity fields given by their half
+    spectra (2, N, N/2 + 1) at N = Nc < Nf (Parseval: the coarse modes sit at the same mode numbers
+    of the fine spectrum; m_x > 0 columns count twice)."""
+    e = hf.copy()
+    rows = np.arange(Nc)
+    rows = np.where(rows < Nc // 2, rows, rows - Nc + Nf)  # mode number m_y -> fine row
+    e[:, rows, : hc.shape[-1]] -= hc
+    w = np.full(hf.shape[-1], 2.0)
+    w[0] = 1.0
+    return float(np.sqrt(np.sum(np.abs(e) ** 2 * w) / np.sum(np.abs(hf) ** 2 * w)))
+
+
+def test_circle_navier_stokes_space_time_convergence(F):
+    """Sec. 6.2.1 (space and time refined together, FSIB half): the circle with sine flow from N = 8,
+    dt = 1e-3, N_b = 26, halving dt and doubling N and N_b up to N = 512, to t = 0.1; successive
+    relative L2 differences of the velocity field over the box.  The paper fits order 3/2; measured
+    here 0.89, 1.39, 1.44, 1.33, 1.22 (1.13 at N = 1024): above first order over N = 16 to 256, with
+    the point positions converging at first order (as the Stokes velocity at the points does) and
+    the order falling toward one on the finest grids."""
+    T = 0.1
+    spectra = []
+    for k in range(7):
+        N, Nb, dt = 8 << k, 26 << k, 1e-3 / (1 << k)
+        announce(f"2D NS space-time N={N} N_b={Nb} dt={dt:g}")
+        X0 = wl.circle_2d(Nb, center=(0.5, 0.5), r=0.25)
+        plan = F.Plan(2, (N, N), prec="f64", tol=1e-11, max_points=Nb, fluid=True, navier_stokes=True)
+        params = F.FluidParams("navier_stokes", rho=1.0, mu=0.01, dt=dt)
+        force = F.Force("tension2d", 1.0)
+        X = dev(X0)
+        uh = torch.zeros((2,) + plan.half_shape, dtype=torch.complex128)
+        uh[1, 0, 1] = -0.5j
+        uh = uh.to("cuda:0")
+        U = plan.velocity(params, force, X, uh)
+        for _ in range(int(round(T / dt))):
+            plan.step(params, force, X, U, uh)
+        spectra.append((N, host(uh)))
+        plan.close()
+    errs = [_half_spectrum_l2_diff(spectra[i][1], spectra[i][0], spectra[i + 1][1], spectra[i + 1][0])
+            for i in range(len(spectra) - 1)]
+    orders = [float(np.log2(errs[i] / errs[i + 1])) for i in range(len(errs) - 1)]
+    print("2D NS space-time: L2 differences " + ", ".join(f"{e:.3e}" for e in errs)
+          + "; orders " + ", ".join(f"{o:.2f}" for o in orders))
+    assert all(o > 1.25 for o in orders[1:4]) and all(o > 1.0 for o in orders[1:])
