@@ -38,7 +38,6 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
   cplx<T>* twl = buf + (CONTIG ? lpad_len(n * nb) : n * nb);
-  stage_twiddles(a.tw, twl, n);
   // occupancy flags of this workgroup's rows (x passes) or of the entries it loads and stores
   // (strided passes), fetched once; the workgroup leaves when nothing it owns is reached by a point
   uint8_t* fld = flag_area(twl, n);
@@ -107,6 +106,8 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
       }
     }
   }
+  // the twiddles' loads go out behind the data loads, so both latencies overlap
+  stage_twiddles(a.tw, twl, n);
 #pragma unroll
   for (int j = 0; j < kEPT; ++j)
     if (li[j] >= 0) buf[li[j]] = v[j];
@@ -165,7 +166,6 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
     need |= f;
   }
   if (!__syncthreads_or(need)) return;
-  stage_twiddles(a.tw, twl, n);
   cplx<T> v[kEPT];
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
@@ -178,6 +178,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
       if (fl[2 * b + 1]) v[j].y = in[r1 * n + t];
     }
   }
+  stage_twiddles(a.tw, twl, n);  // behind the data loads
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
     const int e = threadIdx.x + j * nthr;
@@ -225,7 +226,6 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
     need |= f;
   }
   if (!__syncthreads_or(need)) return;
-  stage_twiddles(a.tw, twl, n);
   cplx<T> A[kEPT], B[kEPT];
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
@@ -242,6 +242,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
       }
     }
   }
+  stage_twiddles(a.tw, twl, n);  // behind the data loads
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
     const int e = threadIdx.x + j * nthr;

@@ -24,7 +24,6 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nthr = N > 0 ? NTHR : (int)blockDim.x, pp = N > 0 ? PP : pp_arg;
   cplx<T>* twl = buf + lpad_len(FL * pp * n);  // lines padded (lpad)
-  stage_twiddles(a.tw, twl, n);
   const int64_t pair0 = (int64_t)blockIdx.x * pp;
   const int64_t cs = rows * hx;  // component stride of in/out
   // ---- gather the Hermitian-extended lines (inverse) ----
@@ -56,6 +55,7 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
       }
     }
   }
+  stage_twiddles(a.tw, twl, n);  // behind the data loads, so both latencies overlap
 #pragma unroll
   for (int j = 0; j < kEPT; ++j) {
     const int e = threadIdx.x + j * nthr;
