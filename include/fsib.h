@@ -99,6 +99,10 @@ typedef struct {
   int xcd_chunk_interp;  /* interpolation workgroups kept together on one XCD (0: plain order) */
   int xcd_chunk_spread;  /* spreading tiles kept together on one XCD (0: plain order) */
   int split;             /* candidate points per part of a heavy spreading tile */
+  int overlap;           /* Navier-Stokes steps: 1 runs the point side of each half step (positions,
+                            force, sort, spreading, interpolation) on a second stream of the plan,
+                            concurrently with the dealiased products; 0 runs everything on the
+                            caller's stream.  1 by default. */
 } fsib_tuning;
 
 typedef enum { FSIB_STOKES = 0, FSIB_NAVIER_STOKES = 1 } fsib_model;
@@ -173,7 +177,8 @@ fsib_status fsib_plan_profile(fsib_plan plan, int kernel_class, int max_launches
 /* Read (get = 1) or set (get = 0) the launch-shape knobs, e.g. for a timed autotuning search.
  * Results are identical up to the summation order of spreading.  split may not go below the value
  * the plan was created with (its scratch is sized for it; the creation value is 512).  Errors:
- * FSIB_ERR_ARG for NULL or out-of-range values (chunks in [0, 4096], split in [creation, 1 << 20]). */
+ * FSIB_ERR_ARG for NULL or out-of-range values (chunks in [0, 4096], split in [creation, 1 << 20],
+ * overlap 0 or 1). */
 fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* tuning, int get);
 fsib_status fsib_plan_profile_read(fsib_plan plan, double* total_ms /* host */, int64_t* launches /* host */,
                                    double* bytes /* host */);

@@ -39,7 +39,8 @@ class _Params(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("xcd_chunk_interp", ctypes.c_int), ("xcd_chunk_spread", ctypes.c_int), ("split", ctypes.c_int)]
+    _fields_ = [("xcd_chunk_interp", ctypes.c_int), ("xcd_chunk_spread", ctypes.c_int), ("split", ctypes.c_int),
+                ("overlap", ctypes.c_int)]
 
 
 class _Force(ctypes.Structure):
@@ -254,11 +255,14 @@ class Plan:
 
     def tuning(self, **changes):
         """Launch-shape knobs (fsib_plan_tuning): with no arguments returns them as a dict; keyword
-        arguments (xcd_chunk_interp, xcd_chunk_spread, split) set them and return the new dict."""
+        arguments (xcd_chunk_interp, xcd_chunk_spread, split, overlap) set them and return the new dict."""
         t = _Tuning()
         _check(self._lib.fsib_plan_tuning(self._h, ctypes.byref(t), 1), "fsib_plan_tuning")
         if changes:
+            names = {k for k, _ in _Tuning._fields_}
             for k, v in changes.items():
+                if k not in names:
+                    raise ValueError(f"unknown tuning knob {k!r}")
                 setattr(t, k, int(v))
             _check(self._lib.fsib_plan_tuning(self._h, ctypes.byref(t), 0), "fsib_plan_tuning")
         return {k: getattr(t, k) for k, _ in _Tuning._fields_}

@@ -67,6 +67,15 @@ void free_plan(Plan& p) {
   };
   for (hipEvent_t e : p.prof_ev) (void)hipEventDestroy(e);
   p.prof_ev.clear();
+  for (hipEvent_t& e : p.fj)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+  if (p.aux) {
+    (void)hipStreamDestroy(p.aux);
+    p.aux = nullptr;
+  }
   fr(p.coef);
   for (int a = 0; a < 3; ++a) fr(p.fac[a]);
   for (auto& kv : p.tw) fr(kv.second);
@@ -313,6 +322,10 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
     A.get(p.prod, p.dim == 3 ? p.nprod() * p.nd[2] * p.nd[1] * p.Hx * cs : p.nprod() * p.nd[1] * p.Hx * cs);
   }
   if (A.status != FSIB_OK) return A.status;
+  if (p.ns) {
+    FSIB_HIP(hipStreamCreateWithFlags(&p.aux, hipStreamNonBlocking));
+    for (hipEvent_t& e : p.fj) FSIB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
 
   // tables
   std::vector<double> coef((size_t)(p.deg + 1) * p.w);
@@ -681,12 +694,15 @@ fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
     t->xcd_chunk_interp = p.xcd_chunk_interp;
     t->xcd_chunk_spread = p.xcd_chunk_spread;
     t->split = p.split;
+    t->overlap = p.overlap;
     return FSIB_OK;
   }
   if (t->xcd_chunk_interp < 0 || t->xcd_chunk_interp > 4096 || t->xcd_chunk_spread < 0 || t->xcd_chunk_spread > 4096)
     return fail(FSIB_ERR_ARG, "XCD chunks must be in [0, 4096]");
   if (t->split < p.split_alloc || t->split > (1 << 20))
     return fail(FSIB_ERR_ARG, "split must be in [the creation value, 1 << 20]");
+  if (t->overlap != 0 && t->overlap != 1) return fail(FSIB_ERR_ARG, "overlap must be 0 or 1");
+  p.overlap = t->overlap;
   p.xcd_chunk_interp = t->xcd_chunk_interp;
   p.xcd_chunk_spread = t->xcd_chunk_spread;
   p.split = t->split;
@@ -913,17 +929,35 @@ fsib_status fsib_step(fsib_plan plan, const fsib_fluid_params* params, const fsi
     return FSIB_OK;
   }
   const double Ld = p.dim == 3 ? p.L * p.L * p.L : p.L * p.L;
-  // F^{m+1/2} and fhat^{m+1/2} (eq. force_spreading_quad)
-  FSIB_HIP(fsib::launch_force(*force, p.dim, M, p.Xh, p.F64, st));
-  FSIB_HIP(fsib::launch_weighted_strengths(p, force->kind, M, p.F64, p.S, st));
-  FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, st));
-  FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, st));
-  // uhat^{m+1/2}, uhat^{m+1} (eqs. spatial_2, spatial_3)
-  FSIB_TRY(fluid_impl(p, prm, p.fhat, uhat_half, p.uhat_mid, st));
-  // U^{m+1/2} at X^{m+1/2} (points still sorted), X^{m+1} (eq. spatial_4), U^{m+1} at X^{m+1}
-  FSIB_TRY(velocity_interp_sorted(p, M, p.uhat_mid, p.Uh, st));
-  FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, st));
-  FSIB_HIP(fsib::launch_sort_points(p, M, X, st));
+  // Each half step has a point side that no fluid work reads until the update: it runs on the plan's
+  // second stream, forked from st after the work st holds and joined back before the update.  The
+  // two sides touch disjoint buffers (the fine grid, its FFT buffers, fhat and the sorted points on
+  // one side; the dealiasing buffers and the products on the other).
+  const hipStream_t s2 = p.overlap && p.aux ? p.aux : st;
+  // F^{m+1/2} and fhat^{m+1/2} (eq. force_spreading_quad) beside the products of uhat^m
+  FSIB_HIP(hipEventRecord(p.fj[0], st));
+  FSIB_HIP(hipStreamWaitEvent(s2, p.fj[0], 0));
+  FSIB_HIP(fsib::launch_force(*force, p.dim, M, p.Xh, p.F64, s2));
+  FSIB_HIP(fsib::launch_weighted_strengths(p, force->kind, M, p.F64, p.S, s2));
+  FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, s2));
+  FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, s2));
+  FSIB_HIP(hipEventRecord(p.fj[1], s2));
+  FSIB_TRY(dealiased_products(p, uhat_half, st));
+  FSIB_HIP(hipStreamWaitEvent(st, p.fj[1], 0));
+  // uhat^{m+1/2} (eq. spatial_2)
+  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_HALF, prm, p.fhat, uhat_half, p.uhat_mid, st));
+  // U^{m+1/2} at X^{m+1/2} (points still sorted), X^{m+1} (eq. spatial_4) and its sort beside the
+  // products of uhat^{m+1/2} and the full update (eq. spatial_3)
+  FSIB_HIP(hipEventRecord(p.fj[2], st));
+  FSIB_HIP(hipStreamWaitEvent(s2, p.fj[2], 0));
+  FSIB_TRY(velocity_interp_sorted(p, M, p.uhat_mid, p.Uh, s2));
+  FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, s2));
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, s2));
+  FSIB_HIP(hipEventRecord(p.fj[3], s2));
+  FSIB_TRY(dealiased_products(p, p.uhat_mid, st));
+  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_FULL, prm, p.fhat, uhat_half, uhat_half, st));
+  FSIB_HIP(hipStreamWaitEvent(st, p.fj[3], 0));
+  // U^{m+1} at X^{m+1}
   FSIB_TRY(velocity_interp_sorted(p, M, uhat_half, U, st));
   if (diag) FSIB_HIP(fsib::launch_diag(p, prm, *force, M, p.F64, p.Uh, uhat_half, X, diag, st));
   return FSIB_OK;

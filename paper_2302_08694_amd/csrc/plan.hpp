@@ -96,6 +96,11 @@ struct Plan {
   double* part = nullptr;  // reduction partials
   int npart = 0;
   int64_t ws_bytes = 0;
+  // Navier-Stokes steps: a second stream (default priority) for the point side of each half step
+  // and the events that fork it from and join it to the caller's stream
+  hipStream_t aux = nullptr;
+  int overlap = 1;
+  hipEvent_t fj[4] = {nullptr, nullptr, nullptr, nullptr};
   // optional timing of one kernel class with HIP events on the launch stream
   int prof_class = -1;
   std::vector<hipEvent_t> prof_ev;  // start/stop pairs

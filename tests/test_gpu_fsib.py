@@ -253,3 +253,63 @@ def test_translation_invariance_gpu(F):
     Xa, _, _, _ = _run_gpu(F, plan, params, force, X0, np.zeros((M, 3)), z, 4)
     Xb, _, _, _ = _run_gpu(F, plan, params, force, X0 + r, np.zeros((M, 3)), z, 4)
     assert rel_l2(Xb - r - X0, Xa - X0) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ns_overlap_matches_serial_and_graph_replays(F, prec):
+    """The point side of each Navier-Stokes half step runs on the plan's second stream (tuning knob
+    overlap = 1, the default) or on the caller's stream (overlap = 0): the two agree to rounding
+    (spreading sums in the order the sort's counting atomics leave).  The forked step also records
+    into a HIP graph (the fork and join become parallel branches); every replay of two captured steps,
+    with eager work and synchronisations in between, matches the same steps run eagerly."""
+    announce(f"ns overlap {prec}")
+    X0, tris, Ns = _ns3d_small()
+    M = X0.shape[0]
+    plan = F.Plan(3, Ns, prec=prec, tol=TOL[prec], max_points=M, fluid=True, navier_stokes=True)
+    assert plan.tuning()["overlap"] == 1
+    ptr, idx = workloads.vertex_triangle_csr(tris, M)
+    force = F.Force("surface3d", 1.0, dev(tris), dev(ptr), dev(idx))
+    params = F.FluidParams("navier_stokes", rho=1.0, mu=0.01, dt=2e-3)
+    U0, uh0 = np.zeros((M, 3)), np.zeros((3,) + plan.half_shape, complex)
+    ref = _run_gpu(F, plan, params, force, X0, U0, uh0, 5)[:3]
+    plan.tuning(overlap=0)
+    ser = _run_gpu(F, plan, params, force, X0, U0, uh0, 5)[:3]
+    bar = 1e-12 if prec == "f64" else 1e-5
+
+    def same(r, s):  # displacements, velocities, spectra
+        return max(rel_l2(r[0] - X0, s[0] - X0), rel_l2(r[1], s[1]), rel_l2(r[2], s[2]))
+
+    assert same(ref, ser) < bar
+    with pytest.raises(ValueError):
+        plan.tuning(overlapp=1)
+    with pytest.raises(F.FSIBError):
+        plan.tuning(overlap=2)
+    plan.tuning(overlap=1)
+    # graph capture of two forked steps
+    X, U, uh = dev(X0), dev(U0, plan.rdtype), dev(uh0, plan.cdtype)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        plan.step(params, force, X, U, uh)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    X.copy_(dev(X0))
+    U.zero_()
+    uh.zero_()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(2):
+            plan.step(params, force, X, U, uh)
+    for rep in range(3):
+        X.copy_(dev(X0))
+        U.zero_()
+        uh.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (host(X), host(U), host(uh))
+        eager = _run_gpu(F, plan, params, force, X0, U0, uh0, 2)[:3]
+        assert same(got, eager) < bar, rep
+    g = None
+    plan.close()
