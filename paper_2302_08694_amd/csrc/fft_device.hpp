@@ -193,14 +193,19 @@ constexpr int ct_p_before(int n, int s) {
 }
 
 // NTHR = blockDim.x (N * NB / kEPT for the passes; the fused nonlinear kernel runs fewer lines
-// than threads in its inverse half)
-template <typename T, bool CONTIG, int N, int NB, int NTHR, int R, int P>
+// than threads in its inverse half).  SIGN = +1 or -1 fixes the transform direction at compile time
+// (the products by +-1 in the butterflies and the conjugation of the twiddles fold away); SIGN = 0
+// takes it from `sign` (one code path for both directions).  In the padded contiguous
+// layout lpad(x + y) = lpad(x) + lpad(y) when y is a multiple of 8, so a butterfly whose stride (M
+// for its inputs, P for its outputs) is a multiple of 8 computes one padded index and reaches the
+// others by constant offsets.
+template <typename T, bool CONTIG, int N, int NB, int NTHR, int R, int P, int SIGN>
 __device__ __forceinline__ void stage_ct(cplx<T>* buf, const cplx<T>* twl, int sign) {
   constexpr int M = N / R;
   constexpr int TOTAL = M * NB;
   constexpr int NBF = (TOTAL + NTHR - 1) / NTHR;
   constexpr int TWS = N / (P * R);
-  const T sg = (T)sign;
+  const T sg = SIGN != 0 ? (T)SIGN : (T)sign;
   cplx<T> u[NBF][R];
   int ii[NBF], bb[NBF];
 #pragma unroll
@@ -219,8 +224,14 @@ __device__ __forceinline__ void stage_ct(cplx<T>* buf, const cplx<T>* twl, int s
       }
       ii[j] = i;
       bb[j] = b;
+      if constexpr (CONTIG && M % 8 == 0) {
+        const int base = lpad(b * N + i);
 #pragma unroll
-      for (int q = 0; q < R; ++q) u[j][q] = buf[lidx<CONTIG>(i + q * M, b, N, NB)];
+        for (int q = 0; q < R; ++q) u[j][q] = buf[base + q * lpad(M)];
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) u[j][q] = buf[lidx<CONTIG>(i + q * M, b, N, NB)];
+      }
     }
   }
   __syncthreads();
@@ -234,25 +245,38 @@ __device__ __forceinline__ void stage_ct(cplx<T>* buf, const cplx<T>* twl, int s
 #pragma unroll
         for (int q = 1; q < R; ++q) {
           cplx<T> w = twl[q * k * TWS];
-          if (sign > 0) w.y = -w.y;
+          if (SIGN > 0 || (SIGN == 0 && sign > 0)) w.y = -w.y;
           u[j][q] = cmul(u[j][q], w);
         }
       }
       bfly<T, R>(u[j], sg);
       const int j0 = (i - k) * R + k;
+      if constexpr (CONTIG && P % 8 == 0) {
+        const int base = lpad(b * N + j0);
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[lidx<CONTIG>(j0 + q * P, b, N, NB)] = u[j][q];
+        for (int q = 0; q < R; ++q) buf[base + q * lpad(P)] = u[j][q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) buf[lidx<CONTIG>(j0 + q * P, b, N, NB)] = u[j][q];
+      }
     }
   }
   __syncthreads();
 }
 
-template <typename T, bool CONTIG, int N, int NB, int NTHR = N * NB / kEPT, int S = 0>
-__device__ __forceinline__ void stockham_ct(cplx<T>* buf, const cplx<T>* twl, int sign) {
+template <typename T, bool CONTIG, int N, int NB, int NTHR, int SIGN, int S = 0>
+__device__ __forceinline__ void stockham_ct_dir(cplx<T>* buf, const cplx<T>* twl, int sign = SIGN) {
   if constexpr (S < ct_nstages(N)) {
-    stage_ct<T, CONTIG, N, NB, NTHR, ct_radix_at(N, S), ct_p_before(N, S)>(buf, twl, sign);
-    stockham_ct<T, CONTIG, N, NB, NTHR, S + 1>(buf, twl, sign);
+    stage_ct<T, CONTIG, N, NB, NTHR, ct_radix_at(N, S), ct_p_before(N, S), SIGN>(buf, twl, sign);
+    stockham_ct_dir<T, CONTIG, N, NB, NTHR, SIGN, S + 1>(buf, twl, sign);
   }
+}
+
+// Direction known only at run time (a single code path serves both; two unrolled copies measured
+// no faster).
+template <typename T, bool CONTIG, int N, int NB, int NTHR = N * NB / kEPT>
+__device__ __forceinline__ void stockham_ct(cplx<T>* buf, const cplx<T>* twl, int sign) {
+  stockham_ct_dir<T, CONTIG, N, NB, NTHR, 0>(buf, twl, sign);
 }
 
 }  // namespace fsib

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
   }
   __syncthreads();
   if constexpr (N > 0)
-    stockham_ct<T, true, N, IL * PP, NTHR>(buf, twl, +1);
+    stockham_ct_dir<T, true, N, IL * PP, NTHR, +1>(buf, twl);
   else
     stockham<T, true>(a, buf, twl, IL * pp, +1);
   // ---- products, packed two rows per complex line: line (q, f) = prod_f(row a) + i prod_f(row b) ----
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
   }
   __syncthreads();
   if constexpr (N > 0)
-    stockham_ct<T, true, N, FL * PP, NTHR>(buf, twl, -1);
+    stockham_ct_dir<T, true, N, FL * PP, NTHR, -1>(buf, twl);
   else
     stockham<T, true>(a, buf, twl, FL * pp, -1);
   // ---- unpack the two rows of each line, keep m < Hx ----
