@@ -300,6 +300,15 @@ fsib_status fsib_velocity(fsib_plan plan, const fsib_fluid_params* params, const
 #define FSIB_DIAG_COUNT 11
 fsib_status fsib_step(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force,
                       int64_t M, double* X, void* U, void* uhat_half, double* diag, void* stream);
+/* nsteps >= 0 consecutive steps of Alg. 1, exactly as nsteps calls of fsib_step (results equal to
+ * rounding: spreading sums in the order the sort leaves), with the same arguments; diag, if given,
+ * is that of the last step.  Between the steps of one call the interpolation of U^{m+1} runs on the
+ * plan's second stream (tuning knob overlap) beside the products of uhat^{m+1} that open the next
+ * step; U, X and uhat_half are complete in the order of `stream` when the last step has run.
+ * Errors as fsib_step; FSIB_ERR_ARG for nsteps < 0. */
+fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force,
+                       int64_t M, double* X, void* U, void* uhat_half, int nsteps, double* diag,
+                       void* stream);
 
 #ifdef __cplusplus
 }

@@ -89,6 +89,9 @@ _SIGS = {
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fsib_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fsib_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
 }
 
 _lib = None
@@ -440,3 +443,14 @@ class Plan:
             _need(diag, "diag", torch.float64, (DIAG_COUNT,))
         _check(self._lib.fsib_step(self._h, ctypes.byref(params._s), ctypes.byref(force._s), M, _ptr(X), _ptr(U),
                                    _ptr(uhat), _ptr(diag), _stream()), "fsib_step")
+
+    def steps(self, params, force, X, U, uhat, nsteps, diag=None):
+        """nsteps steps of Alg. 1 in one call (fsib_steps): as nsteps calls of step(), with the
+        interpolation of each step's U on the plan's second stream beside the next step's products."""
+        M = self._X(X)
+        _need(U, "U", self.rdtype, (M, self.dim))
+        _need(uhat, "uhat", self.cdtype, self.field_shape)
+        if diag is not None:
+            _need(diag, "diag", torch.float64, (DIAG_COUNT,))
+        _check(self._lib.fsib_steps(self._h, ctypes.byref(params._s), ctypes.byref(force._s), M, _ptr(X), _ptr(U),
+                                    _ptr(uhat), int(nsteps), _ptr(diag), _stream()), "fsib_steps")

@@ -907,59 +907,83 @@ fsib_status fsib_velocity(fsib_plan plan, const fsib_fluid_params* params, const
 
 fsib_status fsib_step(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force, int64_t M, double* X,
                       void* U, void* uhat_half, double* diag, void* stream) {
+  return fsib_steps(plan, params, force, M, X, U, uhat_half, 1, diag, stream);
+}
+
+fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fsib_force* force, int64_t M, double* X,
+                       void* U, void* uhat_half, int nsteps, double* diag, void* stream) {
   if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
   Plan& p = plan->p;
   FSIB_TRY(check_fluid(p, params));
   FSIB_TRY(check_points(p, M, X));
   FSIB_TRY(check_force(force, p.dim, M));
   FSIB_TRY(check_instances(p, M, force));
+  if (nsteps < 0) return fail(FSIB_ERR_ARG, "nsteps must be >= 0");
   if (p.ninst > 1 && diag) return fail(FSIB_ERR_ARG, "diag is not available on multi-instance plans");
   if (M > 0 && !U) return fail(FSIB_ERR_ARG, "U is NULL");
   if (!uhat_half) return fail(FSIB_ERR_ARG, "uhat_half is NULL");
   const hipStream_t st = S(stream);
   const fsib_fluid_params& prm = *params;
   const double dt = prm.dt;
-  // X^{m+1/2} = X^m + dt/2 U^m (eq. spatial_1)
-  FSIB_HIP(fsib::launch_axpy_positions(p, M, p.Xh, X, U, 0.5 * dt, st));
   if (prm.model == FSIB_STOKES) {
-    FSIB_TRY(stokes_velocity(p, prm, *force, M, p.Xh, p.Uh, p.uhat_mid, st));
-    FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, st));
-    FSIB_TRY(stokes_velocity(p, prm, *force, M, X, U, uhat_half, st));
-    if (diag) FSIB_HIP(fsib::launch_diag(p, prm, *force, M, p.F64, U, uhat_half, X, diag, st));
+    for (int n = 0; n < nsteps; ++n) {
+      // X^{m+1/2} = X^m + dt/2 U^m (eq. spatial_1), then the midpoint rule with Stokes velocities
+      FSIB_HIP(fsib::launch_axpy_positions(p, M, p.Xh, X, U, 0.5 * dt, st));
+      FSIB_TRY(stokes_velocity(p, prm, *force, M, p.Xh, p.Uh, p.uhat_mid, st));
+      FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, st));
+      FSIB_TRY(stokes_velocity(p, prm, *force, M, X, U, uhat_half, st));
+    }
+    if (diag && nsteps > 0) FSIB_HIP(fsib::launch_diag(p, prm, *force, M, p.F64, U, uhat_half, X, diag, st));
     return FSIB_OK;
   }
   const double Ld = p.dim == 3 ? p.L * p.L * p.L : p.L * p.L;
   // Each half step has a point side that no fluid work reads until the update: it runs on the plan's
-  // second stream, forked from st after the work st holds and joined back before the update.  The
+  // second stream s2, forked from st after the work st holds and joined back before the update.  The
   // two sides touch disjoint buffers (the fine grid, its FFT buffers, fhat and the sorted points on
-  // one side; the dealiasing buffers and the products on the other).
+  // one side; the dealiasing buffers and the products on the other).  Between the steps of one call
+  // the interpolation of U^{m+1} also stays on s2, beside the products of uhat^{m+1} that open the
+  // next step (they do not read U); the last step joins it to st, so U is complete in st's order.
   const hipStream_t s2 = p.overlap && p.aux ? p.aux : st;
-  // F^{m+1/2} and fhat^{m+1/2} (eq. force_spreading_quad) beside the products of uhat^m
-  FSIB_HIP(hipEventRecord(p.fj[0], st));
-  FSIB_HIP(hipStreamWaitEvent(s2, p.fj[0], 0));
-  FSIB_HIP(fsib::launch_force(*force, p.dim, M, p.Xh, p.F64, s2));
-  FSIB_HIP(fsib::launch_weighted_strengths(p, force->kind, M, p.F64, p.S, s2));
-  FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, s2));
-  FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, s2));
-  FSIB_HIP(hipEventRecord(p.fj[1], s2));
-  FSIB_TRY(dealiased_products(p, uhat_half, st));
-  FSIB_HIP(hipStreamWaitEvent(st, p.fj[1], 0));
-  // uhat^{m+1/2} (eq. spatial_2)
-  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_HALF, prm, p.fhat, uhat_half, p.uhat_mid, st));
-  // U^{m+1/2} at X^{m+1/2} (points still sorted), X^{m+1} (eq. spatial_4) and its sort beside the
-  // products of uhat^{m+1/2} and the full update (eq. spatial_3)
-  FSIB_HIP(hipEventRecord(p.fj[2], st));
-  FSIB_HIP(hipStreamWaitEvent(s2, p.fj[2], 0));
-  FSIB_TRY(velocity_interp_sorted(p, M, p.uhat_mid, p.Uh, s2));
-  FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, s2));
-  FSIB_HIP(fsib::launch_sort_points(p, M, X, s2));
-  FSIB_HIP(hipEventRecord(p.fj[3], s2));
-  FSIB_TRY(dealiased_products(p, p.uhat_mid, st));
-  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_FULL, prm, p.fhat, uhat_half, uhat_half, st));
-  FSIB_HIP(hipStreamWaitEvent(st, p.fj[3], 0));
-  // U^{m+1} at X^{m+1}
-  FSIB_TRY(velocity_interp_sorted(p, M, uhat_half, U, st));
-  if (diag) FSIB_HIP(fsib::launch_diag(p, prm, *force, M, p.F64, p.Uh, uhat_half, X, diag, st));
+  if (nsteps > 0) {
+    FSIB_HIP(hipEventRecord(p.fj[0], st));
+    FSIB_HIP(hipStreamWaitEvent(s2, p.fj[0], 0));
+  }
+  for (int n = 0; n < nsteps; ++n) {
+    const bool last = n + 1 == nsteps;
+    // X^{m+1/2} = X^m + dt/2 U^m (eq. spatial_1); F^{m+1/2} and fhat^{m+1/2} (eq. force_spreading_quad),
+    // beside the products of uhat^m
+    FSIB_HIP(fsib::launch_axpy_positions(p, M, p.Xh, X, U, 0.5 * dt, s2));
+    FSIB_HIP(fsib::launch_force(*force, p.dim, M, p.Xh, p.F64, s2));
+    FSIB_HIP(fsib::launch_weighted_strengths(p, force->kind, M, p.F64, p.S, s2));
+    FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, s2));
+    FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, s2));
+    FSIB_HIP(hipEventRecord(p.fj[1], s2));
+    FSIB_TRY(dealiased_products(p, uhat_half, st));
+    FSIB_HIP(hipStreamWaitEvent(st, p.fj[1], 0));
+    // uhat^{m+1/2} (eq. spatial_2)
+    FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_HALF, prm, p.fhat, uhat_half, p.uhat_mid, st));
+    // U^{m+1/2} at X^{m+1/2} (points still sorted), X^{m+1} (eq. spatial_4) and its sort beside the
+    // products of uhat^{m+1/2} and the full update (eq. spatial_3)
+    FSIB_HIP(hipEventRecord(p.fj[2], st));
+    FSIB_HIP(hipStreamWaitEvent(s2, p.fj[2], 0));
+    FSIB_TRY(velocity_interp_sorted(p, M, p.uhat_mid, p.Uh, s2));
+    FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, s2));
+    FSIB_HIP(fsib::launch_sort_points(p, M, X, s2));
+    FSIB_TRY(dealiased_products(p, p.uhat_mid, st));
+    FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_FULL, prm, p.fhat, uhat_half, uhat_half, st));
+    // U^{m+1} at X^{m+1}: on s2 after the full update (the next step's products proceed on st), on st
+    // after the last step
+    if (last) {
+      FSIB_HIP(hipEventRecord(p.fj[3], s2));
+      FSIB_HIP(hipStreamWaitEvent(st, p.fj[3], 0));
+      FSIB_TRY(velocity_interp_sorted(p, M, uhat_half, U, st));
+    } else {
+      FSIB_HIP(hipEventRecord(p.fj[0], st));
+      FSIB_HIP(hipStreamWaitEvent(s2, p.fj[0], 0));
+      FSIB_TRY(velocity_interp_sorted(p, M, uhat_half, U, s2));
+    }
+  }
+  if (diag && nsteps > 0) FSIB_HIP(fsib::launch_diag(p, prm, *force, M, p.F64, p.Uh, uhat_half, X, diag, st));
   return FSIB_OK;
 }
 

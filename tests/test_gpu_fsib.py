@@ -313,3 +313,87 @@ def test_ns_overlap_matches_serial_and_graph_replays(F, prec):
         assert same(got, eager) < bar, rep
     g = None
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_steps_call_matches_single_steps(F, prec):
+    """fsib_steps(n) against n fsib_step calls (3D Navier-Stokes with the step interpolation deferred
+    onto the second stream between steps, with and without overlap; 2D Stokes), to rounding; nsteps
+    = 0 is a no-op and a negative count an error; a graph of one 3-step call replays like the eager
+    call."""
+    announce(f"steps call {prec}")
+    X0, tris, Ns = _ns3d_small()
+    M = X0.shape[0]
+    bar = 1e-12 if prec == "f64" else 1e-5
+    plan = F.Plan(3, Ns, prec=prec, tol=TOL[prec], max_points=M, fluid=True, navier_stokes=True)
+    ptr, idx = workloads.vertex_triangle_csr(tris, M)
+    force = F.Force("surface3d", 1.0, dev(tris), dev(ptr), dev(idx))
+    params = F.FluidParams("navier_stokes", rho=1.0, mu=0.01, dt=2e-3)
+
+    def run(n_calls, per_call):
+        X, U = dev(X0), torch.zeros((M, 3), dtype=plan.rdtype, device="cuda")
+        uh = torch.zeros((3,) + plan.half_shape, dtype=plan.cdtype, device="cuda")
+        dg = torch.zeros(F.DIAG_COUNT, dtype=torch.float64, device="cuda")
+        for _ in range(n_calls):
+            if per_call == 1:
+                plan.step(params, force, X, U, uh, dg)
+            else:
+                plan.steps(params, force, X, U, uh, per_call, dg)
+        return host(X) - X0, host(U), host(uh), host(dg)
+
+    def diff(a, b):
+        return max(rel_l2(x, y) for x, y in zip(a, b))
+
+    ref = run(6, 1)
+    for ov in (1, 0):
+        plan.tuning(overlap=ov)
+        assert diff(run(1, 6), ref) < bar
+        assert diff(run(2, 3), ref) < bar
+    plan.tuning(overlap=1)
+    X, U = dev(X0), torch.zeros((M, 3), dtype=plan.rdtype, device="cuda")
+    uh = torch.zeros((3,) + plan.half_shape, dtype=plan.cdtype, device="cuda")
+    plan.steps(params, force, X, U, uh, 0)
+    assert torch.equal(X, dev(X0)) and not bool(U.abs().max() > 0)
+    with pytest.raises(F.FSIBError):
+        plan.steps(params, force, X, U, uh, -1)
+    # graph of one 3-step call
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.steps(params, force, X, U, uh, 3)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.steps(params, force, X, U, uh, 3)
+    want = run(1, 3)[:3]
+    for rep in range(3):
+        X.copy_(dev(X0))
+        U.zero_()
+        uh.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert diff((host(X) - X0, host(U), host(uh)), want) < bar, rep
+        run(1, 1)  # eager work between replays
+    g = None
+    plan.close()
+    # 2D Stokes
+    case = workloads.stokes2d_case()
+    X2 = case["X"]
+    plan = F.Plan(2, case["N"], L=case["L"], prec=prec, tol=TOL[prec], max_points=X2.shape[0], fluid=True)
+    p2 = F.FluidParams("stokes", mu=case["mu"], dt=case["dt"])
+    f2 = F.Force("tension2d", case["K"])
+    outs = []
+    for per in (1, 4):
+        X = dev(X2)
+        uh = torch.zeros((2,) + plan.half_shape, dtype=plan.cdtype, device="cuda")
+        U = plan.velocity(p2, f2, X, uh)
+        for _ in range(4 // per):
+            if per == 1:
+                plan.step(p2, f2, X, U, uh)
+            else:
+                plan.steps(p2, f2, X, U, uh, per)
+        outs.append((host(X) - X2, host(U), host(uh)))
+    assert diff(outs[0], outs[1]) < bar
+    plan.close()
