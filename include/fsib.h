@@ -289,7 +289,12 @@ fsib_status fsib_velocity(fsib_plan plan, const fsib_fluid_params* params, const
  * uhat_half (in/out).  X^{m+1/2} = X^m + dt/2 U^m; F^{m+1/2} = F(X^{m+1/2}); fhat from the spread;
  * the fluid update; U^{m+1/2} = interp(uhat^{m+1/2}, X^{m+1/2}); X^{m+1} = X^m + dt U^{m+1/2};
  * U^{m+1} = interp(uhat^{m+1}, X^{m+1}).  STOKES: uhat is a function of X (see fsib_velocity).
- * X stays double in both precisions.  diag (device, nullable) receives FSIB_DIAG_COUNT doubles:
+ * X stays double in both precisions.  Ordering: the call is asynchronous in the order of `stream`;
+ * NAVIER_STOKES steps fork their point side (positions, force, sort, spreading, interpolation at
+ * X^{m+1/2}) onto the plan's second stream with an event and join it back with another before
+ * returning, so all outputs are ready in the order of `stream` and a captured step records both
+ * branches (tuning knob overlap = 0 keeps everything on `stream`).  Calls on one plan must not
+ * overlap.  diag (device, nullable) receives FSIB_DIAG_COUNT doubles:
  *   [0..2] sum_j w_j F_j^{m+1/2}          (Sec. 5.3; [2] = 0 in 2D)
  *   [3..5] Re uhat^{m+1}(k = 0)
  *   [6]    E_K = rho/2 L^d sum_k |uhat^{m+1}|^2                     (Sec. 5.4)
