@@ -69,6 +69,44 @@ __device__ __forceinline__ int unpack_i0(uint32_t p, int a) {
   return DIM == 3 ? (int)((p >> (10 * a)) & 1023u) : (int)((p >> (16 * a)) & 65535u);
 }
 
+// Coverage bits of tile coordinates [0, L) by the cells [a, a + W) (a may be negative or past L).
+template <int W, int L>
+__device__ __forceinline__ uint32_t run_bits(int a) {
+  static_assert(W <= 16 && L <= 16, "coverage bits fit 32 bits");
+  if (a >= L || a + W <= 0) return 0u;
+  const uint32_t m = (1u << W) - 1u;
+  const uint32_t r = a >= 0 ? (m << a) : (m >> (-a));
+  return r & ((1u << L) - 1u);
+}
+
+// One staging lane per point along one axis: the point's W kernel values v expanded over the tile's
+// L coordinates of the axis (zero outside the support; the support starts st cells after the tile,
+// modulo nfd), and one 64-bit set per group of GW coordinates of the staged points covering it:
+// coordinate c is covered when (c - st) mod nfd < W, i.e. it lies in [st, st + W) or in the wrapped
+// run [st - nfd, st - nfd + W).  Lane 0 writes the sets.
+template <typename T, int W, int L, int GW>
+__device__ __forceinline__ void stage_axis(bool valid, int st, int nfd, const T* v, T* rowp,
+                                           unsigned long long* mskp, int lane) {
+  uint32_t bits = 0u;
+  if (valid) {
+    bits = run_bits<W, L>(st) | run_bits<W, L>(st - nfd);
+#pragma unroll
+    for (int c = 0; c < L; ++c) rowp[c] = (T)0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      int c = st + j;
+      if (c >= nfd) c -= nfd;
+      if (c < L) rowp[c] = v[j];
+    }
+  }
+  constexpr int NG = L / GW;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const unsigned long long b = __ballot(((bits >> (g * GW)) & ((1u << GW) - 1u)) != 0u);
+    if (lane == 0) mskp[g] = b;
+  }
+}
+
 // NCH channels per point: real vector strengths (NCH = components, planar grids) or one complex
 // strength (NCH = 2, interleaved complex grid, transform index = blockIdx.y).
 //
@@ -233,9 +271,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
         const int d = wave;
         const int nfd = a.nf[d];
         int st = 0;
+        T v[W];
         if (valid) {
           const T y = a.s_y[pos * DIM + d];
-          T v[W];
           // runtime degree: a fully unrolled Horner loop here lifts the kernel's VGPRs (68 -> 105 in FP32)
 #pragma unroll
           for (int j = 0; j < W; ++j) v[j] = cf[a.deg * W + j];
@@ -245,36 +283,14 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
           }
           st = unpack_i0<DIM>(a.s_i0[pos], d) - base[d];  // support start relative to the tile
           if (st < 0) st += nfd;
-          // kernel values expanded over the tile's coordinates along d (zero outside the support)
-          const int L = d == 0 ? kTileX : (d == 1 ? TY : TZ);
-          T* rowp = d == 0 ? &wxr[pl][0] : (d == 1 ? &wyr[pl][0] : &wzr[DIM == 3 ? pl : 0][0]);
-          for (int c = 0; c < L; ++c) rowp[c] = (T)0;
-#pragma unroll
-          for (int j = 0; j < W; ++j) {
-            int c = st + j;
-            if (c >= nfd) c -= nfd;
-            if (c < L) rowp[c] = v[j];
-          }
         }
-        // coverage sets of this axis' tile coordinates
-        if (d == 0) {
-          for (int g = 0; g < NXG; ++g) {
-            int off = g * CW - st;
-            if (off < 0) off += nfd;
-            int back = st - g * CW;
-            if (back < 0) back += nfd;
-            const unsigned long long bm = __ballot(valid && (off < W || back < CW));
-            if (lane == 0) msk[TY + (DIM == 3 ? TZ : 0) + g] = bm;
-          }
-        } else {
-          const int L = d == 1 ? TY : TZ;
-          for (int k = 0; k < L; ++k) {
-            int off = k - st;
-            if (off < 0) off += nfd;
-            const unsigned long long bm = __ballot(valid && off < W);
-            if (lane == 0) msk[(d == 1 ? 0 : TY) + k] = bm;
-          }
-        }
+        // kernel values expanded over the tile's coordinates along d and the coverage sets
+        if (d == 0)
+          stage_axis<T, W, kTileX, CW>(valid, st, nfd, v, &wxr[pl][0], &msk[TY + (DIM == 3 ? TZ : 0)], lane);
+        else if (d == 1)
+          stage_axis<T, W, TY, 1>(valid, st, nfd, v, &wyr[pl][0], &msk[0], lane);
+        else
+          stage_axis<T, W, TZ, 1>(valid, st, nfd, v, &wzr[DIM == 3 ? pl : 0][0], &msk[TY], lane);
       } else if (wave == DIM && valid) {
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) sv[pl][ch] = a.sstr[((int64_t)tr * a.M + pos) * NCH + ch];
@@ -284,19 +300,24 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
     // (2) every lane walks the staged points that cover its cells
     unsigned long long m = msk[ly] & msk[TY + (DIM == 3 ? TZ : 0) + xg];
     if (DIM == 3) m &= msk[TY + lz];
-    while (m) {
-      const int pl = __ffsll((long long)m) - 1;
-      m &= m - 1ull;
-      T wyz = wyr[pl][ly];
-      if (DIM == 3) wyz *= wzr[DIM == 3 ? pl : 0][lz];
-      T sw[NCH];
+    // the set in two 32-bit halves, lowest point first (32-bit bit scans are cheaper)
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) sw[ch] = sv[pl][ch] * wyz;
+    for (int h = 0; h < 2; ++h) {
+      uint32_t mm = (uint32_t)(m >> (32 * h));
+      while (mm) {
+        const int pl = 32 * h + __ffs(mm) - 1;
+        mm &= mm - 1u;
+        T wyz = wyr[pl][ly];
+        if (DIM == 3) wyz *= wzr[DIM == 3 ? pl : 0][lz];
+        T sw[NCH];
 #pragma unroll
-      for (int c = 0; c < CW; ++c) {
-        const T wx = wxr[pl][xg * CW + c];
+        for (int ch = 0; ch < NCH; ++ch) sw[ch] = sv[pl][ch] * wyz;
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) acc[c][ch] += wx * sw[ch];
+        for (int c = 0; c < CW; ++c) {
+          const T wx = wxr[pl][xg * CW + c];
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) acc[c][ch] += wx * sw[ch];
+        }
       }
     }
     __syncthreads();
