@@ -492,7 +492,8 @@ __global__ void k_strengths(int64_t n, const double* __restrict__ F, double w, T
 }
 
 double force_weight(int kind, int64_t M) {
-  return kind == FSIB_FORCE_CURVE_TENSION ? 6.283185307179586476925286766559 / (double)M : 1.0;
+  if (kind != FSIB_FORCE_CURVE_TENSION) return 1.0;
+  return M > 0 ? 6.283185307179586476925286766559 / (double)M : 0.0;
 }
 
 hipError_t launch_force_plan(const Plan& p, const fsib_force& f, int64_t M, const double* X, double* F, hipStream_t st) {

@@ -397,3 +397,38 @@ def test_steps_call_matches_single_steps(F, prec):
         outs.append((host(X) - X2, host(U), host(uh)))
     assert diff(outs[0], outs[1]) < bar
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_navier_stokes_steps_without_points(F, prec):
+    """An empty point set (M = 0: the fluid alone) through fsib_step and fsib_steps, with both stream
+    modes: the field follows the oracle's steps of Alg. 1 with no boundary force; the diagnostics
+    stay finite."""
+    announce(f"ns without points {prec}")
+    Ns = (16, 16, 16)
+    L, rho, mu, dt = 1.0, 1.0, 0.02, 5e-3
+    u0 = _divfree_hat(Ns, 31) * 2.0
+    law = step.ForceLaw("surface3d", 1.0, np.zeros((0, 3), dtype=np.int32))
+    X, U, uh = np.zeros((0, 3)), np.zeros((0, 3)), u0.copy()
+    for _ in range(4):
+        X, U, uh = step.ns_step(X, U, uh, law, Ns, L, rho, mu, dt)
+    plan = F.Plan(3, Ns, L=L, prec=prec, tol=TOL[prec], max_points=8, fluid=True, navier_stokes=True)
+    empty_i = dev(np.zeros((0, 3), dtype=np.int32))
+    force = F.Force("surface3d", 1.0, empty_i, dev(np.zeros(1, dtype=np.int32)), dev(np.zeros(0, dtype=np.int32)))
+    params = F.FluidParams("navier_stokes", rho=rho, mu=mu, dt=dt)
+    for ov in (1, 0):
+        plan.tuning(overlap=ov)
+        for per in (1, 4):
+            Xg = dev(np.zeros((0, 3)))
+            Ug = torch.zeros((0, 3), dtype=plan.rdtype, device="cuda")
+            ug = dev(half(u0, Ns[0]), cdtype(prec))
+            dg = torch.zeros(F.DIAG_COUNT, dtype=torch.float64, device="cuda")
+            if per == 1:
+                for _ in range(4):
+                    plan.step(params, force, Xg, Ug, ug, dg)
+            else:
+                plan.steps(params, force, Xg, Ug, ug, 4, dg)
+            e = rel_l2(host(ug), half(uh, Ns[0]))
+            print(f"ns without points {prec} overlap={ov} per-call={per}: uhat {e:.3e}")
+            assert e < BAR[prec] and np.all(np.isfinite(host(dg)))
+    plan.close()
