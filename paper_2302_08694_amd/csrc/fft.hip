@@ -366,7 +366,8 @@ static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int 
   FSIB_C2C_CT(256, 8)
   FSIB_C2C_CT(320, 6)
   FSIB_C2C_CT(384, 4)
-  FSIB_C2C_CT(512, 4) {
+  FSIB_C2C_CT(512, 4)
+  FSIB_C2C_CT(1024, 2) {
     if (contig)
       hipLaunchKernelGGL((k_fft_c2c<T, true>), grid, dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
     else
@@ -430,6 +431,7 @@ static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int6
   FSIB_R2C_CT(320, 6)
   FSIB_R2C_CT(384, 4)
   FSIB_R2C_CT(512, 4)
+  FSIB_R2C_CT(1024, 2)
   hipLaunchKernelGGL(k_fft_r2c_x<T>, grid, dim3(nthr), lds, st, (const T*)in, (cplx<T>*)out, a);
 #undef FSIB_R2C_CT
   if (prof) prof_stop(p, (double)rows * (n * sizeof(T) + nout * sizeof(cplx<T>)), st);
@@ -468,6 +470,7 @@ static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int6
   FSIB_C2R_CT(320, 6)
   FSIB_C2R_CT(384, 4)
   FSIB_C2R_CT(512, 4)
+  FSIB_C2R_CT(1024, 2)
   hipLaunchKernelGGL(k_fft_c2r_x<T>, grid, dim3(nthr), lds, st, (const cplx<T>*)in, (T*)out, a);
 #undef FSIB_C2R_CT
   if (prof) prof_stop(p, (double)rows * (nin * sizeof(cplx<T>) + n * sizeof(T)), st);

@@ -96,13 +96,15 @@ __global__ void k_bin_count(int64_t M, const double* __restrict__ X, Geo g, int*
 }
 
 // Exclusive scan of counts[0..n) into offsets[0..n] (offsets[n] = total).  Segments of
-// kScanSeg = 1024 threads x kScanEpt (32) consecutive entries: each thread loads its run of kScanEpt
-// entries at once, the runs' sums are scanned across the workgroup (wavefront shuffles, then the
-// wavefront totals), and each thread writes its run.  With more than one segment, a first launch
-// stores the segment sums and a second one scans every segment after the sum of the segments
-// before it.
+// kScanSeg = 1024 threads x kScanEpt (4) consecutive entries: each thread loads its run of kScanEpt
+// entries at once (one 16-byte load per lane, consecutive lanes on consecutive runs), the runs' sums
+// are scanned across the workgroup (wavefront shuffles, then the wavefront totals), and each thread
+// writes its run.  With more than one segment, a first launch stores the segment sums and a second
+// one scans every segment after the sum of the segments before it (summed by the whole workgroup).
+// Short segments give the bin counts of a plan (10^4-10^6) several workgroups: with 32 entries per
+// thread a 65k-bin scan had 2 workgroups and lanes 128 bytes apart.
 constexpr int kScanThreads = 1024;
-constexpr int kScanEpt = 32;
+constexpr int kScanEpt = 4;
 constexpr int64_t kScanSeg = (int64_t)kScanThreads * kScanEpt;
 
 // exclusive prefix of v over the workgroup; *total = sum over the workgroup
@@ -146,13 +148,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int64_t n, const int* __r
     v[k] = first + k < n ? counts[first + k] : 0;
     run += v[k];
   }
-  if (FINAL && threadIdx.x == 0) {
-    int b = 0;
-    for (unsigned s = 0; s < blockIdx.x; ++s) b += seg_sum[s];
-    seg_base = b;
-  }
+  int before = 0;  // this thread's share of the sums of the segments before this one
+  if (FINAL)
+    for (unsigned s = threadIdx.x; s < blockIdx.x; s += kScanThreads) before += seg_sum[s];
   int total;
   int excl = block_exclusive_scan(run, wsum, &total);
+  if (FINAL) {
+    int bt;
+    __syncthreads();  // wsum is reused
+    (void)block_exclusive_scan(before, wsum, &bt);
+    if (threadIdx.x == 0) seg_base = bt;
+    __syncthreads();
+  }
   if (!FINAL) {
     if (threadIdx.x == 0) seg_sum[blockIdx.x] = total;
     return;
