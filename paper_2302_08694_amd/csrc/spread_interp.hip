@@ -13,7 +13,13 @@
 
 namespace fsib {
 
-constexpr int kSpreadThreads = 256;
+constexpr int kSpreadThreads = 256;  // the most threads of a spreading workgroup
+// Threads of a spreading workgroup: 256 for 3D tiles (16 x 8 x 8); for 2D tiles (16 x 16) 64 in FP32,
+// so that a lane owns 4 cells of a row as in 3D (with 256 threads a 2D lane owns one cell and spends
+// most of each point on the bit scan and addressing of the walk: 2D batch +8%), and 256 in FP64, whose
+// 21 KiB of LDS per one-wave workgroup would leave too few waves per CU.
+template <int DIM, typename T>
+__host__ __device__ constexpr int spread_threads() { return DIM == 3 || sizeof(T) == 8 ? 256 : 64; }
 constexpr int kChunk = 64;           // points staged per round
 constexpr int kMaxTileCells = 1024;  // cells of one tile
 constexpr int kTileX = 16;           // tile extent along x (one register row per thread)
@@ -128,7 +134,8 @@ struct SpreadTile {
   static constexpr int TY = DIM == 3 ? 8 : 16;               // tile rows along y
   static constexpr int TZ = DIM == 3 ? 8 : 1;                // tile rows along z
   static constexpr int ROWS = TY * TZ;
-  static constexpr int CW = kTileX * ROWS / kSpreadThreads;  // cells per lane along x
+  static constexpr int NT = spread_threads<DIM, T>();       // threads of the workgroup
+  static constexpr int CW = kTileX * ROWS / NT;              // cells per lane along x
   static constexpr int NXG = kTileX / CW;                    // x groups
   static constexpr int XS = kTileX + (sizeof(T) == 4 ? 4 : 2);  // padded LDS strides
   static constexpr int YS = TY + 1;
@@ -196,7 +203,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
       rbeg[tid] = s0;
       rlen[tid] = e0 - s0;
     }
-    for (int i = tid; i < (a.deg + 1) * W; i += kSpreadThreads) cf[i] = a.coef[i];
+    for (int i = tid; i < (a.deg + 1) * W; i += G::NT) cf[i] = a.coef[i];
     __syncthreads();
     if (tid == 0) {
       int nr = 0;
@@ -223,11 +230,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) acc[c][ch] = (T)0;
 
-  // Candidates are taken kSpreadThreads at a time: each thread tests one (support meets the tile
+  // Candidates are taken G::NT at a time: each thread tests one (support meets the tile
   // along every axis, from the packed first cell alone) and the hits are compacted, in order, into
   // sel[]; only those are staged, kChunk at a time.  (With the reach of ceil((w-1)/tile) bins per
   // axis, about half of the candidates miss the tile.)
-  for (int w0 = cbeg; w0 < cend; w0 += kSpreadThreads) {
+  for (int w0 = cbeg; w0 < cend; w0 += G::NT) {
   {
     const int ci = w0 + tid;
     bool hit = false;
@@ -251,24 +258,25 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
     if (lane == 0) wcnt[wave] = __popcll(hb);
     __syncthreads();
     int wbase = 0, nsel = 0;
-    for (int v = 0; v < kSpreadThreads / 64; ++v) {
+    for (int v = 0; v < G::NT / 64; ++v) {
       if (v < wave) wbase += wcnt[v];
       nsel += wcnt[v];
     }
     if (hit) sel[wbase + before] = cpos;
-    if (tid == 0) wcnt[kSpreadThreads / 64] = nsel;
+    if (tid == 0) wcnt[G::NT / 64] = nsel;
     __syncthreads();
   }
-  const int nsel = wcnt[kSpreadThreads / 64];
+  const int nsel = wcnt[G::NT / 64];
   for (int c0 = 0; c0 < nsel; c0 += kChunk) {
     const int cnt = nsel - c0 < kChunk ? nsel - c0 : kChunk;
-    // (1) wavefront d < DIM: axis d of the staged points, lane = point; wavefront DIM: strengths
+    // (1) the wavefronts take the axes d in turn (3D: one each), lane = point; then one wavefront (3D:
+    // the fourth, 2D: the only one) the strengths
     {
       const int pl = lane;
       const bool valid = pl < cnt;
       const int64_t pos = valid ? (int64_t)sel[c0 + pl] : 0;
-      if (wave < DIM) {
-        const int d = wave;
+      constexpr int NW = G::NT / 64;
+      for (int d = wave; d < DIM; d += NW) {
         const int nfd = a.nf[d];
         int st = 0;
         T v[W];
@@ -291,7 +299,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
           stage_axis<T, W, TY, 1>(valid, st, nfd, v, &wyr[pl][0], &msk[0], lane);
         else
           stage_axis<T, W, TZ, 1>(valid, st, nfd, v, &wzr[DIM == 3 ? pl : 0][0], &msk[TY], lane);
-      } else if (wave == DIM && valid) {
+      }
+      if (wave == (DIM < NW ? DIM : 0) && valid) {
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) sv[pl][ch] = a.sstr[((int64_t)tr * a.M + pos) * NCH + ch];
       }
@@ -707,7 +716,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   const bool prof = prof_on(p, PROF_SPREAD);
   if (prof) prof_start(p, st);
   hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX>), dim3((unsigned)p.work_blocks, (unsigned)ntr),
-                     dim3(kSpreadThreads), 0, st, a);
+                     dim3(spread_threads<DIM, T>()), 0, st, a);
   // algorithmic bytes: the grid written once, per point its sorted record and its strengths read
   if (prof)
     prof_stop(p, (double)ntr * p.ninst * p.fine_cells() * NCH * sizeof(T) + (double)M * (8 + DIM * sizeof(T)) +
