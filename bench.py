@@ -277,7 +277,7 @@ def batched_stokes(F, torch, steps=50, graph_steps=10):
     return res
 
 
-def differentiable_stokes(F, torch, reps=3):
+def differentiable_stokes(F, torch, reps=5):
     """Loss and gradients (initial positions, stiffness) of 20 checkpointed Stokes steps at 64^3 modes
     with 10,000 surface-tension points: FP32 and FP64 forward + adjoint, wall time per gradient
     evaluation next to the forward alone, and the FP32 gradients' error against the FP64 ones."""
@@ -305,7 +305,8 @@ def differentiable_stokes(F, torch, reps=3):
             return loss, None, None
 
         for grad in (False, True):
-            evaluate(grad)
+            for _ in range(2):  # warm-up (allocator growth, first autograd graph)
+                evaluate(grad)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
