@@ -117,11 +117,12 @@ __device__ __forceinline__ void stage_axis(bool valid, int st, int nfd, const T*
 // strength (NCH = 2, interleaved complex grid, transform index = blockIdx.y).
 //
 // Inside a tile every lane owns CW consecutive cells of one row along x (3D: 64 rows x 4 groups of
-// 4 cells; 2D: 16 rows x 16 single cells) and accumulates them in registers.  The tile's points are
-// staged 64 at a time, one wavefront per axis with one lane per point: the lane evaluates the
-// point's w kernel values along its axis (Horner), writes them expanded over the tile's
-// coordinates of that axis (zero outside the support), and one ballot per tile coordinate gives the
-// 64-bit set of staged points whose support covers it.  A lane's points are the AND of the sets of
+// 4 cells; 2D FP32: 16 rows x 4 groups of 4 cells on 64 threads; 2D FP64: 16 rows x 16 single cells
+// on 256 threads) and accumulates them in registers.  The tile's points are staged 64 at a time, the
+// wavefronts taking the axes in turn with one lane per point: the lane evaluates the point's w
+// kernel values along the axis (Horner), writes them expanded over the tile's coordinates of that
+// axis (zero outside the support), and one ballot per coordinate group gives the 64-bit set of
+// staged points whose support covers it.  A lane's points are the AND of the sets of
 // its row's y and z and of its x group; every lane walks its own set, lowest point first, so lanes
 // stay busy with different points and no lane visits a point that misses its cells.  Each cell is
 // summed by one lane in point order (deterministic for a given sorted order), no atomics, and each
