@@ -695,6 +695,7 @@ fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
     t->xcd_chunk_spread = p.xcd_chunk_spread;
     t->split = p.split;
     t->overlap = p.overlap;
+    t->interp_points = p.interp_points;
     return FSIB_OK;
   }
   if (t->xcd_chunk_interp < 0 || t->xcd_chunk_interp > 4096 || t->xcd_chunk_spread < 0 || t->xcd_chunk_spread > 4096)
@@ -702,6 +703,9 @@ fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
   if (t->split < p.split_alloc || t->split > (1 << 20))
     return fail(FSIB_ERR_ARG, "split must be in [the creation value, 1 << 20]");
   if (t->overlap != 0 && t->overlap != 1) return fail(FSIB_ERR_ARG, "overlap must be 0 or 1");
+  if (t->interp_points != 4 && t->interp_points != 8 && t->interp_points != 16)
+    return fail(FSIB_ERR_ARG, "interp_points must be 4, 8 or 16");
+  p.interp_points = t->interp_points;
   p.overlap = t->overlap;
   p.xcd_chunk_interp = t->xcd_chunk_interp;
   p.xcd_chunk_spread = t->xcd_chunk_spread;

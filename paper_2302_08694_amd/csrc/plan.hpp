@@ -100,6 +100,7 @@ struct Plan {
   // and the events that fork it from and join it to the caller's stream
   hipStream_t aux = nullptr;
   int overlap = 1;
+  int interp_points = 4;  // points per interpolation wavefront (4 measured faster than 8 and 16)
   hipEvent_t fj[4] = {nullptr, nullptr, nullptr, nullptr};
   // optional timing of one kernel class with HIP events on the launch stream
   int prof_class = -1;

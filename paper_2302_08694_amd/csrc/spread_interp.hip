@@ -446,6 +446,7 @@ struct InterpArgs {
   int64_t M;
   int nf[3];
   int xcd_chunk;  // > 0: workgroups renumbered in runs of this many per XCD (xcd_chunked)
+  int ppw;        // points per wavefront (a multiple of the points summed together)
   // instances (ninst > 1): sorted positions [offsets[i nbins], offsets[(i+1) nbins]) belong to
   // instance i, whose real grids start at channel i * NCH
   const int* offsets;
@@ -472,7 +473,6 @@ __device__ __forceinline__ int sorted_instance(const int* __restrict__ offsets, 
 // and y values by lane permute and the plane's z value by readlane.  The wavefront sum is a
 // butterfly reduction.  Consecutive sorted points go to the same wavefront, so their shared cells
 // hit in the L1 cache, and the next group of points' records is loaded one group ahead.
-constexpr int kIpPointsPerWave = 8;
 
 // Lane permutes and readlanes run with every lane of the wavefront active: the source lane of a
 // permute must be active for its value to be read.
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
   for (int i = 0; i <= DEG; ++i) cfr[i] = jk < W ? a.coef[i * W + jk] : (T)0;
   const int64_t blk = a.xcd_chunk > 0 ? xcd_chunked(blockIdx.x, gridDim.x, a.xcd_chunk) : (int64_t)blockIdx.x;
   const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
-  const int64_t first = wave * kIpPointsPerWave;
+  const int64_t first = wave * a.ppw;
   uint32_t pkn[PB];
   T yn[PB];
   auto records = [&](int k0) {
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
     }
   };
   if (first < a.M) records(0);
-  for (int k0 = 0; k0 < kIpPointsPerWave; k0 += PB) {
+  for (int k0 = 0; k0 < a.ppw; k0 += PB) {
     if (first + k0 >= a.M) break;
     uint32_t pkc[PB];
     T yc[PB];
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
       pkc[b] = pkn[b];
       yc[b] = yn[b];
     }
-    if (k0 + PB < kIpPointsPerWave && first + k0 + PB < a.M) records(k0 + PB);
+    if (k0 + PB < a.ppw && first + k0 + PB < a.M) records(k0 + PB);
     T v[PB];
     int iz[PB], gxb[PB], gyb[PB][YCH];
     int64_t gin[PB];  // first grid channel of the point's instance
@@ -742,12 +742,13 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   a.M = M;
   for (int d = 0; d < 3; ++d) a.nf[d] = (int)p.nf[d];
   a.xcd_chunk = p.xcd_chunk_interp;
+  a.ppw = p.interp_points;
   a.offsets = p.offsets;
   a.nbins = (int)p.nbins;
   a.ninst = p.ninst;
   const bool prof = prof_on(p, PROF_INTERP);
   if (prof) prof_start(p, st);
-  const int64_t per_wg = 4 * kIpPointsPerWave;  // four wavefronts per workgroup
+  const int64_t per_wg = 4 * (int64_t)a.ppw;  // four wavefronts per workgroup
   hipLaunchKernelGGL((k_interp<T, DIM, W, NCH, CPLX>), dim3((unsigned)((M + per_wg - 1) / per_wg), (unsigned)ntr),
                      dim3(256), 0, st, a);
   // algorithmic bytes: per point its sorted record, w^d grid cells per channel, the result
