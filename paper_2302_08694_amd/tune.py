@@ -18,6 +18,7 @@ CANDIDATES = {
     "xcd_chunk_spread": (0, 4, 16, 64),
     "xcd_chunk_interp": (0, 16, 64, 256),
     "split": (512, 1024, 2048),
+    "interp_points": (4, 8),
 }
 
 
