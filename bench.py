@@ -308,12 +308,16 @@ def differentiable_stokes(F, torch, reps=5):
             for _ in range(2):  # warm-up (allocator growth, first autograd graph)
                 evaluate(grad)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
+            # median of separately synchronised evaluations: the 20-step trajectory issues ~20 small
+            # host-side operations per step, so single evaluations carry host jitter
+            ts = []
             for _ in range(reps):
+                t0 = time.perf_counter()
                 out = evaluate(grad)
-            torch.cuda.synchronize()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
             res[f"{prec}_tol"] = tol
-            res[f"{prec}_{'forward_backward' if grad else 'forward'}_ms"] = (time.perf_counter() - t0) / reps * 1e3
+            res[f"{prec}_{'forward_backward' if grad else 'forward'}_ms"] = float(np.median(ts)) * 1e3
         grads[prec] = (float(out[0].detach()), out[1].cpu().numpy(), float(out[2]))
         plan.close()
     (l32, g32, k32), (l64, g64, k64) = grads["f32"], grads["f64"]
