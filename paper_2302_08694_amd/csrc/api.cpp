@@ -703,8 +703,9 @@ fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
   if (t->split < p.split_alloc || t->split > (1 << 20))
     return fail(FSIB_ERR_ARG, "split must be in [the creation value, 1 << 20]");
   if (t->overlap != 0 && t->overlap != 1) return fail(FSIB_ERR_ARG, "overlap must be 0 or 1");
-  if (t->interp_points != 4 && t->interp_points != 8 && t->interp_points != 16)
-    return fail(FSIB_ERR_ARG, "interp_points must be 4, 8 or 16");
+  if (t->interp_points != 1 && t->interp_points != 2 && t->interp_points != 4 && t->interp_points != 8 &&
+      t->interp_points != 16)
+    return fail(FSIB_ERR_ARG, "interp_points must be 1, 2, 4, 8 or 16");
   p.interp_points = t->interp_points;
   p.overlap = t->overlap;
   p.xcd_chunk_interp = t->xcd_chunk_interp;

@@ -516,6 +516,14 @@ __host__ __device__ constexpr int interp_xlanes() {
   return best;
 }
 
+// Points whose cells one wavefront sums together (by the registers one point's cells take).
+template <typename T, int DIM, int W, int NCH, bool CPLX>
+__host__ __device__ constexpr int interp_pb() {
+  constexpr int YCH = (W + 64 / interp_xlanes<W>() - 1) / (64 / interp_xlanes<W>());
+  constexpr int RPP = YCH * (DIM == 3 ? W : 1) * (CPLX ? 2 : NCH) * (int)sizeof(T) / 4;
+  return RPP <= 16 ? 4 : (RPP <= 32 ? 2 : 1);
+}
+
 template <typename T, int DIM, int W, int NCH, bool CPLX>
 __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
   constexpr int XL = interp_xlanes<W>();
@@ -524,7 +532,8 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
   constexpr int NZ = DIM == 3 ? W : 1;
   constexpr int SC = CPLX ? 2 : NCH;
   constexpr int RPP = YCH * NZ * SC * (int)sizeof(T) / 4;  // registers of one point's cells
-  constexpr int PB = RPP <= 16 ? 4 : (RPP <= 32 ? 2 : 1);   // points summed together
+  constexpr int PB = interp_pb<T, DIM, W, NCH, CPLX>();       // points summed together
+  static_assert(PB == (RPP <= 16 ? 4 : (RPP <= 32 ? 2 : 1)), "interp_pb matches the kernel");
   constexpr int GMAX = (PB == 1 ? 32 : 64) / (PB * SC * (int)sizeof(T) / 4);
   constexpr int G = NZ < GMAX ? NZ : GMAX;                  // planes loaded together
   const int lane = threadIdx.x & 63;
@@ -742,7 +751,9 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   a.M = M;
   for (int d = 0; d < 3; ++d) a.nf[d] = (int)p.nf[d];
   a.xcd_chunk = p.xcd_chunk_interp;
-  a.ppw = p.interp_points;
+  // points per wavefront: the plan's knob rounded up to a multiple of the points summed together
+  constexpr int PB = interp_pb<T, DIM, W, NCH, CPLX>();
+  a.ppw = (p.interp_points + PB - 1) / PB * PB;
   a.offsets = p.offsets;
   a.nbins = (int)p.nbins;
   a.ninst = p.ninst;

@@ -195,12 +195,14 @@ def test_tuning_knobs_keep_results(F):
     assert base["split"] == 512
     r0 = (host(plan.spread(X, c)), host(plan.interp(X, f)))
     for knobs in ({"xcd_chunk_spread": 0, "xcd_chunk_interp": 0}, {"xcd_chunk_spread": 64, "split": 2048},
-                  {"xcd_chunk_interp": 256, "split": 600}):
+                  {"xcd_chunk_interp": 256, "split": 600}, {"interp_points": 1}, {"interp_points": 16}):
         plan.tuning(**{**base, **knobs})
         r = (host(plan.spread(X, c)), host(plan.interp(X, f)))
         assert rel_l2(r[0], r0[0]) < 1e-13 and rel_l2(r[1], r0[1]) < 1e-15
     with pytest.raises(F.FSIBError):
         plan.tuning(split=256)  # below the creation value
+    with pytest.raises(F.FSIBError):
+        plan.tuning(interp_points=3)
     res = autotune(plan, lambda: (plan.spread(X, c), plan.interp(X, f)), reps=1)
     assert res["best"] == plan.tuning()
     print(f"autotune chose {res['best']} ({len(res['trials'])} trials)")
