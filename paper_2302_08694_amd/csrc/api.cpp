@@ -949,9 +949,20 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
   // the interpolation of U^{m+1} also stays on s2, beside the products of uhat^{m+1} that open the
   // next step (they do not read U); the last step joins it to st, so U is complete in st's order.
   const hipStream_t s2 = p.overlap && p.aux ? p.aux : st;
+  // On an early error return the work already queued on s2 is joined to st as well, so that nothing
+  // the caller may free or reuse next is still being written behind its back.
+  struct JoinOnExit {
+    hipStream_t st, s2;
+    hipEvent_t ev;
+    bool armed = false;
+    ~JoinOnExit() {
+      if (armed && s2 != st && hipEventRecord(ev, s2) == hipSuccess) (void)hipStreamWaitEvent(st, ev, 0);
+    }
+  } join{st, s2, p.fj[3]};
   if (nsteps > 0) {
     FSIB_HIP(hipEventRecord(p.fj[0], st));
     FSIB_HIP(hipStreamWaitEvent(s2, p.fj[0], 0));
+    join.armed = true;
   }
   for (int n = 0; n < nsteps; ++n) {
     const bool last = n + 1 == nsteps;
@@ -981,6 +992,7 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     if (last) {
       FSIB_HIP(hipEventRecord(p.fj[3], s2));
       FSIB_HIP(hipStreamWaitEvent(st, p.fj[3], 0));
+      join.armed = false;
       FSIB_TRY(velocity_interp_sorted(p, M, uhat_half, U, st));
     } else {
       FSIB_HIP(hipEventRecord(p.fj[0], st));
