@@ -527,3 +527,32 @@ def test_circle_pressure_jump_width_settles_to_a_fixed_multiple_of_h(F):
     print("jump width / h: " + ", ".join(f"{w:.3f}" for w in widths))
     assert all(1.4 < w < 2.2 for w in widths)
     assert abs(widths[-1] - widths[-2]) < 0.05
+
+
+def test_circle_trivial_solution_below_and_above_the_transition(F):
+    """Sec. 6.1 (coupling of N and N_b): N_b = 64 fixed, N = 4 ... 512.  Below the transition
+    (h_b = 2 pi r / N_b < L / N, N <= 64) the normal-force circle's velocity at the points is zero to
+    the transform tolerance (the oracle's direct sums give 1e-16); above it the boundary leaks and the
+    velocity grows (oracle: 6.7e-4, 7.3e-3, 1.3e-2 at N = 128, 256, 512), which the GPU path
+    reproduces."""
+    from oracle import step as ostep
+    M = 64
+    X = wl.circle_2d(M, center=(0.5, 0.5), r=0.125)
+    th = 2 * np.pi * np.arange(M) / M
+    S = (2 * np.pi / M) * np.stack([np.cos(th), np.sin(th)], axis=1)
+    for N in (4, 8, 16, 32, 64, 128, 256, 512):
+        announce(f"transition N={N}")
+        plan = F.Plan(2, (N, N), prec="f64", tol=1e-12, max_points=M, fluid=True)
+        params = F.FluidParams("stokes", mu=1.0)
+        fh = plan.force_spread(dev(X), dev(S), 1.0)
+        uh = torch.zeros_like(fh)
+        plan.fluid_step(params, fh, uh)
+        U = host(plan.velocity_interp(dev(X), uh))
+        plan.close()
+        umax = float(np.abs(U).max())
+        if N <= 64:
+            assert umax < 1e-10, (N, umax)
+        else:
+            Uo, _ = ostep.stokes_map(X, S, (N, N), 1.0, 1.0)
+            assert umax > 1e-4 and rel_l2(U, Uo) < 1e-8, (N, umax)
+        print(f"transition N={N}: max|U| {umax:.2e}")
