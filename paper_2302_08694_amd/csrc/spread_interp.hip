@@ -16,10 +16,11 @@ namespace fsib {
 constexpr int kSpreadThreads = 256;  // the most threads of a spreading workgroup
 // Threads of a spreading workgroup: 256 for 3D tiles (16 x 8 x 8); for 2D tiles (16 x 16) 64 in FP32,
 // so that a lane owns 4 cells of a row as in 3D (with 256 threads a 2D lane owns one cell and spends
-// most of each point on the bit scan and addressing of the walk: 2D batch +8%), and 256 in FP64, whose
-// 21 KiB of LDS per one-wave workgroup would leave too few waves per CU.
+// most of each point on the bit scan and addressing of the walk: 2D batch +8%), and 128 in FP64 (2
+// cells per lane: 21 KiB of LDS per one-wave workgroup would leave too few waves per CU; +2% against
+// 256).
 template <int DIM, typename T>
-__host__ __device__ constexpr int spread_threads() { return DIM == 3 || sizeof(T) == 8 ? 256 : 64; }
+__host__ __device__ constexpr int spread_threads() { return DIM == 3 ? 256 : (sizeof(T) == 8 ? 128 : 64); }
 constexpr int kChunk = 64;           // points staged per round
 constexpr int kMaxTileCells = 1024;  // cells of one tile
 constexpr int kTileX = 16;           // tile extent along x (one register row per thread)
@@ -117,8 +118,8 @@ __device__ __forceinline__ void stage_axis(bool valid, int st, int nfd, const T*
 // strength (NCH = 2, interleaved complex grid, transform index = blockIdx.y).
 //
 // Inside a tile every lane owns CW consecutive cells of one row along x (3D: 64 rows x 4 groups of
-// 4 cells; 2D FP32: 16 rows x 4 groups of 4 cells on 64 threads; 2D FP64: 16 rows x 16 single cells
-// on 256 threads) and accumulates them in registers.  The tile's points are staged 64 at a time, the
+// 4 cells; 2D FP32: 16 rows x 4 groups of 4 cells on 64 threads; 2D FP64: 16 rows x 8 groups of 2
+// cells on 128 threads) and accumulates them in registers.  The tile's points are staged 64 at a time, the
 // wavefronts taking the axes in turn with one lane per point: the lane evaluates the point's w
 // kernel values along the axis (Horner), writes them expanded over the tile's coordinates of that
 // axis (zero outside the support), and one ballot per coordinate group gives the 64-bit set of
