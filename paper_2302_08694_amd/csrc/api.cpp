@@ -265,7 +265,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   A.get(p.s_str, Mx * (2 * p.ntrans > d ? 2 * p.ntrans : d) * rs);
   A.get(p.flag, 256);
   A.get(p.scan_part, fsib::scan_segments(p.nbt) * 4);
-  A.get(p.rowmask, p.nt[1] * p.nt[2]);
+  A.get(p.rowmask, p.nt[1] * p.nt[2] * (p.dim == 2 ? p.ninst : 1));  // 2D: one block per instance
   A.get(p.zmask, p.nt[2]);
   // spreading work list: part bound = tiles + visits / split, visits <= M * prod(q + 1)
   {
@@ -361,16 +361,24 @@ hipStream_t S(void* s) { return (hipStream_t)s; }
 // passes; entries y and lines z of the y passes; entries z of the z passes).
 fsib::PassMasks mask_x(const Plan& p) {
   fsib::PassMasks m;
-  if (p.ninst > 1) return m;  // occupancy masks are kept for single-instance plans only
+  if (p.ninst > 1 && p.dim == 3) return m;  // 3D multi-instance plans run their passes dense
   m.rows = {p.rowmask, (int)p.nf[1], (int)p.nf[2], (int)p.tb[1], (int)p.tb[2], (int)p.nt[1]};
+  if (p.ninst > 1) {  // 2D: rows of instance i follow one another, p.dim fields each
+    m.rows.rpi = (int64_t)p.dim * p.nf[1] * p.nf[2];
+    m.rows.istride = (int)(p.nt[1] * p.nt[2]);
+  }
   return m;
 }
 fsib::PassMasks mask_y(const Plan& p, bool forward) {
   fsib::PassMasks m;
-  if (p.ninst > 1) return m;
+  if (p.ninst > 1 && p.dim == 3) return m;
   if (p.dim == 3) {
     m.line = {p.zmask, (int)p.nf[2], (int)p.tb[2], 1, 0};
     const fsib::StrideMask e{p.rowmask, (int)p.nf[2], (int)p.tb[2], (int)p.nt[1], (int)p.tb[1]};
+    (forward ? m.ld : m.st) = e;
+  } else if (p.ninst > 1) {
+    // outer index o = field of instance o / p.dim: the mask block of that instance
+    const fsib::StrideMask e{p.rowmask, INT32_MAX, p.dim, (int)p.nt[1], (int)p.tb[1]};
     (forward ? m.ld : m.st) = e;
   } else {
     const fsib::StrideMask e{p.rowmask, 1, 1, 0, (int)p.tb[1]};

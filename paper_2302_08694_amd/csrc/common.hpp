@@ -82,10 +82,14 @@ struct StrideMask {
   const uint8_t* m;  // nullptr: no mask
   int omod, odiv, ostride, idiv;
 };
-// For a pass along x over rows r (= ((c * nz + z) * ny + y)): m[((r / ny) % nz / tbz) * nt1 + (r % ny) / tby].
+// For a pass along x over rows r (= ((c * nz + z) * ny + y)): m[((r / ny) % nz / tbz) * nt1 + (r % ny) / tby],
+// plus (r / rpi) * istride on multi-instance plans (rpi rows per instance, istride mask bytes per
+// instance; rpi is huge and istride 0 otherwise).
 struct RowMask {
   const uint8_t* m;  // nullptr: no mask
   int ny, nz, tby, tbz, nt1;
+  int64_t rpi = INT64_MAX;
+  int istride = 0;
 };
 
 __host__ __device__ __forceinline__ int mask_index(const StrideMask& k, int64_t o, int i) {
@@ -93,7 +97,7 @@ __host__ __device__ __forceinline__ int mask_index(const StrideMask& k, int64_t 
 }
 __host__ __device__ __forceinline__ bool row_needed(const RowMask& k, int64_t r) {
   if (!k.m) return true;
-  return k.m[(int)((r / k.ny) % k.nz / k.tbz) * k.nt1 + (int)(r % k.ny) / k.tby] != 0;
+  return k.m[(int)(r / k.rpi) * k.istride + (int)((r / k.ny) % k.nz / k.tbz) * k.nt1 + (int)(r % k.ny) / k.tby] != 0;
 }
 
 struct PassMasks {

@@ -230,19 +230,23 @@ hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st) {
 
 // Block (yb, zb) of x lines is needed when a point of some bin (any bx, by in [yb-qy, yb],
 // bz in [zb-qz, zb]) has a kernel support reaching it.
-__global__ void k_row_masks(int nt0, int nt1, int nt2, int qy, int qz, const int* __restrict__ counts,
+// rowmask[i * nt1 * nt2 + zb * nt1 + yb] for the blocks of instance i < ninst (bins of instance i
+// follow those of instance i - 1)
+__global__ void k_row_masks(int nt0, int nt1, int nt2, int qy, int qz, int ninst, const int* __restrict__ counts,
                             uint8_t* __restrict__ rowmask) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nt1 * nt2) return;
+  const int tg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tg >= nt1 * nt2 * ninst) return;
+  const int inst = tg / (nt1 * nt2), t = tg - inst * nt1 * nt2;
   const int yb = t % nt1, zb = t / nt1;
+  const int* ci = counts + (int64_t)inst * nt0 * nt1 * nt2;
   int any = 0;
   for (int dz = 0; dz <= qz && !any; ++dz)
     for (int dy = 0; dy <= qy && !any; ++dy) {
       const int by = (yb - dy + nt1) % nt1, bz = (zb - dz + nt2) % nt2;
-      const int* c = counts + (int64_t)(bz * nt1 + by) * nt0;
+      const int* c = ci + (int64_t)(bz * nt1 + by) * nt0;
       for (int bx = 0; bx < nt0; ++bx) any |= c[bx];
     }
-  rowmask[t] = any ? 1 : 0;
+  rowmask[tg] = any ? 1 : 0;
 }
 
 __global__ void k_plane_masks(int nt1, int nt2, const uint8_t* __restrict__ rowmask, uint8_t* __restrict__ zmask) {
@@ -254,9 +258,10 @@ __global__ void k_plane_masks(int nt1, int nt2, const uint8_t* __restrict__ rowm
 }
 
 hipError_t launch_row_masks(Plan& p, hipStream_t st) {
-  const int nrb = (int)(p.nt[1] * p.nt[2]);
+  const int ni = p.dim == 2 ? p.ninst : 1;  // 3D multi-instance plans keep no masks
+  const int nrb = (int)(p.nt[1] * p.nt[2]) * ni;
   hipLaunchKernelGGL(k_row_masks, dim3((nrb + 255) / 256), dim3(256), 0, st, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2],
-                     (int)p.qn[1], (int)p.qn[2], (const int*)p.counts, p.rowmask);
+                     (int)p.qn[1], (int)p.qn[2], ni, (const int*)p.counts, p.rowmask);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_plane_masks, dim3((unsigned)((p.nt[2] + 255) / 256)), dim3(256), 0, st, (int)p.nt[1],
@@ -287,7 +292,8 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st)) != hipSuccess) return e;
-  if (p.ninst == 1 && (e = launch_row_masks(p, st)) != hipSuccess) return e;  // masks: one instance only
+  // masks: single-instance plans and 2D multi-instance plans
+  if ((p.ninst == 1 || p.dim == 2) && (e = launch_row_masks(p, st)) != hipSuccess) return e;
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     if (p.prec == FSIB_F64)

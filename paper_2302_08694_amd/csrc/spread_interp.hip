@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   tcoord[1] = (lt / a.nt[0]) % a.nt[1];
   tcoord[2] = DIM == 3 ? lt / (a.nt[0] * a.nt[1]) : 0;
   // no point reaches this tile's block of x lines: those lines are neither read nor written
-  if (a.rowmask && !a.rowmask[tcoord[2] * a.nt[1] + tcoord[1]]) return;
+  if (a.rowmask && !a.rowmask[(int64_t)inst * a.nt[1] * a.nt[2] + tcoord[2] * a.nt[1] + tcoord[1]]) return;
   const int nparts = a.tile_parts[tile_id];
   constexpr int tcells = kTileX * ROWS;
   int base[3] = {0, 0, 0};
@@ -703,7 +703,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   a.tile_slot = p.tile_slot;
   a.scratch = (T*)p.split_scratch;
   a.slots = p.split_slots;
-  a.rowmask = p.ninst > 1 ? nullptr : p.rowmask;  // occupancy masks: single-instance plans only
+  a.rowmask = p.ninst > 1 && DIM == 3 ? nullptr : p.rowmask;  // no masks on 3D multi-instance plans
   a.xcd_chunk = p.xcd_chunk_spread;
   a.ninst = p.ninst;
   a.split = p.split;
