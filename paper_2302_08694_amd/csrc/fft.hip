@@ -55,8 +55,10 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
       need |= f;
     }
   } else {
+    // plain numbering only where whole lines may be skipped (a line mask): per-entry masks leave
+    // every workgroup some work, so neighbours stay on one XCD
     const int64_t lin0 = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
-    const int64_t lin = (a.line.m || a.ld.m || a.st.m) ? lin0 : xcd_linear(lin0, (int64_t)gridDim.x * gridDim.y);
+    const int64_t lin = a.line.m ? lin0 : xcd_linear(lin0, (int64_t)gridDim.x * gridDim.y);
     q0 = (lin % gridDim.x) * nb;
     o0 = lin / gridDim.x;
     ncol = (int)(a.inner - q0 < nb ? a.inner - q0 : nb);
