@@ -1,0 +1,130 @@
+"""GPU parity of the plans the benchmark times, at the full 3D Navier-Stokes size, against the oracle.
+
+Workload: the lat-long ellipsoid of 40,000 points, N = 128^3 modes, surface tension, rho = 1,
+mu = 0.01, dt = 5e-4 (Alg. 1, Sec. 3.3; force of Sec. 6.2.3).
+
+* The FP64 plan at tol 1e-5 with automatic oversampling -- the benchmark's headline plan -- must be
+  the low-memory configuration (oversampling 1.25, kernel width 10, fine grid 160^3), and its force
+  spreading (512 sampled modes) and velocity interpolation (256 sampled points) must match the
+  oracle's direct sums (App. A, eqs. type1 and type2) to the plan's tolerance.
+* Three full Alg. 1 steps from rest against the committed oracle trajectory
+  (tests/golden/ns3d_128_three_steps.json, written by make_ns3d_steps.py from the oracle alone):
+  displacement and velocity at 1024 sampled points and uhat at 512 sampled modes, relative l2 over
+  the sample.  Bars: 1e-10 for FP64 at tol 1e-11; 3 x tol for the tol 1e-5 plans in FP64 and FP32
+  (each step composes a spread and two interpolations, each within tol, through a linear update).
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import nudft, fluid, step
+from oracle.modes import mode_numbers
+from tests.gpu_helpers import announce, cdtype, dev, half, host, rdtype, rel_l2
+from tests.helpers import random_real_field_hat
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "ns3d_128_three_steps.json")
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2302_08694_amd as F
+    assert F.device_count() > 0, "no HIP device visible"
+    return F
+
+
+@pytest.fixture(scope="module")
+def ns3d():
+    case = workloads.ns3d_case()
+    ptr, idx = workloads.vertex_triangle_csr(case["tris"], case["X"].shape[0])
+    case.update(ptr=ptr, idx=idx)
+    return case
+
+
+def _plan(F, case, prec, tol, upsampfac=0.0):
+    M = case["X"].shape[0]
+    return F.Plan(3, case["N"], L=case["L"], prec=prec, tol=tol, max_points=M, fluid=True, navier_stokes=True,
+                  upsampfac=upsampfac)
+
+
+def test_headline_plan_configuration(F, ns3d):
+    announce("headline plan configuration f64 tol 1e-5")
+    plan = _plan(F, ns3d, "f64", 1e-5)
+    info = plan.info()
+    assert info["w"] == 10
+    assert tuple(info["n_fine"]) == (160, 160, 160)
+    plan.close()
+
+
+def test_headline_force_spread(F, ns3d):
+    announce("headline plan force spread f64 tol 1e-5, 512 sampled modes")
+    X = ns3d["X"]
+    M = X.shape[0]
+    Ns = ns3d["N"]
+    S = np.random.default_rng(51).standard_normal((M, 3))
+    plan = _plan(F, ns3d, "f64", 1e-5)
+    out = host(plan.force_spread(dev(X), dev(S), scale=1.0))
+    rng = np.random.default_rng(52)
+    ix, iy, iz = rng.integers(0, Ns[0] // 2, 512), rng.integers(0, Ns[1], 512), rng.integers(0, Ns[2], 512)
+    m = np.stack([mode_numbers(Ns[0])[ix], mode_numbers(Ns[1])[iy], mode_numbers(Ns[2])[iz]], axis=1)
+    ref = np.stack([nudft.type1_at_modes(X, S[:, a], m) for a in range(3)])
+    err = rel_l2(out[:, iz, iy, ix], ref)
+    print(f"headline force spread: rel_l2 {err:.3e}")
+    assert err < 1e-5
+    plan.close()
+
+
+def test_headline_velocity_interp(F, ns3d):
+    announce("headline plan velocity interp f64 tol 1e-5, 256 sampled points")
+    X = ns3d["X"]
+    M = X.shape[0]
+    Ns = ns3d["N"]
+    uh = fluid.zero_nyquist(random_real_field_hat(Ns, 3, 53), Ns)
+    plan = _plan(F, ns3d, "f64", 1e-5)
+    U = host(plan.velocity_interp(dev(X), dev(half(uh, Ns[0]))))
+    sel = np.random.default_rng(54).choice(M, 256, replace=False)
+    err = rel_l2(U[sel], step.interp_velocity(X[sel], uh, Ns, 1.0))
+    print(f"headline velocity interp: rel_l2 {err:.3e}")
+    assert err < 1e-5
+    plan.close()
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-11, 1e-10), ("f64", 1e-5, 3e-5), ("f32", 1e-5, 3e-5)])
+def test_three_steps_against_oracle(F, ns3d, golden, prec, tol, bar):
+    announce(f"three full-size NS steps {prec} tol {tol} against the oracle fixture")
+    X0 = ns3d["X"]
+    M = X0.shape[0]
+    assert golden["N"] == list(ns3d["N"]) and golden["steps"] == 3
+    plan = _plan(F, ns3d, prec, tol)
+    force = F.Force("surface3d", ns3d["K"], dev(ns3d["tris"]), dev(ns3d["ptr"]), dev(ns3d["idx"]))
+    params = F.FluidParams("navier_stokes", rho=ns3d["rho"], mu=ns3d["mu"], dt=ns3d["dt"])
+    X = dev(X0)
+    U = torch.zeros((M, 3), dtype=rdtype(prec), device="cuda")
+    uh = torch.zeros((3,) + plan.half_shape, dtype=cdtype(prec), device="cuda")
+    for _ in range(3):
+        plan.step(params, force, X, U, uh)
+    Xh, Uh, uhh = host(X), host(U), host(uh)
+    assert np.all(np.isfinite(Xh))
+    pts = np.asarray(golden["points"])
+    e_disp = rel_l2(Xh[pts] - X0[pts], np.asarray(golden["disp"]))
+    e_U = rel_l2(Uh[pts].astype(np.float64), np.asarray(golden["U"]))
+    iz, iy, ix = np.asarray(golden["modes_index_zyx"]).T
+    ref_uh = np.asarray(golden["uhat_re"]) + 1j * np.asarray(golden["uhat_im"])
+    e_uh = rel_l2(uhh[:, iz, iy, ix].astype(np.complex128), ref_uh)
+    e_norm = abs(np.linalg.norm(Xh - X0) - golden["disp_norm"]) / golden["disp_norm"]
+    print(f"three steps {prec} tol {tol}: displacement {e_disp:.3e}, U {e_U:.3e}, uhat {e_uh:.3e}, "
+          f"|disp| {e_norm:.3e}")
+    assert max(e_disp, e_U, e_uh, e_norm) < bar
+    plan.close()
