@@ -81,6 +81,12 @@ typedef struct {
                            ntrans = 1 (Stokes instances); every stage of a step then runs as one
                            launch over all instances.  Points are given instance after instance
                            (fsib_plan_set_instances), half spectra as [ninst][dim][...]. */
+  int deterministic;    /* 0: points inside a spreading bin are ordered as the sort's atomic run claims
+                           arrive, so spreading sums agree between runs to rounding only; 1: every bin
+                           lists its points in ascending original index (one more pass over the points
+                           per sort), so every output of every call is bitwise reproducible for the same
+                           inputs, including across HIP graph replays and checkpoint/resume of fsib_step
+                           trajectories (Sec. 5: the method itself is deterministic). */
 } fsib_plan_opts;
 
 /* Read-only facts about a plan (host struct filled by fsib_plan_info). */

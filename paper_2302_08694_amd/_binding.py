@@ -24,7 +24,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_modes", ctypes.c_int64 * 3), ("L", ctypes.c_double),
                 ("prec", ctypes.c_int), ("tol", ctypes.c_double), ("upsampfac", ctypes.c_double),
                 ("ntrans", ctypes.c_int), ("max_points", ctypes.c_int64), ("fluid", ctypes.c_int),
-                ("navier_stokes", ctypes.c_int), ("ninst", ctypes.c_int)]
+                ("navier_stokes", ctypes.c_int), ("ninst", ctypes.c_int), ("deterministic", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -231,7 +231,7 @@ def force_jvp(force, X, V):
 
 class Plan:
     def __init__(self, dim, n_modes, L=1.0, prec="f64", tol=1e-6, ntrans=1, max_points=1 << 16, fluid=False,
-                 navier_stokes=False, upsampfac=0.0, ninst=1):
+                 navier_stokes=False, upsampfac=0.0, ninst=1, deterministic=False):
         lib = load_library()
         nm = list(n_modes) + [1] * (3 - len(n_modes))
         self.dim = int(dim)
@@ -244,7 +244,7 @@ class Plan:
         self.max_points = int(max_points)
         opts = _Opts(self.dim, (ctypes.c_int64 * 3)(*nm), self.L, FSIB_F64 if prec == "f64" else FSIB_F32,
                      float(tol), float(upsampfac), self.ntrans, self.max_points, int(bool(fluid)),
-                     int(bool(navier_stokes)), int(ninst))
+                     int(bool(navier_stokes)), int(ninst), int(bool(deterministic)))
         self.ninst = max(1, int(ninst))
         h = ctypes.c_void_p()
         _check(lib.fsib_plan_create(ctypes.byref(opts), ctypes.byref(h)), "fsib_plan_create")

@@ -85,6 +85,7 @@ void free_plan(Plan& p) {
   fr(p.inst_off);
   fr(p.pt_bin);
   fr(p.pt_rank);
+  fr(p.det_key);
   fr(p.s_idx);
   fr(p.s_i0);
   fr(p.s_y);
@@ -153,6 +154,7 @@ fsib_status validate_opts(const fsib_plan_opts* o) {
   if (o->prec == FSIB_F64 && !(o->tol >= 1e-14)) return fail(FSIB_ERR_TOL, "FP64 plans reach tol >= 1e-14");
   if (o->prec == FSIB_F32 && !(o->tol >= 1e-6)) return fail(FSIB_ERR_TOL, "FP32 plans reach tol >= 1e-6");
   if (o->navier_stokes && !o->fluid) return fail(FSIB_ERR_ARG, "navier_stokes needs fluid = 1");
+  if (o->deterministic != 0 && o->deterministic != 1) return fail(FSIB_ERR_ARG, "deterministic must be 0 or 1");
   if (o->ninst < 0 || o->ninst > 4096) return fail(FSIB_ERR_ARG, "ninst must be in [0, 4096]");
   if (o->ninst > 1 && (!o->fluid || o->navier_stokes || o->ntrans != 1))
     return fail(FSIB_ERR_ARG, "ninst > 1 needs fluid = 1, navier_stokes = 0 and ntrans = 1");
@@ -175,6 +177,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   p.max_points = o->max_points;
   p.fluid = o->fluid ? 1 : 0;
   p.ns = o->navier_stokes ? 1 : 0;
+  p.deterministic = o->deterministic ? 1 : 0;
   FSIB_HIP(hipGetDevice(&p.device));
   FSIB_HIP(hipDeviceGetAttribute(&p.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
   // workgroup-to-XCD run lengths (tuning knobs; the defaults are the measured best)
@@ -259,6 +262,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   A.get(p.inst_off, (int64_t)(p.ninst + 1) * 8);
   A.get(p.pt_bin, Mx * 4);
   A.get(p.pt_rank, Mx * 4);
+  if (p.deterministic) A.get(p.det_key, Mx * 4);
   A.get(p.s_idx, Mx * 4);
   A.get(p.s_i0, Mx * 4);
   A.get(p.s_y, Mx * d * rs);
@@ -770,6 +774,7 @@ fsib_status fsib_spread(fsib_plan plan, int64_t M, const double* X, const void* 
   if (!std::isfinite(scale)) return fail(FSIB_ERR_ARG, "scale must be finite");
   return type1_complex(p, M, X, c, fhat, scale, S(stream));
 }
+
 
 fsib_status fsib_interp(fsib_plan plan, int64_t M, const double* X, const void* fhat, void* c, void* stream) {
   if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");

@@ -193,6 +193,33 @@ __global__ void k_bin_scatter(int64_t M, const double* __restrict__ X, Geo g, co
   s_i0[pos] = packed;
 }
 
+// Deterministic placement (plans created with deterministic = 1).  The run claims of k_bin_count give
+// correct bin counts but an arrival-dependent order inside each bin, and with it the summation order
+// of spreading.  Here every point's rank inside its bin becomes the number of points of the same bin
+// with a smaller original index, so each bin lists its points in ascending index and the sums are
+// bitwise reproducible.  First the points are placed by the claimed ranks (key[pos] = index), then
+// each point counts the smaller indices in its bin's segment (its own bin's entries are read by
+// neighbouring points of the mesh too, from the cache).  The cost is linear in the points for bins of
+// bounded population and quadratic in a bin's population in general.
+__global__ void k_bin_place(int64_t M, const int* __restrict__ offsets, const int* __restrict__ pt_bin,
+                            const int* __restrict__ pt_rank, int* __restrict__ key) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  key[(int64_t)offsets[pt_bin[j]] + pt_rank[j]] = (int)j;
+}
+
+__global__ void k_stable_rank(int64_t M, const int* __restrict__ offsets, const int* __restrict__ pt_bin,
+                              const int* __restrict__ key, int* __restrict__ pt_rank) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const int b = pt_bin[j];
+  const int s = offsets[b], e = offsets[b + 1];
+  const int jj = (int)j;
+  int r = 0;
+  for (int q = s; q < e; ++q) r += key[q] < jj ? 1 : 0;
+  pt_rank[j] = r;
+}
+
 __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -294,6 +321,15 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
   if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st)) != hipSuccess) return e;
   // masks: single-instance plans and 2D multi-instance plans
   if ((p.ninst == 1 || p.dim == 2) && (e = launch_row_masks(p, st)) != hipSuccess) return e;
+  if (M > 0 && p.deterministic) {  // ranks by original index inside each bin
+    const unsigned nblk = (unsigned)((M + 255) / 256);
+    hipLaunchKernelGGL(k_bin_place, dim3(nblk), dim3(256), 0, st, M, (const int*)p.offsets, (const int*)p.pt_bin,
+                       (const int*)p.pt_rank, p.det_key);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stable_rank, dim3(nblk), dim3(256), 0, st, M, (const int*)p.offsets, (const int*)p.pt_bin,
+                       (const int*)p.det_key, p.pt_rank);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     if (p.prec == FSIB_F64)

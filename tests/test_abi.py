@@ -35,10 +35,11 @@ def test_version_and_status_strings():
 
 def _opts(**kw):
     o = dict(dim=3, n_modes=(16, 16, 16), L=1.0, prec=0, tol=1e-6, upsampfac=2.0, ntrans=1, max_points=100,
-             fluid=0, navier_stokes=0, ninst=0)
+             fluid=0, navier_stokes=0, ninst=0, deterministic=0)
     o.update(kw)
     return B._Opts(o["dim"], (ctypes.c_int64 * 3)(*o["n_modes"]), o["L"], o["prec"], o["tol"], o["upsampfac"],
-                   o["ntrans"], o["max_points"], o["fluid"], o["navier_stokes"], o["ninst"])
+                   o["ntrans"], o["max_points"], o["fluid"], o["navier_stokes"], o["ninst"],
+                   o["deterministic"])
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -46,7 +47,7 @@ def _opts(**kw):
     (dict(prec=7), 1), (dict(upsampfac=1.5), 1), (dict(upsampfac=1.25, tol=1e-10), 2), (dict(upsampfac=1.25, prec=1, tol=1e-4), 2), (dict(ntrans=0), 1), (dict(max_points=-1), 1),
     (dict(navier_stokes=1, fluid=0), 1),
     (dict(ninst=2), 1), (dict(ninst=2, fluid=1, navier_stokes=1), 1), (dict(ninst=2, fluid=1, ntrans=2), 1),
-    (dict(ninst=5000, fluid=1), 1), (dict(ninst=-1), 1),
+    (dict(ninst=5000, fluid=1), 1), (dict(ninst=-1), 1), (dict(deterministic=2), 1),
     (dict(prec=1, tol=1e-10), 2), (dict(prec=0, tol=1e-16), 2), (dict(tol=0.5), 2),
 ])
 def test_plan_argument_errors_come_before_device_use(kw, status):
