@@ -204,6 +204,25 @@ fsib_status fsib_spread(fsib_plan plan, int64_t M, const double* X, const void* 
 fsib_status fsib_interp(fsib_plan plan, int64_t M, const double* X, const void* fhat, void* c,
                         void* stream);
 
+/* ---- Type-1 without allocation ----------------------------------------------------------------
+ * For callers that cannot allocate device memory at call time or hold a plan's per-call workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): fsib_spread
+ * with every per-call buffer (point sort, spreading work list and partial tiles, fine grid, FFT
+ * intermediates) carved from a static device array of FSIB_NOALLOC_SCRATCH_BYTES per GPU, held by
+ * the library from its first use on that GPU until the process ends.  Makes no hipMalloc, hipFree
+ * or other allocating call.  Same arguments, layout and results as fsib_spread (to rounding; bitwise
+ * on deterministic plans) with these differences:
+ *   - M may exceed the plan's max_points; the buffers for (M, the plan's grid and ntrans) must fit the
+ *     static array, else FSIB_ERR_ARG with the number of bytes needed (nothing is enqueued);
+ *   - the plan must have fluid = 0 (FSIB_ERR_STATE otherwise) and be used on its own device
+ *     (FSIB_ERR_ARG otherwise); its own workspace is neither read nor written;
+ *   - every call on one GPU shares that GPU's array and leaves its contents behind: calls that may
+ *     overlap in time on one GPU (different streams, threads or plans) race and must be ordered by
+ *     the caller.  Nothing in the array needs to be cleared by the caller. */
+#define FSIB_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+fsib_status fsib_spread_noalloc(fsib_plan plan, int64_t M, const double* X, const void* c, void* fhat,
+                                double scale, void* stream);
+
 /* ---- Adjoint building blocks (gradients of the transforms) ------------------------------------
  * For a real loss, the gradient of the strengths of type-1 is a type-2 sum of the gradient of its
  * output (and vice versa), and the gradient of the positions needs the phase derivative

@@ -64,6 +64,8 @@ _SIGS = {
                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "fsib_spread": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_double, ctypes.c_void_p]),
+    "fsib_spread_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
     "fsib_interp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p]),
     "fsib_spectral_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -343,6 +345,19 @@ class Plan:
         shp = ((self.ntrans,) if self.ntrans > 1 or c.dim() == 2 else ()) + self.spectral_shape
         out = torch.empty(shp, dtype=self.cdtype, device=X.device) if out is None else _need(out, "fhat", self.cdtype, shp)
         _check(self._lib.fsib_spread(self._h, M, _ptr(X), _ptr(c), _ptr(out), float(scale), _stream()), "fsib_spread")
+        return out
+
+    def spread_noalloc(self, X, c, out, scale=1.0):
+        """Type-1 as spread() through the library's static per-GPU scratch (fsib_spread_noalloc): the
+        call allocates nothing; `out` must be given.  M may exceed max_points within the scratch."""
+        M = self._X(X)
+        c = _need(c, "c", self.cdtype)
+        if tuple(c.shape) not in ((self.ntrans, M),) + (((M,),) if self.ntrans == 1 else ()):
+            raise ValueError("c must have shape (ntrans, M) (or (M,) with ntrans = 1)")
+        shp = ((self.ntrans,) if self.ntrans > 1 or c.dim() == 2 else ()) + self.spectral_shape
+        _need(out, "fhat", self.cdtype, shp)
+        _check(self._lib.fsib_spread_noalloc(self._h, M, _ptr(X), _ptr(c), _ptr(out), float(scale), _stream()),
+               "fsib_spread_noalloc")
         return out
 
     def interp(self, X, fhat, out=None):

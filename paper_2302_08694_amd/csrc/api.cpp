@@ -7,6 +7,8 @@
 #include <new>
 #include <set>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "plan.hpp"
@@ -605,6 +607,111 @@ fsib_status stokes_velocity(Plan& p, const fsib_fluid_params& prm, const fsib_fo
 }
 
 }  // namespace
+
+namespace fsib {
+
+fsib_status report(fsib_status s, const char* msg) { return fail(s, msg); }
+
+// Per-call buffers of a type-1 transform carved from one device block (each 256-byte aligned), in the
+// sizes build_plan gives them but for M points instead of max_points.  With base == nullptr only the
+// size is computed.  The plan's tables (kernel pieces, deconvolution factors, twiddles, flag) stay.
+struct TransformBuffers {
+  int* counts; int* offsets; int* pt_bin; int* pt_rank; int* det_key; int* s_idx; uint32_t* s_i0; void* s_y;
+  void* s_str; int* scan_part; uint8_t* rowmask; uint8_t* zmask; int* tile_parts; int* part_off; int* work;
+  int* tile_slot; int* slot_ctr; void* split_scratch; void* grid; void* B1; void* B2;
+  int64_t work_blocks, split_slots;
+};
+
+static int64_t carve_transform_buffers(const Plan& p, int64_t M, char* base, TransformBuffers& b) {
+  int64_t off = 0;
+  auto take = [&](auto*& ptr, int64_t bytes) {
+    if (bytes <= 0) bytes = 256;
+    ptr = base ? reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(base + off) : nullptr;
+    off += (bytes + 255) / 256 * 256;
+  };
+  const int64_t rs = (int64_t)p.real_size(), cs = 2 * rs, d = p.dim;
+  const int64_t Mx = M > 0 ? M : 1;
+  take(b.counts, (p.nbt + 1) * 4);
+  take(b.offsets, (p.nbt + 1) * 4);
+  take(b.pt_bin, Mx * 4);
+  take(b.pt_rank, Mx * 4);
+  b.det_key = nullptr;
+  if (p.deterministic) take(b.det_key, Mx * 4);
+  take(b.s_idx, Mx * 4);
+  take(b.s_i0, Mx * 4);
+  take(b.s_y, Mx * d * rs);
+  take(b.s_str, Mx * (2 * p.ntrans > d ? 2 * p.ntrans : d) * rs);
+  take(b.scan_part, scan_segments(p.nbt) * 4);
+  take(b.rowmask, p.nt[1] * p.nt[2]);
+  take(b.zmask, p.nt[2]);
+  int64_t reach = 1;
+  for (int a = 0; a < p.dim; ++a) reach *= p.qn[a] + 1;
+  const int64_t visits = Mx * reach;
+  b.work_blocks = p.nbt + visits / p.split + 1;
+  b.split_slots = 2 * visits / p.split + 2;
+  const int64_t nch_bytes = 2 * rs > d * rs ? 2 * rs : d * rs;
+  take(b.tile_parts, p.nbt * 4);
+  take(b.part_off, (p.nbt + 1) * 4);
+  take(b.work, b.work_blocks * 8);
+  take(b.tile_slot, p.nbt * 4);
+  take(b.slot_ctr, 256);
+  take(b.split_scratch, (int64_t)p.ntrans * b.split_slots * 1024 * nch_bytes);
+  take(b.grid, (int64_t)p.ntrans * p.fine_cells() * cs);
+  take(b.B1, p.dim == 3 ? (int64_t)p.ntrans * p.nf[2] * p.nf[1] * p.N[0] * cs : (int64_t)p.ntrans * p.nf[1] * p.N[0] * cs);
+  take(b.B2, p.dim == 3 ? (int64_t)p.ntrans * p.nf[2] * p.N[1] * p.N[0] * cs : 0);
+  return off;
+}
+
+// The plan's per-call buffer fields exchanged with b (twice restores them).
+static void swap_transform_buffers(Plan& p, TransformBuffers& b) {
+  std::swap(p.counts, b.counts);
+  std::swap(p.offsets, b.offsets);
+  std::swap(p.pt_bin, b.pt_bin);
+  std::swap(p.pt_rank, b.pt_rank);
+  std::swap(p.det_key, b.det_key);
+  std::swap(p.s_idx, b.s_idx);
+  std::swap(p.s_i0, b.s_i0);
+  std::swap(p.s_y, b.s_y);
+  std::swap(p.s_str, b.s_str);
+  std::swap(p.scan_part, b.scan_part);
+  std::swap(p.rowmask, b.rowmask);
+  std::swap(p.zmask, b.zmask);
+  std::swap(p.tile_parts, b.tile_parts);
+  std::swap(p.part_off, b.part_off);
+  std::swap(p.work, b.work);
+  std::swap(p.tile_slot, b.tile_slot);
+  std::swap(p.slot_ctr, b.slot_ctr);
+  std::swap(p.split_scratch, b.split_scratch);
+  std::swap(p.grid, b.grid);
+  std::swap(p.B1, b.B1);
+  std::swap(p.B2, b.B2);
+  std::swap(p.work_blocks, b.work_blocks);
+  std::swap(p.split_slots, b.split_slots);
+}
+
+fsib_status spread_in_workspace(fsib_plan plan, int device, int64_t M, const double* X, const void* c, void* fhat,
+                                double scale, void* stream, void* ws, int64_t ws_bytes) {
+  if (!plan) return fail(FSIB_ERR_ARG, "plan is NULL");
+  Plan& p = plan->p;
+  if (device != p.device) return fail(FSIB_ERR_ARG, "the current device is not the plan's device");
+  if (p.fluid) return fail(FSIB_ERR_STATE, "this call takes a plan created with fluid = 0");
+  if (M < 0 || M > ((int64_t)1 << 30)) return fail(FSIB_ERR_ARG, "M must be in [0, 2^30]");
+  if (M > 0 && (!X || !c)) return fail(FSIB_ERR_ARG, "X and c must not be NULL");
+  if (!fhat) return fail(FSIB_ERR_ARG, "fhat is NULL");
+  if (!std::isfinite(scale)) return fail(FSIB_ERR_ARG, "scale must be finite");
+  TransformBuffers b;
+  const int64_t need = carve_transform_buffers(p, M, nullptr, b);
+  if (need > ws_bytes)
+    return fail(FSIB_ERR_ARG, "this transform needs " + std::to_string(need) + " bytes of scratch; the static " +
+                                  "scratch holds " + std::to_string(ws_bytes) + " bytes (fewer points, modes or ntrans)");
+  carve_transform_buffers(p, M, static_cast<char*>(ws), b);
+  swap_transform_buffers(p, b);
+  const fsib_status s = type1_complex(p, M, X, c, fhat, scale, S(stream));
+  swap_transform_buffers(p, b);
+  return s;
+}
+
+}  // namespace fsib
 
 extern "C" {
 

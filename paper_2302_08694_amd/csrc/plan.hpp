@@ -164,6 +164,11 @@ hipError_t launch_diag(const Plan& p, const fsib_fluid_params& prm, const fsib_f
                        const double* F, const void* Uh, const void* uhat, const double* X, double* diag,
                        hipStream_t st);
 
+// api.cpp: the last-error message of this thread, and type-1 through a caller-given device workspace
+fsib_status report(fsib_status s, const char* msg);
+fsib_status spread_in_workspace(fsib_plan plan, int device, int64_t M, const double* X, const void* c, void* fhat,
+                                double scale, void* stream, void* ws, int64_t ws_bytes);
+
 // Kernel classes that fsib_plan_profile can time (values of fsib_prof_class).
 enum { PROF_FFT_STRIDED = 1, PROF_SPREAD = 2, PROF_INTERP = 3, PROF_FFT_X = 4, PROF_NL_X = 5 };
 
