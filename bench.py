@@ -113,6 +113,91 @@ def time_steps(torch, s, steps, warmup, prof_class=None):
     return (el, prof) if prof_class else el
 
 
+def time_reps(torch, s, reps=30):
+    """Median over `reps` repetitions of one round (ROUND steps from the initial state, one fsib_steps
+    call), each timed with a HIP event pair on the stream the steps are issued on; the state reset
+    between repetitions lies outside the events."""
+    plan, force, params = s["plan"], s["force"], s["params"]
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    reset(s)
+    plan.steps(params, force, s["X"], s["U"], s["uh"], ROUND)  # warm-up
+    for e0, e1 in ev:
+        reset(s)
+        e0.record(st)
+        plan.steps(params, force, s["X"], s["U"], s["uh"], ROUND)
+        e1.record(st)
+    torch.cuda.synchronize()
+    ms = sorted(e0.elapsed_time(e1) / ROUND for e0, e1 in ev)
+    return {"reps": reps, "steps_per_rep": ROUND, "median_ms_per_step": ms[len(ms) // 2],
+            "min_ms_per_step": ms[0], "max_ms_per_step": ms[-1], "median_steps_per_s": 1e3 / ms[len(ms) // 2],
+            "method": "HIP events on the issuing stream around each repetition of one fsib_steps call of "
+                      f"{ROUND} steps from the initial state, after one warm-up repetition"}
+
+
+def stokes2d_small(F, torch, reps=30):
+    """The 2D Stokes ellipse (N = 32^2, M = 128, tension K = 1, mu = 1, dt = 1e-3, FP64 at tol 1e-12):
+    10 steps from U^0, eager (one fsib_steps call) and replayed from a HIP graph; median over `reps`
+    repetitions timed with HIP events.  Returns the timings and the final positions."""
+    import workloads
+    c = workloads.stokes2d_case()
+    X0 = c["X"]
+    M = X0.shape[0]
+    dev = "cuda:0"
+    plan = F.Plan(2, c["N"], L=c["L"], prec="f64", tol=1e-12, max_points=M, fluid=True)
+    force = F.Force("tension2d", c["K"])
+    params = F.FluidParams("stokes", mu=c["mu"], dt=c["dt"])
+    Xi = torch.as_tensor(X0).to(dev)
+    X = Xi.clone()
+    U = torch.zeros((M, 2), dtype=torch.float64, device=dev)
+    uh = torch.zeros((2,) + plan.half_shape, dtype=torch.complex128, device=dev)
+
+    def run():
+        X.copy_(Xi)
+        plan.velocity(params, force, X, uh, out=U)
+        plan.steps(params, force, X, U, uh, 10)
+
+    st = torch.cuda.current_stream()
+    run()
+    torch.cuda.synchronize()
+    Xf = X.cpu().numpy()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(st)
+        run()
+        e1.record(st)
+    torch.cuda.synchronize()
+    eager = sorted(e0.elapsed_time(e1) / 10 for e0, e1 in ev)
+    side = torch.cuda.Stream()
+    side.wait_stream(st)
+    with torch.cuda.stream(side):
+        run()
+    st.wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    g.replay()
+    torch.cuda.synchronize()
+    gdiff = float(np.max(np.abs(X.cpu().numpy() - Xf)))
+    for e0, e1 in ev:
+        e0.record(st)
+        g.replay()
+        e1.record(st)
+    torch.cuda.synchronize()
+    graph = sorted(e0.elapsed_time(e1) / 10 for e0, e1 in ev)
+    del g
+    plan.close()
+    med = lambda v: v[len(v) // 2]
+    res = {"workload": "2D Stokes FSIB, N=32^2, M=128 ellipse 0.3/0.2 at a seeded centre, tension K=1, mu=1, "
+                       "dt=1e-3, 10 steps, FP64 tol 1e-12",
+           "eager_steps_per_s": 1e3 / med(eager), "eager_median_ms_per_step": med(eager),
+           "graph_steps_per_s": 1e3 / med(graph), "graph_median_ms_per_step": med(graph),
+           "graph_max_abs_diff_X_vs_eager": gdiff, "reps": reps,
+           "method": "median over repetitions of U^0 (fsib_velocity) + 10 steps (fsib_steps), HIP events"}
+    return res, Xf
+
+
 def time_steps_graph(torch, s, steps):
     """The same rounds (state reset + one fsib_steps call of ROUND steps) captured once in a HIP graph
     and replayed; returns (seconds per step, max |X_graph - X_eager| after one round)."""
@@ -386,6 +471,71 @@ def nufft_micro(F, torch):
     return res
 
 
+def cpu_stokes2d(X_gpu):
+    """The oracle's 10-step trajectory of the 2D Stokes ellipse, on all host cores and on one thread, and
+    the GPU's final positions against it."""
+    import workloads
+    from oracle import step
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        threadpool_limits = None
+    c = workloads.stokes2d_case()
+    force = step.ForceLaw("tension2d", c["K"])
+
+    def traj():
+        X = c["X"].copy()
+        U, _ = step.stokes_velocity(X, force, c["N"], c["L"], c["mu"])
+        for _ in range(10):
+            X, U, _ = step.stokes_step(X, U, force, c["N"], c["L"], c["mu"], c["dt"])
+        return X
+
+    t0 = time.perf_counter()
+    Xo = traj()
+    t_all = (time.perf_counter() - t0) / 10
+    t_one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            traj()
+            t_one = (time.perf_counter() - t0) / 10
+    disp = Xo - c["X"]
+    res = {"seconds_per_step_all_cores": t_all, "steps_per_s_all_cores": 1.0 / t_all,
+           "seconds_per_step_1_thread": t_one, "steps_per_s_1_thread": None if t_one is None else 1.0 / t_one,
+           "sample": "the whole 10-step trajectory (direct sums)"}
+    if X_gpu is not None:
+        res["gpu_rel_err_displacement_vs_oracle"] = float(np.linalg.norm(X_gpu - Xo) / np.linalg.norm(disp))
+    return res
+
+
+def cpu_nufft_micro(nmodes=256, ntargets=4096, N=256, M=2_000_000):
+    """Direct type-1 sums at `nmodes` random modes and type-2 sums at `ntargets` random points of the
+    NUFFT micro-benchmark (256^3 modes, 2e6 points), timed on the host and extrapolated to the full
+    transforms (linear in modes and in targets).  The type-1 subset is 256 modes: the oracle forms one
+    phase per (point, mode) with single-threaded cos/sin, about 16 s for 5e8 phases on the machine's host."""
+    import workloads
+    from oracle import nudft
+    from oracle.modes import mode_numbers
+    X, c = workloads.nufft_points(M, seed=3, dim=3)
+    rng = np.random.default_rng(7)
+    m = np.stack([mode_numbers(N)[rng.integers(0, N, nmodes)] for _ in range(3)], axis=1)
+    t0 = time.perf_counter()
+    nudft.type1_at_modes(X, c, m)
+    t1 = time.perf_counter() - t0
+    f = workloads.random_modes((N, N, N), 38)
+    sel = rng.choice(M, ntargets, replace=False)
+    t0 = time.perf_counter()
+    nudft.type2(X[sel], f, (N, N, N))
+    t2 = time.perf_counter() - t0
+    del f
+    full1 = t1 * N ** 3 / nmodes
+    full2 = t2 * M / ntargets
+    return {"type1_subset_s": t1, "type1_subset": f"{nmodes} random modes x {M} points",
+            "type2_subset_s": t2, "type2_subset": f"{ntargets} random points x {N}^3 modes",
+            "type1_full_extrapolated_s": full1, "type2_full_extrapolated_s": full2,
+            "type1_pts_per_s": M / full1, "type2_pts_per_s": M / full2}
+
+
 def cpu_baseline(N, rings, sample_points=16384):
     """The FP64 oracle on a bounded sample of one step, extrapolated to steps/s.
 
@@ -474,6 +624,8 @@ def main():
     # value: the steps timed without instrumentation; then the same steps again with the dominant
     # kernel (the strided FFT passes along y and z) bracketed by HIP events on its launch stream
     t64 = time_steps(torch, s64, a.steps, a.warmup)
+    reps64 = time_reps(torch, s64)
+    log(f"f64 median of {reps64['reps']} repetitions: {reps64['median_ms_per_step']:.3f} ms/step")
     t64p, (prof_ms, prof_n, prof_bytes) = time_steps(torch, s64, a.steps, 0, ROOFLINE_CLASS)
     log(f"f64 {t64 * 1e3:.3f} ms/step ({t64p * 1e3:.3f} with events); {ROOFLINE_CLASS}: {prof_n} launches, "
         f"{prof_ms:.3f} ms")
@@ -501,7 +653,8 @@ def main():
     log("setup FP32")
     s32 = setup(F, torch, "f32", a.tol, a.n, a.rings, overlap=not a.serial)
     t32 = time_steps(torch, s32, a.steps, a.warmup)
-    log(f"f32 {t32 * 1e3:.3f} ms/step")
+    reps32 = time_reps(torch, s32)
+    log(f"f32 {t32 * 1e3:.3f} ms/step (median of repetitions {reps32['median_ms_per_step']:.3f})")
     X32 = s32["X"].cpu().numpy()
     ws32 = s32["plan"].info()["workspace_bytes"]
     U32max = float(s32["U"].abs().max().item())
@@ -536,13 +689,17 @@ def main():
         "state_after_timed_steps": {"f64_max_abs_U": U64max, "f32_max_abs_U": U32max,
                                     "f64_finite": bool(np.all(np.isfinite(X64))),
                                     "f32_finite": bool(np.all(np.isfinite(X32)))},
-        "fp32": {"steps_per_s": 1.0 / t32, "ms_per_step": t32 * 1e3,
+        "median_of_repetitions": reps64,
+        "fp32": {"steps_per_s": 1.0 / t32, "ms_per_step": t32 * 1e3, "median_of_repetitions": reps32,
                  "rel_err_displacement_vs_fp64": err32, "steps_compared": ROUND},
         "f64_hip_graph": graph64,
         "nufft_at_128": {"f64": nu64, "f32": nu32},
         "roofline": roofline(prof_ms, prof_n, prof_bytes),
         "ms_per_step_with_events": t64p * 1e3,
     }
+    log("2D Stokes, N=32^2, M=128, 10 steps")
+    out["stokes2d_small"], Xc1 = stokes2d_small(F, torch)
+    log(f"  {out['stokes2d_small']}")
     if not a.no_nufft_micro:
         out["nufft_micro"] = nufft_micro(F, torch)
     if not a.no_batch:
@@ -573,6 +730,13 @@ def main():
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.n, a.rings)
+        log("cpu oracle: 2D Stokes trajectory")
+        out["cpu_baseline"]["stokes2d_small"] = cpu_stokes2d(Xc1)
+        log(f"  {out['cpu_baseline']['stokes2d_small']}")
+        if not a.no_nufft_micro:
+            log("cpu oracle: NUFFT micro-benchmark subsets")
+            out["cpu_baseline"]["nufft_micro"] = cpu_nufft_micro()
+            log(f"  {out['cpu_baseline']['nufft_micro']}")
     print(json.dumps(out), flush=True)
 
 
