@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable 3D Stokes leg")
     ap.add_argument("--no-lowmem", action="store_true", help="skip the low-memory (oversampling 1.25) leg")
     ap.add_argument("--nufft-only", action="store_true", help="run only the NUFFT micro-benchmark legs")
+    ap.add_argument("--nufft-case", default=None,
+                    help="with --nufft-only: one case N:M:prec:tol (e.g. 256:2000000:f32:1e-5) instead of all")
+    ap.add_argument("--nufft-reps", type=int, default=10, help="timed transforms per direction and NUFFT case")
     ap.add_argument("--serial", action="store_true",
                     help="run the point side of each half step on the caller's stream (plan tuning overlap = 0) "
                          "instead of concurrently on the plan's second stream")
@@ -459,11 +462,11 @@ NUFFT_MICRO = [(128, 250_000, "f32", 1e-5), (128, 250_000, "f64", 1e-5),
                (256, 2_000_000, "f32", 1e-5), (256, 2_000_000, "f64", 1e-5), (256, 2_000_000, "f64", 1e-10)]
 
 
-def nufft_micro(F, torch):
+def nufft_micro(F, torch, cases=None, reps=10):
     res = []
-    for N, M, prec, tol in NUFFT_MICRO:
+    for N, M, prec, tol in (cases or NUFFT_MICRO):
         log(f"nufft micro N={N} M={M} {prec} tol {tol:g}")
-        r = time_nufft_micro(F, torch, N, M, prec, tol)
+        r = time_nufft_micro(F, torch, N, M, prec, tol, reps)
         log(f"  type1 {r['type1_ms']:.3f} ms type2 {r['type2_ms']:.3f} ms spread kernel {r['spread_kernel_us']:.1f} us "
             f"({r['spread_kernel_frac_hbm']:.2f} HBM) interp kernel {r['interp_kernel_us']:.1f} us "
             f"({r['interp_kernel_frac_hbm']:.2f} HBM)")
@@ -614,8 +617,12 @@ def main():
     if F.device_count() < 1:
         raise SystemExit("no HIP device visible")
     if a.nufft_only:
-        print(json.dumps({"metric": "NUFFT micro-benchmark only (profiling run)", "nufft_micro": nufft_micro(F, torch)}),
-              flush=True)
+        cases = None
+        if a.nufft_case:
+            n_, m_, p_, t_ = a.nufft_case.split(":")
+            cases = [(int(n_), int(m_), p_, float(t_))]
+        print(json.dumps({"metric": "NUFFT micro-benchmark only (profiling run)",
+                          "nufft_micro": nufft_micro(F, torch, cases, a.nufft_reps)}), flush=True)
         return
     log("setup FP64")
     s64 = setup(F, torch, "f64", a.tol, a.n, a.rings, overlap=not a.serial)
