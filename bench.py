@@ -30,6 +30,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--upsampfac", type=float, default=0.0,
+                    help="fine-grid oversampling of the FP64 and FP32 step plans (0: the plan's automatic choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=128, help="modes per axis")
     ap.add_argument("--rings", type=int, default=200)
@@ -625,7 +627,7 @@ def main():
                           "nufft_micro": nufft_micro(F, torch, cases, a.nufft_reps)}), flush=True)
         return
     log("setup FP64")
-    s64 = setup(F, torch, "f64", a.tol, a.n, a.rings, overlap=not a.serial)
+    s64 = setup(F, torch, "f64", a.tol, a.n, a.rings, upsampfac=a.upsampfac, overlap=not a.serial)
     info64 = s64["plan"].info()
     log(f"plan f64: {info64}")
     # value: the steps timed without instrumentation; then the same steps again with the dominant
@@ -658,7 +660,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     log("setup FP32")
-    s32 = setup(F, torch, "f32", a.tol, a.n, a.rings, overlap=not a.serial)
+    s32 = setup(F, torch, "f32", a.tol, a.n, a.rings, upsampfac=a.upsampfac, overlap=not a.serial)
     t32 = time_steps(torch, s32, a.steps, a.warmup)
     reps32 = time_reps(torch, s32)
     log(f"f32 {t32 * 1e3:.3f} ms/step (median of repetitions {reps32['median_ms_per_step']:.3f})")
@@ -714,14 +716,14 @@ def main():
         out["batched_2d_stokes"] = batched_stokes(F, torch)
         log(f"  {out['batched_2d_stokes']}")
     if not a.no_lowmem:
-        log("low-memory form (oversampling 1.25)")
+        log("smaller fine grids (oversampling 1.25 and 1.5)")
         lm = {}
-        for prec, tol in (("f32", 1e-3), ("f64", 1e-5)):
-            s = setup(F, torch, prec, tol, a.n, a.rings, upsampfac=1.25)
+        for prec, tol, up in (("f32", 1e-3, 1.25), ("f64", 1e-5, 1.25), ("f32", 1e-4, 1.5)):
+            s = setup(F, torch, prec, tol, a.n, a.rings, upsampfac=up)
             t = time_steps(torch, s, a.steps, a.warmup)
             info = s["plan"].info()
             Xl = s["X"].cpu().numpy()
-            lm[prec] = {"tol": tol, "w": info["w"], "n_fine": info["n_fine"][0], "steps_per_s": 1.0 / t,
+            lm[f"{prec}_sigma{up:g}"] = {"tol": tol, "w": info["w"], "n_fine": info["n_fine"][0], "steps_per_s": 1.0 / t,
                         "ms_per_step": t * 1e3, "workspace_bytes": info["workspace_bytes"],
                         "rel_err_displacement_vs_fp64": float(np.linalg.norm(Xl - X64) /
                                                               max(np.linalg.norm(d64), 1e-300))}

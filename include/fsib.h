@@ -63,13 +63,14 @@ typedef struct {
   int prec;             /* fsib_prec: arithmetic of grids, FFTs, spectral update, U */
   double tol;           /* relative l2 accuracy asked of the nonuniform transforms:
                            FP64 in [1e-14, 1e-1], FP32 in [1e-6, 1e-1] (else FSIB_ERR_TOL) */
-  double upsampfac;     /* fine-grid oversampling sigma: 2.0, or 1.25 (low-memory form:
-                           fine grid >= 1.25 N per axis, about 4x fewer grid bytes in 3D, a wider
-                           kernel; per-axis error tol/(2 dim) must stay reachable with w <= 16,
-                           i.e. tol >= about 1e-8, and FP32 plans need tol >= 1e-3 (the
-                           deconvolution lifts FP32 rounding by up to ~100x at this
-                           oversampling), else FSIB_ERR_TOL); 0 = automatic: 1.25 for FP64 3D
-                           plans at tol >= 1e-6 with max_points <= N_x N_y N_z / 20, else 2.0
+  double upsampfac;     /* fine-grid oversampling sigma: 2.0, 1.5 or 1.25.  Below 2 the fine grid
+                           is smaller (1.5: about 2.4x fewer grid bytes in 3D; 1.25: about 4x) and
+                           the kernel wider; the per-axis error tol/(2 dim) must stay reachable with
+                           w <= 16 (1.25: tol >= about 1e-8; 1.5: about 1e-11), and the
+                           deconvolution lifts FP32 rounding by up to ~10x (1.5) or ~100x (1.25), so
+                           FP32 plans need tol >= 1e-5 at 1.5 and >= 1e-3 at 1.25, else
+                           FSIB_ERR_TOL.  0 = automatic: for 3D plans with max_points <= N_x N_y N_z
+                           / 20, 1.5 in FP64 at tol >= 1e-6 and in FP32 at tol >= 1e-4; else 2.0
                            (fsib_plan_info reports n_fine) */
   int ntrans;           /* complex transforms per fsib_spread / fsib_interp call, >= 1 */
   int64_t max_points;   /* largest M accepted by any call, >= 0 */

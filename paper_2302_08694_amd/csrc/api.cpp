@@ -129,16 +129,22 @@ fsib_status upload(const Plan& p, void* dst, const std::vector<double>& v) {
   return FSIB_OK;
 }
 
-// Oversampling of a plan: upsampfac 2.0 or 1.25 as asked; 0 picks 1.25 for FP64 3D plans at
-// tol >= 1e-6 whose point count is small against the mode count (max_points <= N^3 / 20), where the
-// FFT passes over the fine grid outweigh the wider kernel (128^3 modes with 4e4 points: 533 against
-// 499 steps/s of the Navier-Stokes step), and 2.0 otherwise.
+// Oversampling of a plan: upsampfac 2.0, 1.5 or 1.25 as asked; 0 picks 1.5 for 3D plans whose point
+// count is small against the mode count (max_points <= N^3 / 20), where the FFT passes over the fine
+// grid outweigh the wider kernel, in FP64 at tol >= 1e-6 (128^3 modes, 4e4 points, tol 1e-5: 1.247 ms
+// per Navier-Stokes step at 1.5 with w = 8, 1.345 ms at 1.25 with w = 10, more at 2.0) and in FP32 at
+// tol >= 1e-4; 2.0 otherwise.
 static double plan_sigma(const fsib_plan_opts* o) {
-  if (o->upsampfac == 1.25) return 1.25;
-  if (o->upsampfac == 2.0) return 2.0;
+  if (o->upsampfac == 1.25 || o->upsampfac == 1.5 || o->upsampfac == 2.0) return o->upsampfac;
   const double modes = (double)o->n_modes[0] * (double)o->n_modes[1] * (o->dim == 3 ? (double)o->n_modes[2] : 1.0);
   const bool small_m = 20.0 * (double)o->max_points <= modes;
-  return (o->prec == FSIB_F64 && o->dim == 3 && o->tol >= 1e-6 && small_m) ? 1.25 : 2.0;
+  if (o->dim == 3 && small_m) {
+    if (o->prec == FSIB_F64 && o->tol >= 1e-6) return 1.5;
+    // FP32 rounding lifted ~8x by the deconvolution at 1.5 puts multi-step results near 3e-5 of the
+    // exact sums: 1.5 only where that is within the tolerance
+    if (o->prec == FSIB_F32 && o->tol >= 1e-4) return 1.5;
+  }
+  return 2.0;
 }
 
 fsib_status validate_opts(const fsib_plan_opts* o) {
@@ -148,8 +154,8 @@ fsib_status validate_opts(const fsib_plan_opts* o) {
     if (o->n_modes[a] < 2 || o->n_modes[a] > 4096) return fail(FSIB_ERR_ARG, "n_modes must be in [2, 4096]");
   if (!(o->L > 0) || !std::isfinite(o->L)) return fail(FSIB_ERR_ARG, "L must be positive and finite");
   if (o->prec != FSIB_F64 && o->prec != FSIB_F32) return fail(FSIB_ERR_ARG, "prec must be FSIB_F64 or FSIB_F32");
-  if (!(o->upsampfac == 0.0 || o->upsampfac == 2.0 || o->upsampfac == 1.25))
-    return fail(FSIB_ERR_ARG, "upsampfac must be 0, 2.0 or 1.25");
+  if (!(o->upsampfac == 0.0 || o->upsampfac == 2.0 || o->upsampfac == 1.5 || o->upsampfac == 1.25))
+    return fail(FSIB_ERR_ARG, "upsampfac must be 0, 2.0, 1.5 or 1.25");
   if (o->ntrans < 1 || o->ntrans > 65535) return fail(FSIB_ERR_ARG, "ntrans must be in [1, 65535]");
   if (o->max_points < 0 || o->max_points > (int64_t)1 << 30) return fail(FSIB_ERR_ARG, "max_points out of range");
   if (!std::isfinite(o->tol) || o->tol > 0.1) return fail(FSIB_ERR_TOL, "tol must be <= 0.1");
@@ -164,6 +170,9 @@ fsib_status validate_opts(const fsib_plan_opts* o) {
   // deconvolution lifts FP32 rounding of the grid by as much: FP32 low-memory plans stop at 1e-3
   if (plan_sigma(o) == 1.25 && o->prec == FSIB_F32 && !(o->tol >= 1e-3))
     return fail(FSIB_ERR_TOL, "FP32 plans with upsampfac 1.25 reach tol >= 1e-3");
+  // at 1.5 the transform falls by about 10x across the retained modes (w = 8): FP32 stops at 1e-5
+  if (plan_sigma(o) == 1.5 && o->prec == FSIB_F32 && !(o->tol >= 1e-5))
+    return fail(FSIB_ERR_TOL, "FP32 plans with upsampfac 1.5 reach tol >= 1e-5");
   if (fsib::choose_width(o->tol, o->dim, plan_sigma(o)) > fsib::kMaxW)
     return fail(FSIB_ERR_TOL, "tol is out of reach of the kernel widths available at this oversampling");
   return FSIB_OK;
@@ -202,7 +211,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
       continue;
     }
     const int64_t tb = p.dim == 3 ? tile3[a] : tile2[a];
-    int64_t need = p.sigma == 2.0 ? 2 * p.N[a] : (5 * p.N[a] + 3) / 4;  // ceil(sigma N)
+    int64_t need = p.sigma == 2.0 ? 2 * p.N[a] : (p.sigma == 1.5 ? (3 * p.N[a] + 1) / 2 : (5 * p.N[a] + 3) / 4);  // ceil(sigma N)
     if (need < 2 * p.w) need = 2 * p.w;
     if (need < tb) need = tb;
     p.nf[a] = fsib::smooth_at_least(need, tb);

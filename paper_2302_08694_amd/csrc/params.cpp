@@ -54,17 +54,26 @@ static const double kErr1d[17] = {1, 1,       3.5e-2,  3.3e-3,  3.6e-4,  4.2e-5,
 static const double kErr1d125[17] = {1, 1,      1.1e-1, 2.6e-2, 5.2e-3, 1.2e-3, 2.7e-4, 6.2e-5, 1.4e-5,
                                      3.5e-6,    7.8e-7, 2.3e-7, 6.2e-8, 1.4e-8, 3.3e-9, 7.3e-10, 1.9e-10};
 
+// The same for oversampling 1.5 with beta = 2.07 w for w >= 5 (1.86, 1.96, 2.04 w below; the best
+// ratios of a scan over beta/w in steps of 0.02), measured the same way.
+static const double kErr1d15[17] = {1, 1,      6.1e-2, 8.2e-3, 1.3e-3, 2.1e-4, 3.6e-5, 5.3e-6, 7.3e-7,
+                                    1.2e-7,    2.2e-8, 4.0e-9, 6.7e-10, 9.5e-11, 1.5e-11, 2.5e-12, 4.0e-13};
+
 int choose_width(double tol, int dim, double sigma) {
   // per-axis errors add up across the dim axes: ask each axis for tol / (2 dim)
   const double target = tol / (2.0 * dim);
-  const double* err = sigma < 1.5 ? kErr1d125 : kErr1d;
+  const double* err = sigma < 1.4 ? kErr1d125 : (sigma < 1.75 ? kErr1d15 : kErr1d);
   for (int w = 2; w <= kMaxW; ++w)
     if (err[w] <= target) return w;
   return kMaxW + 1;  // out of reach: the caller rejects the tolerance
 }
 
 double choose_beta(int w, double sigma) {
-  if (sigma < 1.5) return 1.86 * w;
+  if (sigma < 1.4) return 1.86 * w;
+  if (sigma < 1.75) {
+    static const double r15[5] = {0, 0, 1.86, 1.96, 2.04};
+    return (w < 5 ? r15[w] : 2.07) * w;
+  }
   static const double ratio[6] = {0, 0, 2.143, 2.257, 2.300, 2.329};
   return (w < 6 ? ratio[w] : 2.343) * w;
 }

@@ -44,7 +44,7 @@ def _opts(**kw):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(dim=1), 1), (dict(dim=4), 1), (dict(n_modes=(1, 16, 16)), 1), (dict(L=0.0), 1), (dict(L=float("nan")), 1),
-    (dict(prec=7), 1), (dict(upsampfac=1.5), 1), (dict(upsampfac=1.25, tol=1e-10), 2), (dict(upsampfac=1.25, prec=1, tol=1e-4), 2), (dict(ntrans=0), 1), (dict(max_points=-1), 1),
+    (dict(prec=7), 1), (dict(upsampfac=1.7), 1), (dict(upsampfac=1.5, prec=1, tol=1e-6), 2), (dict(upsampfac=1.25, tol=1e-10), 2), (dict(upsampfac=1.25, prec=1, tol=1e-4), 2), (dict(ntrans=0), 1), (dict(max_points=-1), 1),
     (dict(navier_stokes=1, fluid=0), 1),
     (dict(ninst=2), 1), (dict(ninst=2, fluid=1, navier_stokes=1), 1), (dict(ninst=2, fluid=1, ntrans=2), 1),
     (dict(ninst=5000, fluid=1), 1), (dict(ninst=-1), 1), (dict(deterministic=2), 1),

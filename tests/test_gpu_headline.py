@@ -4,14 +4,15 @@ Workload: the lat-long ellipsoid of 40,000 points, N = 128^3 modes, surface tens
 mu = 0.01, dt = 5e-4 (Alg. 1, Sec. 3.3; force of Sec. 6.2.3).
 
 * The FP64 plan at tol 1e-5 with automatic oversampling -- the benchmark's headline plan -- must be
-  the low-memory configuration (oversampling 1.25, kernel width 10, fine grid 160^3), and its force
+  the configuration the benchmark reports (oversampling 1.5, kernel width 8, fine grid 192^3), and its force
   spreading (512 sampled modes) and velocity interpolation (256 sampled points) must match the
   oracle's direct sums (App. A, eqs. type1 and type2) to the plan's tolerance.
 * Three full Alg. 1 steps from rest against the committed oracle trajectory
   (tests/golden/ns3d_128_three_steps.json, written by make_ns3d_steps.py from the oracle alone):
   displacement and velocity at 1024 sampled points and uhat at 512 sampled modes, relative l2 over
-  the sample.  Bars: 1e-10 for FP64 at tol 1e-11; 3 x tol for the tol 1e-5 plans in FP64 and FP32
-  (each step composes a spread and two interpolations, each within tol, through a linear update).
+  the sample.  Bars: 1e-10 for FP64 at tol 1e-11; 3 x tol for the plans at tol 1e-5 (FP64, FP32) and
+  1e-4 (FP32, oversampling 1.5): each step composes a spread and two interpolations, each within tol,
+  through a linear update.
 """
 
 import json
@@ -57,8 +58,8 @@ def test_headline_plan_configuration(F, ns3d):
     announce("headline plan configuration f64 tol 1e-5")
     plan = _plan(F, ns3d, "f64", 1e-5)
     info = plan.info()
-    assert info["w"] == 10
-    assert tuple(info["n_fine"]) == (160, 160, 160)
+    assert info["w"] == 8
+    assert tuple(info["n_fine"]) == (192, 192, 192)
     plan.close()
 
 
@@ -101,7 +102,8 @@ def golden():
         return json.load(f)
 
 
-@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-11, 1e-10), ("f64", 1e-5, 3e-5), ("f32", 1e-5, 3e-5)])
+@pytest.mark.parametrize("prec,tol,bar", [("f64", 1e-11, 1e-10), ("f64", 1e-5, 3e-5), ("f32", 1e-5, 3e-5),
+                                          ("f32", 1e-4, 3e-4)])
 def test_three_steps_against_oracle(F, ns3d, golden, prec, tol, bar):
     announce(f"three full-size NS steps {prec} tol {tol} against the oracle fixture")
     X0 = ns3d["X"]
