@@ -14,23 +14,28 @@
 namespace fsib {
 
 // N > 0: length N and PP row pairs per workgroup known at compile time; N = 0: from the arguments.
-template <typename T, int DIM, int N = 0, int PP = 0>
+// HX > 0: the half-spectrum length known at compile time too (index divisions become multiplies and
+// the gather and store loops get fixed trip counts).
+template <typename T, int DIM, int N = 0, int PP = 0, int HX = 0>
 __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                                   FftArgs<T> a, int64_t rows, int hx, int pp_arg, T inv_cells) {
+                                                   FftArgs<T> a, int64_t rows, int hx_arg, int pp_arg, T inv_cells) {
   constexpr int IL = DIM == 3 ? 3 : 2;  // inverse lines per row pair
   constexpr int FL = DIM == 3 ? 6 : 3;  // forward lines per row pair (products)
   constexpr int NTHR = (FL * PP * N + kEPT - 1) / kEPT;
+  // loads per thread in the gather: all kEPT slots unless the sizes are compile-time
+  constexpr int GJ = N > 0 ? (IL * PP * N + NTHR - 1) / NTHR : kEPT;
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nthr = N > 0 ? NTHR : (int)blockDim.x, pp = N > 0 ? PP : pp_arg;
+  const int hx = HX > 0 ? HX : hx_arg;
   cplx<T>* twl = buf + lpad_len(FL * pp * n);  // lines padded (lpad)
   const int64_t pair0 = (int64_t)blockIdx.x * pp;
   const int64_t cs = rows * hx;  // component stride of in/out
   // ---- gather the Hermitian-extended lines (inverse) ----
   const int nin = IL * pp * n;
-  cplx<T> A[kEPT], B[kEPT];
+  cplx<T> A[GJ], B[GJ];
 #pragma unroll
-  for (int j = 0; j < kEPT; ++j) {
+  for (int j = 0; j < GJ; ++j) {
     const int e = threadIdx.x + j * nthr;
     A[j] = mk((T)0, (T)0);
     B[j] = mk((T)0, (T)0);
@@ -57,7 +62,7 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
   }
   stage_twiddles(a.tw, twl, n);  // behind the data loads, so both latencies overlap
 #pragma unroll
-  for (int j = 0; j < kEPT; ++j) {
+  for (int j = 0; j < GJ; ++j) {
     const int e = threadIdx.x + j * nthr;
     if (e < nin) {
       const int t = e % n;
@@ -121,7 +126,10 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
     stockham<T, true>(a, buf, twl, FL * pp, -1);
   // ---- unpack the two rows of each line, keep m < Hx ----
   const int nst = FL * pp * hx;
-  for (int e = threadIdx.x; e < nst; e += nthr) {
+  constexpr int SJ = HX > 0 ? (FL * PP * HX + NTHR - 1) / NTHR : 1;  // compile-time trip count
+#pragma unroll
+  for (int j = 0; j < (HX > 0 ? SJ : 1); ++j)
+  for (int e = threadIdx.x + j * nthr; e < nst; e += (HX > 0 ? nst : nthr)) {
     const int ln = e / hx, m = e - ln * hx;
     const int q = ln / FL, f = ln - q * FL;
     const int64_t ra = 2 * (pair0 + q), rb = ra + 1;
@@ -169,7 +177,10 @@ static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t 
   const T inv = (T)(1.0 / (double)p.dealias_cells());
   const bool prof = prof_on(p, PROF_NL_X);
   if (prof) prof_start(p, st);
-  if (p.dim == 3 && n == 192 && pp == 2)
+  if (p.dim == 3 && n == 192 && pp == 2 && p.Hx == 65)
+    hipLaunchKernelGGL((k_nl_xpass<T, 3, 192, 2, 65>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in,
+                       (cplx<T>*)out, a, rows, (int)p.Hx, pp, inv);
+  else if (p.dim == 3 && n == 192 && pp == 2)
     hipLaunchKernelGGL((k_nl_xpass<T, 3, 192, 2>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out,
                        a, rows, (int)p.Hx, pp, inv);
   else if (p.dim == 3 && n == 96 && pp == 4)
