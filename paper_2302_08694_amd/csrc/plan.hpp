@@ -64,7 +64,7 @@ struct Plan {
   uint32_t* s_i0 = nullptr;  // M: packed first support cell (10 bits per axis)
   void* s_y = nullptr;     // M*dim prec: sub-cell position in [-1, 1]
   void* s_str = nullptr;   // strengths in sorted order: max(2 ntrans, dim) * M prec
-  int deterministic = 0;   // 1: each bin lists its points in ascending original index (k_stable_rank)
+  int deterministic = 0;   // 1: each bin lists its points in ascending original index (k_bin_rank)
   int* det_key = nullptr;  // M: original index per claimed slot (deterministic plans only)
   int* flag = nullptr;     // non-finite position seen
   int* scan_part = nullptr;  // segment sums of the exclusive scans over bins

@@ -6,6 +6,8 @@
 // sub-cell position y = 2 (i0 - g + w/2) - 1 in [-1, 1) selects the kernel values (see params.cpp).
 // Only (i0, y) are kept: the integer cell is exact and y is rounded to the plan precision, so FP32
 // plans keep full positional resolution within a cell.
+#include <climits>
+
 #include "plan.hpp"
 
 namespace fsib {
@@ -197,10 +199,11 @@ __global__ void k_bin_scatter(int64_t M, const double* __restrict__ X, Geo g, co
 // correct bin counts but an arrival-dependent order inside each bin, and with it the summation order
 // of spreading.  Here every point's rank inside its bin becomes the number of points of the same bin
 // with a smaller original index, so each bin lists its points in ascending index and the sums are
-// bitwise reproducible.  First the points are placed by the claimed ranks (key[pos] = index), then
-// each point counts the smaller indices in its bin's segment (its own bin's entries are read by
-// neighbouring points of the mesh too, from the cache).  The cost is linear in the points for bins of
-// bounded population and quadratic in a bin's population in general.
+// bitwise reproducible.  The points are first placed by the claimed ranks (key[pos] = index); then one
+// workgroup per bin sorts the bin's keys in LDS (bitonic network over the next power of two, padded
+// with INT_MAX) and gives each point its position in the sorted order.  Bins of more than kRankLds
+// points (far beyond the crowding of the workloads here) count, for every point, the smaller keys of
+// the bin in global memory instead.
 __global__ void k_bin_place(int64_t M, const int* __restrict__ offsets, const int* __restrict__ pt_bin,
                             const int* __restrict__ pt_rank, int* __restrict__ key) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,16 +211,49 @@ __global__ void k_bin_place(int64_t M, const int* __restrict__ offsets, const in
   key[(int64_t)offsets[pt_bin[j]] + pt_rank[j]] = (int)j;
 }
 
-__global__ void k_stable_rank(int64_t M, const int* __restrict__ offsets, const int* __restrict__ pt_bin,
-                              const int* __restrict__ key, int* __restrict__ pt_rank) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= M) return;
-  const int b = pt_bin[j];
-  const int s = offsets[b], e = offsets[b + 1];
-  const int jj = (int)j;
-  int r = 0;
-  for (int q = s; q < e; ++q) r += key[q] < jj ? 1 : 0;
-  pt_rank[j] = r;
+constexpr int kRankThreads = 256;
+constexpr int kRankLds = 4096;  // keys sorted in LDS per bin
+
+__global__ __launch_bounds__(kRankThreads) void k_bin_rank(const int* __restrict__ offsets,
+                                                            const int* __restrict__ key, int* __restrict__ pt_rank) {
+  __shared__ int sk[kRankLds];
+  const int b = blockIdx.x;
+  const int s = offsets[b], n = offsets[b + 1] - s;
+  if (n <= 0) return;
+  if (n == 1) {
+    if (threadIdx.x == 0) pt_rank[key[s]] = 0;
+    return;
+  }
+  if (n > kRankLds) {  // count smaller keys (quadratic; bins this crowded do not occur in the workloads)
+    for (int i = threadIdx.x; i < n; i += kRankThreads) {
+      const int k = key[s + i];
+      int r = 0;
+      for (int q = 0; q < n; ++q) r += key[s + q] < k ? 1 : 0;
+      pt_rank[k] = r;
+    }
+    return;
+  }
+  int P = 2;
+  while (P < n) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += kRankThreads) sk[i] = i < n ? key[s + i] : INT_MAX;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += kRankThreads) {
+        const int l = i ^ j;
+        if (l > i) {
+          const int a = sk[i], c = sk[l];
+          const bool up = (i & k) == 0;
+          if ((a > c) == up) {
+            sk[i] = c;
+            sk[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += kRankThreads) pt_rank[sk[i]] = i;
 }
 
 __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
@@ -326,7 +362,7 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
     hipLaunchKernelGGL(k_bin_place, dim3(nblk), dim3(256), 0, st, M, (const int*)p.offsets, (const int*)p.pt_bin,
                        (const int*)p.pt_rank, p.det_key);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stable_rank, dim3(nblk), dim3(256), 0, st, M, (const int*)p.offsets, (const int*)p.pt_bin,
+    hipLaunchKernelGGL(k_bin_rank, dim3((unsigned)p.nbt), dim3(kRankThreads), 0, st, (const int*)p.offsets,
                        (const int*)p.det_key, p.pt_rank);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
