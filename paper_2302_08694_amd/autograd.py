@@ -14,9 +14,9 @@ Backward (App. A, eqs. type1 and type2; gradients of complex arrays are dL/dRe +
           grad_X[:, a] = Re( conj(grad_c) * type2(i k_a fhat) )
 The adjoint transforms are the library's own spread and interp; the i k_a weighting and the per-point
 combination are library kernels too (fsib_spectral_scale, fsib_grad_combine), so every step runs on
-the device.  Positions are FP64; the plan's precision applies to everything else.  The time stepping
-of stokes_trajectory (X + dt U, the factor w K) is composed from torch elementwise operations, which
-torch differentiates.
+the device.  Positions are FP64; the plan's precision applies to everything else.  stokes_trajectory
+runs the library's own Stokes time step (fsib_step) forward and the adjoint of its midpoint rule
+backward, recomputing each step's velocities from per-step checkpoints.
 """
 
 import math
@@ -178,24 +178,62 @@ def stokes_force_velocity(plan, X, K, force, mu):
     return stokes_velocity(plan, X, S, mu)
 
 
+class _StokesTrajectory(torch.autograd.Function):
+    """X(T) after `steps` Stokes steps from X0.  The forward pass is the library's own time step
+    (fsib_velocity for U^0, then fsib_step: X^{m+1/2} = X^m + dt/2 U(X^m), X^{m+1} = X^m + dt
+    U(X^{m+1/2}), Sec. 6.1 with eqs. spatial_1 and spatial_4), keeping the positions at the start of
+    each step.  The backward pass sweeps the steps in reverse; per step it recomputes the two
+    velocities with the differentiable velocity map and applies the adjoint of the midpoint rule:
+    for g = dL/dX^{m+1}, dL/dX^m = g + a + b with a = (dt U_{X^{m+1/2}})^T g and
+    b = (dt/2 U_{X^m})^T a, and dL/dK gathers the K-derivatives of both velocity products."""
+
+    @staticmethod
+    def forward(ctx, X0, K, plan, force, mu, dt, steps):
+        from ._binding import FluidParams, Force
+        forceK = Force(force.kind, float(K), *force.unit._keep)
+        params = FluidParams("stokes", mu=mu, dt=dt)
+        X = X0.detach().clone().contiguous()
+        M, d = X.shape
+        U = torch.empty((M, d), dtype=plan.rdtype, device=X.device)
+        uh = torch.zeros(plan.field_shape, dtype=plan.cdtype, device=X.device)
+        plan.velocity(params, forceK, X, uh, out=U)  # U^0 = U(X^0)
+        ckpts = []
+        for _ in range(steps):
+            ckpts.append(X.clone())
+            plan.step(params, forceK, X, U, uh)
+        ctx.ckpts = ckpts
+        ctx.K = K.detach()
+        ctx.plan, ctx.force, ctx.mu, ctx.dt = plan, force, mu, dt
+        return X
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, gX):
+        plan, force, mu, dt = ctx.plan, ctx.force, ctx.mu, ctx.dt
+        g = gX.detach().to(torch.float64).contiguous()
+        gK = torch.zeros((), dtype=torch.float64, device=g.device)
+        for Xm in reversed(ctx.ckpts):
+            with torch.enable_grad():
+                x = Xm.detach().requires_grad_(True)
+                k = ctx.K.detach().requires_grad_(True)
+                U = stokes_force_velocity(plan, x, k, force, mu).to(torch.float64)
+                xh = (Xm + (0.5 * dt) * U.detach()).requires_grad_(True)  # X^{m+1/2} as the step forms it
+                Uh = stokes_force_velocity(plan, xh, k, force, mu).to(torch.float64)
+                a, aK = torch.autograd.grad(Uh, (xh, k), dt * g)
+                b, bK = torch.autograd.grad(U, (x, k), (0.5 * dt) * a)
+            g = g + a + b
+            gK = gK + aK + bK
+        ctx.ckpts = None
+        return g, (gK.reshape(ctx.K.shape) if ctx.needs_input_grad[1] else None), None, None, None, None, None
+
+
 def stokes_trajectory(plan, X0, K, force, mu, dt, steps, checkpoint=True):
-    """X after `steps` midpoint steps of the Stokes variant from X0 (the steps of fsib_step for the
-    Stokes model: Xh = X + dt/2 U(X), X <- X + dt U(Xh)), differentiable in X0 and K.
+    """X after `steps` midpoint steps of the Stokes variant from X0 -- the library's fsib_step -- as a
+    function differentiable in X0 and K (a 0-dimensional float64 tensor).
 
-    With checkpoint=True only the positions at the start of each step are kept for the backward
-    pass; the step is recomputed from them (torch.utils.checkpoint), so memory grows by one (M, dim)
-    array per step."""
-
-    def one_step(X, K):
-        U = stokes_force_velocity(plan, X, K, force, mu).to(torch.float64)
-        Xh = X + (0.5 * dt) * U
-        Uh = stokes_force_velocity(plan, Xh, K, force, mu).to(torch.float64)
-        return X + dt * Uh
-
-    X = X0
-    for _ in range(steps):
-        if checkpoint:
-            X = torch.utils.checkpoint.checkpoint(one_step, X, K, use_reentrant=False)
-        else:
-            X = one_step(X, K)
-    return X
+    The forward pass keeps the positions at the start of every step (one (M, dim) array per step) and
+    the backward pass recomputes each step's velocities from them.  `checkpoint` is accepted for
+    compatibility; both values give this checkpointed form."""
+    if not torch.is_tensor(K):
+        K = torch.tensor(float(K), dtype=torch.float64, device=X0.device)
+    return _StokesTrajectory.apply(X0, K, plan, force, mu, dt, int(steps))
