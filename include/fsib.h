@@ -343,6 +343,33 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
                        int64_t M, double* X, void* U, void* uhat_half, int nsteps, double* diag,
                        void* stream);
 
+/* ---- groups: many Stokes simulations of different sizes advanced together ----
+ * Alg. 1 (Sec. 3.3) with the Stokes velocity of Sec. 6.1 (eq. stokeslet) is independent per
+ * simulation; a group lets simulations of different N (each plan may itself hold ninst equal-N
+ * instances) share every launch of a step: each stage of the step (positions, force, point sort,
+ * spreading, the FFT passes, the Stokeslet, interpolation) is one kernel launch whose workgroups are
+ * divided among the plans, each plan's part with that plan's own arguments and grid.  Stages whose
+ * plans need different workgroup sizes (FFT lengths without a common thread count) fall back to one
+ * launch per plan.
+ *
+ * fsib_group_create: nplans in [1, 8] distinct plans (host array) with fluid = 1, navier_stokes = 0,
+ * deterministic = 0, and one device, dim, prec and kernel width w (the same tol and upsampfac give
+ * the same w).  The group keeps the plan handles, not copies: the plans must outlive the group and
+ * are not used on their own while a group call on them may still run.  Errors: FSIB_ERR_ARG. */
+typedef struct fsib_group_s* fsib_group;
+fsib_status fsib_group_create(int nplans, const fsib_plan* plans, fsib_group* out);
+fsib_status fsib_group_destroy(fsib_group group);
+/* nsteps >= 0 Stokes steps of every plan of the group, each as fsib_steps of that plan would run them
+ * (same arithmetic per plan; spreading sums in the order the sort leaves).  Host arrays of nplans
+ * entries, entry g for plan g: params (model STOKES, each plan its own mu and dt), forces, M, and
+ * the device pointers X (double, in/out), U (prec, in U^m, out U^{m+1}) and uhat_half (in/out), as
+ * for fsib_step.  No diagnostics.  Asynchronous in the order of `stream`; allocates nothing, so a
+ * call can be captured in a HIP graph.  Errors as fsib_step, checked for every plan before any
+ * launch. */
+fsib_status fsib_group_steps(fsib_group group, const fsib_fluid_params* params, const fsib_force* forces,
+                             const int64_t* M, double* const* X, void* const* U, void* const* uhat_half,
+                             int nsteps, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

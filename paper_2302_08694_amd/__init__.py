@@ -17,6 +17,8 @@ Entry points (same names as the C ABI):
     plan.fluid_step(params, fhat, uhat)     Alg. 1 Fourier update / Stokeslet
     plan.velocity(params, force, X, uhat)   U at X (U^0 for the first step)
     plan.step(params, force, X, U, uhat)    one Alg. 1 step
+    Group(plans).steps(params, forces, X, U, uhat, n)  Stokes steps of plans of different N, one launch
+                                            per stage over all of them
     compute_force(force, X)                 built-in force laws
     force_jvp(force, X, V)                  their Jacobian products (adjoint)
     spring_stiffness(X0, tris, ...)         edge springs of the elastic sphere (set-up)
@@ -30,6 +32,7 @@ independent 2D Stokes simulations in ``paper_2302_08694_amd.batch``.
 from ._binding import (  # noqa: F401
     FSIBError,
     Plan,
+    Group,
     FluidParams,
     Force,
     compute_force,

@@ -94,6 +94,12 @@ _SIGS = {
     "fsib_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force), ctypes.c_int64,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p]),
+    "fsib_group_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
+    "fsib_group_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fsib_group_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Force),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                        ctypes.c_void_p]),
 }
 
 _lib = None
@@ -470,3 +476,46 @@ class Plan:
             _need(diag, "diag", torch.float64, (DIAG_COUNT,))
         _check(self._lib.fsib_steps(self._h, ctypes.byref(params._s), ctypes.byref(force._s), M, _ptr(X), _ptr(U),
                                     _ptr(uhat), int(nsteps), _ptr(diag), _stream()), "fsib_steps")
+
+
+class Group:
+    """Stokes simulations of several plans (different N, each plan with its own instances) stepped
+    together (fsib_group_create / fsib_group_steps): every stage of a step is one launch over all plans.
+    The plans must stay open while the group is used."""
+
+    def __init__(self, plans):
+        lib = load_library()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib.fsib_group_create(len(self.plans), arr, ctypes.byref(h)), "fsib_group_create")
+        self._h = h
+        self._lib = lib
+
+    def steps(self, params, forces, X, U, uhat, nsteps=1):
+        """nsteps steps; params, forces, X, U, uhat: one entry per plan, as for Plan.step."""
+        n = len(self.plans)
+        if not all(len(a) == n for a in (params, forces, X, U, uhat)):
+            raise ValueError(f"need {n} entries per operand")
+        Ms = []
+        for p, x, u, uh in zip(self.plans, X, U, uhat):
+            M = p._X(x)
+            _need(u, "U", p.rdtype, (M, p.dim))
+            _need(uh, "uhat", p.cdtype, p.field_shape)
+            Ms.append(M)
+        prm = (_Params * n)(*[q._s for q in params])
+        frc = (_Force * n)(*[f._s for f in forces])
+        vp = lambda ts: (ctypes.c_void_p * n)(*[_ptr(t).value for t in ts])
+        _check(self._lib.fsib_group_steps(self._h, prm, frc, (ctypes.c_int64 * n)(*Ms), vp(X), vp(U), vp(uhat),
+                                          int(nsteps), _stream()), "fsib_group_steps")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fsib_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

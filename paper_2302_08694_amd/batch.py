@@ -108,10 +108,12 @@ class StokesBatch:
 class StokesGroupBatch:
     """The same simulations with one multi-instance plan per group of cases that share N, L, mu, dt
     and K (ninst > 1): each stage of a step is one launch over all instances of a group, so a batch
-    step costs a few launches per group instead of per instance.  Groups run on their own streams.
-    Same interface as StokesBatch; `positions()` returns each case's X in the order of `cases`."""
+    step costs a few launches per group instead of per instance.  With fused=True (the default) the
+    groups' plans form one library Group (fsib_group_steps) and each stage is one launch over all
+    groups, of every N; with fused=False the groups run on their own streams.  Same interface as
+    StokesBatch; `positions()` returns each case's X in the order of `cases`."""
 
-    def __init__(self, cases, prec="f32", tol=1e-5, device="cuda"):
+    def __init__(self, cases, prec="f32", tol=1e-5, device="cuda", fused=True):
         self.prec = prec
         keys = {}
         for i, c in enumerate(cases):
@@ -131,6 +133,10 @@ class StokesGroupBatch:
             self.groups.append(dict(plan=plan, params=params, force=force, X=X0.clone(), U=U, uh=uh, X0=X0,
                                     U0=U.clone(), uh0=uh.clone(), idx=idx, counts=counts))
         self.streams = [torch.cuda.Stream() for _ in self.groups]
+        self.fused = None
+        if fused:
+            from ._binding import Group
+            self.fused = Group([g["plan"] for g in self.groups])
         self.graph = None
         self.graph_steps = 0
 
@@ -141,6 +147,11 @@ class StokesGroupBatch:
             g["uh"].copy_(g["uh0"])
 
     def step(self, n=1):
+        if self.fused is not None:
+            gs = self.groups
+            self.fused.steps([g["params"] for g in gs], [g["force"] for g in gs], [g["X"] for g in gs],
+                             [g["U"] for g in gs], [g["uh"] for g in gs], n)
+            return
         main = torch.cuda.current_stream()
         for _ in range(n):
             for s in self.streams:
@@ -199,6 +210,9 @@ class StokesGroupBatch:
 
     def close(self):
         self.graph = None
+        if self.fused is not None:
+            self.fused.close()
+            self.fused = None
         for g in self.groups:
             g["plan"].close()
         self.groups = []

@@ -615,7 +615,83 @@ fsib_status stokes_velocity(Plan& p, const fsib_fluid_params& prm, const fsib_fo
   return FSIB_OK;
 }
 
+// ---- groups: Stokes steps of several plans, every stage one launch over all of them ----
+// The transforms of force_spread_sorted (fine grids -> p.fhat, scaled by 1/L^d) and of
+// velocity_interp_sorted (uhat[g] -> fine grids) for the plans of a group.
+fsib_status group_spread_ffts(const std::vector<Plan*>& ps, hipStream_t st) {
+  std::vector<fsib::FftCall> x, y, z;
+  for (Plan* q : ps) {
+    Plan& p = *q;
+    const int64_t d = (int64_t)p.dim * p.ninst;
+    const double scale = 1.0 / (p.dim == 3 ? p.L * p.L * p.L : p.L * p.L);
+    const int nf0 = (int)p.nf[0], nf1 = (int)p.nf[1], nf2 = (int)p.nf[2], hx = (int)p.Hx;
+    if (p.dim == 3) {
+      x.push_back({&p, p.grid, p.B1, nf0, -1, 1, d * p.nf[2] * p.nf[1], nf0, nf0, hx, hx, nullptr, p.fac[0], 1.0,
+                   mask_x(p)});
+      y.push_back({&p, p.B1, p.B2, nf1, -1, p.Hx, d * p.nf[2], nf1, nf1, (int)p.N[1], (int)ceil_half(p.N[1]), nullptr,
+                   p.fac[1], 1.0, mask_y(p, true)});
+      z.push_back({&p, p.B2, p.fhat, nf2, -1, p.N[1] * p.Hx, d, nf2, nf2, (int)p.N[2], (int)ceil_half(p.N[2]), nullptr,
+                   p.fac[2], scale, mask_z(p, true)});
+    } else {
+      x.push_back({&p, p.grid, p.B1, nf0, -1, 1, d * p.nf[1], nf0, nf0, hx, hx, nullptr, p.fac[0], 1.0, mask_x(p)});
+      y.push_back({&p, p.B1, p.fhat, nf1, -1, p.Hx, d, nf1, nf1, (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, p.fac[1],
+                   scale, mask_y(p, true)});
+    }
+  }
+  FSIB_HIP(fsib::launch_fft_x_group(x, true, st));
+  FSIB_HIP(fsib::launch_fft_c2c_group(y, st));
+  FSIB_HIP(fsib::launch_fft_c2c_group(z, st));
+  return FSIB_OK;
+}
+
+fsib_status group_interp_ffts(const std::vector<Plan*>& ps, void* const* uhat, hipStream_t st) {
+  std::vector<fsib::FftCall> x, y, z;
+  for (size_t g = 0; g < ps.size(); ++g) {
+    Plan& p = *ps[g];
+    const int64_t d = (int64_t)p.dim * p.ninst;
+    const int nf0 = (int)p.nf[0], nf1 = (int)p.nf[1], nf2 = (int)p.nf[2], hx = (int)p.Hx;
+    if (p.dim == 3) {
+      z.push_back({&p, uhat[g], p.B2, nf2, +1, p.N[1] * p.Hx, d, (int)p.N[2], (int)ceil_half(p.N[2]), nf2, nf2,
+                   p.fac[2], nullptr, 1.0, mask_z(p, false)});
+      y.push_back({&p, p.B2, p.B1, nf1, +1, p.Hx, d * p.nf[2], (int)p.N[1], (int)ceil_half(p.N[1]), nf1, nf1, p.fac[1],
+                   nullptr, 1.0, mask_y(p, false)});
+      x.push_back({&p, p.B1, p.grid, nf0, +1, 1, d * p.nf[2] * p.nf[1], hx, hx, nf0, nf0, p.fac[0], nullptr, 1.0,
+                   mask_x(p)});
+    } else {
+      y.push_back({&p, uhat[g], p.B1, nf1, +1, p.Hx, d, (int)p.N[1], (int)ceil_half(p.N[1]), nf1, nf1, p.fac[1],
+                   nullptr, 1.0, mask_y(p, false)});
+      x.push_back({&p, p.B1, p.grid, nf0, +1, 1, d * p.nf[1], hx, hx, nf0, nf0, p.fac[0], nullptr, 1.0, mask_x(p)});
+    }
+  }
+  FSIB_HIP(fsib::launch_fft_c2c_group(z, st));
+  FSIB_HIP(fsib::launch_fft_c2c_group(y, st));
+  FSIB_HIP(fsib::launch_fft_x_group(x, false, st));
+  return FSIB_OK;
+}
+
+// stokes_velocity for every plan of a group: U[g] at X[g], uhat[g] the field.
+fsib_status group_stokes_velocity(const std::vector<Plan*>& ps, const fsib_fluid_params* prm, const fsib_force* f,
+                                  const int64_t* M, const double* const* X, void* const* U, void* const* uhat,
+                                  hipStream_t st) {
+  const size_t n = ps.size();
+  std::vector<const void*> S(n);
+  for (size_t g = 0; g < n; ++g) S[g] = ps[g]->S;
+  FSIB_HIP(fsib::launch_force_strengths_group(ps, f, M, X, st));
+  FSIB_HIP(fsib::launch_sort_points_group(ps, M, X, st));
+  FSIB_HIP(fsib::launch_spread_group(ps, M, S.data(), st));
+  FSIB_TRY(group_spread_ffts(ps, st));
+  FSIB_HIP(fsib::launch_fluid_stokes_group(ps, prm, uhat, st));
+  FSIB_TRY(group_interp_ffts(ps, uhat, st));
+  FSIB_HIP(fsib::launch_interp_group(ps, M, U, st));
+  return FSIB_OK;
+}
+
 }  // namespace
+
+struct fsib_group_s {
+  std::vector<fsib_plan> plans;
+  std::vector<Plan*> ps;
+};
 
 namespace fsib {
 
@@ -1130,6 +1206,82 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     }
   }
   if (diag && nsteps > 0) FSIB_HIP(fsib::launch_diag(p, prm, *force, M, p.F64, p.Uh, uhat_half, X, diag, st));
+  return FSIB_OK;
+}
+
+fsib_status fsib_group_create(int nplans, const fsib_plan* plans, fsib_group* out) {
+  if (!out) return fail(FSIB_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (nplans < 1 || nplans > fsib::kMaxParts) return fail(FSIB_ERR_ARG, "nplans must be in [1, 8]");
+  if (!plans) return fail(FSIB_ERR_ARG, "plans is NULL");
+  std::set<fsib_plan> seen;
+  for (int g = 0; g < nplans; ++g) {
+    if (!plans[g]) return fail(FSIB_ERR_ARG, "a plan of the group is NULL");
+    if (!seen.insert(plans[g]).second) return fail(FSIB_ERR_ARG, "a plan appears twice in the group");
+    const Plan& p = plans[g]->p;
+    const Plan& p0 = plans[0]->p;
+    if (!p.fluid || p.ns) return fail(FSIB_ERR_ARG, "group plans need fluid = 1 and navier_stokes = 0 (Stokes)");
+    if (p.deterministic) return fail(FSIB_ERR_ARG, "deterministic plans cannot join a group");
+    if (p.device != p0.device || p.dim != p0.dim || p.prec != p0.prec || p.w != p0.w || p.deg != p0.deg)
+      return fail(FSIB_ERR_ARG, "group plans need one device, dimension, precision and kernel width");
+  }
+  fsib_group grp = new (std::nothrow) fsib_group_s;
+  if (!grp) return fail(FSIB_ERR_OOM, "out of host memory");
+  for (int g = 0; g < nplans; ++g) {
+    grp->plans.push_back(plans[g]);
+    grp->ps.push_back(&plans[g]->p);
+  }
+  *out = grp;
+  return FSIB_OK;
+}
+
+fsib_status fsib_group_destroy(fsib_group group) {
+  delete group;
+  return FSIB_OK;
+}
+
+fsib_status fsib_group_steps(fsib_group group, const fsib_fluid_params* params, const fsib_force* forces,
+                             const int64_t* M, double* const* X, void* const* U, void* const* uhat_half, int nsteps,
+                             void* stream) {
+  if (!group) return fail(FSIB_ERR_ARG, "group is NULL");
+  if (!params || !forces || !M || !X || !U || !uhat_half) return fail(FSIB_ERR_ARG, "an operand array is NULL");
+  if (nsteps < 0) return fail(FSIB_ERR_ARG, "nsteps must be >= 0");
+  const std::vector<Plan*>& ps = group->ps;
+  const size_t n = ps.size();
+  for (size_t g = 0; g < n; ++g) {
+    const Plan& p = *ps[g];
+    FSIB_TRY(check_fluid(p, &params[g]));
+    if (params[g].model != FSIB_STOKES) return fail(FSIB_ERR_ARG, "group steps take the Stokes model");
+    FSIB_TRY(check_points(p, M[g], X[g]));
+    FSIB_TRY(check_force(&forces[g], p.dim, M[g]));
+    FSIB_TRY(check_instances(p, M[g], &forces[g]));
+    if (M[g] > 0 && !U[g]) return fail(FSIB_ERR_ARG, "U is NULL");
+    if (!uhat_half[g]) return fail(FSIB_ERR_ARG, "uhat_half is NULL");
+  }
+  const hipStream_t st = S(stream);
+  std::vector<double*> Xh(n);
+  std::vector<const double*> Xc(n), Xhc(n);
+  std::vector<void*> Uh(n), umid(n);
+  std::vector<const void*> Uc(n), Uhc(n);
+  std::vector<double> half(n), full(n);
+  for (size_t g = 0; g < n; ++g) {
+    Xh[g] = ps[g]->Xh;
+    Xhc[g] = ps[g]->Xh;
+    Xc[g] = X[g];
+    Uh[g] = ps[g]->Uh;
+    Uhc[g] = ps[g]->Uh;
+    Uc[g] = U[g];
+    umid[g] = ps[g]->uhat_mid;
+    half[g] = 0.5 * params[g].dt;
+    full[g] = params[g].dt;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    // X^{m+1/2} = X^m + dt/2 U^m (eq. spatial_1), then the midpoint rule with Stokes velocities
+    FSIB_HIP(fsib::launch_axpy_positions_group(ps, M, Xh.data(), Xc.data(), Uc.data(), half.data(), st));
+    FSIB_TRY(group_stokes_velocity(ps, params, forces, M, Xhc.data(), Uh.data(), umid.data(), st));
+    FSIB_HIP(fsib::launch_axpy_positions_group(ps, M, X, Xc.data(), Uhc.data(), full.data(), st));
+    FSIB_TRY(group_stokes_velocity(ps, params, forces, M, Xc.data(), U, uhat_half, st));
+  }
   return FSIB_OK;
 }
 

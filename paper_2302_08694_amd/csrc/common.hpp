@@ -62,6 +62,43 @@ __device__ __forceinline__ int64_t xcd_chunked(int64_t i, int64_t n, int64_t C) 
   return s * g + (r % kXcds) * C + r / kXcds;
 }
 
+// ---- launches over several plans ----
+// One launch may carry the workgroups of several independent parts (the plans of a group), each with
+// its own arguments and grid: part g owns workgroups [start[g], start[g+1]) of a one-dimensional
+// launch.  Every part starts at a multiple of kXcds, so its workgroup i still lands on XCD i mod 8
+// and the XCD-aware numbering inside its kernel works as in a launch of its own; the padding
+// workgroups at the end of a part leave at once.  A kernel body sees its workgroup as a Blk: its
+// coordinates and its grid, from the hardware registers in a launch of its own, from the part
+// table in a launch over parts.
+struct Blk {
+  int64_t x, y;    // workgroup coordinates in the part's grid
+  int64_t nx, ny;  // the part's grid
+};
+__device__ __forceinline__ Blk launch_blk() {
+  return Blk{(int64_t)blockIdx.x, (int64_t)blockIdx.y, (int64_t)gridDim.x, (int64_t)gridDim.y};
+}
+
+constexpr int kMaxParts = 8;  // parts of one launch (the kernel arguments stay within 4 KiB)
+template <class A>
+struct Parts {
+  A a[kMaxParts];
+  int64_t start[kMaxParts + 1];
+  int64_t nx[kMaxParts], ny[kMaxParts];
+  int n;
+};
+
+// Part of this workgroup (-1 for a padding workgroup) and its coordinates in the part's grid.
+template <class A>
+__device__ __forceinline__ int part_blk(const Parts<A>& f, Blk& b) {
+  const int64_t w = blockIdx.x;
+  int g = 0;
+  while (g + 1 < f.n && w >= f.start[g + 1]) ++g;
+  const int64_t l = w - f.start[g], nx = f.nx[g], ny = f.ny[g];
+  if (l >= nx * ny) return -1;
+  b = Blk{l % nx, l / nx, nx, ny};
+  return g;
+}
+
 constexpr int kMaxW = 16;       // largest kernel width (fine cells)
 constexpr int kMaxDeg = 19;     // largest polynomial degree of the kernel pieces
 constexpr int kMaxStages = 16;  // FFT stages

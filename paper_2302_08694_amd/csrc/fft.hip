@@ -32,8 +32,8 @@ constexpr int kFftWgEntries = 2048;
 // N > 0: a pass of length N with NB lines per workgroup known at compile time (N * NB / kEPT
 // threads); N = 0: any length, from the arguments.
 template <typename T, bool CONTIG, int N = 0, int NB = 0>
-__global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __restrict__ in,
-                                                            cplx<T>* __restrict__ out, FftArgs<T> a) {
+__device__ __forceinline__ void c2c_body(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                         const FftArgs<T>& a, Blk wb) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
   if (CONTIG) {
     // XCD-contiguous numbering only for unmasked passes: with occupancy masks the reached rows cluster,
     // and contiguous ranges would leave some XCDs most of the work
-    o0 = (a.rows.m ? (int64_t)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x)) * nb;
+    o0 = (a.rows.m ? wb.x : xcd_linear(wb.x, wb.nx)) * nb;
     ncol = (int)(a.outer - o0 < nb ? a.outer - o0 : nb);
     for (int b = threadIdx.x; b < nb; b += nthr) {
       const uint8_t f = b < ncol && row_needed(a.rows, o0 + b);
@@ -57,10 +57,10 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
   } else {
     // plain numbering only where whole lines may be skipped (a line mask): per-entry masks leave
     // every workgroup some work, so neighbours stay on one XCD
-    const int64_t lin0 = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
-    const int64_t lin = a.line.m ? lin0 : xcd_linear(lin0, (int64_t)gridDim.x * gridDim.y);
-    q0 = (lin % gridDim.x) * nb;
-    o0 = lin / gridDim.x;
+    const int64_t lin0 = wb.x + wb.y * wb.nx;
+    const int64_t lin = a.line.m ? lin0 : xcd_linear(lin0, wb.nx * wb.ny);
+    q0 = (lin % wb.nx) * nb;
+    o0 = lin / wb.nx;
     ncol = (int)(a.inner - q0 < nb ? a.inner - q0 : nb);
     const bool line = !a.line.m || a.line.m[mask_index(a.line, o0, 0)];
     for (int i = threadIdx.x; i < a.nin; i += nthr) fld[i] = line && (!a.ld.m || a.ld.m[mask_index(a.ld, o0, i)]);
@@ -149,16 +149,58 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __res
   }
 }
 
+template <typename T, bool CONTIG, int N = 0, int NB = 0>
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c(const cplx<T>* __restrict__ in,
+                                                            cplx<T>* __restrict__ out, FftArgs<T> a) {
+  c2c_body<T, CONTIG, N, NB>(in, out, a, launch_blk());
+}
+
+// One pass of a launch over parts: its operands and description.
+template <typename T>
+struct FftIO {
+  const void* in;
+  void* out;
+  FftArgs<T> a;
+};
+
+// The lengths and line counts with compile-time passes (the standard line count for each length).
+#define FSIB_FFT_CT_LIST(X) X(64, 32) X(96, 16) X(128, 16) X(160, 12) X(192, 8) X(256, 8) X(320, 6) X(384, 4) \
+  X(512, 4) X(1024, 2)
+
+// Launches over parts: CT = true when every part has a compile-time (length, line count) pair (the
+// kernel then holds only those bodies), else the runtime-length body alone (it needs about twice the
+// registers, which would lower the occupancy of the compile-time bodies sharing its kernel).
+template <typename T, bool CONTIG, bool CT>
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2c_parts(Parts<FftIO<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g < 0) return;
+  const FftIO<T>& io = f.a[g];
+  const cplx<T>* in = (const cplx<T>*)io.in;
+  cplx<T>* out = (cplx<T>*)io.out;
+  if constexpr (CT) {
+#define FSIB_C2C_PART(N_, NB_)                        \
+  if (io.a.n == N_ && io.a.nb == NB_) {               \
+    c2c_body<T, CONTIG, N_, NB_>(in, out, io.a, b);   \
+    return;                                           \
+  }
+    FSIB_FFT_CT_LIST(FSIB_C2C_PART)
+#undef FSIB_C2C_PART
+  } else {
+    c2c_body<T, CONTIG>(in, out, io.a, b);
+  }
+}
+
 // Real lines along x -> half spectra: lines 2b and 2b+1 form z = a + i b; A_m = (Z_m + conj Z_{n-m})/2,
 // B_m = (Z_m - conj Z_{n-m})/(2i) for m < nout.  a.outer = number of real lines, a.nb = pairs per block.
 template <typename T, int N = 0, int NB = 0>
-__global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restrict__ in, cplx<T>* __restrict__ out,
-                                                              FftArgs<T> a) {
+__device__ __forceinline__ void r2c_body(const T* __restrict__ in, cplx<T>* __restrict__ out, const FftArgs<T>& a,
+                                         Blk wb) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
   cplx<T>* twl = buf + lpad_len(n * nb);
-  const int64_t pair0 = (a.rows.m ? (int64_t)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x)) * nb;
+  const int64_t pair0 = (a.rows.m ? wb.x : xcd_linear(wb.x, wb.nx)) * nb;
   uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
   int need = 0;
   for (int b = threadIdx.x; b < 2 * nb; b += nthr) {
@@ -208,17 +250,44 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restric
   }
 }
 
+template <typename T, int N = 0, int NB = 0>
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x(const T* __restrict__ in, cplx<T>* __restrict__ out,
+                                                              FftArgs<T> a) {
+  r2c_body<T, N, NB>(in, out, a, launch_blk());
+}
+
+template <typename T, bool CT>
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_r2c_x_parts(Parts<FftIO<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g < 0) return;
+  const FftIO<T>& io = f.a[g];
+  const T* in = (const T*)io.in;
+  cplx<T>* out = (cplx<T>*)io.out;
+  if constexpr (CT) {
+#define FSIB_R2C_PART(N_, NB_)              \
+  if (io.a.n == N_ && io.a.nb == NB_) {     \
+    r2c_body<T, N_, NB_>(in, out, io.a, b); \
+    return;                                 \
+  }
+    FSIB_FFT_CT_LIST(FSIB_R2C_PART)
+#undef FSIB_R2C_PART
+  } else {
+    r2c_body<T>(in, out, io.a, b);
+  }
+}
+
 // Half spectra along x (nin entries m = 0..nin-1, the rest zero) -> real lines of length n; two
 // lines per complex transform: Z_t = A_t + i B_t with A_{n-m} = conj A_m, then Re/Im of the
 // inverse transform.  a.outer = number of real lines, a.nb = pairs per block.
 template <typename T, int N = 0, int NB = 0>
-__global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __restrict__ in, T* __restrict__ out,
-                                                              FftArgs<T> a) {
+__device__ __forceinline__ void c2r_body(const cplx<T>* __restrict__ in, T* __restrict__ out, const FftArgs<T>& a,
+                                         Blk wb) {
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;
   cplx<T>* twl = buf + lpad_len(n * nb);
-  const int64_t pair0 = (a.rows.m ? (int64_t)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x)) * nb;
+  const int64_t pair0 = (a.rows.m ? wb.x : xcd_linear(wb.x, wb.nx)) * nb;
   uint8_t* fl = flag_area(twl, n);  // rows of this workgroup reached by a point
   int need = 0;
   for (int b = threadIdx.x; b < 2 * nb; b += nthr) {
@@ -285,6 +354,33 @@ __global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __r
   }
 }
 
+template <typename T, int N = 0, int NB = 0>
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x(const cplx<T>* __restrict__ in, T* __restrict__ out,
+                                                              FftArgs<T> a) {
+  c2r_body<T, N, NB>(in, out, a, launch_blk());
+}
+
+template <typename T, bool CT>
+__global__ __launch_bounds__(kMaxFftThreads) void k_fft_c2r_x_parts(Parts<FftIO<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g < 0) return;
+  const FftIO<T>& io = f.a[g];
+  const cplx<T>* in = (const cplx<T>*)io.in;
+  T* out = (T*)io.out;
+  if constexpr (CT) {
+#define FSIB_C2R_PART(N_, NB_)              \
+  if (io.a.n == N_ && io.a.nb == NB_) {     \
+    c2r_body<T, N_, NB_>(in, out, io.a, b); \
+    return;                                 \
+  }
+    FSIB_FFT_CT_LIST(FSIB_C2R_PART)
+#undef FSIB_C2R_PART
+  } else {
+    c2r_body<T>(in, out, io.a, b);
+  }
+}
+
 template <typename T>
 static FftArgs<T> base_args(const Plan& p, int n, int sign, const PassMasks& mk) {
   FftArgs<T> a;
@@ -327,58 +423,120 @@ static int lines_per_block(int n, int64_t cap) {
   return nb;
 }
 
+// A (length, line count) pair with compile-time passes.
+static bool ct_pass(int n, int nb) {
+#define FSIB_CT_PAIR(N_, NB_) if (n == N_ && nb == NB_) return true;
+  FSIB_FFT_CT_LIST(FSIB_CT_PAIR)
+#undef FSIB_CT_PAIR
+  return false;
+}
 template <typename T>
-static hipError_t c2c_impl(const Plan& p, const void* in, void* out, int n, int sign, int64_t inner, int64_t outer,
-                           int nin, int pin, int nout, int pout, const void* fin, const void* fout, double scale,
-                           hipStream_t st, const PassMasks& mk) {
-  FftArgs<T> a = base_args<T>(p, n, sign, mk);
-  a.inner = inner;
-  a.outer = outer;
-  a.nin = nin;
-  a.pin = pin;
-  a.nout = nout;
-  a.pout = pout;
-  a.fac_in = (const T*)fin;
-  a.fac_out = (const T*)fout;
-  a.scale = (T)scale;
-  const bool contig = inner == 1;
-  a.nb = lines_per_block<T>(n, contig ? outer : inner);
-  const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)((contig ? lpad_len(n * a.nb) : n * a.nb) + n) * sizeof(cplx<T>) +
-                     flag_bytes(contig ? a.nb : nin);
-  const bool prof = !contig && prof_on(p, PROF_FFT_STRIDED);
-  if (prof) prof_start(p, st);
-  const dim3 grid = contig ? dim3((unsigned)((outer + a.nb - 1) / a.nb))
-                           : dim3((unsigned)((inner + a.nb - 1) / a.nb), (unsigned)outer);
+static bool all_ct(const Parts<FftIO<T>>& f) {
+  for (int g = 0; g < f.n; ++g)
+    if (!ct_pass(f.a[g].a.n, f.a[g].a.nb)) return false;
+  return true;
+}
+
+// Arguments, grid, threads and LDS of one strided or contiguous complex pass.
+template <typename T>
+static PartLaunch<FftIO<T>> c2c_launch(const FftCall& c) {
+  const Plan& p = *c.p;
+  PartLaunch<FftIO<T>> L;
+  FftArgs<T>& a = L.a.a;
+  a = base_args<T>(p, c.n, c.sign, c.mk);
+  a.inner = c.inner;
+  a.outer = c.outer;
+  a.nin = c.nin;
+  a.pin = c.pin;
+  a.nout = c.nout;
+  a.pout = c.pout;
+  a.fac_in = (const T*)c.fac_in;
+  a.fac_out = (const T*)c.fac_out;
+  a.scale = (T)c.scale;
+  const bool contig = c.inner == 1;
+  const int n = c.n;
+  a.nb = lines_per_block<T>(n, contig ? c.outer : c.inner);
+  L.a.in = c.in;
+  L.a.out = c.out;
+  L.threads = n * a.nb / kEPT;
+  L.lds = (size_t)((contig ? lpad_len(n * a.nb) : n * a.nb) + n) * sizeof(cplx<T>) + flag_bytes(contig ? a.nb : c.nin);
+  if (c.outer <= 0 || c.inner <= 0) {
+    L.nx = 0;
+  } else if (contig) {
+    L.nx = (c.outer + a.nb - 1) / a.nb;
+  } else {
+    L.nx = (c.inner + a.nb - 1) / a.nb;
+    L.ny = c.outer;
+  }
+  return L;
+}
+
+template <typename T>
+static hipError_t c2c_one(const PartLaunch<FftIO<T>>& L, bool contig, hipStream_t st) {
+  const FftArgs<T>& a = L.a.a;
+  const int n = a.n;
+  const dim3 grid((unsigned)L.nx, (unsigned)L.ny);
+  const cplx<T>* in = (const cplx<T>*)L.a.in;
+  cplx<T>* out = (cplx<T>*)L.a.out;
   // lengths with compile-time specialisations (when the line count is the standard one for n)
 #define FSIB_C2C_CT(N_, NB_)                                                                               \
   if (n == N_ && a.nb == NB_) {                                                                           \
     if (contig)                                                                                           \
-      hipLaunchKernelGGL((k_fft_c2c<T, true, N_, NB_>), grid, dim3(nthr), lds, st, (const cplx<T>*)in,   \
-                         (cplx<T>*)out, a);                                                               \
+      hipLaunchKernelGGL((k_fft_c2c<T, true, N_, NB_>), grid, dim3(L.threads), L.lds, st, in, out, a);    \
     else                                                                                                  \
-      hipLaunchKernelGGL((k_fft_c2c<T, false, N_, NB_>), grid, dim3(nthr), lds, st, (const cplx<T>*)in,  \
-                         (cplx<T>*)out, a);                                                               \
+      hipLaunchKernelGGL((k_fft_c2c<T, false, N_, NB_>), grid, dim3(L.threads), L.lds, st, in, out, a);   \
   } else
-  FSIB_C2C_CT(64, 32)
-  FSIB_C2C_CT(96, 16)
-  FSIB_C2C_CT(128, 16)
-  FSIB_C2C_CT(160, 12)
-  FSIB_C2C_CT(192, 8)
-  FSIB_C2C_CT(256, 8)
-  FSIB_C2C_CT(320, 6)
-  FSIB_C2C_CT(384, 4)
-  FSIB_C2C_CT(512, 4)
-  FSIB_C2C_CT(1024, 2) {
+  FSIB_FFT_CT_LIST(FSIB_C2C_CT) {
     if (contig)
-      hipLaunchKernelGGL((k_fft_c2c<T, true>), grid, dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
+      hipLaunchKernelGGL((k_fft_c2c<T, true>), grid, dim3(L.threads), L.lds, st, in, out, a);
     else
-      hipLaunchKernelGGL((k_fft_c2c<T, false>), grid, dim3(nthr), lds, st, (const cplx<T>*)in, (cplx<T>*)out, a);
+      hipLaunchKernelGGL((k_fft_c2c<T, false>), grid, dim3(L.threads), L.lds, st, in, out, a);
   }
 #undef FSIB_C2C_CT
-  // algorithmic bytes: every input entry read once, every output entry written once
-  if (prof) prof_stop(p, (double)(nin + nout) * inner * outer * sizeof(cplx<T>), st);
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t c2c_impl(const FftCall& c, hipStream_t st) {
+  const Plan& p = *c.p;
+  const PartLaunch<FftIO<T>> L = c2c_launch<T>(c);
+  const bool contig = c.inner == 1;
+  const bool prof = !contig && prof_on(p, PROF_FFT_STRIDED);
+  if (prof) prof_start(p, st);
+  const hipError_t e = c2c_one<T>(L, contig, st);
+  // algorithmic bytes: every input entry read once, every output entry written once
+  if (prof) prof_stop(p, (double)(c.nin + c.nout) * c.inner * c.outer * sizeof(cplx<T>), st);
+  return e;
+}
+
+// Passes of the plans of a group, one launch for the strided and one for the contiguous ones where
+// their workgroup sizes agree.
+template <typename T>
+static hipError_t c2c_group(const std::vector<FftCall>& calls, hipStream_t st) {
+  for (int contig = 0; contig < 2; ++contig) {
+    std::vector<PartLaunch<FftIO<T>>> v;
+    for (const FftCall& c : calls)
+      if ((c.inner == 1) == (contig == 1)) v.push_back(c2c_launch<T>(c));
+    const bool ct = contig == 1;
+    const hipError_t e = launch_parts(
+        v, [&](const PartLaunch<FftIO<T>>& L) { return c2c_one<T>(L, ct, st); },
+        [&](const Parts<FftIO<T>>& f, int64_t nwg, size_t lds) {
+          const dim3 grid((unsigned)nwg), thr(v[0].threads);
+          const bool c = all_ct(f);
+          if (ct && c) hipLaunchKernelGGL((k_fft_c2c_parts<T, true, true>), grid, thr, lds, st, f);
+          else if (ct) hipLaunchKernelGGL((k_fft_c2c_parts<T, true, false>), grid, thr, lds, st, f);
+          else if (c) hipLaunchKernelGGL((k_fft_c2c_parts<T, false, true>), grid, thr, lds, st, f);
+          else hipLaunchKernelGGL((k_fft_c2c_parts<T, false, false>), grid, thr, lds, st, f);
+          return hipGetLastError();
+        });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_fft_c2c_group(const std::vector<FftCall>& calls, hipStream_t st) {
+  if (calls.empty()) return hipSuccess;
+  return calls[0].p->prec == FSIB_F64 ? c2c_group<double>(calls, st) : c2c_group<float>(calls, st);
 }
 
 // One line of length n per workgroup is the smallest launch of every pass: it must fit the thread
@@ -396,87 +554,114 @@ hipError_t launch_fft_c2c(const Plan& p, const void* in, void* out, int n, int s
                           int nin, int pin, int nout, int pout, const void* fac_in, const void* fac_out, double scale,
                           hipStream_t st, const PassMasks& mk) {
   if (outer <= 0 || inner <= 0) return hipSuccess;
-  return p.prec == FSIB_F64
-             ? c2c_impl<double>(p, in, out, n, sign, inner, outer, nin, pin, nout, pout, fac_in, fac_out, scale, st, mk)
-             : c2c_impl<float>(p, in, out, n, sign, inner, outer, nin, pin, nout, pout, fac_in, fac_out, scale, st, mk);
+  const FftCall c{&p, in, out, n, sign, inner, outer, nin, pin, nout, pout, fac_in, fac_out, scale, mk};
+  return p.prec == FSIB_F64 ? c2c_impl<double>(c, st) : c2c_impl<float>(c, st);
+}
+
+// Contiguous real-data passes along x: c.outer = real rows; r2c keeps c.nout half-spectrum entries
+// (c.fac_out, c.scale), c2r reads c.nin (c.fac_in, c.scale).
+template <typename T>
+static PartLaunch<FftIO<T>> x_launch(const FftCall& c, bool r2c) {
+  const Plan& p = *c.p;
+  PartLaunch<FftIO<T>> L;
+  FftArgs<T>& a = L.a.a;
+  const int n = c.n;
+  a = base_args<T>(p, n, r2c ? -1 : +1, c.mk);
+  a.inner = 1;
+  a.outer = c.outer;
+  if (r2c) {
+    a.nin = n;
+    a.pin = n;
+    a.nout = c.nout;
+    a.pout = c.nout;
+    a.fac_out = (const T*)c.fac_out;
+  } else {
+    a.nin = c.nin;
+    a.pin = c.nin;
+    a.nout = n;
+    a.pout = n;
+    a.fac_in = (const T*)c.fac_in;
+  }
+  a.scale = (T)c.scale;
+  const int64_t pairs = (c.outer + 1) / 2;
+  a.nb = lines_per_block<T>(n, pairs);
+  L.a.in = c.in;
+  L.a.out = c.out;
+  L.threads = n * a.nb / kEPT;
+  L.lds = (size_t)(lpad_len(n * a.nb) + n) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
+  L.nx = c.outer > 0 ? (pairs + a.nb - 1) / a.nb : 0;
+  return L;
+}
+
+template <typename T>
+static hipError_t x_one(const PartLaunch<FftIO<T>>& L, bool r2c, hipStream_t st) {
+  const FftArgs<T>& a = L.a.a;
+  const int n = a.n;
+  const dim3 grid((unsigned)L.nx);
+  if (r2c) {
+    const T* in = (const T*)L.a.in;
+    cplx<T>* out = (cplx<T>*)L.a.out;
+#define FSIB_R2C_CT(N_, NB_) \
+  if (n == N_ && a.nb == NB_) hipLaunchKernelGGL((k_fft_r2c_x<T, N_, NB_>), grid, dim3(L.threads), L.lds, st, in, out, a); else
+    FSIB_FFT_CT_LIST(FSIB_R2C_CT)
+    hipLaunchKernelGGL(k_fft_r2c_x<T>, grid, dim3(L.threads), L.lds, st, in, out, a);
+#undef FSIB_R2C_CT
+  } else {
+    const cplx<T>* in = (const cplx<T>*)L.a.in;
+    T* out = (T*)L.a.out;
+#define FSIB_C2R_CT(N_, NB_) \
+  if (n == N_ && a.nb == NB_) hipLaunchKernelGGL((k_fft_c2r_x<T, N_, NB_>), grid, dim3(L.threads), L.lds, st, in, out, a); else
+    FSIB_FFT_CT_LIST(FSIB_C2R_CT)
+    hipLaunchKernelGGL(k_fft_c2r_x<T>, grid, dim3(L.threads), L.lds, st, in, out, a);
+#undef FSIB_C2R_CT
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t r2c_impl(const Plan& p, const void* in, void* out, int n, int64_t rows, int nout, const void* fout,
                            double scale, hipStream_t st, const PassMasks& mk) {
-  FftArgs<T> a = base_args<T>(p, n, -1, mk);
-  a.inner = 1;
-  a.outer = rows;
-  a.nin = n;
-  a.pin = n;
-  a.nout = nout;
-  a.pout = nout;
-  a.fac_out = (const T*)fout;
-  a.scale = (T)scale;
-  const int64_t pairs = (rows + 1) / 2;
-  a.nb = lines_per_block<T>(n, pairs);
-  const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)(lpad_len(n * a.nb) + n) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
+  const FftCall c{&p, in, out, n, -1, 1, rows, n, n, nout, nout, nullptr, fout, scale, mk};
+  const PartLaunch<FftIO<T>> L = x_launch<T>(c, true);
   const bool prof = prof_on(p, PROF_FFT_X);
   if (prof) prof_start(p, st);
-  const dim3 grid((unsigned)((pairs + a.nb - 1) / a.nb));
-#define FSIB_R2C_CT(N_, NB_)                                                                                   \
-  if (n == N_ && a.nb == NB_)                                                                                 \
-    hipLaunchKernelGGL((k_fft_r2c_x<T, N_, NB_>), grid, dim3(nthr), lds, st, (const T*)in, (cplx<T>*)out, a); \
-  else
-  FSIB_R2C_CT(64, 32)
-  FSIB_R2C_CT(96, 16)
-  FSIB_R2C_CT(128, 16)
-  FSIB_R2C_CT(160, 12)
-  FSIB_R2C_CT(192, 8)
-  FSIB_R2C_CT(256, 8)
-  FSIB_R2C_CT(320, 6)
-  FSIB_R2C_CT(384, 4)
-  FSIB_R2C_CT(512, 4)
-  FSIB_R2C_CT(1024, 2)
-  hipLaunchKernelGGL(k_fft_r2c_x<T>, grid, dim3(nthr), lds, st, (const T*)in, (cplx<T>*)out, a);
-#undef FSIB_R2C_CT
+  const hipError_t e = x_one<T>(L, true, st);
   if (prof) prof_stop(p, (double)rows * (n * sizeof(T) + nout * sizeof(cplx<T>)), st);
-  return hipGetLastError();
+  return e;
 }
 
 template <typename T>
 static hipError_t c2r_impl(const Plan& p, const void* in, void* out, int n, int64_t rows, int nin, const void* fin,
                            double scale, hipStream_t st, const PassMasks& mk) {
-  FftArgs<T> a = base_args<T>(p, n, +1, mk);
-  a.inner = 1;
-  a.outer = rows;
-  a.nin = nin;
-  a.pin = nin;
-  a.nout = n;
-  a.pout = n;
-  a.fac_in = (const T*)fin;
-  a.scale = (T)scale;
-  const int64_t pairs = (rows + 1) / 2;
-  a.nb = lines_per_block<T>(n, pairs);
-  const int nthr = n * a.nb / kEPT;
-  const size_t lds = (size_t)(lpad_len(n * a.nb) + n) * sizeof(cplx<T>) + flag_bytes(2 * a.nb);
+  const FftCall c{&p, in, out, n, +1, 1, rows, nin, nin, n, n, fin, nullptr, scale, mk};
+  const PartLaunch<FftIO<T>> L = x_launch<T>(c, false);
   const bool prof = prof_on(p, PROF_FFT_X);
   if (prof) prof_start(p, st);
-  const dim3 grid((unsigned)((pairs + a.nb - 1) / a.nb));
-#define FSIB_C2R_CT(N_, NB_)                                                                                   \
-  if (n == N_ && a.nb == NB_)                                                                                 \
-    hipLaunchKernelGGL((k_fft_c2r_x<T, N_, NB_>), grid, dim3(nthr), lds, st, (const cplx<T>*)in, (T*)out, a); \
-  else
-  FSIB_C2R_CT(64, 32)
-  FSIB_C2R_CT(96, 16)
-  FSIB_C2R_CT(128, 16)
-  FSIB_C2R_CT(160, 12)
-  FSIB_C2R_CT(192, 8)
-  FSIB_C2R_CT(256, 8)
-  FSIB_C2R_CT(320, 6)
-  FSIB_C2R_CT(384, 4)
-  FSIB_C2R_CT(512, 4)
-  FSIB_C2R_CT(1024, 2)
-  hipLaunchKernelGGL(k_fft_c2r_x<T>, grid, dim3(nthr), lds, st, (const cplx<T>*)in, (T*)out, a);
-#undef FSIB_C2R_CT
+  const hipError_t e = x_one<T>(L, false, st);
   if (prof) prof_stop(p, (double)rows * (nin * sizeof(cplx<T>) + n * sizeof(T)), st);
-  return hipGetLastError();
+  return e;
+}
+
+template <typename T>
+static hipError_t x_group(const std::vector<FftCall>& calls, bool r2c, hipStream_t st) {
+  std::vector<PartLaunch<FftIO<T>>> v;
+  for (const FftCall& c : calls) v.push_back(x_launch<T>(c, r2c));
+  return launch_parts(
+      v, [&](const PartLaunch<FftIO<T>>& L) { return x_one<T>(L, r2c, st); },
+      [&](const Parts<FftIO<T>>& f, int64_t nwg, size_t lds) {
+        const dim3 grid((unsigned)nwg), thr(v[0].threads);
+        const bool c = all_ct(f);
+        if (r2c && c) hipLaunchKernelGGL((k_fft_r2c_x_parts<T, true>), grid, thr, lds, st, f);
+        else if (r2c) hipLaunchKernelGGL((k_fft_r2c_x_parts<T, false>), grid, thr, lds, st, f);
+        else if (c) hipLaunchKernelGGL((k_fft_c2r_x_parts<T, true>), grid, thr, lds, st, f);
+        else hipLaunchKernelGGL((k_fft_c2r_x_parts<T, false>), grid, thr, lds, st, f);
+        return hipGetLastError();
+      });
+}
+
+hipError_t launch_fft_x_group(const std::vector<FftCall>& calls, bool r2c, hipStream_t st) {
+  if (calls.empty()) return hipSuccess;
+  return calls[0].p->prec == FSIB_F64 ? x_group<double>(calls, r2c, st) : x_group<float>(calls, r2c, st);
 }
 
 hipError_t launch_fft_r2c_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nout,

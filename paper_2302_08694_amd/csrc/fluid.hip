@@ -36,14 +36,31 @@ __device__ __forceinline__ int sym_index(int a, int b, int dim) {
   return a == 0 ? b : 2;
 }
 
+template <typename T>
+struct FluidArgs {
+  ModeGeo g;
+  int mode;
+  T rho, mu, dt, b0, b1, b2;
+  const cplx<T>* fhat;
+  const cplx<T>* pihat;
+  const cplx<T>* uin;
+  cplx<T>* uout;
+};
+
 template <typename T, int DIM>
-__global__ void k_fluid(ModeGeo g, int mode, T rho, T mu, T dt, T b0, T b1, T b2, const cplx<T>* __restrict__ fhat,
-                        const cplx<T>* __restrict__ pihat, const cplx<T>* uin, cplx<T>* uout) {
+__device__ __forceinline__ void fluid_body(const FluidArgs<T>& A, Blk wb) {
+  const ModeGeo& g = A.g;
+  const int mode = A.mode;
+  const T rho = A.rho, mu = A.mu, dt = A.dt, b0 = A.b0, b1 = A.b1, b2 = A.b2;
+  const cplx<T>* __restrict__ fhat = A.fhat;
+  const cplx<T>* __restrict__ pihat = A.pihat;
+  const cplx<T>* uin = A.uin;
+  cplx<T>* uout = A.uout;
   const int64_t nm = g.Hx * g.N[1] * (DIM == 3 ? g.N[2] : 1);
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = wb.x * blockDim.x + threadIdx.x;
   if (idx >= nm) return;
-  // instance blockIdx.y of a multi-instance (Stokes) plan: its dim half spectra follow the previous ones
-  const int64_t ib = (int64_t)blockIdx.y * DIM * nm;
+  // instance wb.y of a multi-instance (Stokes) plan: its dim half spectra follow the previous ones
+  const int64_t ib = wb.y * DIM * nm;
   fhat += ib;
   uout += ib;
   if (uin) uin += ib;
@@ -106,42 +123,74 @@ __global__ void k_fluid(ModeGeo g, int mode, T rho, T mu, T dt, T b0, T b1, T b2
   }
 }
 
-hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
-                               const void* uin, void* uout, hipStream_t st) {
+template <typename T, int DIM>
+__global__ void k_fluid(FluidArgs<T> a) { fluid_body<T, DIM>(a, launch_blk()); }
+template <typename T, int DIM>
+__global__ void k_fluid_parts(Parts<FluidArgs<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) fluid_body<T, DIM>(f.a[g], b);
+}
+
+static ModeGeo mode_geo(const Plan& p) {
   ModeGeo g;
   g.dim = p.dim;
   for (int a = 0; a < 3; ++a) g.N[a] = p.N[a];
   g.Hx = p.Hx;
   g.L = p.L;
-  const int64_t nm = p.modes_half();
-  const unsigned nblk = (unsigned)((nm + 255) / 256);
-  const dim3 grid(nblk, (unsigned)p.ninst);  // one row of blocks per instance
-  if (p.prec == FSIB_F64) {
-    using T = double;
-    if (p.dim == 3)
-      hipLaunchKernelGGL((k_fluid<T, 3>), grid, dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
-                         (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
-                         (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
-    else
-      hipLaunchKernelGGL((k_fluid<T, 2>), grid, dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
-                         (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
-                         (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
-  } else {
-    using T = float;
-    if (p.dim == 3)
-      hipLaunchKernelGGL((k_fluid<T, 3>), grid, dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
-                         (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
-                         (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
-    else
-      hipLaunchKernelGGL((k_fluid<T, 2>), grid, dim3(256), 0, st, g, mode, (T)prm.rho, (T)prm.mu, (T)prm.dt,
-                         (T)prm.body[0], (T)prm.body[1], (T)prm.body[2], (const cplx<T>*)fhat,
-                         (const cplx<T>*)p.pihat, (const cplx<T>*)uin, (cplx<T>*)uout);
-  }
+  return g;
+}
+
+template <typename T>
+static PartLaunch<FluidArgs<T>> fluid_launch(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
+                                             const void* uin, void* uout) {
+  PartLaunch<FluidArgs<T>> L;
+  L.a = FluidArgs<T>{mode_geo(p), mode, (T)prm.rho, (T)prm.mu, (T)prm.dt, (T)prm.body[0], (T)prm.body[1],
+                     (T)prm.body[2], (const cplx<T>*)fhat, (const cplx<T>*)p.pihat, (const cplx<T>*)uin,
+                     (cplx<T>*)uout};
+  L.nx = (p.modes_half() + 255) / 256;
+  L.ny = p.ninst;  // one row of blocks per instance
+  return L;
+}
+
+template <typename T, int DIM>
+static hipError_t fluid_one(const PartLaunch<FluidArgs<T>>& L, hipStream_t st) {
+  hipLaunchKernelGGL((k_fluid<T, DIM>), dim3((unsigned)L.nx, (unsigned)L.ny), dim3(256), 0, st, L.a);
   return hipGetLastError();
 }
 
-// Pressure (eq. pressure_poisson_k; Stokes: eq. stokeslet): phat = -i k.(fhat - rho shat)/|k|^2 with
-// shat_a = sum_b i k_b (u_a u_b)^ (ns = 1, products in pihat) or shat = 0 (ns = 0); phat(0) = 0.
+hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
+                               const void* uin, void* uout, hipStream_t st) {
+  if (p.prec == FSIB_F64) {
+    const auto L = fluid_launch<double>(p, mode, prm, fhat, uin, uout);
+    return p.dim == 3 ? fluid_one<double, 3>(L, st) : fluid_one<double, 2>(L, st);
+  }
+  const auto L = fluid_launch<float>(p, mode, prm, fhat, uin, uout);
+  return p.dim == 3 ? fluid_one<float, 3>(L, st) : fluid_one<float, 2>(L, st);
+}
+
+template <typename T, int DIM>
+static hipError_t fluid_stokes_group(const std::vector<Plan*>& ps, const fsib_fluid_params* prm, void* const* uhat,
+                                     hipStream_t st) {
+  std::vector<PartLaunch<FluidArgs<T>>> v(ps.size());
+  for (size_t g = 0; g < ps.size(); ++g) v[g] = fluid_launch<T>(*ps[g], FLUID_STOKES, prm[g], ps[g]->fhat, nullptr, uhat[g]);
+  return launch_parts(
+      v, [&](const PartLaunch<FluidArgs<T>>& L) { return fluid_one<T, DIM>(L, st); },
+      [&](const Parts<FluidArgs<T>>& f, int64_t nwg, size_t) {
+        hipLaunchKernelGGL((k_fluid_parts<T, DIM>), dim3((unsigned)nwg), dim3(256), 0, st, f);
+        return hipGetLastError();
+      });
+}
+
+// The Stokes update of every plan of a group (uhat[g] from plan g's fhat with prm[g]), one launch.
+hipError_t launch_fluid_stokes_group(const std::vector<Plan*>& ps, const fsib_fluid_params* prm, void* const* uhat,
+                                     hipStream_t st) {
+  const bool f64 = ps[0]->prec == FSIB_F64;
+  if (ps[0]->dim == 3)
+    return f64 ? fluid_stokes_group<double, 3>(ps, prm, uhat, st) : fluid_stokes_group<float, 3>(ps, prm, uhat, st);
+  return f64 ? fluid_stokes_group<double, 2>(ps, prm, uhat, st) : fluid_stokes_group<float, 2>(ps, prm, uhat, st);
+}
+
 template <typename T, int DIM>
 __global__ void k_pressure(ModeGeo g, int ns, T rho, const cplx<T>* __restrict__ fhat,
                            const cplx<T>* __restrict__ pihat, cplx<T>* __restrict__ phat) {
@@ -388,6 +437,54 @@ __global__ void k_strengths_inst(int64_t M, int dim, const double* __restrict__ 
   for (int a = 0; a < dim; ++a) S[j * dim + a] = (T)(w * F[j * dim + a]);
 }
 
+// Closed-curve force and its weighted strengths in one pass, for a launch over the plans of a group:
+// point j of instance [s, e) (the plan's instance offsets, or the whole range on a one-instance plan)
+// gets F_j = K (X_{j+1} + X_{j-1} - 2 X_j) / dtheta^2 with dtheta = 2 pi / (e - s), and S_j = (2 pi / (e - s)) F_j
+// in the plan precision -- the values k_force_curve(_inst) and k_strengths(_inst) give.
+template <typename T>
+struct CurveArgs {
+  int64_t M;
+  const double* X;
+  double K;
+  const int64_t* off;  // ninst + 1 offsets, or nullptr: one curve
+  int ninst;
+  double* F;
+  T* S;
+};
+template <typename T>
+__device__ __forceinline__ void curve_force_strengths(const CurveArgs<T>& A, Blk wb) {
+  const int64_t j = wb.x * blockDim.x + threadIdx.x;
+  if (j >= A.M) return;
+  int64_t s = 0, e = A.M;
+  if (A.off) {
+    int lo = 0, hi = A.ninst;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (A.off[mid] <= j) lo = mid;
+      else hi = mid;
+    }
+    s = A.off[lo];
+    e = A.off[lo + 1];
+  }
+  const int64_t jp = j + 1 == e ? s : j + 1, jm = j == s ? e - 1 : j - 1;
+  const double dth = 6.283185307179586476925286766559 / (double)(e - s);
+  const double c = A.K / (dth * dth);
+  const double w = 6.283185307179586476925286766559 / (double)(e - s);
+  for (int a = 0; a < 2; ++a) {
+    const double F = c * (A.X[jp * 2 + a] + A.X[jm * 2 + a] - 2.0 * A.X[j * 2 + a]);
+    A.F[j * 2 + a] = F;
+    A.S[j * 2 + a] = (T)(w * F);
+  }
+}
+template <typename T>
+__global__ void k_curve_force_strengths(CurveArgs<T> a) { curve_force_strengths<T>(a, launch_blk()); }
+template <typename T>
+__global__ void k_curve_force_strengths_parts(Parts<CurveArgs<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) curve_force_strengths<T>(f.a[g], b);
+}
+
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F, hipStream_t st) {
   if (M <= 0) return hipSuccess;
   const unsigned nblk = (unsigned)((M + 255) / 256);
@@ -504,6 +601,44 @@ hipError_t launch_force_plan(const Plan& p, const fsib_force& f, int64_t M, cons
     return hipGetLastError();
   }
   return launch_force(f, p.dim, M, X, F, st);  // the other laws index their mesh globally
+}
+
+template <typename T>
+static hipError_t curve_group(const std::vector<Plan*>& ps, const fsib_force* f, const int64_t* M,
+                              const double* const* X, hipStream_t st) {
+  std::vector<PartLaunch<CurveArgs<T>>> v(ps.size());
+  for (size_t g = 0; g < ps.size(); ++g) {
+    const Plan& p = *ps[g];
+    v[g].a = CurveArgs<T>{M[g], X[g], f[g].K, p.ninst > 1 ? (const int64_t*)p.inst_off : nullptr, p.ninst, p.F64,
+                          (T*)p.S};
+    v[g].nx = (M[g] + 255) / 256;
+  }
+  return launch_parts(
+      v,
+      [&](const PartLaunch<CurveArgs<T>>& L) {
+        hipLaunchKernelGGL(k_curve_force_strengths<T>, dim3((unsigned)L.nx), dim3(256), 0, st, L.a);
+        return hipGetLastError();
+      },
+      [&](const Parts<CurveArgs<T>>& fp, int64_t nwg, size_t) {
+        hipLaunchKernelGGL(k_curve_force_strengths_parts<T>, dim3((unsigned)nwg), dim3(256), 0, st, fp);
+        return hipGetLastError();
+      });
+}
+
+// Force (into each plan's F64) and weighted strengths (into its S) for the plans of a group: one launch
+// when every plan has the closed-curve law, else the plans' own launches.
+hipError_t launch_force_strengths_group(const std::vector<Plan*>& ps, const fsib_force* f, const int64_t* M,
+                                        const double* const* X, hipStream_t st) {
+  bool curves = true;
+  for (size_t g = 0; g < ps.size(); ++g) curves = curves && f[g].kind == FSIB_FORCE_CURVE_TENSION && ps[g]->dim == 2;
+  if (curves)
+    return ps[0]->prec == FSIB_F64 ? curve_group<double>(ps, f, M, X, st) : curve_group<float>(ps, f, M, X, st);
+  for (size_t g = 0; g < ps.size(); ++g) {
+    hipError_t e = launch_force_plan(*ps[g], f[g], M[g], X[g], ps[g]->F64, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_weighted_strengths(*ps[g], f[g].kind, M[g], ps[g]->F64, ps[g]->S, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S, hipStream_t st) {

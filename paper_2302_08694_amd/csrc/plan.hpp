@@ -118,6 +118,51 @@ struct Plan {
   size_t real_size() const { return prec == FSIB_F64 ? 8 : 4; }
 };
 
+// ---- launches over the plans of a group ----
+// One part of such a launch: the arguments, grid, workgroup size and dynamic LDS its kernel would
+// get in a launch of its own.
+template <class A>
+struct PartLaunch {
+  A a;
+  int64_t nx = 0, ny = 1;
+  int threads = 256;
+  size_t lds = 0;
+};
+
+// One launch for all parts when there are several that share a workgroup size (`fused(parts,
+// workgroups, lds)`), else a launch per part (`one(part)`); parts with an empty grid are left out.
+template <class A, class One, class Fused>
+hipError_t launch_parts(const std::vector<PartLaunch<A>>& v, One one, Fused fused) {
+  static_assert(sizeof(Parts<A>) <= 4096, "kernel arguments of a launch over parts");
+  std::vector<const PartLaunch<A>*> live;
+  for (const auto& q : v)
+    if (q.nx * q.ny > 0) live.push_back(&q);
+  if (live.empty()) return hipSuccess;
+  bool same = live.size() <= (size_t)kMaxParts;
+  for (const auto* q : live) same = same && q->threads == live[0]->threads;
+  if (live.size() == 1 || !same) {
+    for (const auto* q : live) {
+      const hipError_t e = one(*q);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  Parts<A> f;
+  f.n = (int)live.size();
+  int64_t s = 0;
+  size_t lds = 0;
+  for (int g = 0; g < f.n; ++g) {
+    f.a[g] = live[g]->a;
+    f.nx[g] = live[g]->nx;
+    f.ny[g] = live[g]->ny;
+    f.start[g] = s;
+    s += (live[g]->nx * live[g]->ny + kXcds - 1) / kXcds * kXcds;
+    lds = lds > live[g]->lds ? lds : live[g]->lds;
+  }
+  for (int g = f.n; g <= kMaxParts; ++g) f.start[g] = s;
+  return fused(f, s, lds);
+}
+
 // ---- launchers (all asynchronous on `st`) ----
 // points.hip
 hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st);
@@ -132,6 +177,39 @@ hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum,
                        hipStream_t st);  // exclusive, n+1 outputs; seg_sum: scan_segments(n) ints
 int64_t scan_segments(int64_t n);
 hipError_t launch_row_masks(Plan& p, hipStream_t st);  // from the sorted bins
+// the same stages for the plans of a group, each one launch over all plans where their workgroup
+// sizes agree (plan g: M[g] points, its operands at index g)
+hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t* M, const double* const* X,
+                                    hipStream_t st);
+hipError_t launch_axpy_positions_group(const std::vector<Plan*>& ps, const int64_t* M, double* const* Y,
+                                       const double* const* X, const void* const* U, const double* a,
+                                       hipStream_t st);
+hipError_t launch_fill_zero_group(const std::vector<void*>& ptr, const std::vector<int64_t>& bytes, hipStream_t st);
+hipError_t launch_scan_group(const std::vector<int64_t>& n, const std::vector<const int*>& counts,
+                             const std::vector<int*>& offsets, const std::vector<int*>& seg_sum, hipStream_t st);
+hipError_t launch_spread_group(const std::vector<Plan*>& ps, const int64_t* M, const void* const* str,
+                               hipStream_t st);  // real strengths with dim components
+hipError_t launch_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st);
+hipError_t launch_force_strengths_group(const std::vector<Plan*>& ps, const fsib_force* f, const int64_t* M,
+                                        const double* const* X, hipStream_t st);  // into each plan's F64, S
+hipError_t launch_fluid_stokes_group(const std::vector<Plan*>& ps, const fsib_fluid_params* prm,
+                                     void* const* uhat, hipStream_t st);  // from each plan's fhat
+// FFT passes of several plans: the operands of one launch_fft_c2c call (x passes: outer = real rows,
+// r2c keeps nout entries with fac_out, c2r reads nin with fac_in)
+struct FftCall {
+  const Plan* p;
+  const void* in;
+  void* out;
+  int n, sign;
+  int64_t inner, outer;
+  int nin, pin, nout, pout;
+  const void* fac_in;
+  const void* fac_out;
+  double scale;
+  PassMasks mk;
+};
+hipError_t launch_fft_c2c_group(const std::vector<FftCall>& calls, hipStream_t st);
+hipError_t launch_fft_x_group(const std::vector<FftCall>& calls, bool r2c, hipStream_t st);
 // spread_interp.hip
 hipError_t launch_spread(Plan& p, int64_t M, const void* strengths, int real_comps, hipStream_t st);
 hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st);

@@ -61,9 +61,23 @@ __device__ __forceinline__ void locate(double x, double L, int64_t nf, int w, in
 // bin, so the lanes of a wavefront form runs of equal bins and the first lane of each run claims
 // the whole run with one atomic add.  (The order of the runs inside a bin follows the order of the
 // atomics.)  Needs blockDim.x a multiple of 64.
-__global__ void k_bin_count(int64_t M, const double* __restrict__ X, Geo g, int* __restrict__ counts,
-                            int* __restrict__ pt_bin, int* __restrict__ pt_rank, int* __restrict__ flag) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+struct BinCountArgs {
+  int64_t M;
+  const double* X;
+  Geo g;
+  int* counts;
+  int* pt_bin;
+  int* pt_rank;
+  int* flag;
+};
+
+__device__ __forceinline__ void bin_count(const BinCountArgs& A, Blk blk) {
+  const int64_t M = A.M;
+  const double* __restrict__ X = A.X;
+  const Geo& g = A.g;
+  int* __restrict__ counts = A.counts;
+  int* __restrict__ flag = A.flag;
+  const int64_t j = blk.x * blockDim.x + threadIdx.x;
   const bool valid = j < M;
   int bin = -1;
   if (valid) {
@@ -92,9 +106,16 @@ __global__ void k_bin_count(int64_t M, const double* __restrict__ X, Geo g, int*
   if (valid && head) base = atomicAdd(&counts[bin], end - lane);
   base = __shfl(base, h, 64);
   if (valid) {
-    pt_bin[j] = bin;
-    pt_rank[j] = base + (lane - h);
+    A.pt_bin[j] = bin;
+    A.pt_rank[j] = base + (lane - h);
   }
+}
+
+__global__ void k_bin_count(BinCountArgs a) { bin_count(a, launch_blk()); }
+__global__ void k_bin_count_parts(Parts<BinCountArgs> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) bin_count(f.a[g], b);
 }
 
 // Exclusive scan of counts[0..n) into offsets[0..n] (offsets[n] = total).  Segments of
@@ -137,12 +158,22 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total
   return wsum[wv] + inc - v;
 }
 
+struct ScanArgs {
+  int64_t n;
+  const int* counts;
+  int* offsets;
+  int* seg_sum;
+};
+
 template <bool FINAL>
-__global__ __launch_bounds__(kScanThreads) void k_scan(int64_t n, const int* __restrict__ counts,
-                                                       int* __restrict__ offsets, int* __restrict__ seg_sum) {
+__device__ __forceinline__ void scan_body(const ScanArgs& A, Blk blk) {
   __shared__ int wsum[65];
   __shared__ int seg_base;
-  const int64_t first = (int64_t)blockIdx.x * kScanSeg + (int64_t)threadIdx.x * kScanEpt;
+  const int64_t n = A.n;
+  const int* __restrict__ counts = A.counts;
+  int* __restrict__ offsets = A.offsets;
+  int* __restrict__ seg_sum = A.seg_sum;
+  const int64_t first = blk.x * kScanSeg + (int64_t)threadIdx.x * kScanEpt;
   int v[kScanEpt];
   int run = 0;
 #pragma unroll
@@ -152,7 +183,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int64_t n, const int* __r
   }
   int before = 0;  // this thread's share of the sums of the segments before this one
   if (FINAL)
-    for (unsigned s = threadIdx.x; s < blockIdx.x; s += kScanThreads) before += seg_sum[s];
+    for (int64_t s = threadIdx.x; s < blk.x; s += kScanThreads) before += seg_sum[s];
   int total;
   int excl = block_exclusive_scan(run, wsum, &total);
   if (FINAL) {
@@ -163,7 +194,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int64_t n, const int* __r
     __syncthreads();
   }
   if (!FINAL) {
-    if (threadIdx.x == 0) seg_sum[blockIdx.x] = total;
+    if (threadIdx.x == 0) seg_sum[blk.x] = total;
     return;
   }
   excl += seg_base;
@@ -174,13 +205,38 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int64_t n, const int* __r
   }
 }
 
+template <bool FINAL>
+__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
+  scan_body<FINAL>(a, launch_blk());
+}
+template <bool FINAL>
+__global__ __launch_bounds__(kScanThreads) void k_scan_parts(Parts<ScanArgs> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) scan_body<FINAL>(f.a[g], b);
+}
+
 template <typename T>
-__global__ void k_bin_scatter(int64_t M, const double* __restrict__ X, Geo g, const int* __restrict__ offsets,
-                              const int* __restrict__ pt_bin, const int* __restrict__ pt_rank,
-                              int* __restrict__ s_idx, uint32_t* __restrict__ s_i0, T* __restrict__ s_y) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= M) return;
-  const int64_t pos = (int64_t)offsets[pt_bin[j]] + pt_rank[j];
+struct ScatterArgs {
+  int64_t M;
+  const double* X;
+  Geo g;
+  const int* offsets;
+  const int* pt_bin;
+  const int* pt_rank;
+  int* s_idx;
+  uint32_t* s_i0;
+  T* s_y;
+};
+
+template <typename T>
+__device__ __forceinline__ void bin_scatter(const ScatterArgs<T>& A, Blk blk) {
+  const Geo& g = A.g;
+  const double* __restrict__ X = A.X;
+  T* __restrict__ s_y = A.s_y;
+  const int64_t j = blk.x * blockDim.x + threadIdx.x;
+  if (j >= A.M) return;
+  const int64_t pos = (int64_t)A.offsets[A.pt_bin[j]] + A.pt_rank[j];
   bool bad = false;
   uint32_t packed = 0;
   const int bits = g.dim == 3 ? 10 : 16;
@@ -191,8 +247,17 @@ __global__ void k_bin_scatter(int64_t M, const double* __restrict__ X, Geo g, co
     packed |= (uint32_t)i0 << (bits * a);
     s_y[pos * g.dim + a] = (T)y;
   }
-  s_idx[pos] = (int)j;
-  s_i0[pos] = packed;
+  A.s_idx[pos] = (int)j;
+  A.s_i0[pos] = packed;
+}
+
+template <typename T>
+__global__ void k_bin_scatter(ScatterArgs<T> a) { bin_scatter<T>(a, launch_blk()); }
+template <typename T>
+__global__ void k_bin_scatter_parts(Parts<ScatterArgs<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) bin_scatter<T>(f.a[g], b);
 }
 
 // Deterministic placement (plans created with deterministic = 1).  The run claims of k_bin_count give
@@ -256,16 +321,47 @@ __global__ __launch_bounds__(kRankThreads) void k_bin_rank(const int* __restrict
   for (int i = threadIdx.x; i < n; i += kRankThreads) pt_rank[sk[i]] = i;
 }
 
-__global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+struct FillArgs {
+  uint32_t* p;
+  int64_t n;
+};
+__device__ __forceinline__ void fill_zero(const FillArgs& A, Blk blk) {
+  const int64_t i = blk.x * blockDim.x + threadIdx.x;
+  if (i < A.n) A.p[i] = 0u;
+}
+__global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) { fill_zero(FillArgs{p, n}, launch_blk()); }
+__global__ void k_fill_zero_parts_one(FillArgs a) { fill_zero(a, launch_blk()); }
+__global__ void k_fill_zero_parts(Parts<FillArgs> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) fill_zero(f.a[g], b);
 }
 
 template <typename T>
+struct AxpyArgs {
+  int64_t n;
+  double* Y;
+  const double* X;
+  const T* U;
+  double a;
+};
+template <typename T>
+__device__ __forceinline__ void axpy_pos(const AxpyArgs<T>& A, Blk blk) {
+  const int64_t i = blk.x * blockDim.x + threadIdx.x;
+  if (i < A.n) A.Y[i] = A.X[i] + A.a * (double)A.U[i];
+}
+template <typename T>
 __global__ void k_axpy_pos(int64_t n, double* __restrict__ Y, const double* __restrict__ X, const T* __restrict__ U,
                            double a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) Y[i] = X[i] + a * (double)U[i];
+  axpy_pos<T>(AxpyArgs<T>{n, Y, X, U, a}, launch_blk());
+}
+template <typename T>
+__global__ void k_axpy_pos_one(AxpyArgs<T> a) { axpy_pos<T>(a, launch_blk()); }
+template <typename T>
+__global__ void k_axpy_pos_parts(Parts<AxpyArgs<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) axpy_pos<T>(f.a[g], b);
 }
 
 static Geo make_geo(const Plan& p) {
@@ -295,9 +391,15 @@ hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st) {
 // bz in [zb-qz, zb]) has a kernel support reaching it.
 // rowmask[i * nt1 * nt2 + zb * nt1 + yb] for the blocks of instance i < ninst (bins of instance i
 // follow those of instance i - 1)
-__global__ void k_row_masks(int nt0, int nt1, int nt2, int qy, int qz, int ninst, const int* __restrict__ counts,
-                            uint8_t* __restrict__ rowmask) {
-  const int tg = blockIdx.x * blockDim.x + threadIdx.x;
+struct RowMaskArgs {
+  int nt0, nt1, nt2, qy, qz, ninst;
+  const int* counts;
+  uint8_t* rowmask;
+};
+__device__ __forceinline__ void row_masks(const RowMaskArgs& A, Blk blk) {
+  const int nt0 = A.nt0, nt1 = A.nt1, nt2 = A.nt2, qy = A.qy, qz = A.qz, ninst = A.ninst;
+  const int* __restrict__ counts = A.counts;
+  const int tg = (int)(blk.x * blockDim.x + threadIdx.x);
   if (tg >= nt1 * nt2 * ninst) return;
   const int inst = tg / (nt1 * nt2), t = tg - inst * nt1 * nt2;
   const int yb = t % nt1, zb = t / nt1;
@@ -309,26 +411,57 @@ __global__ void k_row_masks(int nt0, int nt1, int nt2, int qy, int qz, int ninst
       const int* c = ci + (int64_t)(bz * nt1 + by) * nt0;
       for (int bx = 0; bx < nt0; ++bx) any |= c[bx];
     }
-  rowmask[tg] = any ? 1 : 0;
+  A.rowmask[tg] = any ? 1 : 0;
+}
+__global__ void k_row_masks(RowMaskArgs a) { row_masks(a, launch_blk()); }
+__global__ void k_row_masks_parts(Parts<RowMaskArgs> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) row_masks(f.a[g], b);
 }
 
-__global__ void k_plane_masks(int nt1, int nt2, const uint8_t* __restrict__ rowmask, uint8_t* __restrict__ zmask) {
-  const int zb = blockIdx.x * blockDim.x + threadIdx.x;
-  if (zb >= nt2) return;
+struct PlaneMaskArgs {
+  int nt1, nt2;
+  const uint8_t* rowmask;
+  uint8_t* zmask;
+};
+__device__ __forceinline__ void plane_masks(const PlaneMaskArgs& A, Blk blk) {
+  const int zb = (int)(blk.x * blockDim.x + threadIdx.x);
+  if (zb >= A.nt2) return;
   uint8_t any = 0;
-  for (int yb = 0; yb < nt1; ++yb) any |= rowmask[zb * nt1 + yb];
-  zmask[zb] = any;
+  for (int yb = 0; yb < A.nt1; ++yb) any |= A.rowmask[zb * A.nt1 + yb];
+  A.zmask[zb] = any;
+}
+__global__ void k_plane_masks(PlaneMaskArgs a) { plane_masks(a, launch_blk()); }
+__global__ void k_plane_masks_parts(Parts<PlaneMaskArgs> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) plane_masks(f.a[g], b);
+}
+
+static PartLaunch<RowMaskArgs> row_mask_launch(const Plan& p) {
+  const int ni = p.dim == 2 ? p.ninst : 1;  // 3D multi-instance plans keep no masks
+  const int nrb = (int)(p.nt[1] * p.nt[2]) * ni;
+  PartLaunch<RowMaskArgs> L;
+  L.a = RowMaskArgs{(int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[1], (int)p.qn[2], ni, (const int*)p.counts,
+                    p.rowmask};
+  L.nx = (nrb + 255) / 256;
+  return L;
+}
+static PartLaunch<PlaneMaskArgs> plane_mask_launch(const Plan& p) {
+  PartLaunch<PlaneMaskArgs> L;
+  L.a = PlaneMaskArgs{(int)p.nt[1], (int)p.nt[2], (const uint8_t*)p.rowmask, p.zmask};
+  L.nx = (p.nt[2] + 255) / 256;
+  return L;
 }
 
 hipError_t launch_row_masks(Plan& p, hipStream_t st) {
-  const int ni = p.dim == 2 ? p.ninst : 1;  // 3D multi-instance plans keep no masks
-  const int nrb = (int)(p.nt[1] * p.nt[2]) * ni;
-  hipLaunchKernelGGL(k_row_masks, dim3((nrb + 255) / 256), dim3(256), 0, st, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2],
-                     (int)p.qn[1], (int)p.qn[2], ni, (const int*)p.counts, p.rowmask);
+  const PartLaunch<RowMaskArgs> r = row_mask_launch(p);
+  hipLaunchKernelGGL(k_row_masks, dim3((unsigned)r.nx), dim3(256), 0, st, r.a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_plane_masks, dim3((unsigned)((p.nt[2] + 255) / 256)), dim3(256), 0, st, (int)p.nt[1],
-                     (int)p.nt[2], (const uint8_t*)p.rowmask, p.zmask);
+  const PartLaunch<PlaneMaskArgs> z = plane_mask_launch(p);
+  hipLaunchKernelGGL(k_plane_masks, dim3((unsigned)z.nx), dim3(256), 0, st, z.a);
   return hipGetLastError();
 }
 
@@ -336,13 +469,55 @@ int64_t scan_segments(int64_t n) { return n / kScanSeg + 1; }
 
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum, hipStream_t st) {
   const int64_t nseg = scan_segments(n);
+  const ScanArgs a{n, counts, offsets, seg_sum};
   if (nseg > 1) {
-    hipLaunchKernelGGL(k_scan<false>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, n, counts, offsets, seg_sum);
+    hipLaunchKernelGGL(k_scan<false>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_scan<true>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, n, counts, offsets, seg_sum);
+  hipLaunchKernelGGL(k_scan<true>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, a);
   return hipGetLastError();
+}
+
+// The scans of several plans' arrays (scans[g] = {n, counts, offsets, seg_sum}), one launch per pass.
+static hipError_t launch_scan_parts(const std::vector<ScanArgs>& scans, hipStream_t st) {
+  std::vector<PartLaunch<ScanArgs>> first, fin;
+  for (const ScanArgs& a : scans) {
+    const int64_t nseg = scan_segments(a.n);
+    PartLaunch<ScanArgs> L;
+    L.a = a;
+    L.nx = nseg;
+    L.threads = kScanThreads;
+    fin.push_back(L);
+    if (nseg > 1) first.push_back(L);
+  }
+  auto one = [&](bool final_pass) {
+    return [=](const PartLaunch<ScanArgs>& L) {
+      if (final_pass)
+        hipLaunchKernelGGL(k_scan<true>, dim3((unsigned)L.nx), dim3(kScanThreads), 0, st, L.a);
+      else
+        hipLaunchKernelGGL(k_scan<false>, dim3((unsigned)L.nx), dim3(kScanThreads), 0, st, L.a);
+      return hipGetLastError();
+    };
+  };
+  auto fused = [&](bool final_pass) {
+    return [=](const Parts<ScanArgs>& f, int64_t nwg, size_t) {
+      if (final_pass)
+        hipLaunchKernelGGL(k_scan_parts<true>, dim3((unsigned)nwg), dim3(kScanThreads), 0, st, f);
+      else
+        hipLaunchKernelGGL(k_scan_parts<false>, dim3((unsigned)nwg), dim3(kScanThreads), 0, st, f);
+      return hipGetLastError();
+    };
+  };
+  hipError_t e = launch_parts(first, one(false), fused(false));
+  if (e != hipSuccess) return e;
+  return launch_parts(fin, one(true), fused(true));
+}
+
+template <typename T>
+static ScatterArgs<T> scatter_args(const Plan& p, int64_t M, const double* X) {
+  return ScatterArgs<T>{M, X, make_geo(p), (const int*)p.offsets, (const int*)p.pt_bin, (const int*)p.pt_rank,
+                        p.s_idx, p.s_i0, (T*)p.s_y};
 }
 
 hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st) {
@@ -351,7 +526,8 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
   if (e != hipSuccess) return e;
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
-    hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st, M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag);
+    hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st,
+                       BinCountArgs{M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag});
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st)) != hipSuccess) return e;
@@ -369,14 +545,83 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     if (p.prec == FSIB_F64)
-      hipLaunchKernelGGL(k_bin_scatter<double>, dim3(nblk), dim3(256), 0, st, M, X, g, (const int*)p.offsets,
-                         (const int*)p.pt_bin, (const int*)p.pt_rank, p.s_idx, p.s_i0, (double*)p.s_y);
+      hipLaunchKernelGGL(k_bin_scatter<double>, dim3(nblk), dim3(256), 0, st, scatter_args<double>(p, M, X));
     else
-      hipLaunchKernelGGL(k_bin_scatter<float>, dim3(nblk), dim3(256), 0, st, M, X, g, (const int*)p.offsets,
-                         (const int*)p.pt_bin, (const int*)p.pt_rank, p.s_idx, p.s_i0, (float*)p.s_y);
+      hipLaunchKernelGGL(k_bin_scatter<float>, dim3(nblk), dim3(256), 0, st, scatter_args<float>(p, M, X));
     e = hipGetLastError();
   }
   return e;
+}
+
+// Launch over parts of a kernel whose single-launch form is `k1` and fused form `kp`, with 256 threads.
+#define FSIB_PARTS_256(k1, kp, Args)                                                                          \
+  [&](const PartLaunch<Args>& L) {                                                                           \
+    hipLaunchKernelGGL(k1, dim3((unsigned)L.nx, (unsigned)L.ny), dim3(256), 0, st, L.a);                      \
+    return hipGetLastError();                                                                                \
+  },                                                                                                         \
+      [&](const Parts<Args>& f, int64_t nwg, size_t) {                                                       \
+        hipLaunchKernelGGL(kp, dim3((unsigned)nwg), dim3(256), 0, st, f);                                    \
+        return hipGetLastError();                                                                            \
+      }
+
+template <typename T>
+static hipError_t scatter_group(const std::vector<Plan*>& ps, const int64_t* M, const double* const* X, hipStream_t st) {
+  std::vector<PartLaunch<ScatterArgs<T>>> v(ps.size());
+  for (size_t g = 0; g < ps.size(); ++g) {
+    v[g].a = scatter_args<T>(*ps[g], M[g], X[g]);
+    v[g].nx = (M[g] + 255) / 256;
+  }
+  return launch_parts(v, FSIB_PARTS_256(k_bin_scatter<T>, k_bin_scatter_parts<T>, ScatterArgs<T>));
+}
+
+hipError_t launch_scan_group(const std::vector<int64_t>& n, const std::vector<const int*>& counts,
+                             const std::vector<int*>& offsets, const std::vector<int*>& seg_sum, hipStream_t st) {
+  std::vector<ScanArgs> sc(n.size());
+  for (size_t g = 0; g < n.size(); ++g) sc[g] = ScanArgs{n[g], counts[g], offsets[g], seg_sum[g]};
+  return launch_scan_parts(sc, st);
+}
+
+// launch_sort_points for the plans of a group (plan g with M[g] points at X[g]), each stage one launch
+// over all plans.  The plans are not deterministic ones (the group refuses them).
+hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t* M, const double* const* X,
+                                    hipStream_t st) {
+  const size_t n = ps.size();
+  std::vector<PartLaunch<FillArgs>> fz(n);
+  std::vector<PartLaunch<BinCountArgs>> bc(n);
+  std::vector<ScanArgs> sc(n);
+  std::vector<PartLaunch<RowMaskArgs>> rm;
+  std::vector<PartLaunch<PlaneMaskArgs>> pm;
+  for (size_t g = 0; g < n; ++g) {
+    const Plan& p = *ps[g];
+    const int64_t words = p.nbt + 1;
+    fz[g].a = FillArgs{(uint32_t*)p.counts, words};
+    fz[g].nx = (words + 255) / 256;
+    bc[g].a = BinCountArgs{M[g], X[g], make_geo(p), p.counts, p.pt_bin, p.pt_rank, p.flag};
+    bc[g].nx = (M[g] + 255) / 256;
+    sc[g] = ScanArgs{p.nbt, p.counts, p.offsets, p.scan_part};
+    if (p.ninst == 1 || p.dim == 2) {
+      rm.push_back(row_mask_launch(p));
+      pm.push_back(plane_mask_launch(p));
+    }
+  }
+  hipError_t e = launch_parts(fz, FSIB_PARTS_256(k_fill_zero_parts_one, k_fill_zero_parts, FillArgs));
+  if (e != hipSuccess) return e;
+  if ((e = launch_parts(bc, FSIB_PARTS_256(k_bin_count, k_bin_count_parts, BinCountArgs))) != hipSuccess) return e;
+  if ((e = launch_scan_parts(sc, st)) != hipSuccess) return e;
+  if ((e = launch_parts(rm, FSIB_PARTS_256(k_row_masks, k_row_masks_parts, RowMaskArgs))) != hipSuccess) return e;
+  if ((e = launch_parts(pm, FSIB_PARTS_256(k_plane_masks, k_plane_masks_parts, PlaneMaskArgs))) != hipSuccess)
+    return e;
+  return ps[0]->prec == FSIB_F64 ? scatter_group<double>(ps, M, X, st) : scatter_group<float>(ps, M, X, st);
+}
+
+// Zeroing of several device ranges (ptr[g], bytes[g], whole 4-byte words) in one launch.
+hipError_t launch_fill_zero_group(const std::vector<void*>& ptr, const std::vector<int64_t>& bytes, hipStream_t st) {
+  std::vector<PartLaunch<FillArgs>> v(ptr.size());
+  for (size_t g = 0; g < ptr.size(); ++g) {
+    v[g].a = FillArgs{(uint32_t*)ptr[g], bytes[g] / 4};
+    v[g].nx = (bytes[g] / 4 + 255) / 256;
+  }
+  return launch_parts(v, FSIB_PARTS_256(k_fill_zero_parts_one, k_fill_zero_parts, FillArgs));
 }
 
 hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const double* X, const void* U, double a,
@@ -389,6 +634,25 @@ hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const doub
   else
     hipLaunchKernelGGL(k_axpy_pos<float>, dim3(nblk), dim3(256), 0, st, n, Y, X, (const float*)U, a);
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t axpy_group(const std::vector<Plan*>& ps, const int64_t* M, double* const* Y,
+                             const double* const* X, const void* const* U, const double* a, hipStream_t st) {
+  std::vector<PartLaunch<AxpyArgs<T>>> v(ps.size());
+  for (size_t g = 0; g < ps.size(); ++g) {
+    const int64_t n = M[g] * ps[g]->dim;
+    v[g].a = AxpyArgs<T>{n, Y[g], X[g], (const T*)U[g], a[g]};
+    v[g].nx = (n + 255) / 256;
+  }
+  return launch_parts(v, FSIB_PARTS_256(k_axpy_pos_one<T>, k_axpy_pos_parts<T>, AxpyArgs<T>));
+}
+
+// Y[g] = X[g] + a[g] U[g] for the plans of a group, one launch.
+hipError_t launch_axpy_positions_group(const std::vector<Plan*>& ps, const int64_t* M, double* const* Y,
+                                       const double* const* X, const void* const* U, const double* a,
+                                       hipStream_t st) {
+  return ps[0]->prec == FSIB_F64 ? axpy_group<double>(ps, M, Y, X, U, a, st) : axpy_group<float>(ps, M, Y, X, U, a, st);
 }
 
 }  // namespace fsib

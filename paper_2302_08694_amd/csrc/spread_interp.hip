@@ -146,7 +146,7 @@ struct SpreadTile {
 };
 
 template <typename T, int DIM, int W, int NCH, bool CPLX>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
+__device__ __forceinline__ void spread_body(const SpreadArgs<T>& a, Blk wb) {
   using G = SpreadTile<T, DIM>;
   constexpr int TY = G::TY, TZ = G::TZ, ROWS = G::ROWS, CW = G::CW, NXG = G::NXG;
   __shared__ T wxr[kChunk][G::XS];
@@ -161,13 +161,13 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   __shared__ int wcnt[kSpreadThreads / 64 + 1];
 
   const int tid = threadIdx.x;
-  const int tr = blockIdx.y;
+  const int tr = (int)wb.y;
   const int nbins = a.nt[0] * a.nt[1] * (DIM == 3 ? a.nt[2] : 1);
   const int nbt = nbins * a.ninst;  // tiles of all instances
   int tile_id, part;
   // tiles holding points cluster (surfaces): whole XCD-contiguous ranges of tiles would load the XCDs
   // unevenly, short runs keep neighbouring tiles (which stage the same points) on one L2
-  const int blk = a.xcd_chunk > 0 ? (int)xcd_chunked(blockIdx.x, gridDim.x, a.xcd_chunk) : (int)blockIdx.x;
+  const int blk = a.xcd_chunk > 0 ? (int)xcd_chunked(wb.x, wb.nx, a.xcd_chunk) : (int)wb.x;
   if (blk < nbt) {
     tile_id = blk;
     part = 0;
@@ -358,23 +358,57 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
   (void)tcells;
 }
 
+template <typename T, int DIM, int W, int NCH, bool CPLX>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
+  spread_body<T, DIM, W, NCH, CPLX>(a, launch_blk());
+}
+template <typename T, int DIM, int W, int NCH, bool CPLX>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_parts(Parts<SpreadArgs<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) spread_body<T, DIM, W, NCH, CPLX>(f.a[g], b);
+}
+
 // Strengths permuted into the sorted point order, so that the spreading stages read them contiguously.
+template <typename T>
+struct SortStrArgs {
+  int64_t M;
+  const int* s_idx;
+  const T* str;
+  T* sstr;
+};
 template <typename T, int NCH, bool CPLX>
-__global__ void k_sort_strengths(int64_t M, const int* __restrict__ s_idx, const T* __restrict__ str,
-                                 T* __restrict__ sstr) {
-  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sort_strengths(const SortStrArgs<T>& A, Blk wb) {
+  const int64_t M = A.M;
+  const int64_t pos = wb.x * blockDim.x + threadIdx.x;
   if (pos >= M) return;
-  const int tr = blockIdx.y;
-  const int64_t j = s_idx[pos];
+  const int64_t tr = wb.y;
+  const int64_t j = A.s_idx[pos];
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch)
-    sstr[((int64_t)tr * M + pos) * NCH + ch] = CPLX ? str[((int64_t)tr * M + j) * 2 + ch] : str[j * NCH + ch];
+    A.sstr[(tr * M + pos) * NCH + ch] = CPLX ? A.str[(tr * M + j) * 2 + ch] : A.str[j * NCH + ch];
+}
+template <typename T, int NCH, bool CPLX>
+__global__ void k_sort_strengths(SortStrArgs<T> a) { sort_strengths<T, NCH, CPLX>(a, launch_blk()); }
+template <typename T, int NCH, bool CPLX>
+__global__ void k_sort_strengths_parts(Parts<SortStrArgs<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) sort_strengths<T, NCH, CPLX>(f.a[g], b);
 }
 
 // Points reaching each tile (its bin and the q bins before it per axis) and the parts it splits into.
-__global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1, int q2, int ninst, int split,
-                             const int* __restrict__ offsets, int* __restrict__ tile_parts) {
-  const int tg = blockIdx.x * blockDim.x + threadIdx.x;
+struct TilePartsArgs {
+  int dim, nt0, nt1, nt2, q0, q1, q2, ninst, split;
+  const int* offsets;
+  int* tile_parts;
+};
+__device__ __forceinline__ void tile_parts_body(const TilePartsArgs& A, Blk wb) {
+  const int dim = A.dim, nt0 = A.nt0, nt1 = A.nt1, nt2 = A.nt2, q0 = A.q0, q1 = A.q1, q2 = A.q2, ninst = A.ninst,
+            split = A.split;
+  const int* __restrict__ offsets = A.offsets;
+  int* __restrict__ tile_parts = A.tile_parts;
+  const int tg = (int)(wb.x * blockDim.x + threadIdx.x);
   const int nbins = nt0 * nt1 * nt2;
   if (tg >= nbins * ninst) return;
   const int inst = tg / nbins, t = tg - inst * nbins;
@@ -389,26 +423,45 @@ __global__ void k_tile_parts(int dim, int nt0, int nt1, int nt2, int q0, int q1,
       }
   tile_parts[tg] = total <= split ? 1 : (total + split - 1) / split;
 }
+__global__ void k_tile_parts(TilePartsArgs a) { tile_parts_body(a, launch_blk()); }
+__global__ void k_tile_parts_parts(Parts<TilePartsArgs> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) tile_parts_body(f.a[g], b);
+}
 
 // Work list of the further parts (tile, part >= 1) in tile order, and scratch slots for tiles split
 // into several parts.
-__global__ void k_fill_work(int nbins, const int* __restrict__ part_off, const int* __restrict__ tile_parts,
-                            int2* __restrict__ work, int* __restrict__ tile_slot, int* __restrict__ slot_ctr) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nbins) return;
+struct FillWorkArgs {
+  int nbins;
+  const int* part_off;
+  const int* tile_parts;
+  int2* work;
+  int* tile_slot;
+  int* slot_ctr;
+};
+__device__ __forceinline__ void fill_work(const FillWorkArgs& A, Blk wb) {
+  const int t = (int)(wb.x * blockDim.x + threadIdx.x);
+  if (t >= A.nbins) return;
   // parts 1.. of tile t: entries part_off[t] - t .. (parts before t, less one per tile)
-  const int np = tile_parts[t], off = part_off[t] - t;
-  for (int q = 1; q < np; ++q) work[off + q - 1] = make_int2(t, q);
-  tile_slot[t] = np > 1 ? atomicAdd(slot_ctr, np) : -1;
+  const int np = A.tile_parts[t], off = A.part_off[t] - t;
+  for (int q = 1; q < np; ++q) A.work[off + q - 1] = make_int2(t, q);
+  A.tile_slot[t] = np > 1 ? atomicAdd(A.slot_ctr, np) : -1;
+}
+__global__ void k_fill_work(FillWorkArgs a) { fill_work(a, launch_blk()); }
+__global__ void k_fill_work_parts(Parts<FillWorkArgs> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) fill_work(f.a[g], b);
 }
 
 // Sum the partial tiles of every split tile in part order and write it to the grid.
 template <typename T, int DIM, int NCH, bool CPLX>
-__global__ __launch_bounds__(kSpreadThreads) void k_merge_tiles(SpreadArgs<T> a) {
-  const int t = blockIdx.x;
+__device__ __forceinline__ void merge_tiles(const SpreadArgs<T>& a, Blk wb) {
+  const int t = (int)wb.x;
   const int np = a.tile_parts[t];
   if (np <= 1) return;
-  const int tr = blockIdx.y;
+  const int tr = (int)wb.y;
   const int nbins = a.nt[0] * a.nt[1] * (DIM == 3 ? a.nt[2] : 1);
   const int inst = t / nbins, lt = t - inst * nbins;
   const int tcoord[3] = {lt % a.nt[0], (lt / a.nt[0]) % a.nt[1], DIM == 3 ? lt / (a.nt[0] * a.nt[1]) : 0};
@@ -433,6 +486,16 @@ __global__ __launch_bounds__(kSpreadThreads) void k_merge_tiles(SpreadArgs<T> a)
       for (int ch = 0; ch < NCH; ++ch) a.grid[((int64_t)inst * NCH + ch) * cells + g] = v[ch];
     }
   }
+}
+template <typename T, int DIM, int NCH, bool CPLX>
+__global__ __launch_bounds__(kSpreadThreads) void k_merge_tiles(SpreadArgs<T> a) {
+  merge_tiles<T, DIM, NCH, CPLX>(a, launch_blk());
+}
+template <typename T, int DIM, int NCH, bool CPLX>
+__global__ __launch_bounds__(kSpreadThreads) void k_merge_tiles_parts(Parts<SpreadArgs<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) merge_tiles<T, DIM, NCH, CPLX>(f.a[g], b);
 }
 
 template <typename T>
@@ -526,7 +589,7 @@ __host__ __device__ constexpr int interp_pb() {
 }
 
 template <typename T, int DIM, int W, int NCH, bool CPLX>
-__global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
+__device__ __forceinline__ void interp_body(const InterpArgs<T>& a, Blk wb) {
   constexpr int XL = interp_xlanes<W>();
   constexpr int YL = 64 / XL;
   constexpr int YCH = (W + YL - 1) / YL;  // chunks of YL rows along y
@@ -540,14 +603,14 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
   const int lane = threadIdx.x & 63;
   const int xl = lane % XL, yl = lane / XL;
   const int axis = lane >> 4, jk = lane & 15;  // kernel value jk along axis (lanes 16a + j)
-  const int tr = blockIdx.y;
+  const int tr = (int)wb.y;
   const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
   // coefficient column jk of the kernel pieces
   constexpr int DEG = interp_degree<W>();  // the plan's degree for this width (checked on the host)
   T cfr[DEG + 1];
 #pragma unroll
   for (int i = 0; i <= DEG; ++i) cfr[i] = jk < W ? a.coef[i * W + jk] : (T)0;
-  const int64_t blk = a.xcd_chunk > 0 ? xcd_chunked(blockIdx.x, gridDim.x, a.xcd_chunk) : (int64_t)blockIdx.x;
+  const int64_t blk = a.xcd_chunk > 0 ? xcd_chunked(wb.x, wb.nx, a.xcd_chunk) : wb.x;
   const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
   const int64_t first = wave * a.ppw;
   uint32_t pkn[PB];
@@ -678,9 +741,20 @@ __global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
   }
 }
 
+template <typename T, int DIM, int W, int NCH, bool CPLX>
+__global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
+  interp_body<T, DIM, W, NCH, CPLX>(a, launch_blk());
+}
+template <typename T, int DIM, int W, int NCH, bool CPLX>
+__global__ __launch_bounds__(256) void k_interp_parts(Parts<InterpArgs<T>> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) interp_body<T, DIM, W, NCH, CPLX>(f.a[g], b);
+}
+
 // ---- dispatch over (precision, dim, w, channels) ----
-template <typename T, int DIM, int NCH, bool CPLX, int W>
-static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipStream_t st) {
+template <typename T, int DIM>
+static SpreadArgs<T> spread_args(const Plan& p, int64_t M, const void* str) {
   SpreadArgs<T> a;
   a.coef = (const T*)p.coef;
   a.deg = p.deg;
@@ -708,21 +782,36 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   a.ninst = p.ninst;
   a.split = p.split;
   a.sstr = (T*)p.s_str;
+  return a;
+}
+
+template <int DIM>
+static TilePartsArgs tile_parts_args(const Plan& p) {
+  return TilePartsArgs{DIM, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[0], (int)p.qn[1], (int)p.qn[2],
+                       p.ninst, p.split, (const int*)p.offsets, p.tile_parts};
+}
+
+static FillWorkArgs fill_work_args(const Plan& p) {
+  return FillWorkArgs{(int)p.nbt, (const int*)p.part_off, (const int*)p.tile_parts, (int2*)p.work, p.tile_slot,
+                      p.slot_ctr};
+}
+
+template <typename T, int DIM, int NCH, bool CPLX, int W>
+static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipStream_t st) {
+  const SpreadArgs<T> a = spread_args<T, DIM>(p, M, str);
   const unsigned nb = (unsigned)p.nbt;
   if (M > 0) {
     hipLaunchKernelGGL((k_sort_strengths<T, NCH, CPLX>), dim3((unsigned)((M + 255) / 256), (unsigned)ntr), dim3(256), 0,
-                       st, M, (const int*)p.s_idx, (const T*)str, a.sstr);
+                       st, SortStrArgs<T>{M, (const int*)p.s_idx, (const T*)str, a.sstr});
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
   }
-  hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, DIM, a.nt[0], a.nt[1], a.nt[2], a.q[0],
-                     a.q[1], a.q[2], p.ninst, a.split, (const int*)p.offsets, p.tile_parts);
+  hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, tile_parts_args<DIM>(p));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
   if ((e = launch_fill_zero(p.slot_ctr, 4, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, (int)p.nbt, (const int*)p.part_off,
-                     (const int*)p.tile_parts, (int2*)p.work, p.tile_slot, p.slot_ctr);
+  hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, fill_work_args(p));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const bool prof = prof_on(p, PROF_SPREAD);
   if (prof) prof_start(p, st);
@@ -737,10 +826,68 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   return hipGetLastError();
 }
 
+// A launch over parts of a kernel with `nt` threads per workgroup: `k1` alone, `kp` over parts.
+#define FSIB_PARTS(k1, kp, Args, nt)                                                                          \
+  [&](const PartLaunch<Args>& L) {                                                                           \
+    hipLaunchKernelGGL(k1, dim3((unsigned)L.nx, (unsigned)L.ny), dim3(nt), 0, st, L.a);                       \
+    return hipGetLastError();                                                                                \
+  },                                                                                                         \
+      [&](const Parts<Args>& f, int64_t nwg, size_t) {                                                       \
+        hipLaunchKernelGGL(kp, dim3((unsigned)nwg), dim3(nt), 0, st, f);                                     \
+        return hipGetLastError();                                                                            \
+      }
+
+// run_spread (real strengths, one transform) for the plans of a group, each stage one launch.
+template <typename T, int DIM, int W>
+static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* M, const void* const* str,
+                                   hipStream_t st) {
+  constexpr int NCH = DIM;
+  const size_t n = ps.size();
+  std::vector<PartLaunch<SortStrArgs<T>>> ss(n);
+  std::vector<PartLaunch<TilePartsArgs>> tp(n);
+  std::vector<PartLaunch<FillWorkArgs>> fw(n);
+  std::vector<PartLaunch<SpreadArgs<T>>> sp(n), mg(n);
+  std::vector<int64_t> nbt(n), four(n, 4);
+  std::vector<const int*> tparts(n);
+  std::vector<int*> poff(n), spart(n);
+  std::vector<void*> ctr(n);
+  for (size_t g = 0; g < n; ++g) {
+    Plan& p = *ps[g];
+    const SpreadArgs<T> a = spread_args<T, DIM>(p, M[g], str[g]);
+    ss[g].a = SortStrArgs<T>{M[g], (const int*)p.s_idx, (const T*)str[g], a.sstr};
+    ss[g].nx = (M[g] + 255) / 256;
+    tp[g].a = tile_parts_args<DIM>(p);
+    tp[g].nx = (p.nbt + 255) / 256;
+    fw[g].a = fill_work_args(p);
+    fw[g].nx = (p.nbt + 255) / 256;
+    sp[g].a = a;
+    sp[g].nx = p.work_blocks;
+    sp[g].threads = spread_threads<DIM, T>();
+    mg[g].a = a;
+    mg[g].nx = p.nbt;
+    nbt[g] = p.nbt;
+    tparts[g] = p.tile_parts;
+    poff[g] = p.part_off;
+    spart[g] = p.scan_part;
+    ctr[g] = p.slot_ctr;
+  }
+  hipError_t e = launch_parts(ss, FSIB_PARTS((k_sort_strengths<T, NCH, false>), (k_sort_strengths_parts<T, NCH, false>),
+                                             SortStrArgs<T>, 256));
+  if (e != hipSuccess) return e;
+  if ((e = launch_parts(tp, FSIB_PARTS(k_tile_parts, k_tile_parts_parts, TilePartsArgs, 256))) != hipSuccess) return e;
+  if ((e = launch_scan_group(nbt, tparts, poff, spart, st)) != hipSuccess) return e;
+  if ((e = launch_fill_zero_group(ctr, four, st)) != hipSuccess) return e;
+  if ((e = launch_parts(fw, FSIB_PARTS(k_fill_work, k_fill_work_parts, FillWorkArgs, 256))) != hipSuccess) return e;
+  constexpr int NT = spread_threads<DIM, T>();
+  if ((e = launch_parts(sp, FSIB_PARTS((k_spread<T, DIM, W, NCH, false>), (k_spread_parts<T, DIM, W, NCH, false>),
+                                       SpreadArgs<T>, NT))) != hipSuccess)
+    return e;
+  return launch_parts(mg, FSIB_PARTS((k_merge_tiles<T, DIM, NCH, false>), (k_merge_tiles_parts<T, DIM, NCH, false>),
+                                     SpreadArgs<T>, kSpreadThreads));
+}
+
 template <typename T, int DIM, int NCH, bool CPLX, int W>
-static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t st) {
-  if (M == 0) return hipSuccess;
-  if (p.deg != interp_degree<W>()) return hipErrorInvalidValue;  // the kernel's compile-time degree
+static InterpArgs<T> interp_args(const Plan& p, int64_t M, void* out) {
   InterpArgs<T> a;
   a.coef = (const T*)p.coef;
   a.deg = p.deg;
@@ -758,6 +905,14 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   a.offsets = p.offsets;
   a.nbins = (int)p.nbins;
   a.ninst = p.ninst;
+  return a;
+}
+
+template <typename T, int DIM, int NCH, bool CPLX, int W>
+static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t st) {
+  if (M == 0) return hipSuccess;
+  if (p.deg != interp_degree<W>()) return hipErrorInvalidValue;  // the kernel's compile-time degree
+  const InterpArgs<T> a = interp_args<T, DIM, NCH, CPLX, W>(p, M, out);
   const bool prof = prof_on(p, PROF_INTERP);
   if (prof) prof_start(p, st);
   const int64_t per_wg = 4 * (int64_t)a.ppw;  // four wavefronts per workgroup
@@ -770,6 +925,20 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
     prof_stop(p, (double)M * (8 + DIM * sizeof(T)) + (double)ntr * M * (cellsper + 1) * NCH * sizeof(T), st);
   }
   return hipGetLastError();
+}
+
+template <typename T, int DIM, int W>
+static hipError_t run_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st) {
+  constexpr int NCH = DIM;
+  std::vector<PartLaunch<InterpArgs<T>>> v(ps.size());
+  for (size_t g = 0; g < ps.size(); ++g) {
+    if (ps[g]->deg != interp_degree<W>()) return hipErrorInvalidValue;
+    v[g].a = interp_args<T, DIM, NCH, false, W>(*ps[g], M[g], out[g]);
+    const int64_t per_wg = 4 * (int64_t)v[g].a.ppw;
+    v[g].nx = (M[g] + per_wg - 1) / per_wg;
+  }
+  return launch_parts(v, FSIB_PARTS((k_interp<T, DIM, W, NCH, false>), (k_interp_parts<T, DIM, W, NCH, false>),
+                                    InterpArgs<T>, 256));
 }
 
 #define FSIB_W_SWITCH(W_, CALL)                                     \
@@ -838,6 +1007,37 @@ hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStrea
                : interp_dispatch<float, 2, 2, false>(p, M, out, 1, st);
   return f64 ? interp_dispatch<double, 3, 3, false>(p, M, out, 1, st)
              : interp_dispatch<float, 3, 3, false>(p, M, out, 1, st);
+}
+
+template <typename T, int DIM>
+static hipError_t spread_group_dispatch(const std::vector<Plan*>& ps, const int64_t* M, const void* const* str,
+                                        hipStream_t st) {
+#define CALL_SG(w) run_spread_group<T, DIM, w>(ps, M, str, st)
+  FSIB_W_SWITCH(ps[0]->w, CALL_SG)
+#undef CALL_SG
+}
+
+template <typename T, int DIM>
+static hipError_t interp_group_dispatch(const std::vector<Plan*>& ps, const int64_t* M, void* const* out,
+                                        hipStream_t st) {
+#define CALL_IG(w) run_interp_group<T, DIM, w>(ps, M, out, st)
+  FSIB_W_SWITCH(ps[0]->w, CALL_IG)
+#undef CALL_IG
+}
+
+// The plans of a group share precision, dimension and kernel width (checked when the group is made).
+hipError_t launch_spread_group(const std::vector<Plan*>& ps, const int64_t* M, const void* const* str, hipStream_t st) {
+  const bool f64 = ps[0]->prec == FSIB_F64;
+  if (ps[0]->dim == 2)
+    return f64 ? spread_group_dispatch<double, 2>(ps, M, str, st) : spread_group_dispatch<float, 2>(ps, M, str, st);
+  return f64 ? spread_group_dispatch<double, 3>(ps, M, str, st) : spread_group_dispatch<float, 3>(ps, M, str, st);
+}
+
+hipError_t launch_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st) {
+  const bool f64 = ps[0]->prec == FSIB_F64;
+  if (ps[0]->dim == 2)
+    return f64 ? interp_group_dispatch<double, 2>(ps, M, out, st) : interp_group_dispatch<float, 2>(ps, M, out, st);
+  return f64 ? interp_group_dispatch<double, 3>(ps, M, out, st) : interp_group_dispatch<float, 3>(ps, M, out, st);
 }
 
 }  // namespace fsib

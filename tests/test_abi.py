@@ -120,3 +120,17 @@ def test_tuning_rejects_null_arguments():
     lib = B.load_library()
     t = B._Tuning(0, 0, 512, 1, 8)
     assert lib.fsib_plan_tuning(None, ctypes.byref(t), 1) == 1
+
+
+def test_group_calls_reject_bad_arguments():
+    lib = B.load_library()
+    h = ctypes.c_void_p()
+    assert lib.fsib_group_create(0, None, ctypes.byref(h)) == 1
+    assert lib.fsib_group_create(9, None, ctypes.byref(h)) == 1
+    assert lib.fsib_group_create(1, None, ctypes.byref(h)) == 1
+    assert h.value is None
+    null = (ctypes.c_void_p * 2)(None, None)
+    assert lib.fsib_group_create(2, null, ctypes.byref(h)) == 1
+    assert lib.fsib_group_create(1, null, None) == 1
+    assert lib.fsib_group_steps(None, None, None, None, None, None, None, 1, None) == 1
+    assert lib.fsib_group_destroy(None) == 0
