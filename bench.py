@@ -373,13 +373,20 @@ def batched_stokes(F, torch, steps=50, graph_steps=10):
     num = sum(float(np.sum((x32 - x64) ** 2)) for (x32, _), (x64, _) in zip(finals["f32"], finals["f64"]))
     den = sum(float(np.sum((x64 - x0) ** 2)) for (x64, x0) in finals["f64"])
     res["f32_rel_err_displacement_vs_f64"] = (num / max(den, 1e-300)) ** 0.5
-    # the same cases on multi-instance plans, one per group of equal N: every stage is one launch per
-    # group
+    # the same cases on multi-instance plans, one per group of equal N, stepped through library Groups
+    # (fsib_group_steps): the groups are split into lanes, each lane one Group on its own stream whose
+    # every stage is one launch over the lane's plans of all its N.  The autotuner picks each plan's
+    # knobs and the lane count (1: one launch per stage for the whole batch; the number of groups:
+    # every group on its own stream) from timed batch steps.
     from paper_2302_08694_amd.batch import StokesGroupBatch
     for prec, tol in (("f32", 1e-5), ("f64", 1e-5)):
         b = StokesGroupBatch(cases, prec=prec, tol=tol)
         res["grouped_plans"] = len(b.groups)
-        res[f"{prec}_grouped_tuning"] = {str(k): v for k, v in b.autotune().items()}
+        tuned = b.autotune()
+        lanes = tuned.pop("lanes")
+        res[f"{prec}_grouped_tuning"] = {str(k): v for k, v in tuned.items()}
+        res[f"{prec}_lanes_ms_per_batch_step"] = {str(k): v * 1e3 for k, v in lanes.items()}
+        res[f"{prec}_lanes_chosen"] = b.lanes
         b.step(1)
         rates = []  # median of three timed runs from the initial state
         for _ in range(3):

@@ -112,6 +112,9 @@ typedef struct {
                             caller's stream.  1 by default. */
   int interp_points;     /* points per interpolation wavefront: 1, 2, 4 (default), 8 or 16, rounded
                             up to the points a kernel sums together (up to 4) */
+  int spread_threads;    /* spreading variant: threads per 16 x 16 tile of a 2D plan, 64 (4 cells
+                            per lane), 128 (2) or 256 (1); 0 picks the default (64 in FP32, 128 in
+                            FP64).  3D plans take 0 or 256 (16 x 8 x 8 tiles, 4 cells per lane). */
 } fsib_tuning;
 
 typedef enum { FSIB_STOKES = 0, FSIB_NAVIER_STOKES = 1 } fsib_model;
@@ -187,7 +190,7 @@ fsib_status fsib_plan_profile(fsib_plan plan, int kernel_class, int max_launches
  * Results are identical up to the summation order of spreading.  split may not go below the value
  * the plan was created with (its scratch is sized for it; the creation value is 512).  Errors:
  * FSIB_ERR_ARG for NULL or out-of-range values (chunks in [0, 4096], split in [creation, 1 << 20],
- * overlap 0 or 1, interp_points 1, 2, 4, 8 or 16). */
+ * overlap 0 or 1, interp_points 1, 2, 4, 8 or 16, spread_threads as above). */
 fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* tuning, int get);
 fsib_status fsib_plan_profile_read(fsib_plan plan, double* total_ms /* host */, int64_t* launches /* host */,
                                    double* bytes /* host */);

@@ -107,13 +107,16 @@ class StokesBatch:
 
 class StokesGroupBatch:
     """The same simulations with one multi-instance plan per group of cases that share N, L, mu, dt
-    and K (ninst > 1): each stage of a step is one launch over all instances of a group, so a batch
-    step costs a few launches per group instead of per instance.  With fused=True (the default) the
-    groups' plans form one library Group (fsib_group_steps) and each stage is one launch over all
-    groups, of every N; with fused=False the groups run on their own streams.  Same interface as
-    StokesBatch; `positions()` returns each case's X in the order of `cases`."""
+    and K (ninst > 1): each stage of a step is one launch over all instances of a group.  The groups'
+    plans are split into `lanes` library Groups (fsib_group_steps), each stepped on its own stream:
+    inside a lane every stage is one launch over all of the lane's plans, whatever their N; lanes run
+    concurrently.  lanes=1 gives one launch per stage for the whole batch; lanes equal to the number of
+    groups gives every group its own stream.  Plans are assigned to lanes largest first, each to the
+    lane with the least work so far (work ~ instances x fine-grid cells + points).  fused=False is
+    lanes = number of groups.  `autotune()` picks the plans' knobs and the lane count from timed steps.
+    Same interface as StokesBatch; `positions()` returns each case's X in the order of `cases`."""
 
-    def __init__(self, cases, prec="f32", tol=1e-5, device="cuda", fused=True):
+    def __init__(self, cases, prec="f32", tol=1e-5, device="cuda", fused=True, lanes=None):
         self.prec = prec
         keys = {}
         for i, c in enumerate(cases):
@@ -130,15 +133,32 @@ class StokesGroupBatch:
             force = Force("tension2d", K)
             uh = torch.zeros(plan.field_shape, dtype=plan.cdtype, device=device)
             U = plan.velocity(params, force, X0, uh)
+            fine = plan.info()["n_fine"]
+            work = len(idx) * fine[0] * fine[1] + X0.shape[0]
             self.groups.append(dict(plan=plan, params=params, force=force, X=X0.clone(), U=U, uh=uh, X0=X0,
-                                    U0=U.clone(), uh0=uh.clone(), idx=idx, counts=counts))
-        self.streams = [torch.cuda.Stream() for _ in self.groups]
-        self.fused = None
-        if fused:
-            from ._binding import Group
-            self.fused = Group([g["plan"] for g in self.groups])
+                                    U0=U.clone(), uh0=uh.clone(), idx=idx, counts=counts, work=work))
+        self.lane_groups = []
+        self.streams = []
+        self.set_lanes(lanes if lanes is not None else (1 if fused else len(self.groups)))
         self.graph = None
         self.graph_steps = 0
+
+    def set_lanes(self, lanes):
+        """Split the plans into `lanes` library Groups (largest work first, each to the least loaded
+        lane), each stepped on its own stream."""
+        from ._binding import Group
+        for grp, _ in self.lane_groups:
+            grp.close()
+        lanes = max(1, min(int(lanes), len(self.groups)))
+        load = [0] * lanes
+        members = [[] for _ in range(lanes)]
+        for g in sorted(self.groups, key=lambda g: -g["work"]):
+            k = load.index(min(load))
+            members[k].append(g)
+            load[k] += g["work"]
+        self.lane_groups = [(Group([g["plan"] for g in m]), m) for m in members if m]
+        self.streams = [torch.cuda.Stream() for _ in self.lane_groups]
+        self.lanes = len(self.lane_groups)
 
     def reset(self):
         for g in self.groups:
@@ -147,35 +167,72 @@ class StokesGroupBatch:
             g["uh"].copy_(g["uh0"])
 
     def step(self, n=1):
-        if self.fused is not None:
-            gs = self.groups
-            self.fused.steps([g["params"] for g in gs], [g["force"] for g in gs], [g["X"] for g in gs],
-                             [g["U"] for g in gs], [g["uh"] for g in gs], n)
+        def run(grp, gs):
+            grp.steps([g["params"] for g in gs], [g["force"] for g in gs], [g["X"] for g in gs],
+                      [g["U"] for g in gs], [g["uh"] for g in gs], n)
+        if len(self.lane_groups) == 1:
+            run(*self.lane_groups[0])
             return
         main = torch.cuda.current_stream()
-        for _ in range(n):
-            for s in self.streams:
-                s.wait_stream(main)
-            for g, s in zip(self.groups, self.streams):
-                with torch.cuda.stream(s):
-                    g["plan"].step(g["params"], g["force"], g["X"], g["U"], g["uh"])
-            for s in self.streams:
-                main.wait_stream(s)
+        for s in self.streams:
+            s.wait_stream(main)
+        for (grp, gs), s in zip(self.lane_groups, self.streams):
+            with torch.cuda.stream(s):
+                run(grp, gs)
+        for s in self.streams:
+            main.wait_stream(s)
 
-    def autotune(self, reps=3):
-        """Tune each group's plan knobs (paper_2302_08694_amd.tune) on timed steps of that group;
-        the state is restored afterwards.  Returns {N: chosen knobs}."""
+    def _save(self):
+        return [(g["X"].clone(), g["U"].clone(), g["uh"].clone()) for g in self.groups]
+
+    def _restore(self, saved):
+        for g, (X, U, uh) in zip(self.groups, saved):
+            g["X"].copy_(X)
+            g["U"].copy_(U)
+            g["uh"].copy_(uh)
+        torch.cuda.synchronize()
+
+    def autotune(self, reps=3, lanes=None):
+        """Tune each plan's knobs (paper_2302_08694_amd.tune) on timed steps of that plan alone, give
+        the plans that share a lane the spreading variant of the lane's largest plan (a launch over
+        plans needs one workgroup size), then pick the lane count (candidates `lanes`, default 1, 2
+        and the number of groups) from timed batch steps.  The state is restored afterwards.  Returns
+        {N: chosen knobs, "lanes": {candidate: seconds per batch step}}."""
+        import time
         from .tune import autotune
+        saved = self._save()
         chosen = {}
         for g in self.groups:
-            saved = (g["X"].clone(), g["U"].clone(), g["uh"].clone())
             run = lambda g=g: g["plan"].step(g["params"], g["force"], g["X"], g["U"], g["uh"])
             chosen[g["plan"].n_modes[0]] = autotune(g["plan"], run, reps=reps)["best"]
-            g["X"].copy_(saved[0])
-            g["U"].copy_(saved[1])
-            g["uh"].copy_(saved[2])
-        torch.cuda.synchronize()
+        self._restore(saved)
+        cands = lanes if lanes is not None else sorted({1, min(2, len(self.groups)), len(self.groups)})
+        times = {}
+        for c in cands:
+            self._lanes_with_shared_variant(c)
+            self.step(1)
+            torch.cuda.synchronize()
+            nrep = max(5, reps)
+            t0 = time.perf_counter()
+            for _ in range(nrep):
+                self.step(1)
+            torch.cuda.synchronize()
+            times[c] = (time.perf_counter() - t0) / nrep
+            self._restore(saved)
+        best = min(times, key=times.get)
+        self._lanes_with_shared_variant(best)
+        for g in self.groups:
+            chosen[g["plan"].n_modes[0]] = g["plan"].tuning()
+        chosen["lanes"] = times
         return chosen
+
+    def _lanes_with_shared_variant(self, lanes):
+        self.set_lanes(lanes)
+        for _, gs in self.lane_groups:
+            top = max(gs, key=lambda g: g["work"])
+            v = top["plan"].tuning()["spread_threads"]
+            for g in gs:
+                g["plan"].tuning(**{**g["plan"].tuning(), "spread_threads": v})
 
     def positions(self):
         out = [None] * sum(len(g["idx"]) for g in self.groups)
@@ -185,7 +242,7 @@ class StokesGroupBatch:
         return out
 
     def capture(self, steps):
-        saved = [(g["X"].clone(), g["U"].clone(), g["uh"].clone()) for g in self.groups]
+        saved = self._save()
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
@@ -195,11 +252,7 @@ class StokesGroupBatch:
         gr = torch.cuda.CUDAGraph()
         with torch.cuda.graph(gr):
             self.step(steps)
-        for g, (X, U, uh) in zip(self.groups, saved):
-            g["X"].copy_(X)
-            g["U"].copy_(U)
-            g["uh"].copy_(uh)
-        torch.cuda.synchronize()
+        self._restore(saved)
         self.graph, self.graph_steps = gr, steps
         return gr
 
@@ -210,9 +263,9 @@ class StokesGroupBatch:
 
     def close(self):
         self.graph = None
-        if self.fused is not None:
-            self.fused.close()
-            self.fused = None
+        for grp, _ in self.lane_groups:
+            grp.close()
+        self.lane_groups = []
         for g in self.groups:
             g["plan"].close()
         self.groups = []

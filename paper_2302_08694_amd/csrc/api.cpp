@@ -101,6 +101,7 @@ void free_plan(Plan& p) {
   fr(p.work);
   fr(p.tile_slot);
   fr(p.slot_ctr);
+  fr(p.split_list);
   fr(p.split_scratch);
   fr(p.grid);
   fr(p.B1);
@@ -302,6 +303,7 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
     A.get(p.work, p.work_blocks * 8);
     A.get(p.tile_slot, p.nbt * 4);
     A.get(p.slot_ctr, 256);
+    A.get(p.split_list, (p.split_slots / 2 + 1) * 4);
     A.get(p.split_scratch, tr * p.split_slots * 1024 * nch_bytes);
   }
   // grid and FFT buffers: complex transforms (ntrans) and, for fluid plans, dim real fields
@@ -703,7 +705,7 @@ fsib_status report(fsib_status s, const char* msg) { return fail(s, msg); }
 struct TransformBuffers {
   int* counts; int* offsets; int* pt_bin; int* pt_rank; int* det_key; int* s_idx; uint32_t* s_i0; void* s_y;
   void* s_str; int* scan_part; uint8_t* rowmask; uint8_t* zmask; int* tile_parts; int* part_off; int* work;
-  int* tile_slot; int* slot_ctr; void* split_scratch; void* grid; void* B1; void* B2;
+  int* tile_slot; int* slot_ctr; int* split_list; void* split_scratch; void* grid; void* B1; void* B2;
   int64_t work_blocks, split_slots;
 };
 
@@ -740,6 +742,7 @@ static int64_t carve_transform_buffers(const Plan& p, int64_t M, char* base, Tra
   take(b.work, b.work_blocks * 8);
   take(b.tile_slot, p.nbt * 4);
   take(b.slot_ctr, 256);
+  take(b.split_list, (b.split_slots / 2 + 1) * 4);
   take(b.split_scratch, (int64_t)p.ntrans * b.split_slots * 1024 * nch_bytes);
   take(b.grid, (int64_t)p.ntrans * p.fine_cells() * cs);
   take(b.B1, p.dim == 3 ? (int64_t)p.ntrans * p.nf[2] * p.nf[1] * p.N[0] * cs : (int64_t)p.ntrans * p.nf[1] * p.N[0] * cs);
@@ -766,6 +769,7 @@ static void swap_transform_buffers(Plan& p, TransformBuffers& b) {
   std::swap(p.work, b.work);
   std::swap(p.tile_slot, b.tile_slot);
   std::swap(p.slot_ctr, b.slot_ctr);
+  std::swap(p.split_list, b.split_list);
   std::swap(p.split_scratch, b.split_scratch);
   std::swap(p.grid, b.grid);
   std::swap(p.B1, b.B1);
@@ -900,6 +904,7 @@ fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
     t->split = p.split;
     t->overlap = p.overlap;
     t->interp_points = p.interp_points;
+    t->spread_threads = p.spread_threads;
     return FSIB_OK;
   }
   if (t->xcd_chunk_interp < 0 || t->xcd_chunk_interp > 4096 || t->xcd_chunk_spread < 0 || t->xcd_chunk_spread > 4096)
@@ -910,6 +915,10 @@ fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
   if (t->interp_points != 1 && t->interp_points != 2 && t->interp_points != 4 && t->interp_points != 8 &&
       t->interp_points != 16)
     return fail(FSIB_ERR_ARG, "interp_points must be 1, 2, 4, 8 or 16");
+  const int sthr = t->spread_threads;
+  if (p.dim == 2 ? (sthr != 0 && sthr != 64 && sthr != 128 && sthr != 256) : (sthr != 0 && sthr != 256))
+    return fail(FSIB_ERR_ARG, "spread_threads must be 0, 64, 128 or 256 (2D) or 0 or 256 (3D)");
+  p.spread_threads = sthr;
   p.interp_points = t->interp_points;
   p.overlap = t->overlap;
   p.xcd_chunk_interp = t->xcd_chunk_interp;

@@ -82,20 +82,26 @@ constexpr int kMaxParts = 8;  // parts of one launch (the kernel arguments stay 
 template <class A>
 struct Parts {
   A a[kMaxParts];
-  int64_t start[kMaxParts + 1];
-  int64_t nx[kMaxParts], ny[kMaxParts];
+  uint32_t start[kMaxParts + 1];  // a launch has fewer than 2^32 workgroups
+  uint32_t nx[kMaxParts], ny[kMaxParts];
   int n;
 };
 
-// Part of this workgroup (-1 for a padding workgroup) and its coordinates in the part's grid.
+// Part of this workgroup (-1 for a padding workgroup) and its coordinates in the part's grid.  The
+// coordinates are computed in 32 bits and widened, so the compiler knows their upper halves are zero
+// and keeps the divisions that use them (the XCD renumbering) at 32-bit cost, as with the hardware
+// registers.
 template <class A>
 __device__ __forceinline__ int part_blk(const Parts<A>& f, Blk& b) {
-  const int64_t w = blockIdx.x;
+  const uint32_t w = blockIdx.x;
   int g = 0;
   while (g + 1 < f.n && w >= f.start[g + 1]) ++g;
-  const int64_t l = w - f.start[g], nx = f.nx[g], ny = f.ny[g];
+  const uint32_t l = w - f.start[g], nx = f.nx[g], ny = f.ny[g];
   if (l >= nx * ny) return -1;
-  b = Blk{l % nx, l / nx, nx, ny};
+  if (ny == 1)
+    b = Blk{(int64_t)l, 0, (int64_t)nx, 1};
+  else
+    b = Blk{(int64_t)(l % nx), (int64_t)(l / nx), (int64_t)nx, (int64_t)ny};
   return g;
 }
 

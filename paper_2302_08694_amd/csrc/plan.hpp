@@ -1,6 +1,7 @@
 // Plan (workspace + tables) of the FSIB library and the launchers of its kernels.
 #pragma once
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -76,7 +77,8 @@ struct Plan {
   int* part_off = nullptr;     // nbins+1
   int* work = nullptr;         // 2 ints per part, work_blocks parts at most
   int* tile_slot = nullptr;    // nbins
-  int* slot_ctr = nullptr;
+  int* slot_ctr = nullptr;     // [0]: scratch slots claimed, [1]: split tiles listed
+  int* split_list = nullptr;   // the split tiles (at most split_slots / 2 + 1)
   void* split_scratch = nullptr;
   int64_t work_blocks = 0;     // bound on the number of parts
   int64_t split_slots = 0;     // bound on the partial tiles of split tiles (per transform)
@@ -103,6 +105,7 @@ struct Plan {
   hipStream_t aux = nullptr;
   int overlap = 1;
   int interp_points = 4;  // points per interpolation wavefront (4 measured faster than 8 and 16)
+  int spread_threads = 0; // threads per spreading tile (0: the default of the dimension and precision)
   hipEvent_t fj[4] = {nullptr, nullptr, nullptr, nullptr};
   // optional timing of one kernel class with HIP events on the launch stream
   int prof_class = -1;
@@ -138,6 +141,10 @@ hipError_t launch_parts(const std::vector<PartLaunch<A>>& v, One one, Fused fuse
   for (const auto& q : v)
     if (q.nx * q.ny > 0) live.push_back(&q);
   if (live.empty()) return hipSuccess;
+  // smallest grid first: workgroups are dispatched in order, and a part's long-running workgroups
+  // (the crowded tiles of spreading) then start before the many short ones of the largest grid
+  std::stable_sort(live.begin(), live.end(),
+                   [](const PartLaunch<A>* a, const PartLaunch<A>* b) { return a->nx * a->ny < b->nx * b->ny; });
   bool same = live.size() <= (size_t)kMaxParts;
   for (const auto* q : live) same = same && q->threads == live[0]->threads;
   if (live.size() == 1 || !same) {
@@ -153,13 +160,14 @@ hipError_t launch_parts(const std::vector<PartLaunch<A>>& v, One one, Fused fuse
   size_t lds = 0;
   for (int g = 0; g < f.n; ++g) {
     f.a[g] = live[g]->a;
-    f.nx[g] = live[g]->nx;
-    f.ny[g] = live[g]->ny;
-    f.start[g] = s;
+    f.nx[g] = (uint32_t)live[g]->nx;
+    f.ny[g] = (uint32_t)live[g]->ny;
+    f.start[g] = (uint32_t)s;
     s += (live[g]->nx * live[g]->ny + kXcds - 1) / kXcds * kXcds;
     lds = lds > live[g]->lds ? lds : live[g]->lds;
   }
-  for (int g = f.n; g <= kMaxParts; ++g) f.start[g] = s;
+  if (s >= ((int64_t)1 << 32) - kXcds) return hipErrorInvalidConfiguration;
+  for (int g = f.n; g <= kMaxParts; ++g) f.start[g] = (uint32_t)s;
   return fused(f, s, lds);
 }
 

@@ -49,6 +49,8 @@ struct SpreadArgs {
   const int* tile_slot; // first scratch slot of a split tile
   T* scratch;           // split tiles: [ntrans][slots][NCH][kMaxTileCells] partial tiles
   int64_t slots;        // scratch slots per transform
+  const int* split_list;  // the split tiles, split_cnt[0] of them (k_fill_work)
+  const int* split_cnt;
   const uint8_t* rowmask;  // blocks of x lines reached by some point (lines elsewhere stay unwritten)
   int xcd_chunk;           // > 0: workgroups renumbered in runs of this many per XCD (xcd_chunked)
   int split;               // candidates per part of a heavy tile
@@ -131,12 +133,12 @@ __device__ __forceinline__ void stage_axis(bool valid, int st, int nfd, const T*
 //
 // Workgroup b < nbins spreads (the first part of) tile b; workgroups past nbins take the further
 // parts of heavy tiles from the work list.
-template <typename T, int DIM>
+template <typename T, int DIM, int NT_>
 struct SpreadTile {
   static constexpr int TY = DIM == 3 ? 8 : 16;               // tile rows along y
   static constexpr int TZ = DIM == 3 ? 8 : 1;                // tile rows along z
   static constexpr int ROWS = TY * TZ;
-  static constexpr int NT = spread_threads<DIM, T>();       // threads of the workgroup
+  static constexpr int NT = NT_;                             // threads of the workgroup
   static constexpr int CW = kTileX * ROWS / NT;              // cells per lane along x
   static constexpr int NXG = kTileX / CW;                    // x groups
   static constexpr int XS = kTileX + (sizeof(T) == 4 ? 4 : 2);  // padded LDS strides
@@ -145,9 +147,10 @@ struct SpreadTile {
   static constexpr int NMASK = TY + (DIM == 3 ? TZ : 0) + NXG;
 };
 
-template <typename T, int DIM, int W, int NCH, bool CPLX>
+template <typename T, int DIM, int W, int NCH, bool CPLX, int NT>
 __device__ __forceinline__ void spread_body(const SpreadArgs<T>& a, Blk wb) {
-  using G = SpreadTile<T, DIM>;
+  using G = SpreadTile<T, DIM, NT>;
+  static_assert(NT >= 64 && NT <= kSpreadThreads && kTileX * G::ROWS % NT == 0, "threads of a spreading tile");
   constexpr int TY = G::TY, TZ = G::TZ, ROWS = G::ROWS, CW = G::CW, NXG = G::NXG;
   __shared__ T wxr[kChunk][G::XS];
   __shared__ T wyr[kChunk][G::YS];
@@ -358,15 +361,21 @@ __device__ __forceinline__ void spread_body(const SpreadArgs<T>& a, Blk wb) {
   (void)tcells;
 }
 
-template <typename T, int DIM, int W, int NCH, bool CPLX>
+template <typename T, int DIM, int W, int NCH, bool CPLX, int NT>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<T> a) {
-  spread_body<T, DIM, W, NCH, CPLX>(a, launch_blk());
+  spread_body<T, DIM, W, NCH, CPLX, NT>(a, launch_blk());
 }
-template <typename T, int DIM, int W, int NCH, bool CPLX>
+template <typename T, int DIM, int W, int NCH, bool CPLX, int NT>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_parts(Parts<SpreadArgs<T>> f) {
   Blk b;
   const int g = part_blk(f, b);
-  if (g >= 0) spread_body<T, DIM, W, NCH, CPLX>(f.a[g], b);
+  if (g >= 0) spread_body<T, DIM, W, NCH, CPLX, NT>(f.a[g], b);
+}
+
+// Threads per tile of a plan's spreading launches (its spread_threads knob, else the default).
+template <int DIM, typename T>
+static int plan_spread_threads(const Plan& p) {
+  return DIM == 2 && p.spread_threads > 0 ? p.spread_threads : spread_threads<DIM, T>();
 }
 
 // Strengths permuted into the sorted point order, so that the spreading stages read them contiguously.
@@ -438,7 +447,8 @@ struct FillWorkArgs {
   const int* tile_parts;
   int2* work;
   int* tile_slot;
-  int* slot_ctr;
+  int* slot_ctr;  // [0] scratch slots, [1] split tiles (both zero before the launch)
+  int* split_list;
 };
 __device__ __forceinline__ void fill_work(const FillWorkArgs& A, Blk wb) {
   const int t = (int)(wb.x * blockDim.x + threadIdx.x);
@@ -447,6 +457,7 @@ __device__ __forceinline__ void fill_work(const FillWorkArgs& A, Blk wb) {
   const int np = A.tile_parts[t], off = A.part_off[t] - t;
   for (int q = 1; q < np; ++q) A.work[off + q - 1] = make_int2(t, q);
   A.tile_slot[t] = np > 1 ? atomicAdd(A.slot_ctr, np) : -1;
+  if (np > 1) A.split_list[atomicAdd(A.slot_ctr + 1, 1)] = t;
 }
 __global__ void k_fill_work(FillWorkArgs a) { fill_work(a, launch_blk()); }
 __global__ void k_fill_work_parts(Parts<FillWorkArgs> f) {
@@ -455,13 +466,21 @@ __global__ void k_fill_work_parts(Parts<FillWorkArgs> f) {
   if (g >= 0) fill_work(f.a[g], b);
 }
 
-// Sum the partial tiles of every split tile in part order and write it to the grid.
+// Sum the partial tiles of every split tile in part order and write it to the grid: workgroup k takes
+// entry k of the list of split tiles (launched over a bound on their number; the workgroups past the
+// count leave at once).  The list's order does not matter: each tile is summed on its own.
+template <typename T, int DIM, int NCH, bool CPLX>
+__device__ __forceinline__ void merge_one_tile(const SpreadArgs<T>& a, int t, int np, int tr);
+
 template <typename T, int DIM, int NCH, bool CPLX>
 __device__ __forceinline__ void merge_tiles(const SpreadArgs<T>& a, Blk wb) {
-  const int t = (int)wb.x;
-  const int np = a.tile_parts[t];
-  if (np <= 1) return;
-  const int tr = (int)wb.y;
+  if (wb.x >= a.split_cnt[0]) return;
+  const int t = a.split_list[wb.x];
+  merge_one_tile<T, DIM, NCH, CPLX>(a, t, a.tile_parts[t], (int)wb.y);
+}
+
+template <typename T, int DIM, int NCH, bool CPLX>
+__device__ __forceinline__ void merge_one_tile(const SpreadArgs<T>& a, int t, int np, int tr) {
   const int nbins = a.nt[0] * a.nt[1] * (DIM == 3 ? a.nt[2] : 1);
   const int inst = t / nbins, lt = t - inst * nbins;
   const int tcoord[3] = {lt % a.nt[0], (lt / a.nt[0]) % a.nt[1], DIM == 3 ? lt / (a.nt[0] * a.nt[1]) : 0};
@@ -777,6 +796,8 @@ static SpreadArgs<T> spread_args(const Plan& p, int64_t M, const void* str) {
   a.tile_slot = p.tile_slot;
   a.scratch = (T*)p.split_scratch;
   a.slots = p.split_slots;
+  a.split_list = p.split_list;
+  a.split_cnt = p.slot_ctr + 1;
   a.rowmask = p.ninst > 1 && DIM == 3 ? nullptr : p.rowmask;  // no masks on 3D multi-instance plans
   a.xcd_chunk = p.xcd_chunk_spread;
   a.ninst = p.ninst;
@@ -793,8 +814,11 @@ static TilePartsArgs tile_parts_args(const Plan& p) {
 
 static FillWorkArgs fill_work_args(const Plan& p) {
   return FillWorkArgs{(int)p.nbt, (const int*)p.part_off, (const int*)p.tile_parts, (int2*)p.work, p.tile_slot,
-                      p.slot_ctr};
+                      p.slot_ctr, p.split_list};
 }
+
+// Bound on the split tiles: each takes at least two of the split_slots scratch slots.
+static int64_t merge_blocks(const Plan& p) { return p.split_slots / 2 + 1; }
 
 template <typename T, int DIM, int NCH, bool CPLX, int W>
 static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipStream_t st) {
@@ -810,19 +834,30 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
-  if ((e = launch_fill_zero(p.slot_ctr, 4, st)) != hipSuccess) return e;
+  if ((e = launch_fill_zero(p.slot_ctr, 8, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, fill_work_args(p));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const bool prof = prof_on(p, PROF_SPREAD);
   if (prof) prof_start(p, st);
-  hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX>), dim3((unsigned)p.work_blocks, (unsigned)ntr),
-                     dim3(spread_threads<DIM, T>()), 0, st, a);
+  const dim3 sg((unsigned)p.work_blocks, (unsigned)ntr);
+  const int nt = plan_spread_threads<DIM, T>(p);
+  if constexpr (DIM == 3) {
+    hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX, 256>), sg, dim3(256), 0, st, a);
+  } else {
+    if (nt == 256)
+      hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX, 256>), sg, dim3(256), 0, st, a);
+    else if (nt == 128)
+      hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX, 128>), sg, dim3(128), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, CPLX, 64>), sg, dim3(64), 0, st, a);
+  }
   // algorithmic bytes: the grid written once, per point its sorted record and its strengths read
   if (prof)
     prof_stop(p, (double)ntr * p.ninst * p.fine_cells() * NCH * sizeof(T) + (double)M * (8 + DIM * sizeof(T)) +
                      (double)ntr * M * NCH * sizeof(T), st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_merge_tiles<T, DIM, NCH, CPLX>), dim3(nb, (unsigned)ntr), dim3(kSpreadThreads), 0, st, a);
+  hipLaunchKernelGGL((k_merge_tiles<T, DIM, NCH, CPLX>), dim3((unsigned)merge_blocks(p), (unsigned)ntr),
+                     dim3(kSpreadThreads), 0, st, a);
   return hipGetLastError();
 }
 
@@ -847,7 +882,7 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
   std::vector<PartLaunch<TilePartsArgs>> tp(n);
   std::vector<PartLaunch<FillWorkArgs>> fw(n);
   std::vector<PartLaunch<SpreadArgs<T>>> sp(n), mg(n);
-  std::vector<int64_t> nbt(n), four(n, 4);
+  std::vector<int64_t> nbt(n), eight(n, 8);
   std::vector<const int*> tparts(n);
   std::vector<int*> poff(n), spart(n);
   std::vector<void*> ctr(n);
@@ -862,9 +897,9 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
     fw[g].nx = (p.nbt + 255) / 256;
     sp[g].a = a;
     sp[g].nx = p.work_blocks;
-    sp[g].threads = spread_threads<DIM, T>();
+    sp[g].threads = plan_spread_threads<DIM, T>(p);
     mg[g].a = a;
-    mg[g].nx = p.nbt;
+    mg[g].nx = merge_blocks(p);
     nbt[g] = p.nbt;
     tparts[g] = p.tile_parts;
     poff[g] = p.part_off;
@@ -876,12 +911,44 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
   if (e != hipSuccess) return e;
   if ((e = launch_parts(tp, FSIB_PARTS(k_tile_parts, k_tile_parts_parts, TilePartsArgs, 256))) != hipSuccess) return e;
   if ((e = launch_scan_group(nbt, tparts, poff, spart, st)) != hipSuccess) return e;
-  if ((e = launch_fill_zero_group(ctr, four, st)) != hipSuccess) return e;
+  if ((e = launch_fill_zero_group(ctr, eight, st)) != hipSuccess) return e;
   if ((e = launch_parts(fw, FSIB_PARTS(k_fill_work, k_fill_work_parts, FillWorkArgs, 256))) != hipSuccess) return e;
-  constexpr int NT = spread_threads<DIM, T>();
-  if ((e = launch_parts(sp, FSIB_PARTS((k_spread<T, DIM, W, NCH, false>), (k_spread_parts<T, DIM, W, NCH, false>),
-                                       SpreadArgs<T>, NT))) != hipSuccess)
-    return e;
+  // parts with different spreading variants run as launches of their own (launch_parts)
+  const auto one = [&](const PartLaunch<SpreadArgs<T>>& L) {
+    const dim3 g1((unsigned)L.nx);
+    if constexpr (DIM == 3) {
+      hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, false, 256>), g1, dim3(256), 0, st, L.a);
+    } else {
+      if (L.threads == 256)
+        hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, false, 256>), g1, dim3(256), 0, st, L.a);
+      else if (L.threads == 128)
+        hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, false, 128>), g1, dim3(128), 0, st, L.a);
+      else
+        hipLaunchKernelGGL((k_spread<T, DIM, W, NCH, false, 64>), g1, dim3(64), 0, st, L.a);
+    }
+    return hipGetLastError();
+  };
+  int thr = 0;  // workgroup size of the parts with work (equal in a launch over parts)
+  for (const auto& L : sp)
+    if (L.nx * L.ny > 0) {
+      thr = L.threads;
+      break;
+    }
+  const auto fused = [&](const Parts<SpreadArgs<T>>& f, int64_t nwg, size_t) {
+    const dim3 g1((unsigned)nwg);
+    if constexpr (DIM == 3) {
+      hipLaunchKernelGGL((k_spread_parts<T, DIM, W, NCH, false, 256>), g1, dim3(256), 0, st, f);
+    } else {
+      if (thr == 256)
+        hipLaunchKernelGGL((k_spread_parts<T, DIM, W, NCH, false, 256>), g1, dim3(256), 0, st, f);
+      else if (thr == 128)
+        hipLaunchKernelGGL((k_spread_parts<T, DIM, W, NCH, false, 128>), g1, dim3(128), 0, st, f);
+      else
+        hipLaunchKernelGGL((k_spread_parts<T, DIM, W, NCH, false, 64>), g1, dim3(64), 0, st, f);
+    }
+    return hipGetLastError();
+  };
+  if ((e = launch_parts(sp, one, fused)) != hipSuccess) return e;
   return launch_parts(mg, FSIB_PARTS((k_merge_tiles<T, DIM, NCH, false>), (k_merge_tiles_parts<T, DIM, NCH, false>),
                                      SpreadArgs<T>, kSpreadThreads));
 }

@@ -4,10 +4,11 @@
 
 `run()` performs one representative unit of work on the plan (a time step, a pair of transforms);
 it is called once per trial to warm up and then `reps` times under the clock.  The search is one
-pass of coordinate descent: the XCD run length of spreading, then that of interpolation, then the
-heavy-tile split, each over a short candidate list, keeping the best value of each before moving on.
-The knobs change only the launch shape (and, for the split, the order in which partial tiles are
-summed), so results agree to rounding whatever is chosen.
+pass of coordinate descent: the spreading variant of 2D plans (threads, i.e. cells per lane, of a
+16 x 16 tile), the XCD run length of spreading, then that of interpolation, the heavy-tile split and
+the points per interpolation wavefront, each over a short candidate list, keeping the best value of
+each before moving on.  The knobs change only the launch shape (and, for the split, the order in
+which partial tiles are summed), so results agree to rounding whatever is chosen.
 """
 
 import time
@@ -15,6 +16,7 @@ import time
 import torch
 
 CANDIDATES = {
+    "spread_threads": (64, 128, 256),  # spreading variant: threads (cells per lane) of a 2D tile
     "xcd_chunk_spread": (0, 4, 16, 64),
     "xcd_chunk_interp": (0, 16, 64, 256),
     "split": (512, 1024, 2048),
@@ -34,6 +36,8 @@ def _time(run, reps):
 
 def autotune(plan, run, reps=3, candidates=None):
     cands = dict(CANDIDATES if candidates is None else candidates)
+    if plan.dim == 3:
+        cands.pop("spread_threads", None)  # one spreading variant for 3D tiles
     best = plan.tuning()
     trials = []
     best_t = _time(run, reps)

@@ -118,7 +118,7 @@ def test_set_instances_rejects_null_plan():
 
 def test_tuning_rejects_null_arguments():
     lib = B.load_library()
-    t = B._Tuning(0, 0, 512, 1, 8)
+    t = B._Tuning(0, 0, 512, 1, 8, 0)
     assert lib.fsib_plan_tuning(None, ctypes.byref(t), 1) == 1
 
 

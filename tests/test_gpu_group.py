@@ -60,9 +60,11 @@ def test_group_matches_plans_stepped_alone(F, prec, tol, rep):
     cases = _cases()
     fused = _batch(cases, prec, tol, True)
     alone = _batch(cases, prec, tol, False)
-    assert len(fused.groups) == 3
+    assert len(fused.groups) == 3 and fused.lanes == 1
     fused.step(3)
-    alone.step(3)
+    for _ in range(3):  # each plan on its own (fsib_step)
+        for g in alone.groups:
+            g["plan"].step(g["params"], g["force"], g["X"], g["U"], g["uh"])
     torch.cuda.synchronize()
     _compare(fused, alone, rep, "fused vs alone")
     if prec == "f64":
@@ -77,6 +79,30 @@ def test_group_matches_plans_stepped_alone(F, prec, tol, rep):
             assert e < 1e-10
     fused.close()
     alone.close()
+
+
+def test_group_lanes_and_autotune(F):
+    """Two lanes (two library groups on two streams) and the autotuner's choice agree with one lane."""
+    announce("group lanes and autotune, FP64")
+    cases = _cases()
+    one = _batch(cases, "f64", 1e-11, True)
+    two = _batch(cases, "f64", 1e-11, True)
+    two.set_lanes(2)
+    assert two.lanes == 2 and sorted(len(gs) for _, gs in two.lane_groups) == [1, 2]
+    one.step(2)
+    two.step(2)
+    torch.cuda.synchronize()
+    _compare(two, one, 1e-12, "two lanes vs one")
+    tuned = _batch(cases, "f64", 1e-11, True)
+    res = tuned.autotune(reps=1)
+    assert set(res["lanes"]) == {1, 2, 3} and tuned.lanes in (1, 2, 3)
+    for _, gs in tuned.lane_groups:  # one spreading variant per lane
+        assert len({g["plan"].tuning()["spread_threads"] for g in gs}) == 1
+    tuned.step(2)
+    torch.cuda.synchronize()
+    _compare(tuned, one, 1e-12, "autotuned vs one lane")
+    for b in (one, two, tuned):
+        b.close()
 
 
 def test_group_graph_replays(F):
