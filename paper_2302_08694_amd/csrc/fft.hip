@@ -29,11 +29,151 @@ static size_t flag_bytes(int nflags) { return (size_t)((nflags + 15) / 16 * 16);
 // precisions (measured at 128^3: 1024 or 4096 entries are slower in FP64, 4096 is slower in FP32)
 constexpr int kFftWgEntries = 2048;
 
+// Middle Stockham stages s = S .. SL-1 of a compile-time strided pass (each reads LDS, synchronises,
+// writes LDS and synchronises).
+template <typename T, int N, int NB, int NTHR, int S, int SL>
+__device__ __forceinline__ void middle_stages(cplx<T>* buf, const cplx<T>* twl, int sign) {
+  if constexpr (S < SL) {
+    stage_ct<T, false, N, NB, NTHR, ct_radix_at(N, S), ct_p_before(N, S), 0>(buf, twl, sign);
+    middle_stages<T, N, NB, NTHR, S + 1, SL>(buf, twl, sign);
+  }
+}
+
+// Strided pass with the length and the line count known at compile time, its first and last Stockham
+// stages in registers: the first stage's butterflies read their inputs straight from memory (zero
+// padding and the per-entry factors folded in) and write the outputs to LDS; the middle stages run in
+// LDS; the last stage reads LDS and stores its outputs straight to memory (truncation, factors and
+// the store mask folded in).  Against staging the whole line in LDS this halves the LDS traffic and
+// drops four workgroup barriers.  Thread bf of a stage owns butterfly i = bf / NB of column
+// b = bf % NB, so the lanes of a wavefront read and write runs of NB adjacent columns.
+template <typename T, int N, int NB>
+__device__ __forceinline__ void c2c_strided_ct(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                               const FftArgs<T>& a, Blk wb) {
+  constexpr int NTHR = N * NB / kEPT;
+  constexpr int NS = ct_nstages(N);
+  static_assert(NS >= 2, "two stages at least");
+  extern __shared__ char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* twl = buf + N * NB;
+  uint8_t* fld = flag_area(twl, N);
+  // plain numbering only where whole lines may be skipped (a line mask): per-entry masks leave
+  // every workgroup some work, so neighbours stay on one XCD
+  const int64_t lin0 = wb.x + wb.y * wb.nx;
+  const int64_t lin = a.line.m ? lin0 : xcd_linear(lin0, wb.nx * wb.ny);
+  const int64_t q0 = (lin % wb.nx) * NB;
+  const int64_t o0 = lin / wb.nx;
+  const int ncol = (int)(a.inner - q0 < NB ? a.inner - q0 : NB);
+  const bool line = !a.line.m || a.line.m[mask_index(a.line, o0, 0)];
+  for (int i = threadIdx.x; i < a.nin; i += NTHR) fld[i] = line && (!a.ld.m || a.ld.m[mask_index(a.ld, o0, i)]);
+  if (!__syncthreads_or(line)) return;
+  const int sign = a.sign;
+  const T sg = (T)sign;
+  constexpr int RL = ct_radix_at(N, NS - 1);
+  constexpr int PL = ct_p_before(N, NS - 1);
+  constexpr int ML = N / RL;
+  constexpr int TOTL = ML * NB;
+  constexpr int NBFL = (TOTL + NTHR - 1) / NTHR;
+  static_assert(NBFL * RL <= 64, "store flags fit 64 bits");
+  // store flags of this thread's outputs (bit j * RL + q), fetched before the stages so their
+  // latency overlaps the data loads
+  const int pout = a.pout, hiout = N - (a.nout - a.pout);  // outputs t in [pout, hiout) are dropped
+  uint64_t keep = 0;
+#pragma unroll
+  for (int j = 0; j < NBFL; ++j) {
+    const int bf = threadIdx.x + j * NTHR;
+    if (!(TOTL % NTHR == 0 || bf < TOTL)) continue;
+    const int i = bf / NB, b = bf - (bf / NB) * NB;
+    const int k = i % PL, j0 = (i - k) * RL + k;
+#pragma unroll
+    for (int q = 0; q < RL; ++q) {
+      const int t = j0 + q * PL;
+      const int io = t < pout ? t : (t >= hiout ? t - (N - a.nout) : -1);
+      const bool kp = io >= 0 && b < ncol && (!a.st.m || a.st.m[mask_index(a.st, o0, io)] != 0);
+      if (kp) keep |= 1ull << (j * RL + q);
+    }
+  }
+  // ---- first stage (radix R0, no twiddles) from memory ----
+  {
+    constexpr int R0 = ct_radix_at(N, 0);
+    constexpr int M0 = N / R0;
+    constexpr int TOT = M0 * NB;
+    constexpr int NBF = (TOT + NTHR - 1) / NTHR;
+    const int pin = a.pin, hi = N - (a.nin - a.pin);  // entries t in [pin, hi) are the zero padding
+    cplx<T> u[NBF][R0];
+#pragma unroll
+    for (int j = 0; j < NBF; ++j) {
+      const int bf = threadIdx.x + j * NTHR;
+      const bool valid = TOT % NTHR == 0 || bf < TOT;
+      const int i = bf / NB, b = bf - (bf / NB) * NB;
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        const int t = i + q * M0;
+        const int ie = t < pin ? t : (t >= hi ? t - (N - a.nin) : -1);
+        u[j][q] = mk((T)0, (T)0);
+        if (valid && ie >= 0 && b < ncol && fld[ie]) {
+          cplx<T> v = in[(o0 * a.nin + ie) * a.inner + q0 + b];
+          if (a.fac_in) v = v * a.fac_in[ie];
+          u[j][q] = v;
+        }
+      }
+    }
+    stage_twiddles(a.tw, twl, N);  // behind the data loads
+#pragma unroll
+    for (int j = 0; j < NBF; ++j) {
+      const int bf = threadIdx.x + j * NTHR;
+      if (TOT % NTHR == 0 || bf < TOT) {
+        const int i = bf / NB, b = bf - (bf / NB) * NB;
+        bfly<T, R0>(u[j], sg);
+#pragma unroll
+        for (int q = 0; q < R0; ++q) buf[(i * R0 + q) * NB + b] = u[j][q];
+      }
+    }
+    __syncthreads();
+  }
+  middle_stages<T, N, NB, NTHR, 1, NS - 1>(buf, twl, sign);
+  // ---- last stage from LDS to memory ----
+  {
+    constexpr int TWS = N / (PL * RL);
+#pragma unroll
+    for (int j = 0; j < NBFL; ++j) {
+      const int bf = threadIdx.x + j * NTHR;
+      if (!(TOTL % NTHR == 0 || bf < TOTL)) continue;
+      if (((keep >> (j * RL)) & ((1ull << RL) - 1)) == 0) continue;  // nothing of this butterfly is stored
+      const int i = bf / NB, b = bf - (bf / NB) * NB;
+      cplx<T> u[RL];
+#pragma unroll
+      for (int q = 0; q < RL; ++q) u[q] = buf[(i + q * ML) * NB + b];
+      const int k = i % PL;
+#pragma unroll
+      for (int q = 1; q < RL; ++q) {
+        cplx<T> w = twl[q * k * TWS];
+        if (sign > 0) w.y = -w.y;
+        u[q] = cmul(u[q], w);
+      }
+      bfly<T, RL>(u, sg);
+      const int j0 = (i - k) * RL + k;
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        if (!((keep >> (j * RL + q)) & 1ull)) continue;
+        const int t = j0 + q * PL;
+        const int io = t < pout ? t : t - (N - a.nout);
+        T f = a.scale;
+        if (a.fac_out) f *= a.fac_out[io];
+        out[(o0 * a.nout + io) * a.inner + q0 + b] = u[q] * f;
+      }
+    }
+  }
+}
+
 // N > 0: a pass of length N with NB lines per workgroup known at compile time (N * NB / kEPT
 // threads); N = 0: any length, from the arguments.
 template <typename T, bool CONTIG, int N = 0, int NB = 0>
 __device__ __forceinline__ void c2c_body(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
                                          const FftArgs<T>& a, Blk wb) {
+  if constexpr (!CONTIG && N > 0) {
+    c2c_strided_ct<T, N, NB>(in, out, a, wb);
+    return;
+  }
   extern __shared__ char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n = N > 0 ? N : a.n, nb = N > 0 ? NB : a.nb, nthr = N > 0 ? N * NB / kEPT : (int)blockDim.x;

@@ -165,19 +165,20 @@ struct ScanArgs {
   int* seg_sum;
 };
 
-template <bool FINAL>
+template <bool FINAL, int EPT = kScanEpt>
 __device__ __forceinline__ void scan_body(const ScanArgs& A, Blk blk) {
+  constexpr int64_t SEG = (int64_t)kScanThreads * EPT;
   __shared__ int wsum[65];
   __shared__ int seg_base;
   const int64_t n = A.n;
   const int* __restrict__ counts = A.counts;
   int* __restrict__ offsets = A.offsets;
   int* __restrict__ seg_sum = A.seg_sum;
-  const int64_t first = blk.x * kScanSeg + (int64_t)threadIdx.x * kScanEpt;
-  int v[kScanEpt];
+  const int64_t first = blk.x * SEG + (int64_t)threadIdx.x * EPT;
+  int v[EPT];
   int run = 0;
 #pragma unroll
-  for (int k = 0; k < kScanEpt; ++k) {
+  for (int k = 0; k < EPT; ++k) {
     v[k] = first + k < n ? counts[first + k] : 0;
     run += v[k];
   }
@@ -199,16 +200,19 @@ __device__ __forceinline__ void scan_body(const ScanArgs& A, Blk blk) {
   }
   excl += seg_base;
 #pragma unroll
-  for (int k = 0; k < kScanEpt; ++k) {
+  for (int k = 0; k < EPT; ++k) {
     if (first + k <= n) offsets[first + k] = excl;
     excl += v[k];
   }
 }
 
-template <bool FINAL>
+template <bool FINAL, int EPT = kScanEpt>
 __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
-  scan_body<FINAL>(a, launch_blk());
+  scan_body<FINAL, EPT>(a, launch_blk());
 }
+// One workgroup of 8 entries per thread covers up to 8191 entries in a single pass (the bins of a 3D
+// plan), where the segmented scan would take two launches.
+constexpr int64_t kScanOnePass = (int64_t)kScanThreads * 8;
 template <bool FINAL>
 __global__ __launch_bounds__(kScanThreads) void k_scan_parts(Parts<ScanArgs> f) {
   Blk b;
@@ -404,11 +408,13 @@ __device__ __forceinline__ void row_masks(const RowMaskArgs& A, Blk blk) {
   const int inst = tg / (nt1 * nt2), t = tg - inst * nt1 * nt2;
   const int yb = t % nt1, zb = t / nt1;
   const int* ci = counts + (int64_t)inst * nt0 * nt1 * nt2;
+  // every count of the reaching bins is read (no early exit), so the loads go out together
   int any = 0;
-  for (int dz = 0; dz <= qz && !any; ++dz)
-    for (int dy = 0; dy <= qy && !any; ++dy) {
+  for (int dz = 0; dz <= qz; ++dz)
+    for (int dy = 0; dy <= qy; ++dy) {
       const int by = (yb - dy + nt1) % nt1, bz = (zb - dz + nt2) % nt2;
       const int* c = ci + (int64_t)(bz * nt1 + by) * nt0;
+#pragma unroll 8
       for (int bx = 0; bx < nt0; ++bx) any |= c[bx];
     }
   A.rowmask[tg] = any ? 1 : 0;
@@ -470,6 +476,10 @@ int64_t scan_segments(int64_t n) { return n / kScanSeg + 1; }
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum, hipStream_t st) {
   const int64_t nseg = scan_segments(n);
   const ScanArgs a{n, counts, offsets, seg_sum};
+  if (n < kScanOnePass) {  // n + 1 outputs in one segment
+    hipLaunchKernelGGL((k_scan<true, 8>), dim3(1), dim3(kScanThreads), 0, st, a);
+    return hipGetLastError();
+  }
   if (nseg > 1) {
     hipLaunchKernelGGL(k_scan<false>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, a);
     hipError_t e = hipGetLastError();

@@ -469,29 +469,52 @@ __global__ void k_fill_work_parts(Parts<FillWorkArgs> f) {
 // Sum the partial tiles of every split tile in part order and write it to the grid: workgroup k takes
 // entry k of the list of split tiles (launched over a bound on their number; the workgroups past the
 // count leave at once).  The list's order does not matter: each tile is summed on its own.
+// Workgroups per split tile: one per 256 cells (3D tiles have 1024), so that the sums over the parts
+// of one crowded tile run in parallel.
+template <int DIM>
+__host__ __device__ constexpr int merge_chunks() { return DIM == 3 ? 4 : 1; }
+
 template <typename T, int DIM, int NCH, bool CPLX>
-__device__ __forceinline__ void merge_one_tile(const SpreadArgs<T>& a, int t, int np, int tr);
+__device__ __forceinline__ void merge_one_tile(const SpreadArgs<T>& a, int t, int np, int tr, int chunk);
 
 template <typename T, int DIM, int NCH, bool CPLX>
 __device__ __forceinline__ void merge_tiles(const SpreadArgs<T>& a, Blk wb) {
-  if (wb.x >= a.split_cnt[0]) return;
-  const int t = a.split_list[wb.x];
-  merge_one_tile<T, DIM, NCH, CPLX>(a, t, a.tile_parts[t], (int)wb.y);
+  constexpr int MC = merge_chunks<DIM>();
+  const int64_t k = wb.x / MC;
+  if (k >= a.split_cnt[0]) return;
+  const int t = a.split_list[k];
+  merge_one_tile<T, DIM, NCH, CPLX>(a, t, a.tile_parts[t], (int)wb.y, (int)(wb.x - k * MC));
 }
 
 template <typename T, int DIM, int NCH, bool CPLX>
-__device__ __forceinline__ void merge_one_tile(const SpreadArgs<T>& a, int t, int np, int tr) {
+__device__ __forceinline__ void merge_one_tile(const SpreadArgs<T>& a, int t, int np, int tr, int chunk) {
+  constexpr int MC = merge_chunks<DIM>();
   const int nbins = a.nt[0] * a.nt[1] * (DIM == 3 ? a.nt[2] : 1);
   const int inst = t / nbins, lt = t - inst * nbins;
   const int tcoord[3] = {lt % a.nt[0], (lt / a.nt[0]) % a.nt[1], DIM == 3 ? lt / (a.nt[0] * a.nt[1]) : 0};
   const int rows = a.tb[1] * (DIM == 3 ? a.tb[2] : 1);
   const int64_t cells = (int64_t)a.nf[0] * a.nf[1] * (DIM == 3 ? a.nf[2] : 1);
   const T* src = a.scratch + ((int64_t)tr * a.slots + a.tile_slot[t]) * NCH * kMaxTileCells;
-  for (int i = threadIdx.x; i < kTileX * rows; i += kSpreadThreads) {
+  const int per = kTileX * rows / MC;  // cells of this workgroup's chunk
+  for (int i = chunk * per + threadIdx.x; i < (chunk + 1) * per; i += kSpreadThreads) {
     T v[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) v[ch] = (T)0;
-    for (int q = 0; q < np; ++q)
+    // the partial tiles in part order, eight loads in flight at a time (a crowded tile has tens of
+    // parts, and one load after another left the merge waiting on memory)
+    int q = 0;
+    for (; q + 8 <= np; q += 8) {
+      T l[8][NCH];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) l[u][ch] = src[((int64_t)(q + u) * NCH + ch) * kMaxTileCells + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) v[ch] += l[u][ch];
+    }
+    for (; q < np; ++q)
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) v[ch] += src[((int64_t)q * NCH + ch) * kMaxTileCells + i];
     const int lx = i % kTileX, rw = i / kTileX;
@@ -818,7 +841,9 @@ static FillWorkArgs fill_work_args(const Plan& p) {
 }
 
 // Bound on the split tiles: each takes at least two of the split_slots scratch slots.
-static int64_t merge_blocks(const Plan& p) { return p.split_slots / 2 + 1; }
+static int64_t merge_blocks(const Plan& p) {
+  return (p.split_slots / 2 + 1) * (p.dim == 3 ? merge_chunks<3>() : merge_chunks<2>());
+}
 
 template <typename T, int DIM, int NCH, bool CPLX, int W>
 static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipStream_t st) {
