@@ -33,6 +33,49 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
   const int64_t cs = rows * hx;  // component stride of in/out
   // ---- gather the Hermitian-extended lines (inverse) ----
   const int nin = IL * pp * n;
+  // With every size fixed at compile time and the threads dividing into the lines, each thread owns
+  // JP positions t = tl + TPL j of one line: its line's component, rows and base pointers are worked
+  // out once, and consecutive threads read consecutive modes.
+  constexpr bool LINE_MAP = N > 0 && HX > 0 && NTHR % (IL * PP) == 0 && N % (NTHR / (IL * PP > 0 ? IL * PP : 1)) == 0;
+  if constexpr (LINE_MAP) {
+    constexpr int TPL = NTHR / (IL * PP), JP = N / TPL;
+    const int ln = threadIdx.x / TPL, tl = threadIdx.x - ln * TPL;
+    const int q = ln / IL, l = ln - q * IL;
+    const int64_t ra = 2 * (pair0 + q), rb = ra + 1;
+    // line l: (comp, row) of its real part A and imaginary part B
+    const int ca = l == 2 ? 2 : 0, cb = l == 2 ? 2 : 1;
+    const int64_t rowa = l == 1 ? rb : ra, rowb = l == 0 ? ra : rb;
+    const cplx<T>* pa = rowa < rows ? in + ca * cs + rowa * HX : nullptr;
+    const cplx<T>* pb = rowb < rows ? in + cb * cs + rowb * HX : nullptr;
+    cplx<T> A[JP], B[JP];
+#pragma unroll
+    for (int j = 0; j < JP; ++j) {
+      const int t = tl + TPL * j;
+      const int m = 2 * t <= N ? t : N - t;
+      A[j] = mk((T)0, (T)0);
+      B[j] = mk((T)0, (T)0);
+      if (m < HX) {
+        if (pa) A[j] = pa[m];
+        if (pb) B[j] = pb[m];
+      }
+    }
+    stage_twiddles(a.tw, twl, N);  // behind the data loads, so both latencies overlap
+#pragma unroll
+    for (int j = 0; j < JP; ++j) {
+      const int t = tl + TPL * j;
+      const bool front = 2 * t <= N;
+      const int m = front ? t : N - t;
+      cplx<T> x = A[j], y = B[j];
+      if (m == 0 || 2 * m == N) {
+        x.y = (T)0;
+        y.y = (T)0;
+      } else if (!front) {
+        x = conj(x);
+        y = conj(y);
+      }
+      buf[lpad(ln * N + t)] = mk(x.x - y.y, x.y + y.x);
+    }
+  } else {
   cplx<T> A[GJ], B[GJ];
 #pragma unroll
   for (int j = 0; j < GJ; ++j) {
@@ -78,6 +121,7 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
       }
       buf[lpad(e)] = mk(x.x - y.y, x.y + y.x);
     }
+  }
   }
   __syncthreads();
   if constexpr (N > 0)
@@ -125,6 +169,32 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
   else
     stockham<T, true>(a, buf, twl, FL * pp, -1);
   // ---- unpack the two rows of each line, keep m < Hx ----
+  constexpr bool STORE_MAP = N > 0 && HX > 0 && NTHR % (FL * PP > 0 ? FL * PP : 1) == 0;
+  if constexpr (STORE_MAP) {
+    // each thread owns modes m = ml + TPS j of one line (consecutive threads, consecutive modes)
+    constexpr int TPS = NTHR / (FL * PP), JS = (HX + TPS - 1) / TPS;
+    const int ln = threadIdx.x / TPS, ml = threadIdx.x - ln * TPS;
+    const int q = ln / FL, f = ln - q * FL;
+    const int64_t ra = 2 * (pair0 + q), rb = ra + 1;
+    if (ra < rows) {
+      cplx<T>* oa = out + f * cs + ra * HX;
+      cplx<T>* ob = out + f * cs + rb * HX;
+      const bool hasb = rb < rows;
+      const T sc = (T)0.5 * inv_cells;
+#pragma unroll
+      for (int j = 0; j < JS; ++j) {
+        const int m = ml + TPS * j;
+        if (m < HX) {
+          const cplx<T> Z = buf[lpad(ln * N + m)];
+          const cplx<T> Zc = conj(buf[lpad(ln * N + (m == 0 ? 0 : N - m))]);
+          const cplx<T> su = Z + Zc, d = Z - Zc;
+          oa[m] = su * sc;
+          if (hasb) ob[m] = mk(d.y * sc, -d.x * sc);
+        }
+      }
+    }
+    return;
+  }
   const int nst = FL * pp * hx;
   constexpr int SJ = HX > 0 ? (FL * PP * HX + NTHR - 1) / NTHR : 1;  // compile-time trip count
 #pragma unroll
