@@ -36,7 +36,7 @@ struct Plan {
   int lds_max = 65536;  // LDS bytes one workgroup may allocate on this device
   int xcd_chunk_interp = 64;  // interpolation workgroups kept together per XCD (2048 sorted points)
   int xcd_chunk_spread = 16;  // spreading tiles kept together per XCD (0: plain numbering)
-  int split = 512;            // candidates per part of a heavy spreading tile (sweep: 1024, 512, 256, 128)
+  int split = 512;            // candidates per part of a heavy spreading tile (set at creation: 256 up to 2^18 points)
   int split_alloc = 512;      // the split the work list and scratch were sized for (split >= it)
   // kernel
   int w = 0, deg = 0;

@@ -19,7 +19,7 @@ CANDIDATES = {
     "spread_threads": (64, 128, 256),  # spreading variant: threads (cells per lane) of a 2D tile
     "xcd_chunk_spread": (0, 4, 16, 64),
     "xcd_chunk_interp": (0, 16, 64, 256),
-    "split": (512, 1024, 2048),
+    "split": (256, 512, 1024, 2048),
     "interp_points": (4, 8),
 }
 

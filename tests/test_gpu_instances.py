@@ -192,7 +192,7 @@ def test_tuning_knobs_keep_results(F):
     plan = F.Plan(3, (24, 24, 24), prec="f64", tol=1e-10, max_points=3000)
     X, c, f = dev(X0), dev(c0), dev(f0)
     base = plan.tuning()
-    assert base["split"] == 512
+    assert base["split"] == 256  # the creation value of a plan of at most 2^18 points
     r0 = (host(plan.spread(X, c)), host(plan.interp(X, f)))
     for knobs in ({"xcd_chunk_spread": 0, "xcd_chunk_interp": 0}, {"xcd_chunk_spread": 64, "split": 2048},
                   {"xcd_chunk_interp": 256, "split": 600}, {"interp_points": 1}, {"interp_points": 16}):
@@ -200,7 +200,7 @@ def test_tuning_knobs_keep_results(F):
         r = (host(plan.spread(X, c)), host(plan.interp(X, f)))
         assert rel_l2(r[0], r0[0]) < 1e-13 and rel_l2(r[1], r0[1]) < 1e-15
     with pytest.raises(F.FSIBError):
-        plan.tuning(split=256)  # below the creation value
+        plan.tuning(split=128)  # below the creation value
     with pytest.raises(F.FSIBError):
         plan.tuning(interp_points=3)
     res = autotune(plan, lambda: (plan.spread(X, c), plan.interp(X, f)), reps=1)
