@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--serial", action="store_true",
                     help="run the point side of each half step on the caller's stream (plan tuning overlap = 0) "
                          "instead of concurrently on the plan's second stream")
+    ap.add_argument("--batch-lanes", type=int, default=0,
+                    help="run only a few steps of the 64-instance 2D Stokes batch (FP32, tol 1e-5) with this many "
+                         "lanes of library groups (1: one launch per stage over all plans), e.g. for a kernel trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -598,7 +601,7 @@ ROOFLINE_KERNEL = "fsib::k_fft_c2c<double, false, 192, 8>"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, factors from a plain 512 MiB copy); None once the kernel changes after the counters
-TRAFFIC_BYTES_PER_LAUNCH = 178.3e6
+TRAFFIC_BYTES_PER_LAUNCH = 178.5e6
 TRAFFIC_SOURCE = "profiles/fft_strided_ns128_f64_hbm_counters.md"
 
 
@@ -634,6 +637,21 @@ def main():
             cases = [(int(n_), int(m_), p_, float(t_))]
         print(json.dumps({"metric": "NUFFT micro-benchmark only (profiling run)",
                           "nufft_micro": nufft_micro(F, torch, cases, a.nufft_reps)}), flush=True)
+        return
+    if a.batch_lanes > 0:
+        import workloads
+        from paper_2302_08694_amd.batch import StokesGroupBatch
+        cases = workloads.batched_stokes2d(count=64, seed=4)
+        b = StokesGroupBatch(cases, prec="f32", tol=1e-5, lanes=a.batch_lanes)
+        b.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(5)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 5 * 1e3
+        print(json.dumps({"metric": "batched 2D Stokes steps only (profiling run)", "lanes": b.lanes,
+                          "plans": len(b.groups), "ms_per_batch_step": ms}), flush=True)
+        b.close()
         return
     log("setup FP64")
     s64 = setup(F, torch, "f64", a.tol, a.n, a.rings, upsampfac=a.upsampfac, overlap=not a.serial)
