@@ -479,10 +479,13 @@ def _half_spectrum_l2_diff(hc, Nc, hf, Nf):
 def test_circle_navier_stokes_space_time_convergence(F):
     """Sec. 6.2.1 (space and time refined together, FSIB half): the circle with sine flow from N = 8,
     dt = 1e-3, N_b = 26, halving dt and doubling N and N_b up to N = 512, to t = 0.1; successive
-    relative L2 differences of the velocity field over the box.  The paper fits order 3/2; measured
-    here 0.89, 1.39, 1.44, 1.33, 1.22 (1.13 at N = 1024): above first order over N = 16 to 256, with
-    the point positions converging at first order (as the Stokes velocity at the points does) and
-    the order falling toward one on the finest grids."""
+    relative L2 differences of the velocity field over the box.  The paper fits order 3/2, which is
+    what a velocity with a kink along the curve gives in the box L2 norm: the error is O(h) in a band
+    of width O(h) around the curve, O(h^{3/2}) in L2.  Bars, fixed from that reasoning: the least-squares
+    order over N = 16 to 256 within 3/2 +- 1/4, and every successive order from N = 16 on above one
+    (the first-order floor of the method at the points).  Last runs: successive orders 0.89, 1.39,
+    1.44, 1.33, 1.22 (1.13 at N = 1024), falling toward one on the finest grids, where the points'
+    first-order error (the Stokes velocity at the points converges at first order) takes over."""
     T = 0.1
     spectra = []
     for k in range(7):
@@ -506,7 +509,11 @@ def test_circle_navier_stokes_space_time_convergence(F):
     orders = [float(np.log2(errs[i] / errs[i + 1])) for i in range(len(errs) - 1)]
     print("2D NS space-time: L2 differences " + ", ".join(f"{e:.3e}" for e in errs)
           + "; orders " + ", ".join(f"{o:.2f}" for o in orders))
-    assert all(o > 1.25 for o in orders[1:4]) and all(o > 1.0 for o in orders[1:])
+    # least-squares slope of log(err) against log(N) over the differences N = 16/32 .. 256/512
+    ns = np.log2([spectra[i][0] for i in range(1, 5)])
+    fit = -float(np.polyfit(ns, np.log2(errs[1:5]), 1)[0])
+    print(f"2D NS space-time: fitted order over N = 16..256: {fit:.2f}")
+    assert 1.25 < fit < 1.75 and all(o > 1.0 for o in orders[1:])
 
 
 def test_circle_pressure_jump_width_settles_to_a_fixed_multiple_of_h(F):
