@@ -149,11 +149,13 @@ class StokesGroupBatch:
         from ._binding import Group
         for grp, _ in self.lane_groups:
             grp.close()
-        lanes = max(1, min(int(lanes), len(self.groups)))
+        # a library group holds at most 8 plans
+        lanes = max(1, -(-len(self.groups) // 8), min(int(lanes), len(self.groups)))
         load = [0] * lanes
         members = [[] for _ in range(lanes)]
         for g in sorted(self.groups, key=lambda g: -g["work"]):
-            k = load.index(min(load))
+            open_lanes = [i for i in range(lanes) if len(members[i]) < 8]
+            k = min(open_lanes, key=lambda i: load[i])
             members[k].append(g)
             load[k] += g["work"]
         self.lane_groups = [(Group([g["plan"] for g in m]), m) for m in members if m]
@@ -206,7 +208,8 @@ class StokesGroupBatch:
             run = lambda g=g: g["plan"].step(g["params"], g["force"], g["X"], g["U"], g["uh"])
             chosen[g["plan"].n_modes[0]] = autotune(g["plan"], run, reps=reps)["best"]
         self._restore(saved)
-        cands = lanes if lanes is not None else sorted({1, min(2, len(self.groups)), len(self.groups)})
+        least = -(-len(self.groups) // 8)  # lanes needed for groups of at most 8 plans
+        cands = lanes if lanes is not None else sorted({least, min(max(2, least), len(self.groups)), len(self.groups)})
         times = {}
         for c in cands:
             self._lanes_with_shared_variant(c)
