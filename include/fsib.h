@@ -357,8 +357,9 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
  * launch per plan.
  *
  * fsib_group_create: nplans in [1, 8] distinct plans (host array) with fluid = 1, navier_stokes = 0,
- * deterministic = 0, and one device, dim, prec and kernel width w (the same tol and upsampfac give
- * the same w).  The group keeps the plan handles, not copies: the plans must outlive the group and
+ * and one device, dim, prec and kernel width w (the same tol and upsampfac give the same w).
+ * Deterministic plans keep their bitwise reproducibility in a group (their ranking passes run as
+ * launches of their own).  The group keeps the plan handles, not copies: the plans must outlive the group and
  * are not used on their own while a group call on them may still run.  Errors: FSIB_ERR_ARG. */
 typedef struct fsib_group_s* fsib_group;
 fsib_status fsib_group_create(int nplans, const fsib_plan* plans, fsib_group* out);

@@ -1234,7 +1234,6 @@ fsib_status fsib_group_create(int nplans, const fsib_plan* plans, fsib_group* ou
     const Plan& p = plans[g]->p;
     const Plan& p0 = plans[0]->p;
     if (!p.fluid || p.ns) return fail(FSIB_ERR_ARG, "group plans need fluid = 1 and navier_stokes = 0 (Stokes)");
-    if (p.deterministic) return fail(FSIB_ERR_ARG, "deterministic plans cannot join a group");
     if (p.device != p0.device || p.dim != p0.dim || p.prec != p0.prec || p.w != p0.w || p.deg != p0.deg)
       return fail(FSIB_ERR_ARG, "group plans need one device, dimension, precision and kernel width");
   }

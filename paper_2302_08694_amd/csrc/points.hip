@@ -592,7 +592,7 @@ hipError_t launch_scan_group(const std::vector<int64_t>& n, const std::vector<co
 }
 
 // launch_sort_points for the plans of a group (plan g with M[g] points at X[g]), each stage one launch
-// over all plans.  The plans are not deterministic ones (the group refuses them).
+// over all plans (the ranking passes of deterministic plans one launch per plan).
 hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t* M, const double* const* X,
                                     hipStream_t st) {
   const size_t n = ps.size();
@@ -621,6 +621,16 @@ hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t*
   if ((e = launch_parts(rm, FSIB_PARTS_256(k_row_masks, k_row_masks_parts, RowMaskArgs))) != hipSuccess) return e;
   if ((e = launch_parts(pm, FSIB_PARTS_256(k_plane_masks, k_plane_masks_parts, PlaneMaskArgs))) != hipSuccess)
     return e;
+  for (size_t g = 0; g < n; ++g) {  // deterministic plans: ranks by original index, each plan on its own
+    const Plan& p = *ps[g];
+    if (!p.deterministic || M[g] <= 0) continue;
+    hipLaunchKernelGGL(k_bin_place, dim3((unsigned)((M[g] + 255) / 256)), dim3(256), 0, st, M[g],
+                       (const int*)p.offsets, (const int*)p.pt_bin, (const int*)p.pt_rank, p.det_key);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_rank, dim3((unsigned)p.nbt), dim3(kRankThreads), 0, st, (const int*)p.offsets,
+                       (const int*)p.det_key, p.pt_rank);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   return ps[0]->prec == FSIB_F64 ? scatter_group<double>(ps, M, X, st) : scatter_group<float>(ps, M, X, st);
 }
 

@@ -11,8 +11,8 @@ all plans.
 * Mixed launch shapes: fine-grid lengths without compile-time passes or with other thread counts
   (the stages fall back to one launch per plan), one-instance plans beside multi-instance ones, and
   3D plans with the surface force (the force stage falls back to the plans' own launches).
-* Refusals: plans of different precision or kernel width, Navier-Stokes and deterministic plans,
-  more than 8 plans.
+* Deterministic plans: a group's steps equal the plans' own steps bitwise, and repeat bitwise.
+* Refusals: plans of different precision or kernel width, Navier-Stokes plans, more than 8 plans.
 """
 
 import numpy as np
@@ -200,6 +200,51 @@ def test_group_3d_surface(F):
         p.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_group_deterministic_bitwise(F, prec):
+    """Deterministic plans of N = 24, 32 (two instances) and 40: group steps equal each plan's own
+    fsib_step bitwise, and a second run repeats them bitwise."""
+    announce(f"deterministic group bitwise {prec}")
+    tol = 1e-10 if prec == "f64" else 1e-5
+    specs = [((24, 24), 1, [90]), ((32, 32), 2, [70, 64]), ((40, 40), 1, [120])]
+    def build():
+        plans, params, forces, states = [], [], [], []
+        for k, (N, ni, Ms) in enumerate(specs):
+            Xs = [workloads.ellipse_2d(m, center=(0.45 + 0.03 * i, 0.5 + 0.02 * k), a=0.22, b=0.14) for i, m in enumerate(Ms)]
+            X0 = np.concatenate(Xs)
+            p = F.Plan(2, N, prec=prec, tol=tol, max_points=X0.shape[0], fluid=True, ninst=ni, deterministic=True)
+            if ni > 1:
+                p.set_instances(Ms)
+            prm = F.FluidParams("stokes", mu=1.0, dt=2e-3)
+            frc = F.Force("tension2d", 1.0)
+            plans.append(p)
+            params.append(prm)
+            forces.append(frc)
+            states.append(_plan_state(F, p, prm, frc, X0))
+        return plans, params, forces, states
+    runs = []
+    for _ in range(2):
+        plans, params, forces, states = build()
+        grp = F.Group(plans)
+        grp.steps(params, forces, [s[0] for s in states], [s[1] for s in states], [s[2] for s in states], 3)
+        torch.cuda.synchronize()
+        runs.append([(host(X), host(U), host(uh)) for X, U, uh in states])
+        grp.close()
+        for p in plans:
+            p.close()
+    plans, params, forces, states = build()
+    for p, prm, frc, (X, U, uh) in zip(plans, params, forces, states):
+        for _ in range(3):
+            p.step(prm, frc, X, U, uh)
+    alone = [(host(X), host(U), host(uh)) for X, U, uh in states]
+    for p in plans:
+        p.close()
+    for a, b, c in zip(runs[0], runs[1], alone):
+        for x, y, z in zip(a, b, c):
+            assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+            assert np.array_equal(x.view(np.uint8), z.view(np.uint8))
+
+
 def test_group_refusals(F):
     announce("group refusals")
     a = F.Plan(2, (16, 16), prec="f64", tol=1e-8, max_points=64, fluid=True)
@@ -207,7 +252,8 @@ def test_group_refusals(F):
     c = F.Plan(2, (32, 32), prec="f64", tol=1e-4, max_points=64, fluid=True)  # another kernel width
     d = F.Plan(2, (32, 32), prec="f64", tol=1e-8, max_points=64, fluid=True, navier_stokes=True)
     e = F.Plan(2, (32, 32), prec="f64", tol=1e-8, max_points=64, fluid=True, deterministic=True)
-    for other in (b, c, d, e):
+    F.Group([a, e]).close()  # deterministic plans may join
+    for other in (b, c, d):
         with pytest.raises(F.FSIBError):
             F.Group([a, other])
     with pytest.raises(F.FSIBError):
