@@ -660,8 +660,8 @@ static hipError_t c2c_group(const std::vector<FftCall>& calls, hipStream_t st) {
     const bool ct = contig == 1;
     const hipError_t e = launch_parts(
         v, [&](const PartLaunch<FftIO<T>>& L) { return c2c_one<T>(L, ct, st); },
-        [&](const Parts<FftIO<T>>& f, int64_t nwg, size_t lds) {
-          const dim3 grid((unsigned)nwg), thr(v[0].threads);
+        [&](const Parts<FftIO<T>>& f, int64_t nwg, size_t lds, int nthr) {
+          const dim3 grid((unsigned)nwg), thr(nthr);
           const bool c = all_ct(f);
           if (ct && c) hipLaunchKernelGGL((k_fft_c2c_parts<T, true, true>), grid, thr, lds, st, f);
           else if (ct) hipLaunchKernelGGL((k_fft_c2c_parts<T, true, false>), grid, thr, lds, st, f);
@@ -788,8 +788,8 @@ static hipError_t x_group(const std::vector<FftCall>& calls, bool r2c, hipStream
   for (const FftCall& c : calls) v.push_back(x_launch<T>(c, r2c));
   return launch_parts(
       v, [&](const PartLaunch<FftIO<T>>& L) { return x_one<T>(L, r2c, st); },
-      [&](const Parts<FftIO<T>>& f, int64_t nwg, size_t lds) {
-        const dim3 grid((unsigned)nwg), thr(v[0].threads);
+      [&](const Parts<FftIO<T>>& f, int64_t nwg, size_t lds, int nthr) {
+        const dim3 grid((unsigned)nwg), thr(nthr);
         const bool c = all_ct(f);
         if (r2c && c) hipLaunchKernelGGL((k_fft_r2c_x_parts<T, true>), grid, thr, lds, st, f);
         else if (r2c) hipLaunchKernelGGL((k_fft_r2c_x_parts<T, false>), grid, thr, lds, st, f);

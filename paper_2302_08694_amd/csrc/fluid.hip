@@ -176,7 +176,7 @@ static hipError_t fluid_stokes_group(const std::vector<Plan*>& ps, const fsib_fl
   for (size_t g = 0; g < ps.size(); ++g) v[g] = fluid_launch<T>(*ps[g], FLUID_STOKES, prm[g], ps[g]->fhat, nullptr, uhat[g]);
   return launch_parts(
       v, [&](const PartLaunch<FluidArgs<T>>& L) { return fluid_one<T, DIM>(L, st); },
-      [&](const Parts<FluidArgs<T>>& f, int64_t nwg, size_t) {
+      [&](const Parts<FluidArgs<T>>& f, int64_t nwg, size_t, int) {
         hipLaunchKernelGGL((k_fluid_parts<T, DIM>), dim3((unsigned)nwg), dim3(256), 0, st, f);
         return hipGetLastError();
       });
@@ -619,7 +619,7 @@ static hipError_t curve_group(const std::vector<Plan*>& ps, const fsib_force* f,
         hipLaunchKernelGGL(k_curve_force_strengths<T>, dim3((unsigned)L.nx), dim3(256), 0, st, L.a);
         return hipGetLastError();
       },
-      [&](const Parts<CurveArgs<T>>& fp, int64_t nwg, size_t) {
+      [&](const Parts<CurveArgs<T>>& fp, int64_t nwg, size_t, int) {
         hipLaunchKernelGGL(k_curve_force_strengths_parts<T>, dim3((unsigned)nwg), dim3(256), 0, st, fp);
         return hipGetLastError();
       });

@@ -133,7 +133,8 @@ struct PartLaunch {
 };
 
 // One launch for all parts when there are several that share a workgroup size (`fused(parts,
-// workgroups, lds)`), else a launch per part (`one(part)`); parts with an empty grid are left out.
+// workgroups, lds, threads)`), else a launch per part (`one(part)`); parts with an empty grid are left
+// out.
 template <class A, class One, class Fused>
 hipError_t launch_parts(const std::vector<PartLaunch<A>>& v, One one, Fused fused) {
   static_assert(sizeof(Parts<A>) <= 4096, "kernel arguments of a launch over parts");
@@ -168,7 +169,7 @@ hipError_t launch_parts(const std::vector<PartLaunch<A>>& v, One one, Fused fuse
   }
   if (s >= ((int64_t)1 << 32) - kXcds) return hipErrorInvalidConfiguration;
   for (int g = f.n; g <= kMaxParts; ++g) f.start[g] = (uint32_t)s;
-  return fused(f, s, lds);
+  return fused(f, s, lds, live[0]->threads);
 }
 
 // ---- launchers (all asynchronous on `st`) ----

@@ -511,7 +511,7 @@ static hipError_t launch_scan_parts(const std::vector<ScanArgs>& scans, hipStrea
     };
   };
   auto fused = [&](bool final_pass) {
-    return [=](const Parts<ScanArgs>& f, int64_t nwg, size_t) {
+    return [=](const Parts<ScanArgs>& f, int64_t nwg, size_t, int) {
       if (final_pass)
         hipLaunchKernelGGL(k_scan_parts<true>, dim3((unsigned)nwg), dim3(kScanThreads), 0, st, f);
       else
@@ -569,7 +569,7 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
     hipLaunchKernelGGL(k1, dim3((unsigned)L.nx, (unsigned)L.ny), dim3(256), 0, st, L.a);                      \
     return hipGetLastError();                                                                                \
   },                                                                                                         \
-      [&](const Parts<Args>& f, int64_t nwg, size_t) {                                                       \
+      [&](const Parts<Args>& f, int64_t nwg, size_t, int) {                                                  \
         hipLaunchKernelGGL(kp, dim3((unsigned)nwg), dim3(256), 0, st, f);                                    \
         return hipGetLastError();                                                                            \
       }

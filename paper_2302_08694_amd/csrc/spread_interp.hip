@@ -892,7 +892,7 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
     hipLaunchKernelGGL(k1, dim3((unsigned)L.nx, (unsigned)L.ny), dim3(nt), 0, st, L.a);                       \
     return hipGetLastError();                                                                                \
   },                                                                                                         \
-      [&](const Parts<Args>& f, int64_t nwg, size_t) {                                                       \
+      [&](const Parts<Args>& f, int64_t nwg, size_t, int) {                                                  \
         hipLaunchKernelGGL(kp, dim3((unsigned)nwg), dim3(nt), 0, st, f);                                     \
         return hipGetLastError();                                                                            \
       }
@@ -953,13 +953,7 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
     }
     return hipGetLastError();
   };
-  int thr = 0;  // workgroup size of the parts with work (equal in a launch over parts)
-  for (const auto& L : sp)
-    if (L.nx * L.ny > 0) {
-      thr = L.threads;
-      break;
-    }
-  const auto fused = [&](const Parts<SpreadArgs<T>>& f, int64_t nwg, size_t) {
+  const auto fused = [&](const Parts<SpreadArgs<T>>& f, int64_t nwg, size_t, int thr) {
     const dim3 g1((unsigned)nwg);
     if constexpr (DIM == 3) {
       hipLaunchKernelGGL((k_spread_parts<T, DIM, W, NCH, false, 256>), g1, dim3(256), 0, st, f);
