@@ -612,8 +612,7 @@ fsib_status check_force(const fsib_force* f, int dim, int64_t M) {
 fsib_status stokes_velocity(Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M, const double* X,
                             void* U, void* uhat, hipStream_t st) {
   const double Ld = p.dim == 3 ? p.L * p.L * p.L : p.L * p.L;
-  FSIB_HIP(fsib::launch_force_plan(p, f, M, X, p.F64, st));
-  FSIB_HIP(fsib::launch_weighted_strengths(p, f.kind, M, p.F64, p.S, st));
+  FSIB_HIP(fsib::launch_force_strengths(p, f, M, X, p.F64, p.S, st));
   FSIB_HIP(fsib::launch_sort_points(p, M, X, st));
   FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, st));
   FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_STOKES, prm, p.fhat, nullptr, uhat, st));
@@ -799,8 +798,11 @@ fsib_status spread_in_workspace(fsib_plan plan, int device, int64_t M, const dou
                                   "scratch holds " + std::to_string(ws_bytes) + " bytes (fewer points, modes or ntrans)");
   carve_transform_buffers(p, M, static_cast<char*>(ws), b);
   swap_transform_buffers(p, b);
+  const bool counts_zero = p.counts_zero;
+  p.counts_zero = false;  // the workspace's counts hold whatever the last call left
   const fsib_status s = type1_complex(p, M, X, c, fhat, scale, S(stream));
   swap_transform_buffers(p, b);
+  p.counts_zero = counts_zero;  // the plan's own counts are untouched
   return s;
 }
 
@@ -1187,8 +1189,7 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     // X^{m+1/2} = X^m + dt/2 U^m (eq. spatial_1); F^{m+1/2} and fhat^{m+1/2} (eq. force_spreading_quad),
     // beside the products of uhat^m
     FSIB_HIP(fsib::launch_axpy_positions(p, M, p.Xh, X, U, 0.5 * dt, s2));
-    FSIB_HIP(fsib::launch_force(*force, p.dim, M, p.Xh, p.F64, s2));
-    FSIB_HIP(fsib::launch_weighted_strengths(p, force->kind, M, p.F64, p.S, s2));
+    FSIB_HIP(fsib::launch_force_strengths(p, *force, M, p.Xh, p.F64, p.S, s2));
     FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, s2));
     FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, s2));
     FSIB_HIP(hipEventRecord(p.fj[1], s2));

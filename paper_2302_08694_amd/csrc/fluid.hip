@@ -272,10 +272,14 @@ __global__ void k_force_curve(int64_t M, const double* __restrict__ X, double K,
 // triangle's cyclic order starting at i) of (X_j - X_k) x n, n the unit normal of (X_i, X_j, X_k).
 // One wavefront per vertex: lane l takes the incident triangles l, l + 64, ... of the vertex (a
 // polar fan vertex of a lat-long mesh has hundreds) and the lanes are summed by a fixed butterfly.
+// S64 / S32 (nullable): the strengths S = F (quadrature weight 1) in the plan precision, written in
+// the same pass.
 __global__ __launch_bounds__(256) void k_force_surface(int64_t M, const double* __restrict__ X, double gamma,
                                                        const int32_t* __restrict__ tris,
                                                        const int32_t* __restrict__ ptr,
-                                                       const int32_t* __restrict__ idx, double* __restrict__ F) {
+                                                       const int32_t* __restrict__ idx, double* __restrict__ F,
+                                                       double* __restrict__ S64 = nullptr,
+                                                       float* __restrict__ S32 = nullptr) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= M) return;  // uniform per wavefront
@@ -316,9 +320,20 @@ __global__ __launch_bounds__(256) void k_force_surface(int64_t M, const double* 
     f2 += __shfl_xor(f2, off, 64);
   }
   if (lane == 0) {
-    F[3 * i] = -0.5 * gamma * f0;
-    F[3 * i + 1] = -0.5 * gamma * f1;
-    F[3 * i + 2] = -0.5 * gamma * f2;
+    const double g0 = -0.5 * gamma * f0, g1 = -0.5 * gamma * f1, g2 = -0.5 * gamma * f2;
+    F[3 * i] = g0;
+    F[3 * i + 1] = g1;
+    F[3 * i + 2] = g2;
+    if (S64) {
+      S64[3 * i] = g0;
+      S64[3 * i + 1] = g1;
+      S64[3 * i + 2] = g2;
+    }
+    if (S32) {
+      S32[3 * i] = (float)g0;
+      S32[3 * i + 1] = (float)g1;
+      S32[3 * i + 2] = (float)g2;
+    }
   }
 }
 
@@ -625,8 +640,35 @@ static hipError_t curve_group(const std::vector<Plan*>& ps, const fsib_force* f,
       });
 }
 
+// Force F and weighted strengths S of one plan in one pass where the law allows it (the closed curve,
+// the surface), else the two launches of launch_force_plan and launch_weighted_strengths.
+hipError_t launch_force_strengths(const Plan& p, const fsib_force& f, int64_t M, const double* X, double* F, void* S,
+                                  hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  const unsigned nblk = (unsigned)((M + 255) / 256);
+  if (f.kind == FSIB_FORCE_CURVE_TENSION && p.dim == 2) {
+    const int64_t* off = p.ninst > 1 ? (const int64_t*)p.inst_off : nullptr;
+    if (p.prec == FSIB_F64)
+      hipLaunchKernelGGL(k_curve_force_strengths<double>, dim3(nblk), dim3(256), 0, st,
+                         CurveArgs<double>{M, X, f.K, off, p.ninst, F, (double*)S});
+    else
+      hipLaunchKernelGGL(k_curve_force_strengths<float>, dim3(nblk), dim3(256), 0, st,
+                         CurveArgs<float>{M, X, f.K, off, p.ninst, F, (float*)S});
+    return hipGetLastError();
+  }
+  if (f.kind == FSIB_FORCE_SURFACE_TENSION && p.dim == 3) {
+    hipLaunchKernelGGL(k_force_surface, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, M, X, f.K, f.tris, f.v2t_ptr,
+                       f.v2t_idx, F, p.prec == FSIB_F64 ? (double*)S : nullptr,
+                       p.prec == FSIB_F64 ? nullptr : (float*)S);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_force_plan(p, f, M, X, F, st);
+  if (e != hipSuccess) return e;
+  return launch_weighted_strengths(p, f.kind, M, F, S, st);
+}
+
 // Force (into each plan's F64) and weighted strengths (into its S) for the plans of a group: one launch
-// when every plan has the closed-curve law, else the plans' own launches.
+// when every plan has the closed-curve law, else each plan's own pass.
 hipError_t launch_force_strengths_group(const std::vector<Plan*>& ps, const fsib_force* f, const int64_t* M,
                                         const double* const* X, hipStream_t st) {
   bool curves = true;
@@ -634,9 +676,8 @@ hipError_t launch_force_strengths_group(const std::vector<Plan*>& ps, const fsib
   if (curves)
     return ps[0]->prec == FSIB_F64 ? curve_group<double>(ps, f, M, X, st) : curve_group<float>(ps, f, M, X, st);
   for (size_t g = 0; g < ps.size(); ++g) {
-    hipError_t e = launch_force_plan(*ps[g], f[g], M[g], X[g], ps[g]->F64, st);
+    const hipError_t e = launch_force_strengths(*ps[g], f[g], M[g], X[g], ps[g]->F64, ps[g]->S, st);
     if (e != hipSuccess) return e;
-    if ((e = launch_weighted_strengths(*ps[g], f[g].kind, M[g], ps[g]->F64, ps[g]->S, st)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

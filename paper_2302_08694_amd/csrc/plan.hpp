@@ -58,6 +58,7 @@ struct Plan {
   std::map<int, void*> tw;           // twiddles per FFT length
   // point sort
   int* counts = nullptr;   // nbins+1
+  bool counts_zero = false;  // host-side: counts are all zero (the last sort's scatter cleared them)
   int* offsets = nullptr;  // nbins+1
   int* pt_bin = nullptr;   // M
   int* pt_rank = nullptr;  // M
@@ -245,6 +246,8 @@ hipError_t launch_spring_stiffness(int64_t M, const double* X0, const int32_t* t
 hipError_t launch_force_plan(const Plan& p, const fsib_force& f, int64_t M, const double* X, double* F, hipStream_t st);
 hipError_t launch_force_jvp(const fsib_force& f, int dim, int64_t M, const double* X, const double* V, double* out,
                             hipStream_t st);
+hipError_t launch_force_strengths(const Plan& p, const fsib_force& f, int64_t M, const double* X, double* F, void* S,
+                                  hipStream_t st);  // F and S = w F in one pass where the law allows
 hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S,
                                      hipStream_t st);
 hipError_t launch_diag(const Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M,

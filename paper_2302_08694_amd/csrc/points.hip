@@ -231,6 +231,8 @@ struct ScatterArgs {
   int* s_idx;
   uint32_t* s_i0;
   T* s_y;
+  int* counts;     // the bin counts, cleared here for the next sort (nothing reads them after the masks)
+  int64_t ncounts;
 };
 
 template <typename T>
@@ -239,6 +241,7 @@ __device__ __forceinline__ void bin_scatter(const ScatterArgs<T>& A, Blk blk) {
   const double* __restrict__ X = A.X;
   T* __restrict__ s_y = A.s_y;
   const int64_t j = blk.x * blockDim.x + threadIdx.x;
+  for (int64_t k = j; k < A.ncounts; k += blk.nx * blockDim.x) A.counts[k] = 0;
   if (j >= A.M) return;
   const int64_t pos = (int64_t)A.offsets[A.pt_bin[j]] + A.pt_rank[j];
   bool bad = false;
@@ -527,13 +530,16 @@ static hipError_t launch_scan_parts(const std::vector<ScanArgs>& scans, hipStrea
 template <typename T>
 static ScatterArgs<T> scatter_args(const Plan& p, int64_t M, const double* X) {
   return ScatterArgs<T>{M, X, make_geo(p), (const int*)p.offsets, (const int*)p.pt_bin, (const int*)p.pt_rank,
-                        p.s_idx, p.s_i0, (T*)p.s_y};
+                        p.s_idx, p.s_i0, (T*)p.s_y, p.counts, p.nbt + 1};
 }
 
 hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st) {
   Geo g = make_geo(p);
-  hipError_t e = launch_fill_zero(p.counts, (p.nbt + 1) * (int64_t)sizeof(int), st);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  // the bin counts start at zero: cleared by the last sort's scatter, else here
+  if (!p.counts_zero && (e = launch_fill_zero(p.counts, (p.nbt + 1) * (int64_t)sizeof(int), st)) != hipSuccess)
+    return e;
+  p.counts_zero = true;  // after this sort: zero again (its scatter clears them; with M = 0 nothing is counted)
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st,
@@ -605,7 +611,8 @@ hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t*
     const Plan& p = *ps[g];
     const int64_t words = p.nbt + 1;
     fz[g].a = FillArgs{(uint32_t*)p.counts, words};
-    fz[g].nx = (words + 255) / 256;
+    fz[g].nx = p.counts_zero ? 0 : (words + 255) / 256;  // cleared by the last sort's scatter
+    ps[g]->counts_zero = true;
     bc[g].a = BinCountArgs{M[g], X[g], make_geo(p), p.counts, p.pt_bin, p.pt_rank, p.flag};
     bc[g].nx = (M[g] + 255) / 256;
     sc[g] = ScanArgs{p.nbt, p.counts, p.offsets, p.scan_part};

@@ -411,6 +411,7 @@ struct TilePartsArgs {
   int dim, nt0, nt1, nt2, q0, q1, q2, ninst, split;
   const int* offsets;
   int* tile_parts;
+  int* slot_ctr;  // cleared here (scratch slots and split tiles of k_fill_work)
 };
 __device__ __forceinline__ void tile_parts_body(const TilePartsArgs& A, Blk wb) {
   const int dim = A.dim, nt0 = A.nt0, nt1 = A.nt1, nt2 = A.nt2, q0 = A.q0, q1 = A.q1, q2 = A.q2, ninst = A.ninst,
@@ -418,6 +419,10 @@ __device__ __forceinline__ void tile_parts_body(const TilePartsArgs& A, Blk wb) 
   const int* __restrict__ offsets = A.offsets;
   int* __restrict__ tile_parts = A.tile_parts;
   const int tg = (int)(wb.x * blockDim.x + threadIdx.x);
+  if (tg == 0) {
+    A.slot_ctr[0] = 0;
+    A.slot_ctr[1] = 0;
+  }
   const int nbins = nt0 * nt1 * nt2;
   if (tg >= nbins * ninst) return;
   const int inst = tg / nbins, t = tg - inst * nbins;
@@ -832,7 +837,7 @@ static SpreadArgs<T> spread_args(const Plan& p, int64_t M, const void* str) {
 template <int DIM>
 static TilePartsArgs tile_parts_args(const Plan& p) {
   return TilePartsArgs{DIM, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[0], (int)p.qn[1], (int)p.qn[2],
-                       p.ninst, p.split, (const int*)p.offsets, p.tile_parts};
+                       p.ninst, p.split, (const int*)p.offsets, p.tile_parts, p.slot_ctr};
 }
 
 static FillWorkArgs fill_work_args(const Plan& p) {
@@ -859,7 +864,6 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
-  if ((e = launch_fill_zero(p.slot_ctr, 8, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, fill_work_args(p));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const bool prof = prof_on(p, PROF_SPREAD);
@@ -907,10 +911,9 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
   std::vector<PartLaunch<TilePartsArgs>> tp(n);
   std::vector<PartLaunch<FillWorkArgs>> fw(n);
   std::vector<PartLaunch<SpreadArgs<T>>> sp(n), mg(n);
-  std::vector<int64_t> nbt(n), eight(n, 8);
+  std::vector<int64_t> nbt(n);
   std::vector<const int*> tparts(n);
   std::vector<int*> poff(n), spart(n);
-  std::vector<void*> ctr(n);
   for (size_t g = 0; g < n; ++g) {
     Plan& p = *ps[g];
     const SpreadArgs<T> a = spread_args<T, DIM>(p, M[g], str[g]);
@@ -929,14 +932,12 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
     tparts[g] = p.tile_parts;
     poff[g] = p.part_off;
     spart[g] = p.scan_part;
-    ctr[g] = p.slot_ctr;
   }
   hipError_t e = launch_parts(ss, FSIB_PARTS((k_sort_strengths<T, NCH, false>), (k_sort_strengths_parts<T, NCH, false>),
                                              SortStrArgs<T>, 256));
   if (e != hipSuccess) return e;
   if ((e = launch_parts(tp, FSIB_PARTS(k_tile_parts, k_tile_parts_parts, TilePartsArgs, 256))) != hipSuccess) return e;
   if ((e = launch_scan_group(nbt, tparts, poff, spart, st)) != hipSuccess) return e;
-  if ((e = launch_fill_zero_group(ctr, eight, st)) != hipSuccess) return e;
   if ((e = launch_parts(fw, FSIB_PARTS(k_fill_work, k_fill_work_parts, FillWorkArgs, 256))) != hipSuccess) return e;
   // parts with different spreading variants run as launches of their own (launch_parts)
   const auto one = [&](const PartLaunch<SpreadArgs<T>>& L) {
