@@ -613,7 +613,7 @@ fsib_status stokes_velocity(Plan& p, const fsib_fluid_params& prm, const fsib_fo
                             void* U, void* uhat, hipStream_t st) {
   const double Ld = p.dim == 3 ? p.L * p.L * p.L : p.L * p.L;
   FSIB_HIP(fsib::launch_force_strengths(p, f, M, X, p.F64, p.S, st));
-  FSIB_HIP(fsib::launch_sort_points(p, M, X, st));
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, st, p.S));
   FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, st));
   FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_STOKES, prm, p.fhat, nullptr, uhat, st));
   FSIB_TRY(velocity_interp_sorted(p, M, uhat, U, st));
@@ -682,7 +682,7 @@ fsib_status group_stokes_velocity(const std::vector<Plan*>& ps, const fsib_fluid
   std::vector<const void*> S(n);
   for (size_t g = 0; g < n; ++g) S[g] = ps[g]->S;
   FSIB_HIP(fsib::launch_force_strengths_group(ps, f, M, X, st));
-  FSIB_HIP(fsib::launch_sort_points_group(ps, M, X, st));
+  FSIB_HIP(fsib::launch_sort_points_group(ps, M, X, st, S.data()));
   FSIB_HIP(fsib::launch_spread_group(ps, M, S.data(), st));
   FSIB_TRY(group_spread_ffts(ps, st));
   FSIB_HIP(fsib::launch_fluid_stokes_group(ps, prm, uhat, st));
@@ -1032,7 +1032,7 @@ fsib_status fsib_force_spread(fsib_plan plan, int64_t M, const double* X, const 
   if (M > 0 && !S_) return fail(FSIB_ERR_ARG, "S is NULL");
   if (!fhat_half) return fail(FSIB_ERR_ARG, "fhat_half is NULL");
   if (!std::isfinite(scale)) return fail(FSIB_ERR_ARG, "scale must be finite");
-  FSIB_HIP(fsib::launch_sort_points(p, M, X, S(stream)));
+  FSIB_HIP(fsib::launch_sort_points(p, M, X, S(stream), S_));
   return force_spread_sorted(p, M, S_, fhat_half, scale, S(stream));
 }
 
@@ -1190,7 +1190,7 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     // beside the products of uhat^m
     FSIB_HIP(fsib::launch_axpy_positions(p, M, p.Xh, X, U, 0.5 * dt, s2));
     FSIB_HIP(fsib::launch_force_strengths(p, *force, M, p.Xh, p.F64, p.S, s2));
-    FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, s2));
+    FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, s2, p.S));
     FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, s2));
     FSIB_HIP(hipEventRecord(p.fj[1], s2));
     FSIB_TRY(dealiased_products(p, uhat_half, st));

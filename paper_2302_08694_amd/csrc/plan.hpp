@@ -66,6 +66,7 @@ struct Plan {
   uint32_t* s_i0 = nullptr;  // M: packed first support cell (10 bits per axis)
   void* s_y = nullptr;     // M*dim prec: sub-cell position in [-1, 1]
   void* s_str = nullptr;   // strengths in sorted order: max(2 ntrans, dim) * M prec
+  const void* sstr_src = nullptr;  // host-side: the real strengths the last sort placed in s_str (or none)
   int deterministic = 0;   // 1: each bin lists its points in ascending original index (k_bin_rank)
   int* det_key = nullptr;  // M: original index per claimed slot (deterministic plans only)
   int* flag = nullptr;     // non-finite position seen
@@ -175,7 +176,9 @@ hipError_t launch_parts(const std::vector<PartLaunch<A>>& v, One one, Fused fuse
 
 // ---- launchers (all asynchronous on `st`) ----
 // points.hip
-hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st);
+// str (nullable): real strengths (dim per point, plan precision) that the spreading after this sort
+// will take; the scatter then also places them in sorted order
+hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st, const void* str = nullptr);
 hipError_t launch_spectral_scale(const Plan& p, int layout, int axis, double scale, const void* in, void* out,
                                  hipStream_t st);  // layout 0: ntrans full spectra; 1: dim half spectra
 hipError_t launch_grad_combine(const Plan& p, int64_t M, int kind, const void* u, const void* v, const void* u2,
@@ -186,11 +189,11 @@ hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum,
                        hipStream_t st);  // exclusive, n+1 outputs; seg_sum: scan_segments(n) ints
 int64_t scan_segments(int64_t n);
-hipError_t launch_row_masks(Plan& p, hipStream_t st);  // from the sorted bins
+hipError_t launch_row_masks(Plan& p, int64_t M, hipStream_t st);  // from the bin counts of M points
 // the same stages for the plans of a group, each one launch over all plans where their workgroup
 // sizes agree (plan g: M[g] points, its operands at index g)
 hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t* M, const double* const* X,
-                                    hipStream_t st);
+                                    hipStream_t st, const void* const* str = nullptr);
 hipError_t launch_axpy_positions_group(const std::vector<Plan*>& ps, const int64_t* M, double* const* Y,
                                        const double* const* X, const void* const* U, const double* a,
                                        hipStream_t st);

@@ -69,6 +69,8 @@ struct BinCountArgs {
   int* pt_bin;
   int* pt_rank;
   int* flag;
+  uint8_t* zclear;  // plane masks cleared by workgroup 0 before k_row_masks sets them (nullable)
+  int nz;
 };
 
 __device__ __forceinline__ void bin_count(const BinCountArgs& A, Blk blk) {
@@ -77,6 +79,8 @@ __device__ __forceinline__ void bin_count(const BinCountArgs& A, Blk blk) {
   const Geo& g = A.g;
   int* __restrict__ counts = A.counts;
   int* __restrict__ flag = A.flag;
+  if (A.zclear && blk.x == 0)
+    for (int k = threadIdx.x; k < A.nz; k += blockDim.x) A.zclear[k] = 0;
   const int64_t j = blk.x * blockDim.x + threadIdx.x;
   const bool valid = j < M;
   int bin = -1;
@@ -233,6 +237,9 @@ struct ScatterArgs {
   T* s_y;
   int* counts;     // the bin counts, cleared here for the next sort (nothing reads them after the masks)
   int64_t ncounts;
+  const T* str;    // real strengths, nch per point, placed in sorted order into sstr (nullable)
+  T* sstr;
+  int nch;
 };
 
 template <typename T>
@@ -256,6 +263,8 @@ __device__ __forceinline__ void bin_scatter(const ScatterArgs<T>& A, Blk blk) {
   }
   A.s_idx[pos] = (int)j;
   A.s_i0[pos] = packed;
+  if (A.str)
+    for (int ch = 0; ch < A.nch; ++ch) A.sstr[pos * A.nch + ch] = A.str[j * A.nch + ch];
 }
 
 template <typename T>
@@ -402,6 +411,7 @@ struct RowMaskArgs {
   int nt0, nt1, nt2, qy, qz, ninst;
   const int* counts;
   uint8_t* rowmask;
+  uint8_t* zmask;  // nullable: plane masks of instance 0, zb set when any of its blocks is reached
 };
 __device__ __forceinline__ void row_masks(const RowMaskArgs& A, Blk blk) {
   const int nt0 = A.nt0, nt1 = A.nt1, nt2 = A.nt2, qy = A.qy, qz = A.qz, ninst = A.ninst;
@@ -421,6 +431,9 @@ __device__ __forceinline__ void row_masks(const RowMaskArgs& A, Blk blk) {
       for (int bx = 0; bx < nt0; ++bx) any |= c[bx];
     }
   A.rowmask[tg] = any ? 1 : 0;
+  // the byte of plane block zb, set through its 4-byte word (the masks are 256-byte aligned)
+  if (any && A.zmask && inst == 0)
+    atomicOr(reinterpret_cast<unsigned*>(A.zmask + (zb & ~3)), 1u << (8 * (zb & 3)));
 }
 __global__ void k_row_masks(RowMaskArgs a) { row_masks(a, launch_blk()); }
 __global__ void k_row_masks_parts(Parts<RowMaskArgs> f) {
@@ -429,48 +442,28 @@ __global__ void k_row_masks_parts(Parts<RowMaskArgs> f) {
   if (g >= 0) row_masks(f.a[g], b);
 }
 
-struct PlaneMaskArgs {
-  int nt1, nt2;
-  const uint8_t* rowmask;
-  uint8_t* zmask;
-};
-__device__ __forceinline__ void plane_masks(const PlaneMaskArgs& A, Blk blk) {
-  const int zb = (int)(blk.x * blockDim.x + threadIdx.x);
-  if (zb >= A.nt2) return;
-  uint8_t any = 0;
-  for (int yb = 0; yb < A.nt1; ++yb) any |= A.rowmask[zb * A.nt1 + yb];
-  A.zmask[zb] = any;
-}
-__global__ void k_plane_masks(PlaneMaskArgs a) { plane_masks(a, launch_blk()); }
-__global__ void k_plane_masks_parts(Parts<PlaneMaskArgs> f) {
-  Blk b;
-  const int g = part_blk(f, b);
-  if (g >= 0) plane_masks(f.a[g], b);
-}
+
+// Plane masks exist on 3D one-instance plans (the passes of 3D multi-instance plans run dense).
+static uint8_t* plane_masks_of(const Plan& p) { return p.dim == 3 && p.ninst == 1 ? p.zmask : nullptr; }
 
 static PartLaunch<RowMaskArgs> row_mask_launch(const Plan& p) {
   const int ni = p.dim == 2 ? p.ninst : 1;  // 3D multi-instance plans keep no masks
   const int nrb = (int)(p.nt[1] * p.nt[2]) * ni;
   PartLaunch<RowMaskArgs> L;
   L.a = RowMaskArgs{(int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[1], (int)p.qn[2], ni, (const int*)p.counts,
-                    p.rowmask};
+                    p.rowmask, plane_masks_of(p)};
   L.nx = (nrb + 255) / 256;
   return L;
 }
-static PartLaunch<PlaneMaskArgs> plane_mask_launch(const Plan& p) {
-  PartLaunch<PlaneMaskArgs> L;
-  L.a = PlaneMaskArgs{(int)p.nt[1], (int)p.nt[2], (const uint8_t*)p.rowmask, p.zmask};
-  L.nx = (p.nt[2] + 255) / 256;
-  return L;
-}
 
-hipError_t launch_row_masks(Plan& p, hipStream_t st) {
+// Row masks, and the plane masks with them (cleared beforehand by k_bin_count, or here when no point
+// was counted).
+hipError_t launch_row_masks(Plan& p, int64_t M, hipStream_t st) {
+  hipError_t e;
+  if (M <= 0 && plane_masks_of(p) && (e = launch_fill_zero(p.zmask, (p.nt[2] + 3) / 4 * 4, st)) != hipSuccess)
+    return e;
   const PartLaunch<RowMaskArgs> r = row_mask_launch(p);
   hipLaunchKernelGGL(k_row_masks, dim3((unsigned)r.nx), dim3(256), 0, st, r.a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const PartLaunch<PlaneMaskArgs> z = plane_mask_launch(p);
-  hipLaunchKernelGGL(k_plane_masks, dim3((unsigned)z.nx), dim3(256), 0, st, z.a);
   return hipGetLastError();
 }
 
@@ -528,12 +521,12 @@ static hipError_t launch_scan_parts(const std::vector<ScanArgs>& scans, hipStrea
 }
 
 template <typename T>
-static ScatterArgs<T> scatter_args(const Plan& p, int64_t M, const double* X) {
+static ScatterArgs<T> scatter_args(const Plan& p, int64_t M, const double* X, const void* str) {
   return ScatterArgs<T>{M, X, make_geo(p), (const int*)p.offsets, (const int*)p.pt_bin, (const int*)p.pt_rank,
-                        p.s_idx, p.s_i0, (T*)p.s_y, p.counts, p.nbt + 1};
+                        p.s_idx, p.s_i0, (T*)p.s_y, p.counts, p.nbt + 1, (const T*)str, (T*)p.s_str, p.dim};
 }
 
-hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st) {
+hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st, const void* str) {
   Geo g = make_geo(p);
   hipError_t e = hipSuccess;
   // the bin counts start at zero: cleared by the last sort's scatter, else here
@@ -543,12 +536,12 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st,
-                       BinCountArgs{M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag});
+                       BinCountArgs{M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag, plane_masks_of(p), (int)p.nt[2]});
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st)) != hipSuccess) return e;
   // masks: single-instance plans and 2D multi-instance plans
-  if ((p.ninst == 1 || p.dim == 2) && (e = launch_row_masks(p, st)) != hipSuccess) return e;
+  if ((p.ninst == 1 || p.dim == 2) && (e = launch_row_masks(p, M, st)) != hipSuccess) return e;
   if (M > 0 && p.deterministic) {  // ranks by original index inside each bin
     const unsigned nblk = (unsigned)((M + 255) / 256);
     hipLaunchKernelGGL(k_bin_place, dim3(nblk), dim3(256), 0, st, M, (const int*)p.offsets, (const int*)p.pt_bin,
@@ -561,11 +554,12 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     if (p.prec == FSIB_F64)
-      hipLaunchKernelGGL(k_bin_scatter<double>, dim3(nblk), dim3(256), 0, st, scatter_args<double>(p, M, X));
+      hipLaunchKernelGGL(k_bin_scatter<double>, dim3(nblk), dim3(256), 0, st, scatter_args<double>(p, M, X, str));
     else
-      hipLaunchKernelGGL(k_bin_scatter<float>, dim3(nblk), dim3(256), 0, st, scatter_args<float>(p, M, X));
+      hipLaunchKernelGGL(k_bin_scatter<float>, dim3(nblk), dim3(256), 0, st, scatter_args<float>(p, M, X, str));
     e = hipGetLastError();
   }
+  p.sstr_src = str;
   return e;
 }
 
@@ -581,10 +575,12 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
       }
 
 template <typename T>
-static hipError_t scatter_group(const std::vector<Plan*>& ps, const int64_t* M, const double* const* X, hipStream_t st) {
+static hipError_t scatter_group(const std::vector<Plan*>& ps, const int64_t* M, const double* const* X,
+                                const void* const* str, hipStream_t st) {
   std::vector<PartLaunch<ScatterArgs<T>>> v(ps.size());
   for (size_t g = 0; g < ps.size(); ++g) {
-    v[g].a = scatter_args<T>(*ps[g], M[g], X[g]);
+    v[g].a = scatter_args<T>(*ps[g], M[g], X[g], str ? str[g] : nullptr);
+    ps[g]->sstr_src = str ? str[g] : nullptr;
     v[g].nx = (M[g] + 255) / 256;
   }
   return launch_parts(v, FSIB_PARTS_256(k_bin_scatter<T>, k_bin_scatter_parts<T>, ScatterArgs<T>));
@@ -600,34 +596,33 @@ hipError_t launch_scan_group(const std::vector<int64_t>& n, const std::vector<co
 // launch_sort_points for the plans of a group (plan g with M[g] points at X[g]), each stage one launch
 // over all plans (the ranking passes of deterministic plans one launch per plan).
 hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t* M, const double* const* X,
-                                    hipStream_t st) {
+                                    hipStream_t st, const void* const* str) {
   const size_t n = ps.size();
   std::vector<PartLaunch<FillArgs>> fz(n);
   std::vector<PartLaunch<BinCountArgs>> bc(n);
   std::vector<ScanArgs> sc(n);
   std::vector<PartLaunch<RowMaskArgs>> rm;
-  std::vector<PartLaunch<PlaneMaskArgs>> pm;
   for (size_t g = 0; g < n; ++g) {
     const Plan& p = *ps[g];
     const int64_t words = p.nbt + 1;
     fz[g].a = FillArgs{(uint32_t*)p.counts, words};
     fz[g].nx = p.counts_zero ? 0 : (words + 255) / 256;  // cleared by the last sort's scatter
     ps[g]->counts_zero = true;
-    bc[g].a = BinCountArgs{M[g], X[g], make_geo(p), p.counts, p.pt_bin, p.pt_rank, p.flag};
+    bc[g].a = BinCountArgs{M[g], X[g], make_geo(p), p.counts, p.pt_bin, p.pt_rank, p.flag, plane_masks_of(p),
+                           (int)p.nt[2]};
     bc[g].nx = (M[g] + 255) / 256;
     sc[g] = ScanArgs{p.nbt, p.counts, p.offsets, p.scan_part};
-    if (p.ninst == 1 || p.dim == 2) {
-      rm.push_back(row_mask_launch(p));
-      pm.push_back(plane_mask_launch(p));
-    }
+    if (p.ninst == 1 || p.dim == 2) rm.push_back(row_mask_launch(p));
   }
   hipError_t e = launch_parts(fz, FSIB_PARTS_256(k_fill_zero_parts_one, k_fill_zero_parts, FillArgs));
   if (e != hipSuccess) return e;
   if ((e = launch_parts(bc, FSIB_PARTS_256(k_bin_count, k_bin_count_parts, BinCountArgs))) != hipSuccess) return e;
   if ((e = launch_scan_parts(sc, st)) != hipSuccess) return e;
+  for (size_t g = 0; g < n; ++g)  // plane masks of plans with no point counted (k_bin_count clears the others)
+    if (M[g] <= 0 && plane_masks_of(*ps[g]) &&
+        (e = launch_fill_zero(ps[g]->zmask, (ps[g]->nt[2] + 3) / 4 * 4, st)) != hipSuccess)
+      return e;
   if ((e = launch_parts(rm, FSIB_PARTS_256(k_row_masks, k_row_masks_parts, RowMaskArgs))) != hipSuccess) return e;
-  if ((e = launch_parts(pm, FSIB_PARTS_256(k_plane_masks, k_plane_masks_parts, PlaneMaskArgs))) != hipSuccess)
-    return e;
   for (size_t g = 0; g < n; ++g) {  // deterministic plans: ranks by original index, each plan on its own
     const Plan& p = *ps[g];
     if (!p.deterministic || M[g] <= 0) continue;
@@ -638,7 +633,7 @@ hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t*
                        (const int*)p.det_key, p.pt_rank);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return ps[0]->prec == FSIB_F64 ? scatter_group<double>(ps, M, X, st) : scatter_group<float>(ps, M, X, st);
+  return ps[0]->prec == FSIB_F64 ? scatter_group<double>(ps, M, X, str, st) : scatter_group<float>(ps, M, X, str, st);
 }
 
 // Zeroing of several device ranges (ptr[g], bytes[g], whole 4-byte words) in one launch.

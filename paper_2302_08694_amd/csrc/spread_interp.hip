@@ -854,7 +854,8 @@ template <typename T, int DIM, int NCH, bool CPLX, int W>
 static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipStream_t st) {
   const SpreadArgs<T> a = spread_args<T, DIM>(p, M, str);
   const unsigned nb = (unsigned)p.nbt;
-  if (M > 0) {
+  // real strengths the sort already placed in sorted order (its scatter) are not placed again
+  if (M > 0 && !(!CPLX && ntr == 1 && p.sstr_src == str)) {
     hipLaunchKernelGGL((k_sort_strengths<T, NCH, CPLX>), dim3((unsigned)((M + 255) / 256), (unsigned)ntr), dim3(256), 0,
                        st, SortStrArgs<T>{M, (const int*)p.s_idx, (const T*)str, a.sstr});
     hipError_t e0 = hipGetLastError();
@@ -918,7 +919,7 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
     Plan& p = *ps[g];
     const SpreadArgs<T> a = spread_args<T, DIM>(p, M[g], str[g]);
     ss[g].a = SortStrArgs<T>{M[g], (const int*)p.s_idx, (const T*)str[g], a.sstr};
-    ss[g].nx = (M[g] + 255) / 256;
+    ss[g].nx = p.sstr_src == str[g] ? 0 : (M[g] + 255) / 256;  // placed by the sort's scatter
     tp[g].a = tile_parts_args<DIM>(p);
     tp[g].nx = (p.nbt + 255) / 256;
     fw[g].a = fill_work_args(p);
