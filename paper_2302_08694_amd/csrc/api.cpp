@@ -799,10 +799,12 @@ fsib_status spread_in_workspace(fsib_plan plan, int device, int64_t M, const dou
   carve_transform_buffers(p, M, static_cast<char*>(ws), b);
   swap_transform_buffers(p, b);
   const bool counts_zero = p.counts_zero;
+  const int parts_split = p.parts_split;
   p.counts_zero = false;  // the workspace's counts hold whatever the last call left
   const fsib_status s = type1_complex(p, M, X, c, fhat, scale, S(stream));
   swap_transform_buffers(p, b);
-  p.counts_zero = counts_zero;  // the plan's own counts are untouched
+  p.counts_zero = counts_zero;  // the plan's own counts and tiles' parts are untouched
+  p.parts_split = parts_split;
   return s;
 }
 

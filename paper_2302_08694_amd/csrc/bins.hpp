@@ -1,0 +1,41 @@
+// Per-tile candidate counts of spreading, shared by the point sort (which computes them beside the row
+// masks) and the spreading launcher (which computes them when the sort did not).
+#pragma once
+
+#include "common.hpp"
+
+namespace fsib {
+
+// Points reaching each tile (its bin and the q bins before it per axis) and the parts it splits into.
+struct TilePartsArgs {
+  int dim, nt0, nt1, nt2, q0, q1, q2, ninst, split;
+  const int* offsets;
+  int* tile_parts;
+  int* slot_ctr;  // cleared here (scratch slots and split tiles of k_fill_work)
+};
+
+// Tile tg of all instances (tg < nt0 nt1 nt2 ninst); tg = 0 also clears the split counters.
+__device__ __forceinline__ void tile_parts_at(const TilePartsArgs& A, int tg) {
+  const int dim = A.dim, nt0 = A.nt0, nt1 = A.nt1, nt2 = A.nt2, q0 = A.q0, q1 = A.q1, q2 = A.q2, ninst = A.ninst,
+            split = A.split;
+  const int* __restrict__ offsets = A.offsets;
+  if (tg == 0) {
+    A.slot_ctr[0] = 0;
+    A.slot_ctr[1] = 0;
+  }
+  const int nbins = nt0 * nt1 * nt2;
+  if (tg >= nbins * ninst) return;
+  const int inst = tg / nbins, t = tg - inst * nbins;
+  const int tx = t % nt0, ty = (t / nt0) % nt1, tz = t / (nt0 * nt1);
+  int total = 0;
+  for (int dz = 0; dz <= (dim == 3 ? q2 : 0); ++dz)
+    for (int dy = 0; dy <= q1; ++dy)
+      for (int dx = 0; dx <= q0; ++dx) {
+        const int bx = (tx - dx + nt0) % nt0, by = (ty - dy + nt1) % nt1, bz = dim == 3 ? (tz - dz + nt2) % nt2 : 0;
+        const int b = bx + nt0 * (by + nt1 * bz) + inst * nbins;
+        total += offsets[b + 1] - offsets[b];
+      }
+  A.tile_parts[tg] = total <= split ? 1 : (total + split - 1) / split;
+}
+
+}  // namespace fsib

@@ -76,6 +76,7 @@ struct Plan {
   // spreading work list (heavy tiles split into parts of at most `split` candidates)
   int64_t qn[3] = {0, 0, 0};   // bins before a tile, per axis, whose points can reach it
   int* tile_parts = nullptr;   // nbins
+  int parts_split = 0;         // host-side: the split with which the last sort computed tile_parts (0: none)
   int* part_off = nullptr;     // nbins+1
   int* work = nullptr;         // 2 ints per part, work_blocks parts at most
   int* tile_slot = nullptr;    // nbins

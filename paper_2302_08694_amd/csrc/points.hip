@@ -8,6 +8,7 @@
 // plans keep full positional resolution within a cell.
 #include <climits>
 
+#include "bins.hpp"
 #include "plan.hpp"
 
 namespace fsib {
@@ -412,12 +413,18 @@ struct RowMaskArgs {
   const int* counts;
   uint8_t* rowmask;
   uint8_t* zmask;  // nullable: plane masks of instance 0, zb set when any of its blocks is reached
+  TilePartsArgs tp;  // the spreading tiles' parts, by the threads past the row blocks (ntp of them)
+  int ntp;
 };
 __device__ __forceinline__ void row_masks(const RowMaskArgs& A, Blk blk) {
   const int nt0 = A.nt0, nt1 = A.nt1, nt2 = A.nt2, qy = A.qy, qz = A.qz, ninst = A.ninst;
   const int* __restrict__ counts = A.counts;
   const int tg = (int)(blk.x * blockDim.x + threadIdx.x);
-  if (tg >= nt1 * nt2 * ninst) return;
+  const int nrb = nt1 * nt2 * ninst;
+  if (tg >= nrb) {
+    if (tg - nrb < A.ntp) tile_parts_at(A.tp, tg - nrb);
+    return;
+  }
   const int inst = tg / (nt1 * nt2), t = tg - inst * nt1 * nt2;
   const int yb = t % nt1, zb = t / nt1;
   const int* ci = counts + (int64_t)inst * nt0 * nt1 * nt2;
@@ -446,13 +453,17 @@ __global__ void k_row_masks_parts(Parts<RowMaskArgs> f) {
 // Plane masks exist on 3D one-instance plans (the passes of 3D multi-instance plans run dense).
 static uint8_t* plane_masks_of(const Plan& p) { return p.dim == 3 && p.ninst == 1 ? p.zmask : nullptr; }
 
-static PartLaunch<RowMaskArgs> row_mask_launch(const Plan& p) {
+// Row masks, plane masks and the spreading tiles' parts of a plan (sets p.parts_split).
+static PartLaunch<RowMaskArgs> row_mask_launch(Plan& p) {
   const int ni = p.dim == 2 ? p.ninst : 1;  // 3D multi-instance plans keep no masks
   const int nrb = (int)(p.nt[1] * p.nt[2]) * ni;
   PartLaunch<RowMaskArgs> L;
+  const TilePartsArgs tp{p.dim, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[0], (int)p.qn[1], (int)p.qn[2],
+                         p.ninst, p.split, (const int*)p.offsets, p.tile_parts, p.slot_ctr};
   L.a = RowMaskArgs{(int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[1], (int)p.qn[2], ni, (const int*)p.counts,
-                    p.rowmask, plane_masks_of(p)};
-  L.nx = (nrb + 255) / 256;
+                    p.rowmask, plane_masks_of(p), tp, (int)p.nbt};
+  L.nx = (nrb + p.nbt + 255) / 256;
+  p.parts_split = p.split;
   return L;
 }
 
@@ -529,6 +540,7 @@ static ScatterArgs<T> scatter_args(const Plan& p, int64_t M, const double* X, co
 hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t st, const void* str) {
   Geo g = make_geo(p);
   hipError_t e = hipSuccess;
+  p.parts_split = 0;  // set again where the row-mask pass computes the tiles' parts
   // the bin counts start at zero: cleared by the last sort's scatter, else here
   if (!p.counts_zero && (e = launch_fill_zero(p.counts, (p.nbt + 1) * (int64_t)sizeof(int), st)) != hipSuccess)
     return e;
@@ -603,7 +615,8 @@ hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t*
   std::vector<ScanArgs> sc(n);
   std::vector<PartLaunch<RowMaskArgs>> rm;
   for (size_t g = 0; g < n; ++g) {
-    const Plan& p = *ps[g];
+    Plan& p = *ps[g];
+    p.parts_split = 0;
     const int64_t words = p.nbt + 1;
     fz[g].a = FillArgs{(uint32_t*)p.counts, words};
     fz[g].nx = p.counts_zero ? 0 : (words + 255) / 256;  // cleared by the last sort's scatter

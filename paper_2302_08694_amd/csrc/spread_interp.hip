@@ -9,6 +9,7 @@
 //
 // Interpolation gathers the w^d cells of each point from the grid (sorted order, so neighbouring
 // threads read neighbouring cells) and writes the result at the point's original index.
+#include "bins.hpp"
 #include "plan.hpp"
 
 namespace fsib {
@@ -406,36 +407,8 @@ __global__ void k_sort_strengths_parts(Parts<SortStrArgs<T>> f) {
   if (g >= 0) sort_strengths<T, NCH, CPLX>(f.a[g], b);
 }
 
-// Points reaching each tile (its bin and the q bins before it per axis) and the parts it splits into.
-struct TilePartsArgs {
-  int dim, nt0, nt1, nt2, q0, q1, q2, ninst, split;
-  const int* offsets;
-  int* tile_parts;
-  int* slot_ctr;  // cleared here (scratch slots and split tiles of k_fill_work)
-};
 __device__ __forceinline__ void tile_parts_body(const TilePartsArgs& A, Blk wb) {
-  const int dim = A.dim, nt0 = A.nt0, nt1 = A.nt1, nt2 = A.nt2, q0 = A.q0, q1 = A.q1, q2 = A.q2, ninst = A.ninst,
-            split = A.split;
-  const int* __restrict__ offsets = A.offsets;
-  int* __restrict__ tile_parts = A.tile_parts;
-  const int tg = (int)(wb.x * blockDim.x + threadIdx.x);
-  if (tg == 0) {
-    A.slot_ctr[0] = 0;
-    A.slot_ctr[1] = 0;
-  }
-  const int nbins = nt0 * nt1 * nt2;
-  if (tg >= nbins * ninst) return;
-  const int inst = tg / nbins, t = tg - inst * nbins;
-  const int tx = t % nt0, ty = (t / nt0) % nt1, tz = t / (nt0 * nt1);
-  int total = 0;
-  for (int dz = 0; dz <= (dim == 3 ? q2 : 0); ++dz)
-    for (int dy = 0; dy <= q1; ++dy)
-      for (int dx = 0; dx <= q0; ++dx) {
-        const int bx = (tx - dx + nt0) % nt0, by = (ty - dy + nt1) % nt1, bz = dim == 3 ? (tz - dz + nt2) % nt2 : 0;
-        const int b = bx + nt0 * (by + nt1 * bz) + inst * nbins;
-        total += offsets[b + 1] - offsets[b];
-      }
-  tile_parts[tg] = total <= split ? 1 : (total + split - 1) / split;
+  tile_parts_at(A, (int)(wb.x * blockDim.x + threadIdx.x));
 }
 __global__ void k_tile_parts(TilePartsArgs a) { tile_parts_body(a, launch_blk()); }
 __global__ void k_tile_parts_parts(Parts<TilePartsArgs> f) {
@@ -861,9 +834,11 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
   }
-  hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, tile_parts_args<DIM>(p));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (p.parts_split != p.split) {  // not computed by the sort (with its split)
+    hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, tile_parts_args<DIM>(p));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, fill_work_args(p));
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -921,7 +896,7 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
     ss[g].a = SortStrArgs<T>{M[g], (const int*)p.s_idx, (const T*)str[g], a.sstr};
     ss[g].nx = p.sstr_src == str[g] ? 0 : (M[g] + 255) / 256;  // placed by the sort's scatter
     tp[g].a = tile_parts_args<DIM>(p);
-    tp[g].nx = (p.nbt + 255) / 256;
+    tp[g].nx = p.parts_split == p.split ? 0 : (p.nbt + 255) / 256;  // computed by the sort
     fw[g].a = fill_work_args(p);
     fw[g].nx = (p.nbt + 255) / 256;
     sp[g].a = a;
