@@ -115,6 +115,13 @@ typedef struct {
   int spread_threads;    /* spreading variant: threads per 16 x 16 tile of a 2D plan, 64 (4 cells
                             per lane), 128 (2) or 256 (1); 0 picks the default (64 in FP32, 128 in
                             FP64).  3D plans take 0 or 256 (16 x 8 x 8 tiles, 4 cells per lane). */
+  int nl_stages;         /* Navier-Stokes plans whose dealiasing grid has 192 points along x (128
+                            modes): FFT stages of the fused x pass of the dealiased products (Sec.
+                            3.1), 2 (16 x 12, registers between the stages; fastest alone) or 3 (8 x 8
+                            x 3 through LDS; lower peak demand on memory and LDS, which leaves more of
+                            the GPU to a point side running beside it); 0 picks 3 for FP64 plans whose
+                            point side overlaps (overlap = 1) and 2 otherwise.  Other plans take any of
+                            0, 2, 3 and ignore it. */
 } fsib_tuning;
 
 typedef enum { FSIB_STOKES = 0, FSIB_NAVIER_STOKES = 1 } fsib_model;
@@ -191,7 +198,7 @@ fsib_status fsib_plan_profile(fsib_plan plan, int kernel_class, int max_launches
  * the plan was created with (its scratch is sized for it; the creation value is 256 for plans of at
  * most 2^18 points, else 512).  Errors:
  * FSIB_ERR_ARG for NULL or out-of-range values (chunks in [0, 4096], split in [creation, 1 << 20],
- * overlap 0 or 1, interp_points 1, 2, 4, 8 or 16, spread_threads as above). */
+ * overlap 0 or 1, interp_points 1, 2, 4, 8 or 16, spread_threads as above, nl_stages 0, 2 or 3). */
 fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* tuning, int get);
 fsib_status fsib_plan_profile_read(fsib_plan plan, double* total_ms /* host */, int64_t* launches /* host */,
                                    double* bytes /* host */);

@@ -40,7 +40,8 @@ class _Params(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("xcd_chunk_interp", ctypes.c_int), ("xcd_chunk_spread", ctypes.c_int), ("split", ctypes.c_int),
-                ("overlap", ctypes.c_int), ("interp_points", ctypes.c_int), ("spread_threads", ctypes.c_int)]
+                ("overlap", ctypes.c_int), ("interp_points", ctypes.c_int), ("spread_threads", ctypes.c_int),
+                ("nl_stages", ctypes.c_int)]
 
 
 class _Force(ctypes.Structure):
@@ -266,8 +267,8 @@ class Plan:
 
     def tuning(self, **changes):
         """Launch-shape knobs (fsib_plan_tuning): with no arguments returns them as a dict; keyword
-        arguments (xcd_chunk_interp, xcd_chunk_spread, split, overlap, interp_points, spread_threads) set
-        them and return the new dict."""
+        arguments (xcd_chunk_interp, xcd_chunk_spread, split, overlap, interp_points, spread_threads,
+        nl_stages) set them and return the new dict."""
         t = _Tuning()
         _check(self._lib.fsib_plan_tuning(self._h, ctypes.byref(t), 1), "fsib_plan_tuning")
         if changes:

@@ -913,6 +913,7 @@ fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
     t->overlap = p.overlap;
     t->interp_points = p.interp_points;
     t->spread_threads = p.spread_threads;
+    t->nl_stages = p.nl_stages;
     return FSIB_OK;
   }
   if (t->xcd_chunk_interp < 0 || t->xcd_chunk_interp > 4096 || t->xcd_chunk_spread < 0 || t->xcd_chunk_spread > 4096)
@@ -926,6 +927,9 @@ fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* t, int get) {
   const int sthr = t->spread_threads;
   if (p.dim == 2 ? (sthr != 0 && sthr != 64 && sthr != 128 && sthr != 256) : (sthr != 0 && sthr != 256))
     return fail(FSIB_ERR_ARG, "spread_threads must be 0, 64, 128 or 256 (2D) or 0 or 256 (3D)");
+  if (t->nl_stages != 0 && t->nl_stages != 2 && t->nl_stages != 3)
+    return fail(FSIB_ERR_ARG, "nl_stages must be 0, 2 or 3");
+  p.nl_stages = t->nl_stages;
   p.spread_threads = sthr;
   p.interp_points = t->interp_points;
   p.overlap = t->overlap;

@@ -213,6 +213,241 @@ __global__ __launch_bounds__(1024) void k_nl_xpass(const cplx<T>* __restrict__ i
   }
 }
 
+// ---- length 192 = 16 x 12 in two stages ----
+// The dealiasing grid of the 128^3 workload has 192 points per line.  Split as 16 x 12, each
+// transform is two Stockham stages (radix 16 with no twiddles, then radix 12), and each thread keeps
+// one butterfly's entries in registers, so a line crosses LDS once per direction instead of three
+// times.  The kernel above spends most of its time on LDS traffic (its three radix-8/8/3 stages move
+// every entry through LDS twice per stage, plus the twiddle table); this one also
+//  - loads the first inverse stage's inputs straight from the half spectra (no gather in LDS),
+//  - pairs the rows instead of the components in its inverse lines (line c of a row pair is
+//    u_c(a) + i u_c(b)), so each product u_c1 u_c2 of both rows reads two entries, and forms the
+//    products while loading the first forward stage,
+//  - reads its twiddles through the vector memory path (four table entries per butterfly, which
+//    stay in L1), not from LDS,
+//  - unpacks the two rows of each forward line from registers, fetching the partner entry
+//    Z[N - m] from the lane that holds it.
+// Entries of a line sit in LDS with one pad entry per 16, so the stage-1 writes (16 apart) fall on
+// distinct banks.
+
+// e^{SG i pi j / 8} v for a compile-time j (after unrolling)
+template <typename T, int SG>
+__device__ __forceinline__ cplx<T> rot16(cplx<T> v, int j) {
+  const T sg = (T)SG;
+  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, h = (T)0.70710678118654752440;
+  switch (j & 15) {
+    case 0: return v;
+    case 1: return cmul(v, mk(c1, sg * s1));
+    case 2: return (v + mul_i(v, sg)) * h;
+    case 3: return cmul(v, mk(s1, sg * c1));
+    case 4: return mul_i(v, sg);
+    case 6: return (mul_i(v, sg) - v) * h;
+    case 9: return cmul(v, mk(-c1, -sg * s1));
+    default: return cmul(v, mk(cos((T)3.14159265358979323846 * j / 8), sg * sin((T)3.14159265358979323846 * j / 8)));
+  }
+}
+
+// In-place DFT of 16 entries, x[k] <- sum_n x[n] e^{SG 2 pi i n k / 16}: 4 x 4 Cooley-Tukey.
+template <typename T, int SG>
+__device__ __forceinline__ void dft16(cplx<T>* x) {
+  const T sg = (T)SG;
+  cplx<T> y[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    cplx<T> u[4] = {x[n1], x[n1 + 4], x[n1 + 8], x[n1 + 12]};
+    bfly<T, 4>(u, sg);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) y[n1 * 4 + k2] = rot16<T, SG>(u[k2], n1 * k2);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    cplx<T> u[4] = {y[k2], y[4 + k2], y[8 + k2], y[12 + k2]};
+    bfly<T, 4>(u, sg);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) x[4 * k1 + k2] = u[k1];
+  }
+}
+
+// In-place DFT of 12 entries (prime-factor 3 x 4, no twiddles): input n = (4 n1 + 3 n2) mod 12,
+// output k = (4 k1 + 9 k2) mod 12, so that n k = 4 n1 k1 + 3 n2 k2 (mod 12).
+template <typename T, int SG>
+__device__ __forceinline__ void dft12(cplx<T>* x) {
+  const T sg = (T)SG;
+  cplx<T> y[3][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cplx<T> u[3] = {x[(3 * n2) % 12], x[(4 + 3 * n2) % 12], x[(8 + 3 * n2) % 12]};
+    bfly<T, 3>(u, sg);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) y[k1][n2] = u[k1];
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    cplx<T> u[4] = {y[k1][0], y[k1][1], y[k1][2], y[k1][3]};
+    bfly<T, 4>(u, sg);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) x[(4 * k1 + 9 * k2) % 12] = u[k2];
+  }
+}
+
+__device__ __forceinline__ constexpr int at16(int t) { return t + (t >> 4); }
+
+// z[j] *= w^j (j = 1..11) for w = tw[r] = e^{-2 pi i r / 192}, conjugated when CONJ.  Four table
+// entries are loaded (w, w^2, w^4, w^8, exact to rounding) and the others formed as products of two
+// or three of them, so the eleven twiddles never sit in registers at once.
+template <typename T, bool CONJ>
+__device__ __forceinline__ void twiddle12(cplx<T>* z, const cplx<T>* __restrict__ tw, int r) {
+  cplx<T> w1 = tw[r], w2 = tw[2 * r], w4 = tw[4 * r], w8 = tw[8 * r];
+  if (CONJ) {
+    w1 = conj(w1);
+    w2 = conj(w2);
+    w4 = conj(w4);
+    w8 = conj(w8);
+  }
+  const cplx<T> w3 = cmul(w1, w2);
+  z[1] = cmul(z[1], w1);
+  z[2] = cmul(z[2], w2);
+  z[3] = cmul(z[3], w3);
+  z[4] = cmul(z[4], w4);
+  z[5] = cmul(z[5], cmul(w1, w4));
+  z[6] = cmul(z[6], cmul(w2, w4));
+  z[7] = cmul(z[7], cmul(w3, w4));
+  z[8] = cmul(z[8], w8);
+  z[9] = cmul(z[9], cmul(w1, w8));
+  z[10] = cmul(z[10], cmul(w2, w8));
+  z[11] = cmul(z[11], cmul(w3, w8));
+}
+constexpr int kNl192Threads = 192;         // 12 lines of 16 lanes
+constexpr int kNl192LineStride = 192 + 12;  // padded line in LDS
+
+// Two row pairs per workgroup: 6 inverse lines (row pair q, component c), then 12 forward lines
+// (row pair q, product f) in the same LDS buffer.  Thread (line = tid / 16, r = tid % 16).
+template <typename T, int HX>
+__global__ __launch_bounds__(kNl192Threads) void k_nl_xpass_16x12(const cplx<T>* __restrict__ in,
+                                                                  cplx<T>* __restrict__ out,
+                                                                  const cplx<T>* __restrict__ tw, int64_t rows,
+                                                                  T inv_cells) {
+  constexpr int N = 192, LS = kNl192LineStride;
+  extern __shared__ char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tid = threadIdx.x, ln = tid >> 4, r = tid & 15;
+  const int64_t pair0 = (int64_t)blockIdx.x * 2;
+  const int64_t cs = rows * HX;
+  // ---- inverse, stage 1 (radix 16 over t = r + 12 j), inputs from the half spectra ----
+  if (ln < 6 && r < 12) {
+    const int q = ln / 3, c = ln - 3 * q;
+    const int64_t ra = 2 * (pair0 + q), rb = ra + 1;
+    const cplx<T>* pa = ra < rows ? in + c * cs + ra * HX : nullptr;
+    const cplx<T>* pb = rb < rows ? in + c * cs + rb * HX : nullptr;
+    cplx<T> x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int t = r + 12 * j;
+      const bool front = 2 * t <= N;
+      const int m = front ? t : N - t;
+      cplx<T> A = mk((T)0, (T)0), B = mk((T)0, (T)0);
+      if (m < HX) {
+        if (pa) A = pa[m];
+        if (pb) B = pb[m];
+      }
+      if (m == 0) {  // 2 m = N never holds a mode (HX <= N / 2)
+        A.y = (T)0;
+        B.y = (T)0;
+      } else if (!front) {
+        A = conj(A);
+        B = conj(B);
+      }
+      x[j] = mk(A.x - B.y, A.y + B.x);
+    }
+    dft16<T, +1>(x);
+    cplx<T>* L = buf + ln * LS;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) L[at16(16 * r + j)] = x[j];
+  }
+  __syncthreads();
+  // ---- inverse, stage 2 (radix 12 over t = r + 16 j, twiddles e^{+2 pi i j r / N}), in place ----
+  if (ln < 6) {
+    cplx<T> z[12];
+    cplx<T>* L = buf + ln * LS;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) z[j] = L[at16(r + 16 * j)];
+    twiddle12<T, true>(z, tw, r);
+    dft12<T, +1>(z);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) L[at16(r + 16 * j)] = z[j];
+  }
+  __syncthreads();
+  // ---- products of both rows packed as prod_f(a) + i prod_f(b), forward stage 1 (radix 16) ----
+  const int q = ln / 6, f = ln - 6 * q;
+  cplx<T> x[16];
+  if (r < 12) {
+    // product f = u_c1 u_c2 in the order xx, xy, xz, yy, yz, zz
+    const int c1 = f < 3 ? 0 : (f < 5 ? 1 : 2);
+    const int c2 = f < 3 ? f : (f < 5 ? f - 2 : 2);
+    const cplx<T>* L1 = buf + (3 * q + c1) * LS;
+    const cplx<T>* L2 = buf + (3 * q + c2) * LS;
+    // squares and cross products on separate paths: a select between the two (one read for a
+    // square) kept both operands of all 16 positions in registers (128 VGPRs in FP64)
+    if (c1 == c2) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const cplx<T> v = L1[at16(r + 12 * j)];
+        x[j] = mk(v.x * v.x, v.y * v.y);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int t = at16(r + 12 * j);
+        const cplx<T> v1 = L1[t], v2 = L2[t];
+        x[j] = mk(v1.x * v2.x, v1.y * v2.y);
+      }
+    }
+    dft16<T, -1>(x);
+  }
+  __syncthreads();  // every inverse entry has been read
+  if (r < 12) {
+    cplx<T>* L = buf + ln * LS;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) L[at16(16 * r + j)] = x[j];
+  }
+  __syncthreads();
+  // ---- forward, stage 2 (radix 12, twiddles e^{-2 pi i j r / N}) and the unpack ----
+  cplx<T> z[12];
+  {
+    const cplx<T>* L = buf + ln * LS;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) z[j] = L[at16(r + 16 * j)];
+    twiddle12<T, false>(z, tw, r);
+    dft12<T, -1>(z);
+  }
+  // This thread holds Z[r + 16 j].  Modes m = r + 16 s < HX (s <= 3, and s = 4 for r = 0) need
+  // Z[N - m]: for r > 0 that is Z[(16 - r) + 16 (11 - s)] of lane 16 - r of the same line, for r = 0
+  // it is this thread's Z[16 ((12 - s) mod 12)].
+  const int partner = (threadIdx.x & 63 & ~15) | ((16 - r) & 15);
+  const int64_t ra = 2 * (pair0 + q), rb = ra + 1;
+  const T sc = (T)0.5 * inv_cells;
+  cplx<T>* oa = out + f * cs + ra * HX;
+  cplx<T>* ob = out + f * cs + rb * HX;
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    cplx<T> zc;
+    if (s < 4) {
+      zc.x = __shfl(z[11 - s].x, partner, 64);
+      zc.y = __shfl(z[11 - s].y, partner, 64);
+      if (r == 0) zc = z[(12 - s) % 12];
+    } else {
+      zc = z[8];
+    }
+    const int m = r + 16 * s;
+    if ((s < 4 || r == 0) && m < HX && ra < rows) {
+      zc = conj(zc);
+      const cplx<T> su = z[s] + zc, d = z[s] - zc;
+      oa[m] = su * sc;
+      if (rb < rows) ob[m] = mk(d.y * sc, -d.x * sc);
+    }
+  }
+}
+
 template <typename T>
 static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t st) {
   const int n = (int)p.nd[0];
@@ -247,7 +482,18 @@ static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t 
   const T inv = (T)(1.0 / (double)p.dealias_cells());
   const bool prof = prof_on(p, PROF_NL_X);
   if (prof) prof_start(p, st);
-  if (p.dim == 3 && n == 192 && pp == 2 && p.Hx == 65)
+  // Two or three stages on 192-point lines.  The two-stage kernel is faster alone (95 against 119 us
+  // per launch in FP64 at 128^3), but it draws memory and LDS at a higher rate, and beside the point
+  // side of an overlapped FP64 step (latency-bound sorting, spreading and interpolation on the second
+  // stream) the step measured 1.185 ms against 1.158 with the three-stage kernel; in FP32 and in
+  // steps that do not overlap it wins (serial FP64 step 1.278 against 1.333 ms).
+  const bool overlapped = p.overlap && p.aux;
+  const int stages = p.nl_stages != 0 ? p.nl_stages : (sizeof(T) == 8 && overlapped ? 3 : 2);
+  if (p.dim == 3 && n == 192 && pp == 2 && p.Hx == 65 && stages == 2)
+    hipLaunchKernelGGL((k_nl_xpass_16x12<T, 65>), dim3(nblk), dim3(kNl192Threads),
+                       (size_t)12 * kNl192LineStride * sizeof(cplx<T>), st, (const cplx<T>*)in, (cplx<T>*)out, a.tw,
+                       rows, inv);
+  else if (p.dim == 3 && n == 192 && pp == 2 && p.Hx == 65)
     hipLaunchKernelGGL((k_nl_xpass<T, 3, 192, 2, 65>), dim3(nblk), dim3(nthr), lds, st, (const cplx<T>*)in,
                        (cplx<T>*)out, a, rows, (int)p.Hx, pp, inv);
   else if (p.dim == 3 && n == 192 && pp == 2)

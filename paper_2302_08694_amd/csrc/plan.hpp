@@ -109,6 +109,7 @@ struct Plan {
   int overlap = 1;
   int interp_points = 4;  // points per interpolation wavefront (4 measured faster than 8 and 16)
   int spread_threads = 0; // threads per spreading tile (0: the default of the dimension and precision)
+  int nl_stages = 0;      // FFT stages of the fused products x pass on 192-point lines (0: automatic)
   hipEvent_t fj[4] = {nullptr, nullptr, nullptr, nullptr};
   // optional timing of one kernel class with HIP events on the launch stream
   int prof_class = -1;

@@ -5,9 +5,10 @@
 `run()` performs one representative unit of work on the plan (a time step, a pair of transforms);
 it is called once per trial to warm up and then `reps` times under the clock.  The search is one
 pass of coordinate descent: the spreading variant of 2D plans (threads, i.e. cells per lane, of a
-16 x 16 tile), the XCD run length of spreading, then that of interpolation, the heavy-tile split and
-the points per interpolation wavefront, each over a short candidate list, keeping the best value of
-each before moving on.  The knobs change only the launch shape (and, for the split, the order in
+16 x 16 tile), the XCD run length of spreading, then that of interpolation, the heavy-tile split,
+the points per interpolation wavefront and, on Navier-Stokes plans with 192-point dealiasing lines,
+the FFT stages of the fused products pass, each over a short candidate list, keeping the best value
+of each before moving on.  The knobs change only the launch shape (and, for the split, the order in
 which partial tiles are summed), so results agree to rounding whatever is chosen.
 """
 
@@ -21,6 +22,7 @@ CANDIDATES = {
     "xcd_chunk_interp": (0, 16, 64, 256),
     "split": (256, 512, 1024, 2048),
     "interp_points": (4, 8),
+    "nl_stages": (2, 3),  # fused products x pass: 16 x 12 in registers or 8 x 8 x 3 through LDS
 }
 
 
@@ -38,6 +40,8 @@ def autotune(plan, run, reps=3, candidates=None):
     cands = dict(CANDIDATES if candidates is None else candidates)
     if plan.dim == 3:
         cands.pop("spread_threads", None)  # one spreading variant for 3D tiles
+    if plan.info()["n_dealias"][0] != 192:
+        cands.pop("nl_stages", None)  # one products kernel for other dealiasing lengths
     best = plan.tuning()
     trials = []
     best_t = _time(run, reps)

@@ -118,8 +118,17 @@ def test_set_instances_rejects_null_plan():
 
 def test_tuning_rejects_null_arguments():
     lib = B.load_library()
-    t = B._Tuning(0, 0, 512, 1, 8, 0)
+    t = B._Tuning(0, 0, 512, 1, 8, 0, 0)
     assert lib.fsib_plan_tuning(None, ctypes.byref(t), 1) == 1
+
+
+def test_tuning_struct_matches_header():
+    """The binding's tuning struct lists the header's fields in order (seven ints)."""
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "fsib.h")).read()
+    body = hdr[hdr.index("/* Launch-shape knobs of a plan"):hdr.index("} fsib_tuning;")]
+    fields = re.findall(r"^\s*int (\w+);", body, re.M)
+    assert fields == [k for k, _ in B._Tuning._fields_]
+    assert ctypes.sizeof(B._Tuning) == 4 * len(fields) == 28
 
 
 def test_group_calls_reject_bad_arguments():

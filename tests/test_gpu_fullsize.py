@@ -111,6 +111,36 @@ def test_fluid_update_full_size(F, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("stages", [2, 3])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fluid_update_192_lines_flat_box(F, prec, stages):
+    """Lines of 192 dealiasing points on a flat mode box (128 x 10 x 6 modes, dealiasing grid
+    192 x 16 x 10), both products kernels (tuning nl_stages: 16 x 12 in registers, 8 x 8 x 3 through
+    LDS), against the oracle's update."""
+    announce(f"fluid update, 192-point lines, flat box {prec}, {stages} stages")
+    Ns = (128, 10, 6)
+    L, rho, mu, dt = 1.0, 1.0, 0.01, 5e-4
+    u0 = fluid.zero_nyquist(fluid.project(random_real_field_hat(Ns, 3, 37), Ns, L), Ns) * 20.0
+    fh = random_real_field_hat(Ns, 3, 38) * 100.0
+    mid_ref, new_ref = fluid.ns_update(fh, u0, Ns, L, rho, mu, dt, npad=(200, 16, 10))
+    plan = F.Plan(3, Ns, prec=prec, tol=1e-11 if prec == "f64" else 1e-5, max_points=8, fluid=True,
+                  navier_stokes=True)
+    nd = plan.info()["n_dealias"]
+    assert tuple(nd) == (192, 16, 10), nd
+    plan.tuning(nl_stages=stages)
+    with pytest.raises(F.FSIBError):
+        plan.tuning(nl_stages=1)
+    assert plan.tuning()["nl_stages"] == stages
+    u = dev(half(u0, Ns[0]), cdtype(prec))
+    mid = torch.zeros_like(u)
+    plan.fluid_step(F.FluidParams("navier_stokes", rho=rho, mu=mu, dt=dt), dev(half(fh, Ns[0]), cdtype(prec)), u, mid)
+    e1 = rel_l2(host(mid), half(mid_ref, Ns[0]))
+    e2 = rel_l2(host(u), half(new_ref, Ns[0]))
+    print(f"fluid update {Ns} dealias {nd} {prec} {stages} stages: mid {e1:.3e} new {e2:.3e}")
+    assert max(e1, e2) < (1e-12 if prec == "f64" else 1e-5)
+    plan.close()
+
+
 def test_step_invariants_full_size(F, ns3d):
     """One Alg. 1 step at the benchmark size: k.u = 0, zero net force, constant mean flow, volume."""
     announce("full-size step invariants f64")
