@@ -528,8 +528,9 @@ fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U
 
 // dealiased products of the field uhat (dim half spectra) -> p.pihat (nprod half spectra):
 // inverse passes along z and y onto the dealiasing grid, the fused x pass (inverse transform,
-// products, forward transform), forward passes along y and z back to K_N.
-fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st) {
+// products, forward transform), forward passes along y and z back to K_N.  With last = false the
+// pass along z is left out (the products wait in p.D1 for the pass fused with the update).
+fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st, bool last = true) {
   const int64_t d = p.dim, np = p.nprod();
   if (p.dim == 3) {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.D1, (int)p.nd[2], +1, p.N[1] * p.Hx, d, (int)p.N[2],
@@ -539,8 +540,9 @@ fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st) {
     FSIB_HIP(fsib::launch_nl_xpass(p, p.D2, p.prod, st));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.prod, p.D1, (int)p.nd[1], -1, p.Hx, np * p.nd[2], (int)p.nd[1], (int)p.nd[1],
                                   (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_fft_c2c(p, p.D1, p.pihat, (int)p.nd[2], -1, p.N[1] * p.Hx, np, (int)p.nd[2], (int)p.nd[2],
-                                  (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, nullptr, 1.0, st));
+    if (last)
+      FSIB_HIP(fsib::launch_fft_c2c(p, p.D1, p.pihat, (int)p.nd[2], -1, p.N[1] * p.Hx, np, (int)p.nd[2],
+                                    (int)p.nd[2], (int)p.N[2], (int)ceil_half(p.N[2]), nullptr, nullptr, 1.0, st));
   } else {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.D2, (int)p.nd[1], +1, p.Hx, d, (int)p.N[1], (int)ceil_half(p.N[1]),
                                   (int)p.nd[1], (int)p.nd[1], nullptr, nullptr, 1.0, st));
@@ -548,6 +550,21 @@ fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st) {
     FSIB_HIP(fsib::launch_fft_c2c(p, p.prod, p.pihat, (int)p.nd[1], -1, p.Hx, np, (int)p.nd[1], (int)p.nd[1],
                                   (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, nullptr, 1.0, st));
   }
+  return FSIB_OK;
+}
+
+// Navier-Stokes update (mode FLUID_NS_HALF or FLUID_NS_FULL) uout <- update(fhat, uin) with the dealiased
+// products of `field`; `ev` (when not null) is waited for before anything reads fhat.  Plans with 128
+// modes and 192 dealiasing points along z run the products' last pass and the update as one kernel.
+fsib_status ns_update(Plan& p, int mode, const fsib_fluid_params& prm, const void* field, const void* fhat,
+                      const void* uin, void* uout, hipEvent_t ev, hipStream_t st) {
+  const bool fused = fsib::products_z_fluid_fits(p);
+  FSIB_TRY(dealiased_products(p, field, st, !fused));
+  if (ev) FSIB_HIP(hipStreamWaitEvent(st, ev, 0));
+  if (fused)
+    FSIB_HIP(fsib::launch_products_z_fluid(p, mode, prm, fhat, uin, uout, st));
+  else
+    FSIB_HIP(fsib::launch_fluid_update(p, mode, prm, fhat, uin, uout, st));
   return FSIB_OK;
 }
 
@@ -560,10 +577,8 @@ fsib_status fluid_impl(Plan& p, const fsib_fluid_params& prm, const void* fhat, 
     return FSIB_OK;
   }
   void* mid = umid ? umid : p.uhat_mid;
-  FSIB_TRY(dealiased_products(p, uhat, st));
-  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_HALF, prm, fhat, uhat, mid, st));
-  FSIB_TRY(dealiased_products(p, mid, st));
-  FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_FULL, prm, fhat, uhat, uhat, st));
+  FSIB_TRY(ns_update(p, fsib::FLUID_NS_HALF, prm, uhat, fhat, uhat, mid, nullptr, st));
+  FSIB_TRY(ns_update(p, fsib::FLUID_NS_FULL, prm, mid, fhat, uhat, uhat, nullptr, st));
   return FSIB_OK;
 }
 
@@ -1199,10 +1214,8 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, s2, p.S));
     FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, s2));
     FSIB_HIP(hipEventRecord(p.fj[1], s2));
-    FSIB_TRY(dealiased_products(p, uhat_half, st));
-    FSIB_HIP(hipStreamWaitEvent(st, p.fj[1], 0));
-    // uhat^{m+1/2} (eq. spatial_2)
-    FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_HALF, prm, p.fhat, uhat_half, p.uhat_mid, st));
+    // uhat^{m+1/2} (eq. spatial_2), once fhat^{m+1/2} is complete
+    FSIB_TRY(ns_update(p, fsib::FLUID_NS_HALF, prm, uhat_half, p.fhat, uhat_half, p.uhat_mid, p.fj[1], st));
     // U^{m+1/2} at X^{m+1/2} (points still sorted), X^{m+1} (eq. spatial_4) and its sort beside the
     // products of uhat^{m+1/2} and the full update (eq. spatial_3)
     FSIB_HIP(hipEventRecord(p.fj[2], st));
@@ -1210,8 +1223,7 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     FSIB_TRY(velocity_interp_sorted(p, M, p.uhat_mid, p.Uh, s2));
     FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, s2));
     FSIB_HIP(fsib::launch_sort_points(p, M, X, s2));
-    FSIB_TRY(dealiased_products(p, p.uhat_mid, st));
-    FSIB_HIP(fsib::launch_fluid_update(p, fsib::FLUID_NS_FULL, prm, p.fhat, uhat_half, uhat_half, st));
+    FSIB_TRY(ns_update(p, fsib::FLUID_NS_FULL, prm, p.uhat_mid, p.fhat, uhat_half, uhat_half, nullptr, st));
     // U^{m+1} at X^{m+1}: on s2 after the full update (the next step's products proceed on st), on st
     // after the last step
     if (last) {

@@ -29,16 +29,6 @@ static size_t flag_bytes(int nflags) { return (size_t)((nflags + 15) / 16 * 16);
 // precisions (measured at 128^3: 1024 or 4096 entries are slower in FP64, 4096 is slower in FP32)
 constexpr int kFftWgEntries = 2048;
 
-// Middle Stockham stages s = S .. SL-1 of a compile-time strided pass (each reads LDS, synchronises,
-// writes LDS and synchronises).
-template <typename T, int N, int NB, int NTHR, int S, int SL>
-__device__ __forceinline__ void middle_stages(cplx<T>* buf, const cplx<T>* twl, int sign) {
-  if constexpr (S < SL) {
-    stage_ct<T, false, N, NB, NTHR, ct_radix_at(N, S), ct_p_before(N, S), 0>(buf, twl, sign);
-    middle_stages<T, N, NB, NTHR, S + 1, SL>(buf, twl, sign);
-  }
-}
-
 // Strided pass with the length and the line count known at compile time, its first and last Stockham
 // stages in registers: the first stage's butterflies read their inputs straight from memory (zero
 // padding and the per-entry factors folded in) and write the outputs to LDS; the middle stages run in

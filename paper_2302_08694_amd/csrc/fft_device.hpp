@@ -272,6 +272,16 @@ __device__ __forceinline__ void stockham_ct_dir(cplx<T>* buf, const cplx<T>* twl
   }
 }
 
+// Middle Stockham stages s = S .. SL-1 of a compile-time strided pass (each reads LDS, synchronises,
+// writes LDS and synchronises).
+template <typename T, int N, int NB, int NTHR, int S, int SL>
+__device__ __forceinline__ void middle_stages(cplx<T>* buf, const cplx<T>* twl, int sign) {
+  if constexpr (S < SL) {
+    stage_ct<T, false, N, NB, NTHR, ct_radix_at(N, S), ct_p_before(N, S), 0>(buf, twl, sign);
+    middle_stages<T, N, NB, NTHR, S + 1, SL>(buf, twl, sign);
+  }
+}
+
 // Direction known only at run time (a single code path serves both; two unrolled copies measured
 // no faster).
 template <typename T, bool CONTIG, int N, int NB, int NTHR = N * NB / kEPT>

@@ -10,31 +10,10 @@
 //   form of eq. nonlinear_physical for the divergence-free fields the update produces; the
 //   products are formed on the dealiasing grid (three-halves rule, Sec. 3.1).
 //   Modes with any m_a = -N_a/2 (even N_a) are set to zero so the field stays real.
+#include "fluid_device.hpp"
 #include "plan.hpp"
 
 namespace fsib {
-
-struct ModeGeo {
-  int dim;
-  int64_t N[3];
-  int64_t Hx;
-  double L;
-};
-
-__device__ __forceinline__ int64_t mode_of(int64_t i, int64_t n) { return i < (n + 1) / 2 ? i : i - n; }
-
-__device__ __forceinline__ int sym_index(int a, int b, int dim) {
-  if (a > b) {
-    const int t = a;
-    a = b;
-    b = t;
-  }
-  if (dim == 3) {
-    const int base[3] = {0, 3, 5};
-    return base[a] + (b - a);
-  }
-  return a == 0 ? b : 2;
-}
 
 template <typename T>
 struct FluidArgs {
@@ -98,29 +77,17 @@ __device__ __forceinline__ void fluid_body(const FluidArgs<T>& A, Blk wb) {
     return;
   }
   // Navier-Stokes
-  cplx<T> P[3];
-  cplx<T> kP = mk((T)0, (T)0);
-  const T inv_rho = (T)1 / rho;
+  cplx<T> sh[3], f[3], u[3], r[3];
   for (int a = 0; a < DIM; ++a) {
-    cplx<T> s = mk((T)0, (T)0);
-    for (int b = 0; b < DIM; ++b) s = s + mul_i(pihat[sym_index(a, b, DIM) * nm + idx], k[b]);
-    P[a] = fhat[a * nm + idx] * inv_rho - s;
-    if (k2 == (T)0) P[a].x += (a == 0 ? b0 : (a == 1 ? b1 : b2)) * inv_rho;  // uniform body force
-    kP = kP + P[a] * k[a];
+    cplx<T> acc = mk((T)0, (T)0);
+    for (int b = 0; b < DIM; ++b) acc = acc + mul_i(pihat[sym_index(a, b, DIM) * nm + idx], k[b]);
+    sh[a] = acc;
+    f[a] = fhat[a * nm + idx];
+    u[a] = uin[a * nm + idx];
   }
-  const T k2p = k2 == (T)0 ? (T)1 : k2;
-  const T av = mu * dt * k2 / ((T)2 * rho);
-  const T den = (T)1 / ((T)1 + av);
-  for (int a = 0; a < DIM; ++a) {
-    const cplx<T> Q = P[a] - kP * (k[a] / k2p);
-    const cplx<T> u = uin[a * nm + idx];
-    cplx<T> r;
-    if (mode == FLUID_NS_HALF)
-      r = (Q * (dt * (T)0.5) + u) * den;
-    else
-      r = (Q * dt + u * ((T)1 - av)) * den;
-    uout[a * nm + idx] = r;
-  }
+  const T body[3] = {b0, b1, b2};
+  ns_mode_update<T, DIM>(mode, rho, mu, dt, body, k, k2, sh, f, u, r);
+  for (int a = 0; a < DIM; ++a) uout[a * nm + idx] = r[a];
 }
 
 template <typename T, int DIM>

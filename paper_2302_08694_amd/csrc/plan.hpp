@@ -240,6 +240,11 @@ hipError_t launch_fft_c2r_x(const Plan& p, const void* in, void* out, int n, int
 hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, hipStream_t st);  // nonlinear.hip
 bool fft_line_fits(const Plan& p, int n);  // fft.hip
 bool nl_line_fits(const Plan& p, int n);   // nonlinear.hip
+// products_fluid.hip: the forward z pass of the products (from p.D1) fused with the Navier-Stokes
+// update, for 3D plans with 128 modes and 192 dealiasing points along z
+bool products_z_fluid_fits(const Plan& p);
+hipError_t launch_products_z_fluid(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
+                                   const void* uin, void* uout, hipStream_t st);
 hipError_t launch_fluid_update(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat,
                                const void* uin, void* uout, hipStream_t st);
 hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X, double* F,

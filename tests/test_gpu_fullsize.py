@@ -141,6 +141,34 @@ def test_fluid_update_192_lines_flat_box(F, prec, stages):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fluid_update_products_z_fused(F, prec):
+    """128 modes and 192 dealiasing points along z: the products' last pass and the update run as one
+    kernel; a narrow box (12 x 10 x 128 modes, 70 (ky, kx) columns, the last workgroup partly
+    filled, a uniform body force) against the oracle's update, both half and full step."""
+    announce(f"fluid update, fused z pass, narrow box {prec}")
+    Ns = (12, 10, 128)
+    L, rho, mu, dt = 1.0, 1.0, 0.01, 5e-4
+    u0 = fluid.zero_nyquist(fluid.project(random_real_field_hat(Ns, 3, 39), Ns, L), Ns) * 20.0
+    fh = random_real_field_hat(Ns, 3, 40) * 100.0
+    body = np.array([0.3, -0.2, 0.1])
+    fh_ref = fh.copy()
+    fh_ref[:, 0, 0, 0] += body  # a uniform body force is an extra k = 0 force density
+    mid_ref, new_ref = fluid.ns_update(fh_ref, u0, Ns, L, rho, mu, dt, npad=(20, 16, 200))
+    plan = F.Plan(3, Ns, prec=prec, tol=1e-11 if prec == "f64" else 1e-5, max_points=8, fluid=True,
+                  navier_stokes=True)
+    assert tuple(plan.info()["n_dealias"]) == (18, 16, 192)
+    u = dev(half(u0, Ns[0]), cdtype(prec))
+    mid = torch.zeros_like(u)
+    plan.fluid_step(F.FluidParams("navier_stokes", rho=rho, mu=mu, dt=dt, body=tuple(body)),
+                    dev(half(fh, Ns[0]), cdtype(prec)), u, mid)
+    e1 = rel_l2(host(mid), half(mid_ref, Ns[0]))
+    e2 = rel_l2(host(u), half(new_ref, Ns[0]))
+    print(f"fluid update {Ns} fused z pass {prec}: mid {e1:.3e} new {e2:.3e}")
+    assert max(e1, e2) < (1e-12 if prec == "f64" else 1e-5)
+    plan.close()
+
+
 def test_step_invariants_full_size(F, ns3d):
     """One Alg. 1 step at the benchmark size: k.u = 0, zero net force, constant mean flow, volume."""
     announce("full-size step invariants f64")
