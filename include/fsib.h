@@ -119,9 +119,10 @@ typedef struct {
                             modes): FFT stages of the fused x pass of the dealiased products (Sec.
                             3.1), 2 (16 x 12, registers between the stages; fastest alone) or 3 (8 x 8
                             x 3 through LDS; lower peak demand on memory and LDS, which leaves more of
-                            the GPU to a point side running beside it); 0 picks 3 for FP64 plans whose
-                            point side overlaps (overlap = 1) and 2 otherwise.  Other plans take any of
-                            0, 2, 3 and ignore it. */
+                            the GPU to a point side running beside it); 0 picks 3 for the first half
+                            step of FP64 steps whose point side overlaps (overlap = 1), where that side
+                            is the critical path, and 2 otherwise.  Other plans take any of 0, 2, 3
+                            and ignore it. */
 } fsib_tuning;
 
 typedef enum { FSIB_STOKES = 0, FSIB_NAVIER_STOKES = 1 } fsib_model;

@@ -526,18 +526,32 @@ fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U
   return FSIB_OK;
 }
 
+// FFT stages of the fused products x pass on 192-point lines: the tuning knob, else two (the faster
+// kernel alone: 95 against 119 us per launch at 128^3 in FP64) unless an FP64 first half step runs
+// it beside its point side.  There the point side (sorting, spreading, the type-1 passes) is the
+// step's critical path, and the two-stage kernel's higher draw on memory and LDS slows it more than
+// the products gain: 128^3 FP64 steps measured 1.113 ms with three stages in the first half and two
+// in the second, 1.123 with three in both, 1.141 with two in both, 1.152 with two then three.
+static int products_stages(const Plan& p, bool beside_point_side) {
+  if (p.nl_stages != 0) return p.nl_stages;
+  return p.prec == FSIB_F64 && beside_point_side ? 3 : 2;
+}
+
 // dealiased products of the field uhat (dim half spectra) -> p.pihat (nprod half spectra):
 // inverse passes along z and y onto the dealiasing grid, the fused x pass (inverse transform,
 // products, forward transform), forward passes along y and z back to K_N.  With last = false the
 // pass along z is left out (the products wait in p.D1 for the pass fused with the update).
-fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st, bool last = true) {
+// beside_point_side: the first half step's point side runs concurrently (picks the x-pass kernel).
+fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st, bool last = true,
+                               bool beside_point_side = false) {
+  const int stages = products_stages(p, beside_point_side);
   const int64_t d = p.dim, np = p.nprod();
   if (p.dim == 3) {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.D1, (int)p.nd[2], +1, p.N[1] * p.Hx, d, (int)p.N[2],
                                   (int)ceil_half(p.N[2]), (int)p.nd[2], (int)p.nd[2], nullptr, nullptr, 1.0, st));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.D1, p.D2, (int)p.nd[1], +1, p.Hx, d * p.nd[2], (int)p.N[1],
                                   (int)ceil_half(p.N[1]), (int)p.nd[1], (int)p.nd[1], nullptr, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_nl_xpass(p, p.D2, p.prod, st));
+    FSIB_HIP(fsib::launch_nl_xpass(p, p.D2, p.prod, stages, st));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.prod, p.D1, (int)p.nd[1], -1, p.Hx, np * p.nd[2], (int)p.nd[1], (int)p.nd[1],
                                   (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, nullptr, 1.0, st));
     if (last)
@@ -546,7 +560,7 @@ fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st, bool l
   } else {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.D2, (int)p.nd[1], +1, p.Hx, d, (int)p.N[1], (int)ceil_half(p.N[1]),
                                   (int)p.nd[1], (int)p.nd[1], nullptr, nullptr, 1.0, st));
-    FSIB_HIP(fsib::launch_nl_xpass(p, p.D2, p.prod, st));
+    FSIB_HIP(fsib::launch_nl_xpass(p, p.D2, p.prod, stages, st));
     FSIB_HIP(fsib::launch_fft_c2c(p, p.prod, p.pihat, (int)p.nd[1], -1, p.Hx, np, (int)p.nd[1], (int)p.nd[1],
                                   (int)p.N[1], (int)ceil_half(p.N[1]), nullptr, nullptr, 1.0, st));
   }
@@ -556,10 +570,11 @@ fsib_status dealiased_products(Plan& p, const void* uhat, hipStream_t st, bool l
 // Navier-Stokes update (mode FLUID_NS_HALF or FLUID_NS_FULL) uout <- update(fhat, uin) with the dealiased
 // products of `field`; `ev` (when not null) is waited for before anything reads fhat.  Plans with 128
 // modes and 192 dealiasing points along z run the products' last pass and the update as one kernel.
+// beside_point_side as for dealiased_products.
 fsib_status ns_update(Plan& p, int mode, const fsib_fluid_params& prm, const void* field, const void* fhat,
-                      const void* uin, void* uout, hipEvent_t ev, hipStream_t st) {
+                      const void* uin, void* uout, hipEvent_t ev, hipStream_t st, bool beside_point_side = false) {
   const bool fused = fsib::products_z_fluid_fits(p);
-  FSIB_TRY(dealiased_products(p, field, st, !fused));
+  FSIB_TRY(dealiased_products(p, field, st, !fused, beside_point_side));
   if (ev) FSIB_HIP(hipStreamWaitEvent(st, ev, 0));
   if (fused)
     FSIB_HIP(fsib::launch_products_z_fluid(p, mode, prm, fhat, uin, uout, st));
@@ -1215,7 +1230,7 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, s2));
     FSIB_HIP(hipEventRecord(p.fj[1], s2));
     // uhat^{m+1/2} (eq. spatial_2), once fhat^{m+1/2} is complete
-    FSIB_TRY(ns_update(p, fsib::FLUID_NS_HALF, prm, uhat_half, p.fhat, uhat_half, p.uhat_mid, p.fj[1], st));
+    FSIB_TRY(ns_update(p, fsib::FLUID_NS_HALF, prm, uhat_half, p.fhat, uhat_half, p.uhat_mid, p.fj[1], st, s2 != st));
     // U^{m+1/2} at X^{m+1/2} (points still sorted), X^{m+1} (eq. spatial_4) and its sort beside the
     // products of uhat^{m+1/2} and the full update (eq. spatial_3)
     FSIB_HIP(hipEventRecord(p.fj[2], st));

@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kNl192Threads) void k_nl_xpass_16x12(const cplx<T>*
 }
 
 template <typename T>
-static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t st) {
+static hipError_t nl_impl(const Plan& p, const void* in, void* out, int stages, hipStream_t st) {
   const int n = (int)p.nd[0];
   FftArgs<T> a;
   const PassMasks none;
@@ -482,13 +482,7 @@ static hipError_t nl_impl(const Plan& p, const void* in, void* out, hipStream_t 
   const T inv = (T)(1.0 / (double)p.dealias_cells());
   const bool prof = prof_on(p, PROF_NL_X);
   if (prof) prof_start(p, st);
-  // Two or three stages on 192-point lines.  The two-stage kernel is faster alone (95 against 119 us
-  // per launch in FP64 at 128^3), but it draws memory and LDS at a higher rate, and beside the point
-  // side of an overlapped FP64 step (latency-bound sorting, spreading and interpolation on the second
-  // stream) the step measured 1.185 ms against 1.158 with the three-stage kernel; in FP32 and in
-  // steps that do not overlap it wins (serial FP64 step 1.278 against 1.333 ms).
-  const bool overlapped = p.overlap && p.aux;
-  const int stages = p.nl_stages != 0 ? p.nl_stages : (sizeof(T) == 8 && overlapped ? 3 : 2);
+  // two or three FFT stages on 192-point lines (the caller's choice)
   if (p.dim == 3 && n == 192 && pp == 2 && p.Hx == 65 && stages == 2)
     hipLaunchKernelGGL((k_nl_xpass_16x12<T, 65>), dim3(nblk), dim3(kNl192Threads),
                        (size_t)12 * kNl192LineStride * sizeof(cplx<T>), st, (const cplx<T>*)in, (cplx<T>*)out, a.tw,
@@ -525,8 +519,8 @@ bool nl_line_fits(const Plan& p, int n) {
   return (size_t)(lpad_len(fl * n) + n) * cs <= (size_t)p.lds_max;
 }
 
-hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, hipStream_t st) {
-  return p.prec == FSIB_F64 ? nl_impl<double>(p, in, out, st) : nl_impl<float>(p, in, out, st);
+hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, int stages, hipStream_t st) {
+  return p.prec == FSIB_F64 ? nl_impl<double>(p, in, out, stages, st) : nl_impl<float>(p, in, out, stages, st);
 }
 
 }  // namespace fsib

@@ -237,7 +237,8 @@ hipError_t launch_fft_r2c_x(const Plan& p, const void* in, void* out, int n, int
 hipError_t launch_fft_c2r_x(const Plan& p, const void* in, void* out, int n, int64_t rows, int nin,
                             const void* fac_in, double scale, hipStream_t st, const PassMasks& mk = PassMasks());
 // fluid.hip
-hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, hipStream_t st);  // nonlinear.hip
+// nonlinear.hip; stages (2 or 3) picks the kernel of 192-point lines, other lengths have one
+hipError_t launch_nl_xpass(const Plan& p, const void* in, void* out, int stages, hipStream_t st);
 bool fft_line_fits(const Plan& p, int n);  // fft.hip
 bool nl_line_fits(const Plan& p, int n);   // nonlinear.hip
 // products_fluid.hip: the forward z pass of the products (from p.D1) fused with the Navier-Stokes
