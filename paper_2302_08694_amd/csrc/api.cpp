@@ -505,7 +505,9 @@ fsib_status force_spread_sorted(Plan& p, int64_t M, const void* S_, void* fhat, 
 }
 
 // dim half spectra -> real vector velocity at the sorted point set
-fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U, hipStream_t st) {
+// U at the sorted points from uhat; move (nullable): X += move_a U in the same pass.
+fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U, hipStream_t st,
+                                   double* move = nullptr, double move_a = 0) {
   const int64_t d = (int64_t)p.dim * p.ninst;  // real fields of all instances
   if (p.dim == 3) {
     FSIB_HIP(fsib::launch_fft_c2c(p, uhat, p.B2, (int)p.nf[2], +1, p.N[1] * p.Hx, d, (int)p.N[2],
@@ -522,7 +524,7 @@ fsib_status velocity_interp_sorted(Plan& p, int64_t M, const void* uhat, void* U
     FSIB_HIP(fsib::launch_fft_c2r_x(p, p.B1, p.grid, (int)p.nf[0], d * p.nf[1], (int)p.Hx, p.fac[0], 1.0, st,
                                     mask_x(p)));
   }
-  FSIB_HIP(fsib::launch_interp(p, M, U, p.dim, st));
+  FSIB_HIP(fsib::launch_interp(p, M, U, p.dim, st, move, move_a));
   return FSIB_OK;
 }
 
@@ -1224,8 +1226,7 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     const bool last = n + 1 == nsteps;
     // X^{m+1/2} = X^m + dt/2 U^m (eq. spatial_1); F^{m+1/2} and fhat^{m+1/2} (eq. force_spreading_quad),
     // beside the products of uhat^m
-    FSIB_HIP(fsib::launch_axpy_positions(p, M, p.Xh, X, U, 0.5 * dt, s2));
-    FSIB_HIP(fsib::launch_force_strengths(p, *force, M, p.Xh, p.F64, p.S, s2));
+    FSIB_HIP(fsib::launch_move_force_strengths(p, *force, M, p.Xh, X, U, 0.5 * dt, p.F64, p.S, s2));
     FSIB_HIP(fsib::launch_sort_points(p, M, p.Xh, s2, p.S));
     FSIB_TRY(force_spread_sorted(p, M, p.S, p.fhat, 1.0 / Ld, s2));
     FSIB_HIP(hipEventRecord(p.fj[1], s2));
@@ -1235,8 +1236,7 @@ fsib_status fsib_steps(fsib_plan plan, const fsib_fluid_params* params, const fs
     // products of uhat^{m+1/2} and the full update (eq. spatial_3)
     FSIB_HIP(hipEventRecord(p.fj[2], st));
     FSIB_HIP(hipStreamWaitEvent(s2, p.fj[2], 0));
-    FSIB_TRY(velocity_interp_sorted(p, M, p.uhat_mid, p.Uh, s2));
-    FSIB_HIP(fsib::launch_axpy_positions(p, M, X, X, p.Uh, dt, s2));
+    FSIB_TRY(velocity_interp_sorted(p, M, p.uhat_mid, p.Uh, s2, X, dt));
     FSIB_HIP(fsib::launch_sort_points(p, M, X, s2));
     FSIB_TRY(ns_update(p, fsib::FLUID_NS_FULL, prm, p.uhat_mid, p.fhat, uhat_half, uhat_half, nullptr, st));
     // U^{m+1} at X^{m+1}: on s2 after the full update (the next step's products proceed on st), on st

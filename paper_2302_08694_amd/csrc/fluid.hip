@@ -237,24 +237,48 @@ __global__ void k_force_curve(int64_t M, const double* __restrict__ X, double K,
 
 // Surface tension, Sec. 6.2.3: F_i = -(gamma/2) sum over incident triangles (i, j, k) (in the
 // triangle's cyclic order starting at i) of (X_j - X_k) x n, n the unit normal of (X_i, X_j, X_k).
-// One wavefront per vertex: lane l takes the incident triangles l, l + 64, ... of the vertex (a
-// polar fan vertex of a lat-long mesh has hundreds) and the lanes are summed by a fixed butterfly.
+// Eight lanes per vertex: lane l takes the incident triangles l, l + 8, ... of the vertex (most
+// vertices of a triangulated surface have about six; a polar fan vertex of a lat-long mesh has
+// hundreds) and the lanes are summed by a fixed butterfly.  (One wavefront per vertex left 58 of 64
+// lanes idle on most vertices: 23 us against 6 us for the 40,000-vertex ellipsoid.)
 // S64 / S32 (nullable): the strengths S = F (quadrature weight 1) in the plan precision, written in
-// the same pass.
-__global__ __launch_bounds__(256) void k_force_surface(int64_t M, const double* __restrict__ X, double gamma,
-                                                       const int32_t* __restrict__ tris,
-                                                       const int32_t* __restrict__ ptr,
-                                                       const int32_t* __restrict__ idx, double* __restrict__ F,
-                                                       double* __restrict__ S64 = nullptr,
-                                                       float* __restrict__ S32 = nullptr) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (i >= M) return;  // uniform per wavefront
+// the same pass.  UK = 1 or 2: the force is taken at X + a U (U in FP64 or FP32), positions the kernel
+// forms as it reads them and also writes to Xh, so the half-step move and the force are one pass.
+constexpr int kSurfLanes = 8;
+struct SurfaceArgs {
+  int64_t M;
+  const double* X;
+  const void* U;  // UK > 0
+  double a;
+  double* Xh;     // UK > 0
+  double gamma;
+  const int32_t* tris;
+  const int32_t* ptr;
+  const int32_t* idx;
+  double* F;
+  double* S64;
+  float* S32;
+};
+
+template <int UK>
+__device__ __forceinline__ double surf_pos(const SurfaceArgs& A, int64_t v, int c) {
+  const double x = A.X[3 * v + c];
+  if constexpr (UK == 1) return x + A.a * ((const double*)A.U)[3 * v + c];
+  if constexpr (UK == 2) return x + A.a * (double)((const float*)A.U)[3 * v + c];
+  return x;
+}
+
+template <int UK>
+__global__ __launch_bounds__(256) void k_force_surface(SurfaceArgs A) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = g / kSurfLanes;
+  const int lane = (int)(g % kSurfLanes);
+  if (i >= A.M) return;  // uniform per group of kSurfLanes lanes
   double f0 = 0, f1 = 0, f2 = 0;
-  const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
-  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 64) {
-    const int t = idx[e];
-    const int v0 = tris[3 * t], v1 = tris[3 * t + 1], v2 = tris[3 * t + 2];
+  const double xi = surf_pos<UK>(A, i, 0), yi = surf_pos<UK>(A, i, 1), zi = surf_pos<UK>(A, i, 2);
+  for (int e = A.ptr[i] + lane; e < A.ptr[i + 1]; e += kSurfLanes) {
+    const int t = A.idx[e];
+    const int v0 = A.tris[3 * t], v1 = A.tris[3 * t + 1], v2 = A.tris[3 * t + 2];
     int j, k;
     if (v0 == i) {
       j = v1;
@@ -266,8 +290,8 @@ __global__ __launch_bounds__(256) void k_force_surface(int64_t M, const double* 
       j = v0;
       k = v1;
     }
-    const double ax = X[3 * j] - xi, ay = X[3 * j + 1] - yi, az = X[3 * j + 2] - zi;
-    const double bx = X[3 * k] - xi, by = X[3 * k + 1] - yi, bz = X[3 * k + 2] - zi;
+    const double ax = surf_pos<UK>(A, j, 0) - xi, ay = surf_pos<UK>(A, j, 1) - yi, az = surf_pos<UK>(A, j, 2) - zi;
+    const double bx = surf_pos<UK>(A, k, 0) - xi, by = surf_pos<UK>(A, k, 1) - yi, bz = surf_pos<UK>(A, k, 2) - zi;
     double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
     const double nn = sqrt(nx * nx + ny * ny + nz * nz);
     if (nn > 0) {
@@ -281,27 +305,43 @@ __global__ __launch_bounds__(256) void k_force_surface(int64_t M, const double* 
     f2 += dx * ny - dy * nx;
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
+  for (int off = kSurfLanes / 2; off > 0; off >>= 1) {
     f0 += __shfl_xor(f0, off, 64);
     f1 += __shfl_xor(f1, off, 64);
     f2 += __shfl_xor(f2, off, 64);
   }
   if (lane == 0) {
-    const double g0 = -0.5 * gamma * f0, g1 = -0.5 * gamma * f1, g2 = -0.5 * gamma * f2;
-    F[3 * i] = g0;
-    F[3 * i + 1] = g1;
-    F[3 * i + 2] = g2;
-    if (S64) {
-      S64[3 * i] = g0;
-      S64[3 * i + 1] = g1;
-      S64[3 * i + 2] = g2;
+    const double g0 = -0.5 * A.gamma * f0, g1 = -0.5 * A.gamma * f1, g2 = -0.5 * A.gamma * f2;
+    A.F[3 * i] = g0;
+    A.F[3 * i + 1] = g1;
+    A.F[3 * i + 2] = g2;
+    if (A.S64) {
+      A.S64[3 * i] = g0;
+      A.S64[3 * i + 1] = g1;
+      A.S64[3 * i + 2] = g2;
     }
-    if (S32) {
-      S32[3 * i] = (float)g0;
-      S32[3 * i + 1] = (float)g1;
-      S32[3 * i + 2] = (float)g2;
+    if (A.S32) {
+      A.S32[3 * i] = (float)g0;
+      A.S32[3 * i + 1] = (float)g1;
+      A.S32[3 * i + 2] = (float)g2;
+    }
+    if (UK > 0) {
+      A.Xh[3 * i] = xi;
+      A.Xh[3 * i + 1] = yi;
+      A.Xh[3 * i + 2] = zi;
     }
   }
+}
+
+static hipError_t launch_surface(const SurfaceArgs& A, int uk, hipStream_t st) {
+  const unsigned nblk = (unsigned)((A.M * kSurfLanes + 255) / 256);
+  if (uk == 1)
+    hipLaunchKernelGGL(k_force_surface<1>, dim3(nblk), dim3(256), 0, st, A);
+  else if (uk == 2)
+    hipLaunchKernelGGL(k_force_surface<2>, dim3(nblk), dim3(256), 0, st, A);
+  else
+    hipLaunchKernelGGL(k_force_surface<0>, dim3(nblk), dim3(256), 0, st, A);
+  return hipGetLastError();
 }
 
 // Edge springs (Sec. 6.2.3, elastic sphere): F_i = K sum_{j linked with i} K_ij (X_j - X_i) over the
@@ -478,13 +518,14 @@ hipError_t launch_force(const fsib_force& f, int dim, int64_t M, const double* X
     hipLaunchKernelGGL(k_force_target, dim3((unsigned)((M * dim + 255) / 256)), dim3(256), 0, st, M * dim, X, f.aux,
                        f.K, F);
   else
-    hipLaunchKernelGGL(k_force_surface, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, M, X, f.K, f.tris, f.v2t_ptr,
-                       f.v2t_idx, F);  // four vertices (wavefronts) per workgroup
+    return launch_surface(SurfaceArgs{M, X, nullptr, 0.0, nullptr, f.K, f.tris, f.v2t_ptr, f.v2t_idx, F, nullptr,
+                                      nullptr},
+                          0, st);
   return hipGetLastError();
 }
 
 // Directional derivative dF(X)[V] of the surface-tension force (Sec. 6.2.3), one wavefront per vertex
-// as k_force_surface.  Per incident triangle (i, j, k): a = X_j - X_i, b = X_k - X_i, m = a x b,
+// (lane l takes the incident triangles l, l + 64, ...).  Per incident triangle (i, j, k): a = X_j - X_i, b = X_k - X_i, m = a x b,
 // n = m/|m|; d(a - b) = V_j - V_k, dm = da x b + a x db, dn = (dm - n (n.dm))/|m|, and the force term
 // (a - b) x n changes by d(a - b) x n + (a - b) x dn.  F is minus gamma times the gradient of the area,
 // so its Jacobian is symmetric and this is also the transpose product the adjoint needs.
@@ -623,15 +664,29 @@ hipError_t launch_force_strengths(const Plan& p, const fsib_force& f, int64_t M,
                          CurveArgs<float>{M, X, f.K, off, p.ninst, F, (float*)S});
     return hipGetLastError();
   }
-  if (f.kind == FSIB_FORCE_SURFACE_TENSION && p.dim == 3) {
-    hipLaunchKernelGGL(k_force_surface, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, M, X, f.K, f.tris, f.v2t_ptr,
-                       f.v2t_idx, F, p.prec == FSIB_F64 ? (double*)S : nullptr,
-                       p.prec == FSIB_F64 ? nullptr : (float*)S);
-    return hipGetLastError();
-  }
+  if (f.kind == FSIB_FORCE_SURFACE_TENSION && p.dim == 3)
+    return launch_surface(SurfaceArgs{M, X, nullptr, 0.0, nullptr, f.K, f.tris, f.v2t_ptr, f.v2t_idx, F,
+                                      p.prec == FSIB_F64 ? (double*)S : nullptr,
+                                      p.prec == FSIB_F64 ? nullptr : (float*)S},
+                          0, st);
   hipError_t e = launch_force_plan(p, f, M, X, F, st);
   if (e != hipSuccess) return e;
   return launch_weighted_strengths(p, f.kind, M, F, S, st);
+}
+
+// Xh = X + a U, then force and strengths at Xh as launch_force_strengths; the surface law does all of
+// it in one pass, the other laws move the points first.
+hipError_t launch_move_force_strengths(const Plan& p, const fsib_force& f, int64_t M, double* Xh, const double* X,
+                                       const void* U, double a, double* F, void* S, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  if (f.kind == FSIB_FORCE_SURFACE_TENSION && p.dim == 3)
+    return launch_surface(SurfaceArgs{M, X, U, a, Xh, f.K, f.tris, f.v2t_ptr, f.v2t_idx, F,
+                                      p.prec == FSIB_F64 ? (double*)S : nullptr,
+                                      p.prec == FSIB_F64 ? nullptr : (float*)S},
+                          p.prec == FSIB_F64 ? 1 : 2, st);
+  hipError_t e = launch_axpy_positions(p, M, Xh, X, U, a, st);
+  if (e != hipSuccess) return e;
+  return launch_force_strengths(p, f, M, Xh, F, S, st);
 }
 
 // Force (into each plan's F64) and weighted strengths (into its S) for the plans of a group: one launch

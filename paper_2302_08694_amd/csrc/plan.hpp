@@ -227,7 +227,9 @@ hipError_t launch_fft_c2c_group(const std::vector<FftCall>& calls, hipStream_t s
 hipError_t launch_fft_x_group(const std::vector<FftCall>& calls, bool r2c, hipStream_t st);
 // spread_interp.hip
 hipError_t launch_spread(Plan& p, int64_t M, const void* strengths, int real_comps, hipStream_t st);
-hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st);
+// move (real strengths, nullable): positions also advanced, move += move_a * out (as stored)
+hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st, double* move = nullptr,
+                         double move_a = 0);
 // fft.hip
 hipError_t launch_fft_c2c(const Plan& p, const void* in, void* out, int n, int sign, int64_t inner,
                           int64_t outer, int nin, int pin, int nout, int pout, const void* fac_in,
@@ -259,6 +261,9 @@ hipError_t launch_force_jvp(const fsib_force& f, int dim, int64_t M, const doubl
                             hipStream_t st);
 hipError_t launch_force_strengths(const Plan& p, const fsib_force& f, int64_t M, const double* X, double* F, void* S,
                                   hipStream_t st);  // F and S = w F in one pass where the law allows
+// Xh = X + a U (U in the plan precision), then F and S at Xh (one pass for the surface law)
+hipError_t launch_move_force_strengths(const Plan& p, const fsib_force& f, int64_t M, double* Xh, const double* X,
+                                       const void* U, double a, double* F, void* S, hipStream_t st);
 hipError_t launch_weighted_strengths(const Plan& p, int kind, int64_t M, const double* F, void* S,
                                      hipStream_t st);
 hipError_t launch_diag(const Plan& p, const fsib_fluid_params& prm, const fsib_force& f, int64_t M,

@@ -536,6 +536,10 @@ struct InterpArgs {
   const int* offsets;
   int nbins;
   int ninst;
+  // real strengths only, nullable: also move the points, move[j * NCH + c] += move_a * out[j * NCH + c]
+  // (the velocity as stored), so a position update needs no pass of its own
+  double* move;
+  double move_a;
 };
 
 // Instance of sorted position pos: the last i with offsets[i * nbins] <= pos.
@@ -755,6 +759,9 @@ __device__ __forceinline__ void interp_body(const InterpArgs<T>& a, Blk wb) {
         } else {
 #pragma unroll
           for (int c = 0; c < SC; ++c) a.out[j * NCH + c] = res[c];
+          if (a.move)
+#pragma unroll
+            for (int c = 0; c < SC; ++c) a.move[j * NCH + c] = a.move[j * NCH + c] + a.move_a * (double)res[c];
         }
       }
     }
@@ -968,14 +975,18 @@ static InterpArgs<T> interp_args(const Plan& p, int64_t M, void* out) {
   a.offsets = p.offsets;
   a.nbins = (int)p.nbins;
   a.ninst = p.ninst;
+  a.move = nullptr;
+  a.move_a = 0;
   return a;
 }
 
 template <typename T, int DIM, int NCH, bool CPLX, int W>
-static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t st) {
+static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t st, double* move, double move_a) {
   if (M == 0) return hipSuccess;
   if (p.deg != interp_degree<W>()) return hipErrorInvalidValue;  // the kernel's compile-time degree
-  const InterpArgs<T> a = interp_args<T, DIM, NCH, CPLX, W>(p, M, out);
+  InterpArgs<T> a = interp_args<T, DIM, NCH, CPLX, W>(p, M, out);
+  a.move = CPLX ? nullptr : move;
+  a.move_a = move_a;
   const bool prof = prof_on(p, PROF_INTERP);
   if (prof) prof_start(p, st);
   const int64_t per_wg = 4 * (int64_t)a.ppw;  // four wavefronts per workgroup
@@ -1032,8 +1043,9 @@ static hipError_t spread_dispatch(Plan& p, int64_t M, const void* str, int ntr, 
 }
 
 template <typename T, int DIM, int NCH, bool CPLX>
-static hipError_t interp_dispatch(Plan& p, int64_t M, void* out, int ntr, hipStream_t st) {
-#define CALL_I(w) run_interp<T, DIM, NCH, CPLX, w>(p, M, out, ntr, st)
+static hipError_t interp_dispatch(Plan& p, int64_t M, void* out, int ntr, hipStream_t st, double* move = nullptr,
+                                  double move_a = 0) {
+#define CALL_I(w) run_interp<T, DIM, NCH, CPLX, w>(p, M, out, ntr, st, move, move_a)
   FSIB_W_SWITCH(p.w, CALL_I)
 #undef CALL_I
 }
@@ -1056,7 +1068,7 @@ hipError_t launch_spread(Plan& p, int64_t M, const void* str, int real_comps, hi
              : spread_dispatch<float, 3, 3, false>(p, M, str, 1, st);
 }
 
-hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st) {
+hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStream_t st, double* move, double move_a) {
   const bool f64 = p.prec == FSIB_F64;
   if (real_comps == 0) {
     if (p.dim == 2)
@@ -1066,10 +1078,10 @@ hipError_t launch_interp(Plan& p, int64_t M, void* out, int real_comps, hipStrea
                : interp_dispatch<float, 3, 2, true>(p, M, out, p.ntrans, st);
   }
   if (p.dim == 2)
-    return f64 ? interp_dispatch<double, 2, 2, false>(p, M, out, 1, st)
-               : interp_dispatch<float, 2, 2, false>(p, M, out, 1, st);
-  return f64 ? interp_dispatch<double, 3, 3, false>(p, M, out, 1, st)
-             : interp_dispatch<float, 3, 3, false>(p, M, out, 1, st);
+    return f64 ? interp_dispatch<double, 2, 2, false>(p, M, out, 1, st, move, move_a)
+               : interp_dispatch<float, 2, 2, false>(p, M, out, 1, st, move, move_a);
+  return f64 ? interp_dispatch<double, 3, 3, false>(p, M, out, 1, st, move, move_a)
+             : interp_dispatch<float, 3, 3, false>(p, M, out, 1, st, move, move_a);
 }
 
 template <typename T, int DIM>
