@@ -276,33 +276,48 @@ __global__ __launch_bounds__(256) void k_force_surface(SurfaceArgs A) {
   if (i >= A.M) return;  // uniform per group of kSurfLanes lanes
   double f0 = 0, f1 = 0, f2 = 0;
   const double xi = surf_pos<UK>(A, i, 0), yi = surf_pos<UK>(A, i, 1), zi = surf_pos<UK>(A, i, 2);
-  for (int e = A.ptr[i] + lane; e < A.ptr[i + 1]; e += kSurfLanes) {
-    const int t = A.idx[e];
-    const int v0 = A.tris[3 * t], v1 = A.tris[3 * t + 1], v2 = A.tris[3 * t + 2];
-    int j, k;
-    if (v0 == i) {
-      j = v1;
-      k = v2;
-    } else if (v1 == i) {
-      j = v2;
-      k = v0;
-    } else {
-      j = v0;
-      k = v1;
+  // four triangles per lane and round, their loads issued together: a polar fan vertex (hundreds of
+  // triangles) would otherwise wait on a chain of dependent loads per triangle
+  const int e1 = A.ptr[i + 1];
+  for (int e0 = A.ptr[i] + lane; e0 < e1; e0 += 4 * kSurfLanes) {
+    int tt[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tt[u] = e0 + u * kSurfLanes < e1 ? A.idx[e0 + u * kSurfLanes] : -1;
+    int jj[4], kk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      jj[u] = kk[u] = (int)i;
+      if (tt[u] < 0) continue;
+      const int v0 = A.tris[3 * tt[u]], v1 = A.tris[3 * tt[u] + 1], v2 = A.tris[3 * tt[u] + 2];
+      if (v0 == i) {
+        jj[u] = v1;
+        kk[u] = v2;
+      } else if (v1 == i) {
+        jj[u] = v2;
+        kk[u] = v0;
+      } else {
+        jj[u] = v0;
+        kk[u] = v1;
+      }
     }
-    const double ax = surf_pos<UK>(A, j, 0) - xi, ay = surf_pos<UK>(A, j, 1) - yi, az = surf_pos<UK>(A, j, 2) - zi;
-    const double bx = surf_pos<UK>(A, k, 0) - xi, by = surf_pos<UK>(A, k, 1) - yi, bz = surf_pos<UK>(A, k, 2) - zi;
-    double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
-    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-    if (nn > 0) {
-      nx /= nn;
-      ny /= nn;
-      nz /= nn;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (tt[u] < 0) continue;
+      const int j = jj[u], k = kk[u];
+      const double ax = surf_pos<UK>(A, j, 0) - xi, ay = surf_pos<UK>(A, j, 1) - yi, az = surf_pos<UK>(A, j, 2) - zi;
+      const double bx = surf_pos<UK>(A, k, 0) - xi, by = surf_pos<UK>(A, k, 1) - yi, bz = surf_pos<UK>(A, k, 2) - zi;
+      double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+      const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+      if (nn > 0) {
+        nx /= nn;
+        ny /= nn;
+        nz /= nn;
+      }
+      const double dx = ax - bx, dy = ay - by, dz = az - bz;  // X_j - X_k
+      f0 += dy * nz - dz * ny;
+      f1 += dz * nx - dx * nz;
+      f2 += dx * ny - dy * nx;
     }
-    const double dx = ax - bx, dy = ay - by, dz = az - bz;  // X_j - X_k
-    f0 += dy * nz - dz * ny;
-    f1 += dz * nx - dx * nz;
-    f2 += dx * ny - dy * nx;
   }
 #pragma unroll
   for (int off = kSurfLanes / 2; off > 0; off >>= 1) {
