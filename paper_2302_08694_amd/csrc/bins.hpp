@@ -38,4 +38,23 @@ __device__ __forceinline__ void tile_parts_at(const TilePartsArgs& A, int tg) {
   A.tile_parts[tg] = total <= split ? 1 : (total + split - 1) / split;
 }
 
+// Work list of the further parts (tile, part >= 1) in tile order, and scratch slots for tiles split
+// into several parts.
+struct FillWorkArgs {
+  int nbins;
+  const int* part_off;
+  const int* tile_parts;
+  int2* work;
+  int* tile_slot;
+  int* slot_ctr;  // [0] scratch slots, [1] split tiles (both zero before the launch)
+  int* split_list;
+};
+__device__ __forceinline__ void fill_work_tile(const FillWorkArgs& A, int t) {
+  // parts 1.. of tile t: entries part_off[t] - t .. (parts before t, less one per tile)
+  const int np = A.tile_parts[t], off = A.part_off[t] - t;
+  for (int q = 1; q < np; ++q) A.work[off + q - 1] = make_int2(t, q);
+  A.tile_slot[t] = np > 1 ? atomicAdd(A.slot_ctr, np) : -1;
+  if (np > 1) A.split_list[atomicAdd(A.slot_ctr + 1, 1)] = t;
+}
+
 }  // namespace fsib

@@ -191,6 +191,11 @@ hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum,
                        hipStream_t st);  // exclusive, n+1 outputs; seg_sum: scan_segments(n) ints
 int64_t scan_segments(int64_t n);
+// entries a single-pass scan takes (up to, not including), and that scan followed in the same
+// workgroup by the spreading work list of tile part counts `counts` (n < scan_one_pass())
+int64_t scan_one_pass();
+struct FillWorkArgs;
+hipError_t launch_scan_fill_work(int64_t n, const int* counts, int* offsets, const FillWorkArgs& f, hipStream_t st);
 hipError_t launch_row_masks(Plan& p, int64_t M, hipStream_t st);  // from the bin counts of M points
 // the same stages for the plans of a group, each one launch over all plans where their workgroup
 // sizes agree (plan g: M[g] points, its operands at index g)

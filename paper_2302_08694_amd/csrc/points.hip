@@ -480,6 +480,22 @@ hipError_t launch_row_masks(Plan& p, int64_t M, hipStream_t st) {
 
 int64_t scan_segments(int64_t n) { return n / kScanSeg + 1; }
 
+// The single-pass scan followed, in the same workgroup, by the spreading work list from its offsets
+// (one launch fewer on the spreading path).
+__global__ __launch_bounds__(kScanThreads) void k_scan_fill_work(ScanArgs a, FillWorkArgs f) {
+  scan_body<true, 8>(a, launch_blk());
+  __syncthreads();  // the offsets are complete and visible to the workgroup
+  for (int t = threadIdx.x; t < f.nbins; t += kScanThreads) fill_work_tile(f, t);
+}
+
+int64_t scan_one_pass() { return kScanOnePass; }
+
+hipError_t launch_scan_fill_work(int64_t n, const int* counts, int* offsets, const FillWorkArgs& f, hipStream_t st) {
+  if (n >= kScanOnePass) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_fill_work, dim3(1), dim3(kScanThreads), 0, st, ScanArgs{n, counts, offsets, nullptr}, f);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum, hipStream_t st) {
   const int64_t nseg = scan_segments(n);
   const ScanArgs a{n, counts, offsets, seg_sum};

@@ -417,25 +417,9 @@ __global__ void k_tile_parts_parts(Parts<TilePartsArgs> f) {
   if (g >= 0) tile_parts_body(f.a[g], b);
 }
 
-// Work list of the further parts (tile, part >= 1) in tile order, and scratch slots for tiles split
-// into several parts.
-struct FillWorkArgs {
-  int nbins;
-  const int* part_off;
-  const int* tile_parts;
-  int2* work;
-  int* tile_slot;
-  int* slot_ctr;  // [0] scratch slots, [1] split tiles (both zero before the launch)
-  int* split_list;
-};
 __device__ __forceinline__ void fill_work(const FillWorkArgs& A, Blk wb) {
   const int t = (int)(wb.x * blockDim.x + threadIdx.x);
-  if (t >= A.nbins) return;
-  // parts 1.. of tile t: entries part_off[t] - t .. (parts before t, less one per tile)
-  const int np = A.tile_parts[t], off = A.part_off[t] - t;
-  for (int q = 1; q < np; ++q) A.work[off + q - 1] = make_int2(t, q);
-  A.tile_slot[t] = np > 1 ? atomicAdd(A.slot_ctr, np) : -1;
-  if (np > 1) A.split_list[atomicAdd(A.slot_ctr + 1, 1)] = t;
+  if (t < A.nbins) fill_work_tile(A, t);
 }
 __global__ void k_fill_work(FillWorkArgs a) { fill_work(a, launch_blk()); }
 __global__ void k_fill_work_parts(Parts<FillWorkArgs> f) {
@@ -846,9 +830,14 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
     hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, tile_parts_args<DIM>(p));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, fill_work_args(p));
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the parts' offsets and the work list: one workgroup does both when the tiles fit its single pass
+  if (p.nbt < scan_one_pass()) {
+    if ((e = launch_scan_fill_work(p.nbt, p.tile_parts, p.part_off, fill_work_args(p), st)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, fill_work_args(p));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const bool prof = prof_on(p, PROF_SPREAD);
   if (prof) prof_start(p, st);
   const dim3 sg((unsigned)p.work_blocks, (unsigned)ntr);
