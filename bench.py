@@ -601,7 +601,7 @@ ROOFLINE_KERNEL = "fsib::k_fft_c2c<double, false, 192, 8>"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, factors from a plain 512 MiB copy); None once the kernel changes after the counters
-TRAFFIC_BYTES_PER_LAUNCH = 178.5e6
+TRAFFIC_BYTES_PER_LAUNCH = 165.4e6
 TRAFFIC_SOURCE = "profiles/fft_strided_ns128_f64_hbm_counters.md"
 
 
