@@ -706,10 +706,11 @@ fsib_status group_interp_ffts(const std::vector<Plan*>& ps, void* const* uhat, h
   return FSIB_OK;
 }
 
-// stokes_velocity for every plan of a group: U[g] at X[g], uhat[g] the field.
+// stokes_velocity for every plan of a group: U[g] at X[g], uhat[g] the field; mv (nullable): position
+// updates from U done by the interpolation pass.
 fsib_status group_stokes_velocity(const std::vector<Plan*>& ps, const fsib_fluid_params* prm, const fsib_force* f,
                                   const int64_t* M, const double* const* X, void* const* U, void* const* uhat,
-                                  hipStream_t st) {
+                                  hipStream_t st, const fsib::GroupMove* mv = nullptr) {
   const size_t n = ps.size();
   std::vector<const void*> S(n);
   for (size_t g = 0; g < n; ++g) S[g] = ps[g]->S;
@@ -719,7 +720,7 @@ fsib_status group_stokes_velocity(const std::vector<Plan*>& ps, const fsib_fluid
   FSIB_TRY(group_spread_ffts(ps, st));
   FSIB_HIP(fsib::launch_fluid_stokes_group(ps, prm, uhat, st));
   FSIB_TRY(group_interp_ffts(ps, uhat, st));
-  FSIB_HIP(fsib::launch_interp_group(ps, M, U, st));
+  FSIB_HIP(fsib::launch_interp_group(ps, M, U, st, mv));
   return FSIB_OK;
 }
 
@@ -1321,12 +1322,17 @@ fsib_status fsib_group_steps(fsib_group group, const fsib_fluid_params* params, 
     half[g] = 0.5 * params[g].dt;
     full[g] = params[g].dt;
   }
+  // The position updates ride on the interpolation passes: the one of U^{m+1/2} writes X^{m+1} = X^m +
+  // dt U^{m+1/2}, the one of U^{m+1} writes the next step's X^{m+3/2} = X^{m+1} + dt/2 U^{m+1} (no
+  // interpolation reads the positions it moves: it reads the sorted records).
+  const fsib::GroupMove to_full{X, Xc.data(), full.data()};
+  const fsib::GroupMove to_half{Xh.data(), Xc.data(), half.data()};
   for (int k = 0; k < nsteps; ++k) {
     // X^{m+1/2} = X^m + dt/2 U^m (eq. spatial_1), then the midpoint rule with Stokes velocities
-    FSIB_HIP(fsib::launch_axpy_positions_group(ps, M, Xh.data(), Xc.data(), Uc.data(), half.data(), st));
-    FSIB_TRY(group_stokes_velocity(ps, params, forces, M, Xhc.data(), Uh.data(), umid.data(), st));
-    FSIB_HIP(fsib::launch_axpy_positions_group(ps, M, X, Xc.data(), Uhc.data(), full.data(), st));
-    FSIB_TRY(group_stokes_velocity(ps, params, forces, M, Xc.data(), U, uhat_half, st));
+    if (k == 0) FSIB_HIP(fsib::launch_axpy_positions_group(ps, M, Xh.data(), Xc.data(), Uc.data(), half.data(), st));
+    FSIB_TRY(group_stokes_velocity(ps, params, forces, M, Xhc.data(), Uh.data(), umid.data(), st, &to_full));
+    FSIB_TRY(group_stokes_velocity(ps, params, forces, M, Xc.data(), U, uhat_half, st,
+                                   k + 1 < nsteps ? &to_half : nullptr));
   }
   return FSIB_OK;
 }

@@ -11,7 +11,7 @@ struct TilePartsArgs {
   int dim, nt0, nt1, nt2, q0, q1, q2, ninst, split;
   const int* offsets;
   int* tile_parts;
-  int* slot_ctr;  // cleared here (scratch slots and split tiles of k_fill_work)
+  int* slot_ctr;  // cleared here (scratch slots and split tiles of the work list)
 };
 
 // Tile tg of all instances (tg < nt0 nt1 nt2 ninst); tg = 0 also clears the split counters.

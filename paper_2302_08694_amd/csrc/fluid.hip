@@ -263,8 +263,8 @@ struct SurfaceArgs {
 template <int UK>
 __device__ __forceinline__ double surf_pos(const SurfaceArgs& A, int64_t v, int c) {
   const double x = A.X[3 * v + c];
-  if constexpr (UK == 1) return x + A.a * ((const double*)A.U)[3 * v + c];
-  if constexpr (UK == 2) return x + A.a * (double)((const float*)A.U)[3 * v + c];
+  if constexpr (UK == 1) return fma(A.a, ((const double*)A.U)[3 * v + c], x);  // as k_axpy_pos
+  if constexpr (UK == 2) return fma(A.a, (double)((const float*)A.U)[3 * v + c], x);
   return x;
 }
 

@@ -191,11 +191,14 @@ hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum,
                        hipStream_t st);  // exclusive, n+1 outputs; seg_sum: scan_segments(n) ints
 int64_t scan_segments(int64_t n);
-// entries a single-pass scan takes (up to, not including), and that scan followed in the same
-// workgroup by the spreading work list of tile part counts `counts` (n < scan_one_pass())
-int64_t scan_one_pass();
+// the scan of the tiles' part counts `counts`, whose final pass also writes the spreading work list
+// (points.hip); per plan of a group in one launch per pass
 struct FillWorkArgs;
-hipError_t launch_scan_fill_work(int64_t n, const int* counts, int* offsets, const FillWorkArgs& f, hipStream_t st);
+hipError_t launch_scan_fill_work(int64_t n, const int* counts, int* offsets, int* seg_sum, const FillWorkArgs& f,
+                                 hipStream_t st);
+hipError_t launch_scan_fill_work_group(const std::vector<int64_t>& n, const std::vector<const int*>& counts,
+                                       const std::vector<int*>& offsets, const std::vector<int*>& seg_sum,
+                                       const std::vector<FillWorkArgs>& f, hipStream_t st);
 hipError_t launch_row_masks(Plan& p, int64_t M, hipStream_t st);  // from the bin counts of M points
 // the same stages for the plans of a group, each one launch over all plans where their workgroup
 // sizes agree (plan g: M[g] points, its operands at index g)
@@ -209,7 +212,14 @@ hipError_t launch_scan_group(const std::vector<int64_t>& n, const std::vector<co
                              const std::vector<int*>& offsets, const std::vector<int*>& seg_sum, hipStream_t st);
 hipError_t launch_spread_group(const std::vector<Plan*>& ps, const int64_t* M, const void* const* str,
                                hipStream_t st);  // real strengths with dim components
-hipError_t launch_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st);
+// position updates done by an interpolation pass over a group: out[g] = in[g] + a[g] U[g] (U as stored)
+struct GroupMove {
+  double* const* out;
+  const double* const* in;
+  const double* a;
+};
+hipError_t launch_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st,
+                               const GroupMove* mv = nullptr);
 hipError_t launch_force_strengths_group(const std::vector<Plan*>& ps, const fsib_force* f, const int64_t* M,
                                         const double* const* X, hipStream_t st);  // into each plan's F64, S
 hipError_t launch_fluid_stokes_group(const std::vector<Plan*>& ps, const fsib_fluid_params* prm,

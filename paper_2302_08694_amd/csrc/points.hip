@@ -365,7 +365,8 @@ struct AxpyArgs {
 template <typename T>
 __device__ __forceinline__ void axpy_pos(const AxpyArgs<T>& A, Blk blk) {
   const int64_t i = blk.x * blockDim.x + threadIdx.x;
-  if (i < A.n) A.Y[i] = A.X[i] + A.a * (double)A.U[i];
+  // one rounding (fma), as the position updates folded into the force and interpolation passes
+  if (i < A.n) A.Y[i] = fma(A.a, (double)A.U[i], A.X[i]);
 }
 template <typename T>
 __global__ void k_axpy_pos(int64_t n, double* __restrict__ Y, const double* __restrict__ X, const T* __restrict__ U,
@@ -480,20 +481,87 @@ hipError_t launch_row_masks(Plan& p, int64_t M, hipStream_t st) {
 
 int64_t scan_segments(int64_t n) { return n / kScanSeg + 1; }
 
-// The single-pass scan followed, in the same workgroup, by the spreading work list from its offsets
-// (one launch fewer on the spreading path).
-__global__ __launch_bounds__(kScanThreads) void k_scan_fill_work(ScanArgs a, FillWorkArgs f) {
-  scan_body<true, 8>(a, launch_blk());
-  __syncthreads();  // the offsets are complete and visible to the workgroup
-  for (int t = threadIdx.x; t < f.nbins; t += kScanThreads) fill_work_tile(f, t);
+// The scan of the tiles' part counts with the spreading work list: the final pass's workgroup for a
+// segment, once it has written that segment's offsets, lists the further parts of the segment's tiles
+// (one launch fewer on the spreading path; a tile's entries need only its own offset).
+struct ScanFillArgs {
+  ScanArgs s;
+  FillWorkArgs f;
+};
+template <int EPT>
+__device__ __forceinline__ void scan_fill_body(const ScanFillArgs& A, Blk blk) {
+  constexpr int64_t SEG = (int64_t)kScanThreads * EPT;
+  scan_body<true, EPT>(A.s, blk);
+  __syncthreads();  // the segment's offsets are complete and visible to the workgroup
+  const int64_t t1 = (blk.x + 1) * SEG < (int64_t)A.f.nbins ? (blk.x + 1) * SEG : (int64_t)A.f.nbins;
+  for (int64_t t = blk.x * SEG + threadIdx.x; t < t1; t += kScanThreads) fill_work_tile(A.f, (int)t);
+}
+template <int EPT>
+__global__ __launch_bounds__(kScanThreads) void k_scan_fill(ScanFillArgs a) {
+  scan_fill_body<EPT>(a, launch_blk());
+}
+__global__ __launch_bounds__(kScanThreads) void k_scan_fill_parts(Parts<ScanFillArgs> f) {
+  Blk b;
+  const int g = part_blk(f, b);
+  if (g >= 0) scan_fill_body<kScanEpt>(f.a[g], b);
 }
 
-int64_t scan_one_pass() { return kScanOnePass; }
-
-hipError_t launch_scan_fill_work(int64_t n, const int* counts, int* offsets, const FillWorkArgs& f, hipStream_t st) {
-  if (n >= kScanOnePass) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_scan_fill_work, dim3(1), dim3(kScanThreads), 0, st, ScanArgs{n, counts, offsets, nullptr}, f);
+hipError_t launch_scan_fill_work(int64_t n, const int* counts, int* offsets, int* seg_sum, const FillWorkArgs& f,
+                                 hipStream_t st) {
+  const ScanFillArgs a{ScanArgs{n, counts, offsets, seg_sum}, f};
+  if (n < kScanOnePass) {  // one workgroup of 8 entries per thread
+    hipLaunchKernelGGL(k_scan_fill<8>, dim3(1), dim3(kScanThreads), 0, st, a);
+    return hipGetLastError();
+  }
+  const int64_t nseg = scan_segments(n);
+  hipLaunchKernelGGL(k_scan<false>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, a.s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_fill<kScanEpt>, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, a);
   return hipGetLastError();
+}
+
+hipError_t launch_scan_fill_work_group(const std::vector<int64_t>& n, const std::vector<const int*>& counts,
+                                       const std::vector<int*>& offsets, const std::vector<int*>& seg_sum,
+                                       const std::vector<FillWorkArgs>& f, hipStream_t st) {
+  std::vector<PartLaunch<ScanArgs>> first;
+  std::vector<PartLaunch<ScanFillArgs>> fin;
+  for (size_t g = 0; g < n.size(); ++g) {
+    const int64_t nseg = scan_segments(n[g]);
+    PartLaunch<ScanFillArgs> L;
+    L.a = ScanFillArgs{ScanArgs{n[g], counts[g], offsets[g], seg_sum[g]}, f[g]};
+    L.nx = nseg;
+    L.threads = kScanThreads;
+    fin.push_back(L);
+    if (nseg > 1) {
+      PartLaunch<ScanArgs> F;
+      F.a = L.a.s;
+      F.nx = nseg;
+      F.threads = kScanThreads;
+      first.push_back(F);
+    }
+  }
+  hipError_t e = launch_parts(
+      first,
+      [&](const PartLaunch<ScanArgs>& L) {
+        hipLaunchKernelGGL(k_scan<false>, dim3((unsigned)L.nx), dim3(kScanThreads), 0, st, L.a);
+        return hipGetLastError();
+      },
+      [&](const Parts<ScanArgs>& pf, int64_t nwg, size_t, int) {
+        hipLaunchKernelGGL(k_scan_parts<false>, dim3((unsigned)nwg), dim3(kScanThreads), 0, st, pf);
+        return hipGetLastError();
+      });
+  if (e != hipSuccess) return e;
+  return launch_parts(
+      fin,
+      [&](const PartLaunch<ScanFillArgs>& L) {
+        hipLaunchKernelGGL(k_scan_fill<kScanEpt>, dim3((unsigned)L.nx), dim3(kScanThreads), 0, st, L.a);
+        return hipGetLastError();
+      },
+      [&](const Parts<ScanFillArgs>& pf, int64_t nwg, size_t, int) {
+        hipLaunchKernelGGL(k_scan_fill_parts, dim3((unsigned)nwg), dim3(kScanThreads), 0, st, pf);
+        return hipGetLastError();
+      });
 }
 
 hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum, hipStream_t st) {

@@ -50,7 +50,7 @@ struct SpreadArgs {
   const int* tile_slot; // first scratch slot of a split tile
   T* scratch;           // split tiles: [ntrans][slots][NCH][kMaxTileCells] partial tiles
   int64_t slots;        // scratch slots per transform
-  const int* split_list;  // the split tiles, split_cnt[0] of them (k_fill_work)
+  const int* split_list;  // the split tiles, split_cnt[0] of them (written with the work list)
   const int* split_cnt;
   const uint8_t* rowmask;  // blocks of x lines reached by some point (lines elsewhere stay unwritten)
   int xcd_chunk;           // > 0: workgroups renumbered in runs of this many per XCD (xcd_chunked)
@@ -417,16 +417,7 @@ __global__ void k_tile_parts_parts(Parts<TilePartsArgs> f) {
   if (g >= 0) tile_parts_body(f.a[g], b);
 }
 
-__device__ __forceinline__ void fill_work(const FillWorkArgs& A, Blk wb) {
-  const int t = (int)(wb.x * blockDim.x + threadIdx.x);
-  if (t < A.nbins) fill_work_tile(A, t);
-}
-__global__ void k_fill_work(FillWorkArgs a) { fill_work(a, launch_blk()); }
-__global__ void k_fill_work_parts(Parts<FillWorkArgs> f) {
-  Blk b;
-  const int g = part_blk(f, b);
-  if (g >= 0) fill_work(f.a[g], b);
-}
+
 
 // Sum the partial tiles of every split tile in part order and write it to the grid: workgroup k takes
 // entry k of the list of split tiles (launched over a bound on their number; the workgroups past the
@@ -520,9 +511,10 @@ struct InterpArgs {
   const int* offsets;
   int nbins;
   int ninst;
-  // real strengths only, nullable: also move the points, move[j * NCH + c] += move_a * out[j * NCH + c]
-  // (the velocity as stored), so a position update needs no pass of its own
+  // real strengths only, nullable: also move the points, move[j * NCH + c] = move_in[j * NCH + c] +
+  // move_a * out[j * NCH + c] (the velocity as stored), so a position update needs no pass of its own
   double* move;
+  const double* move_in;
   double move_a;
 };
 
@@ -745,7 +737,7 @@ __device__ __forceinline__ void interp_body(const InterpArgs<T>& a, Blk wb) {
           for (int c = 0; c < SC; ++c) a.out[j * NCH + c] = res[c];
           if (a.move)
 #pragma unroll
-            for (int c = 0; c < SC; ++c) a.move[j * NCH + c] = a.move[j * NCH + c] + a.move_a * (double)res[c];
+            for (int c = 0; c < SC; ++c) a.move[j * NCH + c] = fma(a.move_a, (double)res[c], a.move_in[j * NCH + c]);
         }
       }
     }
@@ -830,14 +822,9 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
     hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, tile_parts_args<DIM>(p));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  // the parts' offsets and the work list: one workgroup does both when the tiles fit its single pass
-  if (p.nbt < scan_one_pass()) {
-    if ((e = launch_scan_fill_work(p.nbt, p.tile_parts, p.part_off, fill_work_args(p), st)) != hipSuccess) return e;
-  } else {
-    if ((e = launch_scan(p.nbt, p.tile_parts, p.part_off, p.scan_part, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_work, dim3((nb + 255) / 256), dim3(256), 0, st, fill_work_args(p));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  // the parts' offsets, and the work list from the scan's final pass
+  if ((e = launch_scan_fill_work(p.nbt, p.tile_parts, p.part_off, p.scan_part, fill_work_args(p), st)) != hipSuccess)
+    return e;
   const bool prof = prof_on(p, PROF_SPREAD);
   if (prof) prof_start(p, st);
   const dim3 sg((unsigned)p.work_blocks, (unsigned)ntr);
@@ -881,7 +868,7 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
   const size_t n = ps.size();
   std::vector<PartLaunch<SortStrArgs<T>>> ss(n);
   std::vector<PartLaunch<TilePartsArgs>> tp(n);
-  std::vector<PartLaunch<FillWorkArgs>> fw(n);
+  std::vector<FillWorkArgs> fw(n);
   std::vector<PartLaunch<SpreadArgs<T>>> sp(n), mg(n);
   std::vector<int64_t> nbt(n);
   std::vector<const int*> tparts(n);
@@ -893,8 +880,7 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
     ss[g].nx = p.sstr_src == str[g] ? 0 : (M[g] + 255) / 256;  // placed by the sort's scatter
     tp[g].a = tile_parts_args<DIM>(p);
     tp[g].nx = p.parts_split == p.split ? 0 : (p.nbt + 255) / 256;  // computed by the sort
-    fw[g].a = fill_work_args(p);
-    fw[g].nx = (p.nbt + 255) / 256;
+    fw[g] = fill_work_args(p);
     sp[g].a = a;
     sp[g].nx = p.work_blocks;
     sp[g].threads = plan_spread_threads<DIM, T>(p);
@@ -909,8 +895,7 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
                                              SortStrArgs<T>, 256));
   if (e != hipSuccess) return e;
   if ((e = launch_parts(tp, FSIB_PARTS(k_tile_parts, k_tile_parts_parts, TilePartsArgs, 256))) != hipSuccess) return e;
-  if ((e = launch_scan_group(nbt, tparts, poff, spart, st)) != hipSuccess) return e;
-  if ((e = launch_parts(fw, FSIB_PARTS(k_fill_work, k_fill_work_parts, FillWorkArgs, 256))) != hipSuccess) return e;
+  if ((e = launch_scan_fill_work_group(nbt, tparts, poff, spart, fw, st)) != hipSuccess) return e;
   // parts with different spreading variants run as launches of their own (launch_parts)
   const auto one = [&](const PartLaunch<SpreadArgs<T>>& L) {
     const dim3 g1((unsigned)L.nx);
@@ -965,6 +950,7 @@ static InterpArgs<T> interp_args(const Plan& p, int64_t M, void* out) {
   a.nbins = (int)p.nbins;
   a.ninst = p.ninst;
   a.move = nullptr;
+  a.move_in = nullptr;
   a.move_a = 0;
   return a;
 }
@@ -975,6 +961,7 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
   if (p.deg != interp_degree<W>()) return hipErrorInvalidValue;  // the kernel's compile-time degree
   InterpArgs<T> a = interp_args<T, DIM, NCH, CPLX, W>(p, M, out);
   a.move = CPLX ? nullptr : move;
+  a.move_in = move;
   a.move_a = move_a;
   const bool prof = prof_on(p, PROF_INTERP);
   if (prof) prof_start(p, st);
@@ -991,12 +978,18 @@ static hipError_t run_interp(Plan& p, int64_t M, void* out, int ntr, hipStream_t
 }
 
 template <typename T, int DIM, int W>
-static hipError_t run_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st) {
+static hipError_t run_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st,
+                                   const GroupMove* mv) {
   constexpr int NCH = DIM;
   std::vector<PartLaunch<InterpArgs<T>>> v(ps.size());
   for (size_t g = 0; g < ps.size(); ++g) {
     if (ps[g]->deg != interp_degree<W>()) return hipErrorInvalidValue;
     v[g].a = interp_args<T, DIM, NCH, false, W>(*ps[g], M[g], out[g]);
+    if (mv) {
+      v[g].a.move = mv->out[g];
+      v[g].a.move_in = mv->in[g];
+      v[g].a.move_a = mv->a[g];
+    }
     const int64_t per_wg = 4 * (int64_t)v[g].a.ppw;
     v[g].nx = (M[g] + per_wg - 1) / per_wg;
   }
@@ -1083,8 +1076,8 @@ static hipError_t spread_group_dispatch(const std::vector<Plan*>& ps, const int6
 
 template <typename T, int DIM>
 static hipError_t interp_group_dispatch(const std::vector<Plan*>& ps, const int64_t* M, void* const* out,
-                                        hipStream_t st) {
-#define CALL_IG(w) run_interp_group<T, DIM, w>(ps, M, out, st)
+                                        hipStream_t st, const GroupMove* mv) {
+#define CALL_IG(w) run_interp_group<T, DIM, w>(ps, M, out, st, mv)
   FSIB_W_SWITCH(ps[0]->w, CALL_IG)
 #undef CALL_IG
 }
@@ -1097,11 +1090,14 @@ hipError_t launch_spread_group(const std::vector<Plan*>& ps, const int64_t* M, c
   return f64 ? spread_group_dispatch<double, 3>(ps, M, str, st) : spread_group_dispatch<float, 3>(ps, M, str, st);
 }
 
-hipError_t launch_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st) {
+hipError_t launch_interp_group(const std::vector<Plan*>& ps, const int64_t* M, void* const* out, hipStream_t st,
+                               const GroupMove* mv) {
   const bool f64 = ps[0]->prec == FSIB_F64;
   if (ps[0]->dim == 2)
-    return f64 ? interp_group_dispatch<double, 2>(ps, M, out, st) : interp_group_dispatch<float, 2>(ps, M, out, st);
-  return f64 ? interp_group_dispatch<double, 3>(ps, M, out, st) : interp_group_dispatch<float, 3>(ps, M, out, st);
+    return f64 ? interp_group_dispatch<double, 2>(ps, M, out, st, mv)
+               : interp_group_dispatch<float, 2>(ps, M, out, st, mv);
+  return f64 ? interp_group_dispatch<double, 3>(ps, M, out, st, mv)
+             : interp_group_dispatch<float, 3>(ps, M, out, st, mv);
 }
 
 }  // namespace fsib
