@@ -22,7 +22,7 @@ CANDIDATES = {
     "xcd_chunk_interp": (0, 16, 64, 256),
     "split": (256, 512, 1024, 2048),
     "interp_points": (4, 8),
-    "nl_stages": (2, 3),  # fused products x pass: 16 x 12 in registers or 8 x 8 x 3 through LDS
+    "nl_stages": (0, 2, 3),  # fused products x pass: per half step (0), 16 x 12 in registers, 8 x 8 x 3 via LDS
 }
 
 
