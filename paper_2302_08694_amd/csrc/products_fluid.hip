@@ -69,9 +69,10 @@ __device__ __forceinline__ void update_mode(const ZFluidArgs<T>& A, int64_t nm, 
 // whose outputs t = i and t = i + 128 are the modes kz = i and kz = i - 64 (t = i + 64 is dropped by
 // the truncation to 128 modes).  With NTHR = 32 NB each thread owns two last-stage butterflies (four
 // modes, 12 complex shat accumulators); the first and middle stages leave a quarter of the threads
-// idle.  Four columns per workgroup (rows of 64 bytes; the neighbouring workgroup, on the same XCD,
-// reads the other half of each 128-byte line): 128^3 FP64 step 1.107 ms, against 1.111 with 8
-// columns, 1.162 with 2, and 1.113 with 4 columns on 64 NB threads (1.157 unfused).
+// idle.  FP64 takes four columns per workgroup (rows of 64 bytes; the neighbouring workgroup, on the
+// same XCD, reads the other half of each 128-byte line): 128^3 step 1.107 ms, against 1.111 with 8
+// columns, 1.162 with 2, and 1.113 with 4 columns on 64 NB threads (1.157 unfused).  FP32 takes
+// eight (rows of 64 bytes again): 0.812 ms against 0.835 with four.
 template <typename T, int NB, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_products_z_fluid(ZFluidArgs<T> A) {
   constexpr int N = kZfN;
@@ -163,7 +164,7 @@ bool products_z_fluid_fits(const Plan& p) {
 template <typename T>
 static hipError_t zf_impl(const Plan& p, int mode, const fsib_fluid_params& prm, const void* fhat, const void* uin,
                           void* uout, hipStream_t st) {
-  constexpr int NB = 4, NTHR = 32 * NB;
+  constexpr int NB = sizeof(T) == 8 ? 4 : 8, NTHR = 32 * NB;
   ZFluidArgs<T> A;
   A.prod = (const cplx<T>*)p.D1;
   A.tw = (const cplx<T>*)p.tw.at(kZfN);
