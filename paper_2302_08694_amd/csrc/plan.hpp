@@ -188,8 +188,9 @@ hipError_t launch_grad_combine(const Plan& p, int64_t M, int kind, const void* u
 hipError_t launch_axpy_positions(const Plan& p, int64_t M, double* Y, const double* X, const void* U,
                                  double a, hipStream_t st);  // Y = X + a*U
 hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t st);
-hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum,
-                       hipStream_t st);  // exclusive, n+1 outputs; seg_sum: scan_segments(n) ints
+// exclusive, n+1 outputs; seg_sum: scan_segments(n) ints; clear (nullable): three ints zeroed
+hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum, hipStream_t st,
+                       int* clear = nullptr);
 int64_t scan_segments(int64_t n);
 // the scan of the tiles' part counts `counts`, whose final pass also writes the spreading work list
 // (points.hip); per plan of a group in one launch per pass

@@ -168,6 +168,7 @@ struct ScanArgs {
   const int* counts;
   int* offsets;
   int* seg_sum;
+  int* clear = nullptr;  // nullable: three counters zeroed by the final pass (the spreading tiles' counters)
 };
 
 template <bool FINAL, int EPT = kScanEpt>
@@ -203,6 +204,7 @@ __device__ __forceinline__ void scan_body(const ScanArgs& A, Blk blk) {
     if (threadIdx.x == 0) seg_sum[blk.x] = total;
     return;
   }
+  if (A.clear && blk.x == 0 && threadIdx.x < 3) A.clear[threadIdx.x] = 0;
   excl += seg_base;
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
@@ -459,8 +461,10 @@ static PartLaunch<RowMaskArgs> row_mask_launch(Plan& p) {
   const int ni = p.dim == 2 ? p.ninst : 1;  // 3D multi-instance plans keep no masks
   const int nrb = (int)(p.nt[1] * p.nt[2]) * ni;
   PartLaunch<RowMaskArgs> L;
+  // the tiles' parts and, directly, the spreading work list (counters cleared by the bin scan)
   const TilePartsArgs tp{p.dim, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[0], (int)p.qn[1], (int)p.qn[2],
-                         p.ninst, p.split, (const int*)p.offsets, p.tile_parts, p.slot_ctr};
+                         p.ninst, p.split, (const int*)p.offsets, p.tile_parts, p.slot_ctr, 1, (int2*)p.work,
+                         p.tile_slot, p.split_list};
   L.a = RowMaskArgs{(int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[1], (int)p.qn[2], ni, (const int*)p.counts,
                     p.rowmask, plane_masks_of(p), tp, (int)p.nbt};
   L.nx = (nrb + p.nbt + 255) / 256;
@@ -493,8 +497,11 @@ __device__ __forceinline__ void scan_fill_body(const ScanFillArgs& A, Blk blk) {
   constexpr int64_t SEG = (int64_t)kScanThreads * EPT;
   scan_body<true, EPT>(A.s, blk);
   __syncthreads();  // the segment's offsets are complete and visible to the workgroup
+  const int64_t n = A.s.n;
   const int64_t t1 = (blk.x + 1) * SEG < (int64_t)A.f.nbins ? (blk.x + 1) * SEG : (int64_t)A.f.nbins;
   for (int64_t t = blk.x * SEG + threadIdx.x; t < t1; t += kScanThreads) fill_work_tile(A.f, (int)t);
+  // the number of entries, from the segment holding the total
+  if (threadIdx.x == 0 && blk.x * SEG <= n && n < (blk.x + 1) * SEG) A.f.slot_ctr[2] = A.s.offsets[n] - (int)n;
 }
 template <int EPT>
 __global__ __launch_bounds__(kScanThreads) void k_scan_fill(ScanFillArgs a) {
@@ -564,9 +571,9 @@ hipError_t launch_scan_fill_work_group(const std::vector<int64_t>& n, const std:
       });
 }
 
-hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum, hipStream_t st) {
+hipError_t launch_scan(int64_t n, const int* counts, int* offsets, int* seg_sum, hipStream_t st, int* clear) {
   const int64_t nseg = scan_segments(n);
-  const ScanArgs a{n, counts, offsets, seg_sum};
+  const ScanArgs a{n, counts, offsets, seg_sum, clear};
   if (n < kScanOnePass) {  // n + 1 outputs in one segment
     hipLaunchKernelGGL((k_scan<true, 8>), dim3(1), dim3(kScanThreads), 0, st, a);
     return hipGetLastError();
@@ -635,7 +642,7 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
                        BinCountArgs{M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag, plane_masks_of(p), (int)p.nt[2]});
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st)) != hipSuccess) return e;
+  if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st, p.slot_ctr)) != hipSuccess) return e;
   // masks: single-instance plans and 2D multi-instance plans
   if ((p.ninst == 1 || p.dim == 2) && (e = launch_row_masks(p, M, st)) != hipSuccess) return e;
   if (M > 0 && p.deterministic) {  // ranks by original index inside each bin
@@ -708,7 +715,7 @@ hipError_t launch_sort_points_group(const std::vector<Plan*>& ps, const int64_t*
     bc[g].a = BinCountArgs{M[g], X[g], make_geo(p), p.counts, p.pt_bin, p.pt_rank, p.flag, plane_masks_of(p),
                            (int)p.nt[2]};
     bc[g].nx = (M[g] + 255) / 256;
-    sc[g] = ScanArgs{p.nbt, p.counts, p.offsets, p.scan_part};
+    sc[g] = ScanArgs{p.nbt, p.counts, p.offsets, p.scan_part, p.slot_ctr};
     if (p.ninst == 1 || p.dim == 2) rm.push_back(row_mask_launch(p));
   }
   hipError_t e = launch_parts(fz, FSIB_PARTS_256(k_fill_zero_parts_one, k_fill_zero_parts, FillArgs));

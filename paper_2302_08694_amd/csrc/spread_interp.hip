@@ -44,7 +44,7 @@ struct SpreadArgs {
   int nt[3];
   int q[3];             // neighbour bins to visit per axis (0..q)
   // work list: entry e = (t, q), q >= 1: workgroup nbins + e spreads candidates [q*split, (q+1)*split) of tile t
-  const int* part_off;  // nbins+1 (exclusive scan of tile_parts)
+  const int* nwork;     // the number of work list entries (the further parts)
   const int2* work;     // (t, q) per part
   const int* tile_parts;
   const int* tile_slot; // first scratch slot of a split tile
@@ -177,7 +177,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs<T>& a, Blk wb) {
     part = 0;
   } else {
     const int e = blk - nbt;
-    if (e >= a.part_off[nbt] - nbt) return;  // beyond the further parts
+    if (e >= a.nwork[0]) return;  // beyond the further parts
     const int2 wk = a.work[e];
     tile_id = wk.x;
     part = wk.y;
@@ -774,7 +774,7 @@ static SpreadArgs<T> spread_args(const Plan& p, int64_t M, const void* str) {
     a.nt[d] = (int)p.nt[d];
     a.q[d] = (int)p.qn[d];
   }
-  a.part_off = p.part_off;
+  a.nwork = p.slot_ctr + 2;
   a.work = (const int2*)p.work;
   a.tile_parts = p.tile_parts;
   a.tile_slot = p.tile_slot;
@@ -793,7 +793,8 @@ static SpreadArgs<T> spread_args(const Plan& p, int64_t M, const void* str) {
 template <int DIM>
 static TilePartsArgs tile_parts_args(const Plan& p) {
   return TilePartsArgs{DIM, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[0], (int)p.qn[1], (int)p.qn[2],
-                       p.ninst, p.split, (const int*)p.offsets, p.tile_parts, p.slot_ctr};
+                       p.ninst, p.split, (const int*)p.offsets, p.tile_parts, p.slot_ctr, 0, nullptr, nullptr,
+                       nullptr};
 }
 
 static FillWorkArgs fill_work_args(const Plan& p) {
@@ -818,13 +819,14 @@ static hipError_t run_spread(Plan& p, int64_t M, const void* str, int ntr, hipSt
     if (e0 != hipSuccess) return e0;
   }
   hipError_t e;
-  if (p.parts_split != p.split) {  // not computed by the sort (with its split)
+  // the sort's row-mask pass built the tiles' parts and the work list with its split; else the parts
+  // here, and their offsets and the work list from a scan
+  if (p.parts_split != p.split) {
     hipLaunchKernelGGL(k_tile_parts, dim3((nb + 255) / 256), dim3(256), 0, st, tile_parts_args<DIM>(p));
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan_fill_work(p.nbt, p.tile_parts, p.part_off, p.scan_part, fill_work_args(p), st)) != hipSuccess)
+      return e;
   }
-  // the parts' offsets, and the work list from the scan's final pass
-  if ((e = launch_scan_fill_work(p.nbt, p.tile_parts, p.part_off, p.scan_part, fill_work_args(p), st)) != hipSuccess)
-    return e;
   const bool prof = prof_on(p, PROF_SPREAD);
   if (prof) prof_start(p, st);
   const dim3 sg((unsigned)p.work_blocks, (unsigned)ntr);
@@ -868,11 +870,11 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
   const size_t n = ps.size();
   std::vector<PartLaunch<SortStrArgs<T>>> ss(n);
   std::vector<PartLaunch<TilePartsArgs>> tp(n);
-  std::vector<FillWorkArgs> fw(n);
+  std::vector<FillWorkArgs> fw;  // the plans whose parts and work list the sort did not build
   std::vector<PartLaunch<SpreadArgs<T>>> sp(n), mg(n);
-  std::vector<int64_t> nbt(n);
-  std::vector<const int*> tparts(n);
-  std::vector<int*> poff(n), spart(n);
+  std::vector<int64_t> nbt;
+  std::vector<const int*> tparts;
+  std::vector<int*> poff, spart;
   for (size_t g = 0; g < n; ++g) {
     Plan& p = *ps[g];
     const SpreadArgs<T> a = spread_args<T, DIM>(p, M[g], str[g]);
@@ -880,22 +882,24 @@ static hipError_t run_spread_group(const std::vector<Plan*>& ps, const int64_t* 
     ss[g].nx = p.sstr_src == str[g] ? 0 : (M[g] + 255) / 256;  // placed by the sort's scatter
     tp[g].a = tile_parts_args<DIM>(p);
     tp[g].nx = p.parts_split == p.split ? 0 : (p.nbt + 255) / 256;  // computed by the sort
-    fw[g] = fill_work_args(p);
+    if (p.parts_split != p.split) {
+      fw.push_back(fill_work_args(p));
+      nbt.push_back(p.nbt);
+      tparts.push_back(p.tile_parts);
+      poff.push_back(p.part_off);
+      spart.push_back(p.scan_part);
+    }
     sp[g].a = a;
     sp[g].nx = p.work_blocks;
     sp[g].threads = plan_spread_threads<DIM, T>(p);
     mg[g].a = a;
     mg[g].nx = merge_blocks(p);
-    nbt[g] = p.nbt;
-    tparts[g] = p.tile_parts;
-    poff[g] = p.part_off;
-    spart[g] = p.scan_part;
   }
   hipError_t e = launch_parts(ss, FSIB_PARTS((k_sort_strengths<T, NCH, false>), (k_sort_strengths_parts<T, NCH, false>),
                                              SortStrArgs<T>, 256));
   if (e != hipSuccess) return e;
   if ((e = launch_parts(tp, FSIB_PARTS(k_tile_parts, k_tile_parts_parts, TilePartsArgs, 256))) != hipSuccess) return e;
-  if ((e = launch_scan_fill_work_group(nbt, tparts, poff, spart, fw, st)) != hipSuccess) return e;
+  if (!fw.empty() && (e = launch_scan_fill_work_group(nbt, tparts, poff, spart, fw, st)) != hipSuccess) return e;
   // parts with different spreading variants run as launches of their own (launch_parts)
   const auto one = [&](const PartLaunch<SpreadArgs<T>>& L) {
     const dim3 g1((unsigned)L.nx);
