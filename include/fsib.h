@@ -196,8 +196,11 @@ typedef enum {
 fsib_status fsib_plan_profile(fsib_plan plan, int kernel_class, int max_launches);
 /* Read (get = 1) or set (get = 0) the launch-shape knobs, e.g. for a timed autotuning search.
  * Results are identical up to the summation order of spreading.  split may not go below the value
- * the plan was created with (its scratch is sized for it; the creation value is 256 for plans of at
- * most 2^18 points, else 512).  Errors:
+ * the plan was created with (its scratch is sized for it).  The creation value is 256 for plans of
+ * at most 2^18 points (128 for FP32 Navier-Stokes ones), else 512; the environment variable
+ * FSIB_SPREAD_SPLIT, read at plan creation, replaces it (clamped to [64, 2^20]), and
+ * FSIB_XCD_CHUNK_INTERP and FSIB_XCD_CHUNK_SPREAD likewise replace the two chunk defaults (values
+ * outside [0, 4096] ignored).  Errors:
  * FSIB_ERR_ARG for NULL or out-of-range values (chunks in [0, 4096], split in [creation, 1 << 20],
  * overlap 0 or 1, interp_points 1, 2, 4, 8 or 16, spread_threads as above, nl_stages 0, 2 or 3). */
 fsib_status fsib_plan_tuning(fsib_plan plan, fsib_tuning* tuning, int get);

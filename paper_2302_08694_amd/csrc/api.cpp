@@ -193,9 +193,15 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
   FSIB_HIP(hipGetDevice(&p.device));
   FSIB_HIP(hipDeviceGetAttribute(&p.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
   // workgroup-to-XCD run lengths (tuning knobs; the defaults are the measured best)
-  if (const char* e = std::getenv("FSIB_XCD_CHUNK_INTERP")) p.xcd_chunk_interp = std::atoi(e);
-  if (const char* e = std::getenv("FSIB_XCD_CHUNK_SPREAD")) p.xcd_chunk_spread = std::atoi(e);
-  if (const char* e = std::getenv("FSIB_SPREAD_SPLIT")) p.split = std::atoi(e) >= 64 ? std::atoi(e) : 64;
+  // (the environment may replace them at creation; values outside [0, 4096] are ignored)
+  auto env_chunk = [](const char* name, int& v) {
+    if (const char* e = std::getenv(name)) {
+      const int c = std::atoi(e);
+      if (c >= 0 && c <= 4096) v = c;
+    }
+  };
+  env_chunk("FSIB_XCD_CHUNK_INTERP", p.xcd_chunk_interp);
+  env_chunk("FSIB_XCD_CHUNK_SPREAD", p.xcd_chunk_spread);
   // kernel (App. A.3): width from tol, Kaiser-Bessel shape, polynomial degree
   p.sigma = plan_sigma(o);
   p.w = fsib::choose_width(p.tol, p.dim, p.sigma);
@@ -293,10 +299,17 @@ fsib_status build_plan(Plan& p, const fsib_plan_opts* o) {
       reach *= q + 1;
     }
     const int64_t visits = Mx * reach;
-    // crowded tiles split into parts of 256 candidates (measured best at the 128^3 surface step:
-    // 1.186 -> 1.174 ms, 128 slower); plans of many points keep 512, which halves the bound on the
-    // partial-tile scratch
-    p.split = Mx <= ((int64_t)1 << 18) ? 256 : 512;
+    // crowded tiles split into parts of 256 candidates (measured best for the FP64 step of the 128^3
+    // surface: 1.099 ms against 1.104 with 192 and 1.108 with 128), 128 in FP32 Navier-Stokes plans
+    // (0.792 against 0.799 ms with 256: at oversampling 2 the tiles are smaller against the kernel);
+    // plans of many points keep 512, which halves the bound on the partial-tile scratch
+    p.split = Mx <= ((int64_t)1 << 18) ? (p.ns && p.prec == FSIB_F32 ? 128 : 256) : 512;
+    // FSIB_SPREAD_SPLIT overrides it at creation (clamped to [64, 2^20]); the tuning knob can only
+    // raise it
+    if (const char* e = std::getenv("FSIB_SPREAD_SPLIT")) {
+      const int v = std::atoi(e);
+      p.split = v < 64 ? 64 : (v > (1 << 20) ? (1 << 20) : v);
+    }
     p.split_alloc = p.split;
     p.work_blocks = p.nbt + visits / p.split + 1;
     p.split_slots = 2 * visits / p.split + 2;

@@ -207,3 +207,24 @@ def test_tuning_knobs_keep_results(F):
     assert res["best"] == plan.tuning()
     print(f"autotune chose {res['best']} ({len(res['trials'])} trials)")
     plan.close()
+
+
+def test_environment_knobs_at_creation(F, monkeypatch):
+    """FSIB_SPREAD_SPLIT and the XCD chunk variables replace the defaults when a plan is created
+    (split below the default, its scratch sized for it; out-of-range chunks ignored); results agree
+    to rounding with a default plan's."""
+    import workloads as wl
+    announce("environment knobs at plan creation")
+    X0, c0 = wl.nufft_points(3000, seed=7, dim=3)
+    X, c = dev(X0), dev(c0)
+    ref_plan = F.Plan(3, (24, 24, 24), prec="f64", tol=1e-10, max_points=3000)
+    ref = host(ref_plan.spread(X, c))
+    ref_plan.close()
+    monkeypatch.setenv("FSIB_SPREAD_SPLIT", "96")
+    monkeypatch.setenv("FSIB_XCD_CHUNK_INTERP", "0")
+    monkeypatch.setenv("FSIB_XCD_CHUNK_SPREAD", "5000")
+    plan = F.Plan(3, (24, 24, 24), prec="f64", tol=1e-10, max_points=3000)
+    t = plan.tuning()
+    assert (t["split"], t["xcd_chunk_interp"], t["xcd_chunk_spread"]) == (96, 0, 16)
+    assert rel_l2(host(plan.spread(X, c)), ref) < 1e-13
+    plan.close()
