@@ -237,14 +237,21 @@ __global__ void k_force_curve(int64_t M, const double* __restrict__ X, double K,
 
 // Surface tension, Sec. 6.2.3: F_i = -(gamma/2) sum over incident triangles (i, j, k) (in the
 // triangle's cyclic order starting at i) of (X_j - X_k) x n, n the unit normal of (X_i, X_j, X_k).
-// Eight lanes per vertex: lane l takes the incident triangles l, l + 8, ... of the vertex (most
-// vertices of a triangulated surface have about six; a polar fan vertex of a lat-long mesh has
-// hundreds) and the lanes are summed by a fixed butterfly.  (One wavefront per vertex left 58 of 64
-// lanes idle on most vertices: 23 us against 6 us for the 40,000-vertex ellipsoid.)
+// A workgroup takes 32 vertices.  Their incident triangles (entries of the vertex -> triangle CSR)
+// are spread evenly over the workgroup's 256 lanes, four per lane with their loads issued together,
+// and each triangle's term goes to LDS; then eight lanes per vertex sum its terms, lane l the terms
+// l, l + 8, ... in order, and a fixed butterfly sums the lanes.  The per-triangle work is thus
+// balanced whatever the degrees: a polar fan vertex of a lat-long mesh (about 200 triangles) no
+// longer holds its workgroup for seven rounds of dependent loads (the 40,000-vertex ellipsoid: 27.9
+// -> 9 us).  A workgroup whose vertices have more than kSurfTris triangles in all takes them per
+// vertex instead (eight lanes per vertex, the same summation order).
 // S64 / S32 (nullable): the strengths S = F (quadrature weight 1) in the plan precision, written in
 // the same pass.  UK = 1 or 2: the force is taken at X + a U (U in FP64 or FP32), positions the kernel
 // forms as it reads them and also writes to Xh, so the half-step move and the force are one pass.
 constexpr int kSurfLanes = 8;
+constexpr int kSurfThreads = 256;
+constexpr int kSurfVerts = kSurfThreads / kSurfLanes;  // vertices per workgroup
+constexpr int kSurfTris = 4 * kSurfThreads;           // triangle terms a workgroup holds in LDS
 struct SurfaceArgs {
   int64_t M;
   const double* X;
@@ -268,55 +275,128 @@ __device__ __forceinline__ double surf_pos(const SurfaceArgs& A, int64_t v, int 
   return x;
 }
 
+// The other two corners (j, k) of triangle t in its cyclic order starting at vertex i.
+__device__ __forceinline__ void surf_corners(const SurfaceArgs& A, int t, int i, int& j, int& k) {
+  const int v0 = A.tris[3 * t], v1 = A.tris[3 * t + 1], v2 = A.tris[3 * t + 2];
+  if (v0 == i) {
+    j = v1;
+    k = v2;
+  } else if (v1 == i) {
+    j = v2;
+    k = v0;
+  } else {
+    j = v0;
+    k = v1;
+  }
+}
+
+// The term (X_j - X_k) x n of triangle (i, j, k), X_i = (xi, yi, zi).
 template <int UK>
-__global__ __launch_bounds__(256) void k_force_surface(SurfaceArgs A) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = g / kSurfLanes;
-  const int lane = (int)(g % kSurfLanes);
-  if (i >= A.M) return;  // uniform per group of kSurfLanes lanes
-  double f0 = 0, f1 = 0, f2 = 0;
-  const double xi = surf_pos<UK>(A, i, 0), yi = surf_pos<UK>(A, i, 1), zi = surf_pos<UK>(A, i, 2);
-  // four triangles per lane and round, their loads issued together: a polar fan vertex (hundreds of
-  // triangles) would otherwise wait on a chain of dependent loads per triangle
-  const int e1 = A.ptr[i + 1];
-  for (int e0 = A.ptr[i] + lane; e0 < e1; e0 += 4 * kSurfLanes) {
-    int tt[4];
+__device__ __forceinline__ void surf_term(const SurfaceArgs& A, int j, int k, double xi, double yi, double zi,
+                                          double& t0, double& t1, double& t2) {
+  const double ax = surf_pos<UK>(A, j, 0) - xi, ay = surf_pos<UK>(A, j, 1) - yi, az = surf_pos<UK>(A, j, 2) - zi;
+  const double bx = surf_pos<UK>(A, k, 0) - xi, by = surf_pos<UK>(A, k, 1) - yi, bz = surf_pos<UK>(A, k, 2) - zi;
+  double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+  const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+  if (nn > 0) {
+    nx /= nn;
+    ny /= nn;
+    nz /= nn;
+  }
+  const double dx = ax - bx, dy = ay - by, dz = az - bz;  // X_j - X_k
+  t0 = dy * nz - dz * ny;
+  t1 = dz * nx - dx * nz;
+  t2 = dx * ny - dy * nx;
+}
+
+template <int UK>
+__global__ __launch_bounds__(kSurfThreads) void k_force_surface(SurfaceArgs A) {
+  __shared__ int s_beg[kSurfVerts + 1];    // the workgroup's terms: vertex s owns [s_beg[s], s_beg[s + 1])
+  __shared__ int s_ptr[kSurfVerts];        // CSR offset of each vertex's first triangle
+  __shared__ double s_pos[kSurfVerts][3];  // (moved) vertex positions
+  __shared__ double s_term[3][kSurfTris];
+  const int tid = threadIdx.x;
+  const int64_t v0 = (int64_t)blockIdx.x * kSurfVerts;
+  // degrees and their prefix sums (wavefront 0: one lane per vertex, a shuffle scan)
+  if (tid < 64) {
+    const int64_t v = v0 + tid;
+    int deg = 0;
+    if (tid < kSurfVerts && v < A.M) {
+      const int p0 = A.ptr[v];
+      deg = A.ptr[v + 1] - p0;
+      s_ptr[tid] = p0;
+      s_pos[tid][0] = surf_pos<UK>(A, v, 0);
+      s_pos[tid][1] = surf_pos<UK>(A, v, 1);
+      s_pos[tid][2] = surf_pos<UK>(A, v, 2);
+    }
+    int incl = deg;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) tt[u] = e0 + u * kSurfLanes < e1 ? A.idx[e0 + u * kSurfLanes] : -1;
-    int jj[4], kk[4];
+    for (int off = 1; off < kSurfVerts; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if ((tid & 63) >= off) incl += y;
+    }
+    if (tid < kSurfVerts) s_beg[tid + 1] = incl;
+    if (tid == 0) s_beg[0] = 0;
+  }
+  __syncthreads();
+  const int total = s_beg[kSurfVerts];
+  const int vs = tid / kSurfLanes, lane = tid % kSurfLanes;
+  const int64_t i = v0 + vs;
+  double f0 = 0, f1 = 0, f2 = 0;
+  if (total <= kSurfTris) {
+    // every term of the workgroup: entry e of vertex s (upper bound of e in s_beg), four per lane
+    int jj[4], kk[4], ss[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      jj[u] = kk[u] = (int)i;
-      if (tt[u] < 0) continue;
-      const int v0 = A.tris[3 * tt[u]], v1 = A.tris[3 * tt[u] + 1], v2 = A.tris[3 * tt[u] + 2];
-      if (v0 == i) {
-        jj[u] = v1;
-        kk[u] = v2;
-      } else if (v1 == i) {
-        jj[u] = v2;
-        kk[u] = v0;
-      } else {
-        jj[u] = v0;
-        kk[u] = v1;
+      const int e = tid + u * kSurfThreads;
+      ss[u] = -1;
+      if (e < total) {
+        int lo = 0, hi = kSurfVerts;  // the last s with s_beg[s] <= e
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_beg[mid] <= e) lo = mid;
+          else hi = mid;
+        }
+        ss[u] = lo;
+        const int t = A.idx[s_ptr[lo] + (e - s_beg[lo])];
+        surf_corners(A, t, (int)(v0 + lo), jj[u], kk[u]);
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (tt[u] < 0) continue;
-      const int j = jj[u], k = kk[u];
-      const double ax = surf_pos<UK>(A, j, 0) - xi, ay = surf_pos<UK>(A, j, 1) - yi, az = surf_pos<UK>(A, j, 2) - zi;
-      const double bx = surf_pos<UK>(A, k, 0) - xi, by = surf_pos<UK>(A, k, 1) - yi, bz = surf_pos<UK>(A, k, 2) - zi;
-      double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
-      const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-      if (nn > 0) {
-        nx /= nn;
-        ny /= nn;
-        nz /= nn;
+      if (ss[u] < 0) continue;
+      const int e = tid + u * kSurfThreads;
+      double t0, t1, t2;
+      surf_term<UK>(A, jj[u], kk[u], s_pos[ss[u]][0], s_pos[ss[u]][1], s_pos[ss[u]][2], t0, t1, t2);
+      s_term[0][e] = t0;
+      s_term[1][e] = t1;
+      s_term[2][e] = t2;
+    }
+    __syncthreads();
+    const int e1 = s_beg[vs + 1];
+    for (int e = s_beg[vs] + lane; e < e1; e += kSurfLanes) {
+      f0 += s_term[0][e];
+      f1 += s_term[1][e];
+      f2 += s_term[2][e];
+    }
+  } else if (i < A.M) {
+    // per vertex: lane l takes the vertex's triangles l, l + 8, ..., four per round
+    const double xi = s_pos[vs][0], yi = s_pos[vs][1], zi = s_pos[vs][2];
+    const int e1 = s_ptr[vs] + (s_beg[vs + 1] - s_beg[vs]);
+    for (int e0 = s_ptr[vs] + lane; e0 < e1; e0 += 4 * kSurfLanes) {
+      int jj[4], kk[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * kSurfLanes < e1) surf_corners(A, A.idx[e0 + u * kSurfLanes], (int)i, jj[u], kk[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (e0 + u * kSurfLanes >= e1) continue;
+        double t0, t1, t2;
+        surf_term<UK>(A, jj[u], kk[u], xi, yi, zi, t0, t1, t2);
+        f0 += t0;
+        f1 += t1;
+        f2 += t2;
       }
-      const double dx = ax - bx, dy = ay - by, dz = az - bz;  // X_j - X_k
-      f0 += dy * nz - dz * ny;
-      f1 += dz * nx - dx * nz;
-      f2 += dx * ny - dy * nx;
     }
   }
 #pragma unroll
@@ -325,7 +405,7 @@ __global__ __launch_bounds__(256) void k_force_surface(SurfaceArgs A) {
     f1 += __shfl_xor(f1, off, 64);
     f2 += __shfl_xor(f2, off, 64);
   }
-  if (lane == 0) {
+  if (lane == 0 && i < A.M) {
     const double g0 = -0.5 * A.gamma * f0, g1 = -0.5 * A.gamma * f1, g2 = -0.5 * A.gamma * f2;
     A.F[3 * i] = g0;
     A.F[3 * i + 1] = g1;
@@ -341,21 +421,21 @@ __global__ __launch_bounds__(256) void k_force_surface(SurfaceArgs A) {
       A.S32[3 * i + 2] = (float)g2;
     }
     if (UK > 0) {
-      A.Xh[3 * i] = xi;
-      A.Xh[3 * i + 1] = yi;
-      A.Xh[3 * i + 2] = zi;
+      A.Xh[3 * i] = s_pos[vs][0];
+      A.Xh[3 * i + 1] = s_pos[vs][1];
+      A.Xh[3 * i + 2] = s_pos[vs][2];
     }
   }
 }
 
 static hipError_t launch_surface(const SurfaceArgs& A, int uk, hipStream_t st) {
-  const unsigned nblk = (unsigned)((A.M * kSurfLanes + 255) / 256);
+  const unsigned nblk = (unsigned)((A.M + kSurfVerts - 1) / kSurfVerts);
   if (uk == 1)
-    hipLaunchKernelGGL(k_force_surface<1>, dim3(nblk), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_force_surface<1>, dim3(nblk), dim3(kSurfThreads), 0, st, A);
   else if (uk == 2)
-    hipLaunchKernelGGL(k_force_surface<2>, dim3(nblk), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_force_surface<2>, dim3(nblk), dim3(kSurfThreads), 0, st, A);
   else
-    hipLaunchKernelGGL(k_force_surface<0>, dim3(nblk), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_force_surface<0>, dim3(nblk), dim3(kSurfThreads), 0, st, A);
   return hipGetLastError();
 }
 
