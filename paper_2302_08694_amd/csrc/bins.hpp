@@ -22,6 +22,7 @@ struct TilePartsArgs {
   int2* work;
   int* tile_slot;
   int* split_list;
+  const int* counts = nullptr;  // the bin counts, read instead of offset differences when not null
 };
 
 // Tile tg of all instances (tg < nt0 nt1 nt2 ninst).
@@ -44,7 +45,7 @@ __device__ __forceinline__ void tile_parts_at(const TilePartsArgs& A, int tg) {
       for (int dx = 0; dx <= q0; ++dx) {
         const int bx = (tx - dx + nt0) % nt0, by = (ty - dy + nt1) % nt1, bz = dim == 3 ? (tz - dz + nt2) % nt2 : 0;
         const int b = bx + nt0 * (by + nt1 * bz) + inst * nbins;
-        total += offsets[b + 1] - offsets[b];
+        total += A.counts ? A.counts[b] : offsets[b + 1] - offsets[b];
       }
   const int np = total <= split ? 1 : (total + split - 1) / split;
   A.tile_parts[tg] = np;

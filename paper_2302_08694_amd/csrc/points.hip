@@ -72,6 +72,7 @@ struct BinCountArgs {
   int* flag;
   uint8_t* zclear;  // plane masks cleared by workgroup 0 before k_row_masks sets them (nullable)
   int nz;
+  int* clear = nullptr;  // three counters zeroed by workgroup 0 (the spreading tiles' counters; nullable)
 };
 
 __device__ __forceinline__ void bin_count(const BinCountArgs& A, Blk blk) {
@@ -82,6 +83,7 @@ __device__ __forceinline__ void bin_count(const BinCountArgs& A, Blk blk) {
   int* __restrict__ flag = A.flag;
   if (A.zclear && blk.x == 0)
     for (int k = threadIdx.x; k < A.nz; k += blockDim.x) A.zclear[k] = 0;
+  if (A.clear && blk.x == 0 && threadIdx.x < 3) A.clear[threadIdx.x] = 0;
   const int64_t j = blk.x * blockDim.x + threadIdx.x;
   const bool valid = j < M;
   int bin = -1;
@@ -461,10 +463,11 @@ static PartLaunch<RowMaskArgs> row_mask_launch(Plan& p) {
   const int ni = p.dim == 2 ? p.ninst : 1;  // 3D multi-instance plans keep no masks
   const int nrb = (int)(p.nt[1] * p.nt[2]) * ni;
   PartLaunch<RowMaskArgs> L;
-  // the tiles' parts and, directly, the spreading work list (counters cleared by the bin scan)
+  // the tiles' parts (from the bin counts, which the scatter clears only later) and, directly, the
+  // spreading work list (counters cleared by the bin scan or the bin count)
   const TilePartsArgs tp{p.dim, (int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[0], (int)p.qn[1], (int)p.qn[2],
                          p.ninst, p.split, (const int*)p.offsets, p.tile_parts, p.slot_ctr, 1, (int2*)p.work,
-                         p.tile_slot, p.split_list};
+                         p.tile_slot, p.split_list, (const int*)p.counts};
   L.a = RowMaskArgs{(int)p.nt[0], (int)p.nt[1], (int)p.nt[2], (int)p.qn[1], (int)p.qn[2], ni, (const int*)p.counts,
                     p.rowmask, plane_masks_of(p), tp, (int)p.nbt};
   L.nx = (nrb + p.nbt + 255) / 256;
@@ -484,6 +487,24 @@ hipError_t launch_row_masks(Plan& p, int64_t M, hipStream_t st) {
 }
 
 int64_t scan_segments(int64_t n) { return n / kScanSeg + 1; }
+
+// The bin scan and the row-mask pass of one plan in one launch: workgroup 0 scans the bin counts (at
+// most kScanMaskBins bins, 32 per thread) while the others compute the masks and the tiles' parts,
+// which read the counts, not the offsets.  The spreading tiles' counters are then cleared by the bin
+// count.  Both halves have a latency-bound chain of a few microseconds; side by side they take one.
+constexpr int kScanMaskEpt = 32;
+constexpr int64_t kScanMaskBins = 256 * kScanMaskEpt - 1;  // n + 1 offsets from 256 threads
+struct ScanMaskArgs {
+  ScanArgs s;
+  RowMaskArgs m;
+};
+__global__ __launch_bounds__(256) void k_scan_row_masks(ScanMaskArgs a) {
+  if (blockIdx.x == 0) {
+    scan_body<true, kScanMaskEpt>(a.s, Blk{0, 0, 1, 1});
+    return;
+  }
+  row_masks(a.m, Blk{(int64_t)blockIdx.x - 1, 0, (int64_t)gridDim.x - 1, 1});
+}
 
 // The scan of the tiles' part counts with the spreading work list: the final pass's workgroup for a
 // segment, once it has written that segment's offsets, lists the further parts of the segment's tiles
@@ -636,15 +657,26 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
   if (!p.counts_zero && (e = launch_fill_zero(p.counts, (p.nbt + 1) * (int64_t)sizeof(int), st)) != hipSuccess)
     return e;
   p.counts_zero = true;  // after this sort: zero again (its scatter clears them; with M = 0 nothing is counted)
+  // masks: single-instance plans and 2D multi-instance plans; with points counted and few bins the
+  // scan runs inside the row-mask launch
+  const bool masks = p.ninst == 1 || p.dim == 2;
+  const bool fused = masks && M > 0 && p.nbt <= kScanMaskBins;
   if (M > 0) {
     const unsigned nblk = (unsigned)((M + 255) / 256);
     hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, st,
-                       BinCountArgs{M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag, plane_masks_of(p), (int)p.nt[2]});
+                       BinCountArgs{M, X, g, p.counts, p.pt_bin, p.pt_rank, p.flag, plane_masks_of(p), (int)p.nt[2],
+                                    fused ? p.slot_ctr : nullptr});
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st, p.slot_ctr)) != hipSuccess) return e;
-  // masks: single-instance plans and 2D multi-instance plans
-  if ((p.ninst == 1 || p.dim == 2) && (e = launch_row_masks(p, M, st)) != hipSuccess) return e;
+  if (fused) {
+    const PartLaunch<RowMaskArgs> r = row_mask_launch(p);
+    const ScanMaskArgs a{ScanArgs{p.nbt, p.counts, p.offsets, p.scan_part, nullptr}, r.a};
+    hipLaunchKernelGGL(k_scan_row_masks, dim3((unsigned)r.nx + 1), dim3(256), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st, p.slot_ctr)) != hipSuccess) return e;
+    if (masks && (e = launch_row_masks(p, M, st)) != hipSuccess) return e;
+  }
   if (M > 0 && p.deterministic) {  // ranks by original index inside each bin
     const unsigned nblk = (unsigned)((M + 255) / 256);
     hipLaunchKernelGGL(k_bin_place, dim3(nblk), dim3(256), 0, st, M, (const int*)p.offsets, (const int*)p.pt_bin,
