@@ -488,19 +488,21 @@ hipError_t launch_row_masks(Plan& p, int64_t M, hipStream_t st) {
 
 int64_t scan_segments(int64_t n) { return n / kScanSeg + 1; }
 
-// The bin scan and the row-mask pass of one plan in one launch: workgroup 0 scans the bin counts (at
-// most kScanMaskBins bins, 32 per thread) while the others compute the masks and the tiles' parts,
-// which read the counts, not the offsets.  The spreading tiles' counters are then cleared by the bin
-// count.  Both halves have a latency-bound chain of a few microseconds; side by side they take one.
-constexpr int kScanMaskEpt = 32;
-constexpr int64_t kScanMaskBins = 256 * kScanMaskEpt - 1;  // n + 1 offsets from 256 threads
+// The bin scan and the row-mask pass of one plan in one launch of 1024-thread workgroups: workgroup 0
+// scans the bin counts (EPT per thread, at most kScanMaskBins bins) while the others compute the masks
+// and the tiles' parts, which read the counts, not the offsets.  The spreading tiles' counters are then
+// cleared by the bin count.  Both halves are latency-bound chains of a few microseconds; side by side
+// they take one.
+constexpr int kScanMaskThreads = kScanThreads;
+constexpr int64_t kScanMaskBins = (int64_t)kScanMaskThreads * 24 - 1;  // n + 1 offsets at 24 per thread
 struct ScanMaskArgs {
   ScanArgs s;
   RowMaskArgs m;
 };
-__global__ __launch_bounds__(256) void k_scan_row_masks(ScanMaskArgs a) {
+template <int EPT>
+__global__ __launch_bounds__(kScanMaskThreads) void k_scan_row_masks(ScanMaskArgs a) {
   if (blockIdx.x == 0) {
-    scan_body<true, kScanMaskEpt>(a.s, Blk{0, 0, 1, 1});
+    scan_body<true, EPT>(a.s, Blk{0, 0, 1, 1});
     return;
   }
   row_masks(a.m, Blk{(int64_t)blockIdx.x - 1, 0, (int64_t)gridDim.x - 1, 1});
@@ -671,7 +673,12 @@ hipError_t launch_sort_points(Plan& p, int64_t M, const double* X, hipStream_t s
   if (fused) {
     const PartLaunch<RowMaskArgs> r = row_mask_launch(p);
     const ScanMaskArgs a{ScanArgs{p.nbt, p.counts, p.offsets, p.scan_part, nullptr}, r.a};
-    hipLaunchKernelGGL(k_scan_row_masks, dim3((unsigned)r.nx + 1), dim3(256), 0, st, a);
+    const int nrb = (int)(p.nt[1] * p.nt[2]) * (p.dim == 2 ? (int)p.ninst : 1);
+    const dim3 grid((unsigned)((nrb + p.nbt + kScanMaskThreads - 1) / kScanMaskThreads + 1));
+    if (p.nbt < (int64_t)kScanMaskThreads * 8)
+      hipLaunchKernelGGL(k_scan_row_masks<8>, grid, dim3(kScanMaskThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_scan_row_masks<24>, grid, dim3(kScanMaskThreads), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else {
     if ((e = launch_scan(p.nbt, p.counts, p.offsets, p.scan_part, st, p.slot_ctr)) != hipSuccess) return e;
