@@ -94,6 +94,26 @@ def test_surface_tension_force(F):
     assert rel_l2(out, ref) < 1e-13
 
 
+@pytest.mark.parametrize("K", [200, 1200])
+def test_surface_tension_force_high_degree(F, K):
+    """A bipyramid: two apexes joined to a ring of K vertices, so the apexes have degree K.  With K = 200
+    the first workgroup's 32 vertices hold 520 triangle terms, spread over its lanes; with K = 1200
+    they hold 2,520, past what a workgroup keeps in LDS, and take the per-vertex path."""
+    announce(f"surface tension force, bipyramid of {K} ring vertices")
+    rng = np.random.default_rng(27)
+    t = 2 * np.pi * np.arange(K) / K
+    ring = np.stack([0.5 + 0.3 * np.cos(t), 0.5 + 0.25 * np.sin(t), 0.5 + 0.01 * rng.standard_normal(K)], axis=1)
+    X = np.concatenate([[[0.5, 0.5, 0.8], [0.5, 0.5, 0.2]], ring]) + 1e-3 * rng.standard_normal((K + 2, 3))
+    i = np.arange(K)
+    a, b = 2 + i, 2 + (i + 1) % K
+    tris = np.concatenate([np.stack([np.zeros(K, int), a, b], 1), np.stack([np.ones(K, int), b, a], 1)]).astype(np.int32)
+    ptr, idx = workloads.vertex_triangle_csr(tris, X.shape[0])
+    force = F.Force("surface3d", 1.3, dev(tris), dev(ptr), dev(idx))
+    out = host(F.compute_force(force, dev(X)))
+    ref = forces.surface_tension_force_3d(X, tris, 1.3)
+    assert rel_l2(out, ref) < 1e-13
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("Ns", [(16, 12), (12, 10, 8), (9, 10, 11)])
 def test_fluid_step_stokes(F, prec, Ns):
